@@ -1,0 +1,198 @@
+/*
+ * ddsolve.h -- C ABI of the MI355X (gfx950) Clover-Wilson quark solver:
+ * Dirac apply, SAP domain-decomposition preconditioner, BiCGStab with
+ * mixed-precision defect correction.
+ *
+ * The operator is the Clover-Wilson Dirac matrix of arXiv 2109.10687,
+ * appendix "Clover-Wilson Dirac operator":
+ *
+ *     D = 1 + C - kappa H,
+ *     (H x)(n) = sum_mu [ (1 - gamma_mu) U_mu(n) x(n+mu)
+ *                        + (1 + gamma_mu) U_mu(n-mu)^dagger x(n-mu) ],
+ *     C = (i/2) kappa c_SW sigma_{mu nu} F_{mu nu}(n)   (four-leaf F),
+ *
+ * with the gamma matrices printed there (Dirac representation, gamma_4
+ * diagonal), and A = C_inv D = I - kappa C_inv H with C_inv = (1 + C)^{-1}
+ * (Sec. 3).  The Schwarz preconditioner M_SAP is Alg. 1 of Sec. 3 with the
+ * block Jacobi of Alg. 2; BiCGStab is Alg. 5; the mixed-precision outer loop
+ * is the defect correction of Alg. 4.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Lattice dims = {Lx, Ly, Lz, Lt}; direction mu = 0..3 is the paper's
+ *    mu = 1..4 (mu = 3 is the direction of gamma_4).  Lexicographic site
+ *    index n = x + Lx*(y + Ly*(z + Lz*t)).
+ *  - Canonical spinor field: complex double (re, im interleaved), layout
+ *    [Lt][Lz][Ly][Lx][colour 3][spin 4] -- the paper's K-computer order
+ *    (Sec. 4): colour outer, spin inner.  24 doubles per site.
+ *  - Canonical gauge field: complex double, [mu 4][Lt][Lz][Ly][Lx][3][3],
+ *    U_mu(n)[a][b] row-major.  Links should be SU(3); the 12-real FP16 copy
+ *    rebuilds the third row from the first two, which holds only for SU(3).
+ *  - Boundary conditions are not stated in the paper: a hop that crosses
+ *    the lattice edge in direction mu is multiplied by phase_mu (forward)
+ *    or conj(phase_mu) (backward).  {1, 1, 1, -1} is periodic in space and
+ *    antiperiodic in time.  The clover term is built from the links alone.
+ *  - All *_dev pointers are device (HBM) addresses owned by the caller;
+ *    the library never frees them.  The library owns its packed fields and
+ *    work vectors: they are allocated in dd_create / dd_load_gauge and freed
+ *    in dd_destroy.  No entry point allocates device memory during a solve.
+ *  - Work runs on the HIP stream given to dd_create (NULL = default stream).
+ *    dirac_apply and sap_precondition are asynchronous on that stream;
+ *    bicgstab_solve synchronises it.
+ *  - Every function returns a dd_status and never throws.  A negative status
+ *    means the outputs were not written; dd_last_error gives the reason.
+ *  - A context is not thread-safe: use one context per host thread.
+ */
+#ifndef DDSOLVE_H
+#define DDSOLVE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DD_OK = 0,
+    DD_NOT_CONVERGED = 1,      /* maxiter reached; x holds the last iterate       */
+    DD_BREAKDOWN = 2,          /* a BiCGStab denominator vanished or went non-finite */
+    DD_ERR_ARG = -1,           /* null pointer, bad enum, bad tolerance            */
+    DD_ERR_GEOMETRY = -2,      /* dims/blocks not compatible (see dd_params)       */
+    DD_ERR_HIP = -3,           /* a HIP runtime call failed                        */
+    DD_ERR_NOMEM = -4,         /* device allocation failed in dd_create            */
+    DD_ERR_NONFINITE = -5,     /* the source or the gauge field holds NaN or Inf   */
+    DD_ERR_CLOVER_NOT_PD = -6, /* 1 + C is not positive definite at some site      */
+    DD_ERR_STATE = -7          /* no gauge field loaded yet                        */
+} dd_status;
+
+typedef enum { DD_F64 = 0, DD_F32 = 1, DD_F16 = 2 } dd_prec;
+
+typedef enum {
+    DD_OP_D = 0,    /* D x = (1 + C) x - kappa H x                         */
+    DD_OP_A = 1,    /* A x = x - kappa C_inv H x                           */
+    DD_OP_DDAG = 2  /* D^dagger x = gamma_5 D gamma_5 x                    */
+} dd_op;
+
+typedef enum {
+    /* plain BiCGStab (Alg. 5 without preconditioner) on D in FP64; tol is the
+     * true relative residual |b - D x| / |b|, recomputed at exit */
+    DD_SOLVE_F64_PLAIN = 0,
+    /* BiCGStab on A M_SAP in FP32 with an FP32 SAP preconditioner, source
+     * C_inv b, zero start (Alg. 5 as printed); tol is Alg. 5's test on the
+     * recursive FP32 residual of the A-system */
+    DD_SOLVE_F32_SAP = 1,
+    /* defect correction (Alg. 4) in FP64 around FP32 SAP-BiCGStab with an FP16
+     * preconditioner (per-site-scaled FP16 spinors, 12-real FP16 links, FP16
+     * C_inv); tol is the true FP64 relative residual |b - D x| / |b| */
+    DD_SOLVE_MIXED = 2
+} dd_solve_mode;
+
+typedef struct {
+    int dims[4];        /* Lx, Ly, Lz, Lt                                       */
+    int block[4];       /* SAP block extent per direction: a power of two in 2..16,
+                           block volume <= 1024, dims[mu] / block[mu] even         */
+    double kappa;       /* hopping parameter                                     */
+    double csw;         /* clover coefficient c_SW                               */
+    double phase_re[4]; /* boundary phase per direction                          */
+    double phase_im[4];
+    int n_sap;          /* loop count of Alg. 1: M = K sum_{j=0}^{n_sap} (1 - A K)^j */
+    int n_jac;          /* A_EE applications in Alg. 2: B = sum_{j=0}^{n_jac} (1 - A_EE)^j */
+    double inner_tol;   /* relative tolerance of each inner FP32 solve in DD_SOLVE_MIXED
+                           (0 = 1e-6, the per-pass reduction Sec. 3 expects)       */
+    int inner_maxiter;  /* iteration cap of each inner solve (0 = 2000)            */
+} dd_params;
+
+typedef struct {
+    int iters_outer;          /* defect-correction passes (1 for the single-level modes) */
+    int iters_inner_total;    /* BiCGStab loop passes summed over all solves      */
+    double relres_true;       /* |b - D x| / |b| in FP64 at exit                  */
+    double relres_inner_last; /* last recursive residual of the last inner solve  */
+    double seconds;           /* wall time of the call                            */
+    int status_detail;        /* which breakdown: 1 <r~|q> = 0, 2 |t|^2 = 0, 3 omega = 0,
+                                 4 non-finite scalar, 5 outer stagnation          */
+} dd_solve_info;
+
+typedef struct dd_ctx dd_ctx;
+
+/* Create a context: checks the geometry, allocates every packed field and work
+ * vector for all three solve modes (about 4.6 KB per site), binds the stream.
+ * hip_stream is a hipStream_t (NULL = default stream).  Geometry rules: each
+ * dims[mu] is a multiple of 2*block[mu]; block[mu] is a power of two; the block
+ * volume is at most 1024.  Returns DD_ERR_GEOMETRY or DD_ERR_NOMEM on failure. */
+dd_status dd_create(const dd_params *params, void *hip_stream, dd_ctx **out);
+
+/* Free every device buffer the context owns.  NULL is accepted. */
+dd_status dd_destroy(dd_ctx *ctx);
+
+/* Load a gauge field (canonical layout, device memory, read only): packs the
+ * FP64, FP32 and 12-real FP16 link copies, builds the four-leaf clover in
+ * FP64, 1 + C as two 6x6 Hermitian blocks in the gamma_5-diagonal basis, and
+ * C_inv by a Cholesky inverse in FP64 (stored in FP32 and FP16).  Synchronises
+ * the stream.  DD_ERR_CLOVER_NOT_PD if 1 + C fails the Cholesky at any site,
+ * DD_ERR_NONFINITE if a link holds NaN or Inf. */
+dd_status dd_load_gauge(dd_ctx *ctx, const void *U_dev);
+
+/* out = op(in) for canonical spinor fields (device, caller-owned, 24 doubles
+ * per site; in and out must not overlap).  The field is packed into the
+ * internal layout at precision prec, the operator is applied at that precision
+ * (FP16: per-site-scaled FP16 storage, FP32 arithmetic), and the result is
+ * unpacked to complex double.  DD_OP_D is available at every precision,
+ * DD_OP_A at FP32 and FP16 (and FP64), DD_OP_DDAG at FP64.  Asynchronous. */
+dd_status dirac_apply(dd_ctx *ctx, void *out_dev, const void *in_dev, dd_prec prec, dd_op op);
+
+/* x = M_SAP b (Alg. 1 with loop count n_sap, Jacobi count n_jac from the
+ * params) for canonical fields, computed with internal storage at precision
+ * prec (DD_F32: FP32 spinors/links/C_inv; DD_F16: FP16 storage, FP32
+ * arithmetic; DD_F64: FP64 throughout).  Asynchronous. */
+dd_status sap_precondition(dd_ctx *ctx, void *x_dev, const void *b_dev, dd_prec prec);
+
+/* Solve D x = b (canonical fields on the device).  On entry x holds the
+ * initial guess for DD_SOLVE_F64_PLAIN and DD_SOLVE_MIXED (pass zeros for a
+ * cold start; a previous solution resumes the solve) and is ignored for
+ * DD_SOLVE_F32_SAP; on exit it holds the solution.  maxiter bounds the
+ * BiCGStab loop passes of a single-level solve, or the defect-correction
+ * passes of DD_SOLVE_MIXED.  Returns DD_OK, DD_NOT_CONVERGED or DD_BREAKDOWN
+ * (x then holds the best iterate) and fills info (may be NULL).  A source
+ * with NaN or Inf returns DD_ERR_NONFINITE without touching x.
+ * Synchronises the stream. */
+dd_status bicgstab_solve(dd_ctx *ctx, void *x_dev, const void *b_dev, double tol, int maxiter,
+                         dd_solve_mode mode, dd_solve_info *info);
+
+/* Text of the last error on this context (never NULL). */
+const char *dd_last_error(const dd_ctx *ctx);
+
+/* ---- internal-layout entry points (benchmarks, no pack/unpack) ----------- */
+
+/* Bytes of one internal spinor field at precision prec (FP16 includes the
+ * per-site scales).  The caller allocates such buffers, 256-byte aligned. */
+long long dd_field_bytes(const dd_ctx *ctx, dd_prec prec);
+
+/* Pack a canonical spinor into the internal layout (dst) and back. */
+dd_status dd_pack_spinor(dd_ctx *ctx, void *dst_internal, const void *src_canonical, dd_prec prec);
+dd_status dd_unpack_spinor(dd_ctx *ctx, void *dst_canonical, const void *src_internal, dd_prec prec);
+
+/* dirac_apply on internal-layout fields (same operator set as dirac_apply). */
+dd_status dirac_apply_packed(dd_ctx *ctx, void *out_internal, const void *in_internal, dd_prec prec, dd_op op);
+
+/* ---- kernel timing for roofline reporting -------------------------------- */
+
+typedef enum {
+    DD_KT_DIRAC_F64 = 0,  /* full-lattice Dirac apply, FP64                     */
+    DD_KT_DIRAC_F32 = 1,  /* full-lattice Dirac apply, FP32                     */
+    DD_KT_DIRAC_F16 = 2,  /* full-lattice Dirac apply, FP16 storage             */
+    DD_KT_SAP = 3,        /* SAP half-sweep kernels (all precisions)            */
+    DD_KT_BLAS = 4,       /* vector updates and reductions                      */
+    DD_KT_COUNT = 5
+} dd_kernel_class;
+
+/* When enabled, every launch of the timed classes is bracketed by HIP events
+ * on the context's stream.  Enabling clears the counters. */
+dd_status dd_timing_enable(dd_ctx *ctx, int on);
+
+/* Launch count and summed launch time (ms) of one class since enabling;
+ * synchronises the stream. */
+dd_status dd_timing_query(dd_ctx *ctx, dd_kernel_class cls, long long *launches, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDSOLVE_H */

@@ -1,0 +1,281 @@
+"""ctypes binding of libddsolve.so (include/ddsolve.h), argument marshalling only.
+
+The functions carry the C names.  Fields are torch tensors on the GPU in the
+canonical layout (complex128):
+
+  gauge   U[mu][t][z][y][x][3][3]        (mu = 0..3 is the paper's mu = 1..4)
+  spinor  psi[t][z][y][x][colour][spin]
+
+Every step of the solver runs in the HIP library.  There is no fallback: if
+libddsolve.so is missing or fails to load, every call raises.
+"""
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddsolve.so")
+
+DD_F64, DD_F32, DD_F16 = 0, 1, 2
+DD_OP_D, DD_OP_A, DD_OP_DDAG = 0, 1, 2
+DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED = 0, 1, 2
+DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS = range(5)
+
+STATUS = {0: "DD_OK", 1: "DD_NOT_CONVERGED", 2: "DD_BREAKDOWN", -1: "DD_ERR_ARG", -2: "DD_ERR_GEOMETRY",
+          -3: "DD_ERR_HIP", -4: "DD_ERR_NOMEM", -5: "DD_ERR_NONFINITE", -6: "DD_ERR_CLOVER_NOT_PD",
+          -7: "DD_ERR_STATE"}
+
+EXPORTS = ["dd_create", "dd_destroy", "dd_load_gauge", "dirac_apply", "sap_precondition", "bicgstab_solve",
+           "dd_last_error", "dd_field_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dirac_apply_packed",
+           "dd_timing_enable", "dd_timing_query"]
+
+
+class DDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("block", ctypes.c_int * 4), ("kappa", ctypes.c_double),
+                ("csw", ctypes.c_double), ("phase_re", ctypes.c_double * 4), ("phase_im", ctypes.c_double * 4),
+                ("n_sap", ctypes.c_int), ("n_jac", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("inner_maxiter", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters_outer", ctypes.c_int), ("iters_inner_total", ctypes.c_int),
+                ("relres_true", ctypes.c_double), ("relres_inner_last", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("status_detail", ctypes.c_int)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libddsolve.so; raises when it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
+                               "or python paper_2109_10687_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+        sig = {
+            "dd_create": (i, [ctypes.POINTER(_Params), vp, ctypes.POINTER(vp)]),
+            "dd_destroy": (i, [vp]),
+            "dd_load_gauge": (i, [vp, vp]),
+            "dirac_apply": (i, [vp, vp, vp, i, i]),
+            "sap_precondition": (i, [vp, vp, vp, i]),
+            "bicgstab_solve": (i, [vp, vp, vp, d, i, i, ctypes.POINTER(_Info)]),
+            "dd_last_error": (ctypes.c_char_p, [vp]),
+            "dd_field_bytes": (ll, [vp, i]),
+            "dd_pack_spinor": (i, [vp, vp, vp, i]),
+            "dd_unpack_spinor": (i, [vp, vp, vp, i]),
+            "dirac_apply_packed": (i, [vp, vp, vp, i, i]),
+            "dd_timing_enable": (i, [vp, i]),
+            "dd_timing_query": (i, [vp, i, ctypes.POINTER(ll), ctypes.POINTER(d)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+@dataclass
+class Params:
+    """dd_params: dims = (Lx, Ly, Lz, Lt); block = SAP block extents."""
+    dims: tuple
+    kappa: float
+    csw: float
+    block: tuple = (4, 4, 4, 4)
+    phases: tuple = (1.0, 1.0, 1.0, -1.0)
+    n_sap: int = 2
+    n_jac: int = 4
+    inner_tol: float = 1e-6
+    inner_maxiter: int = 2000
+
+    def c(self):
+        p = _Params()
+        for mu in range(4):
+            p.dims[mu] = int(self.dims[mu])
+            p.block[mu] = int(self.block[mu])
+            ph = complex(self.phases[mu])
+            p.phase_re[mu] = ph.real
+            p.phase_im[mu] = ph.imag
+        p.kappa = float(self.kappa)
+        p.csw = float(self.csw)
+        p.n_sap = int(self.n_sap)
+        p.n_jac = int(self.n_jac)
+        p.inner_tol = float(self.inner_tol)
+        p.inner_maxiter = int(self.inner_maxiter)
+        return p
+
+    @property
+    def volume(self):
+        return math.prod(self.dims)
+
+    @property
+    def shape(self):
+        Lx, Ly, Lz, Lt = self.dims
+        return (Lt, Lz, Ly, Lx)
+
+
+def _check(ctx, st):
+    if st < 0:
+        raise DDError(st, lib().dd_last_error(ctx).decode())
+    return st
+
+
+def _dev(t, shape=None, what="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a torch tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _c128(t, shape, what):
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{what} must be complex128")
+    return _dev(t, shape, what)
+
+
+# ------------------------------------------------------------------ C names
+
+def dd_create(params, stream=None):
+    """Create a context bound to `stream` (default: torch's current stream)."""
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    out = ctypes.c_void_p()
+    p = params.c()
+    st = lib().dd_create(ctypes.byref(p), h, ctypes.byref(out))
+    if st < 0:
+        raise DDError(st, "dd_create failed")
+    return out
+
+
+def dd_destroy(ctx):
+    return lib().dd_destroy(ctx)
+
+
+def dd_load_gauge(ctx, U, shape):
+    return _check(ctx, lib().dd_load_gauge(ctx, _c128(U, (4,) + shape + (3, 3), "gauge field")))
+
+
+def dirac_apply(ctx, out, inp, prec, op, shape):
+    sp = shape + (3, 4)
+    return _check(ctx, lib().dirac_apply(ctx, _c128(out, sp, "out"), _c128(inp, sp, "in"), prec, op))
+
+
+def sap_precondition(ctx, x, b, prec, shape):
+    sp = shape + (3, 4)
+    return _check(ctx, lib().sap_precondition(ctx, _c128(x, sp, "x"), _c128(b, sp, "b"), prec))
+
+
+def bicgstab_solve(ctx, x, b, tol, maxiter, mode, shape):
+    sp = shape + (3, 4)
+    info = _Info()
+    st = _check(ctx, lib().bicgstab_solve(ctx, _c128(x, sp, "x"), _c128(b, sp, "b"), float(tol), int(maxiter),
+                                          int(mode), ctypes.byref(info)))
+    return st, {k: getattr(info, k) for k, _ in _Info._fields_}
+
+
+def dd_field_bytes(ctx, prec):
+    return lib().dd_field_bytes(ctx, prec)
+
+
+def dd_pack_spinor(ctx, dst, src, prec):
+    return _check(ctx, lib().dd_pack_spinor(ctx, _dev(dst, what="dst"), _dev(src, what="src"), prec))
+
+
+def dd_unpack_spinor(ctx, dst, src, prec):
+    return _check(ctx, lib().dd_unpack_spinor(ctx, _dev(dst, what="dst"), _dev(src, what="src"), prec))
+
+
+def dirac_apply_packed(ctx, out, inp, prec, op):
+    return _check(ctx, lib().dirac_apply_packed(ctx, _dev(out, what="out"), _dev(inp, what="in"), prec, op))
+
+
+def dd_timing_enable(ctx, on):
+    return _check(ctx, lib().dd_timing_enable(ctx, int(on)))
+
+
+def dd_timing_query(ctx, cls):
+    n = ctypes.c_longlong(0)
+    ms = ctypes.c_double(0)
+    _check(ctx, lib().dd_timing_query(ctx, cls, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+# ------------------------------------------------------------------ convenience
+
+class Solver:
+    """A context with its gauge field: Dirac apply, SAP and BiCGStab on torch tensors."""
+
+    def __init__(self, params, U=None, stream=None):
+        self.params = params
+        self.shape = params.shape
+        self.ctx = dd_create(params, stream)
+        if U is not None:
+            self.load_gauge(U)
+
+    def close(self):
+        if self.ctx:
+            dd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_gauge(self, U):
+        dd_load_gauge(self.ctx, U, self.shape)
+
+    def new_spinor(self):
+        return torch.zeros(self.shape + (3, 4), dtype=torch.complex128, device="cuda")
+
+    def apply(self, x, op=DD_OP_D, prec=DD_F64, out=None):
+        out = self.new_spinor() if out is None else out
+        dirac_apply(self.ctx, out, x, prec, op, self.shape)
+        return out
+
+    def precondition(self, b, prec=DD_F32, out=None):
+        out = self.new_spinor() if out is None else out
+        sap_precondition(self.ctx, out, b, prec, self.shape)
+        return out
+
+    def solve(self, b, tol=1e-10, maxiter=10000, mode=DD_SOLVE_MIXED, x0=None):
+        x = self.new_spinor() if x0 is None else x0.clone()
+        st, info = bicgstab_solve(self.ctx, x, b, tol, maxiter, mode, self.shape)
+        info["status"] = STATUS[st]
+        return x, info
+
+    def field(self, prec):
+        """An internal-layout field buffer for the packed entry points."""
+        n = dd_field_bytes(self.ctx, prec)
+        return torch.empty((n + 255) // 256 * 256, dtype=torch.uint8, device="cuda")
+
+    def pack(self, x, prec, out=None):
+        out = self.field(prec) if out is None else out
+        dd_pack_spinor(self.ctx, out, x, prec)
+        return out
+
+    def unpack(self, f, prec, out=None):
+        out = self.new_spinor() if out is None else out
+        dd_unpack_spinor(self.ctx, out, f, prec)
+        return out
+
+    def apply_packed(self, out, inp, op=DD_OP_A, prec=DD_F32):
+        dirac_apply_packed(self.ctx, out, inp, prec, op)
+        return out

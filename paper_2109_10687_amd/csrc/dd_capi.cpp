@@ -1,0 +1,765 @@
+// dd_capi.cpp -- the C ABI of include/ddsolve.h: context and field ownership,
+// gauge loading, the Dirac and SAP entry points, and the solver loops:
+//   plain FP64 BiCGStab on D (Alg. 5 without preconditioner),
+//   FP32 BiCGStab on A M_SAP (Alg. 5 with Alg. 1 as right preconditioner),
+//   FP64 defect correction (Alg. 4) around the FP32 solver with an FP16 SAP.
+// Every step of the path runs in the kernels of dd_kernels.hip; this file
+// only sequences launches and evaluates the BiCGStab scalars.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ddsolve.h"
+#include "dd_launch.h"
+
+using dd::Geom;
+using cplx = std::complex<double>;
+
+namespace {
+
+constexpr int N64 = 7, N32 = 10, N16 = 5;
+
+struct TimerRec {
+    int cls;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct dd_ctx {
+    dd_params prm{};
+    Geom g{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool gauge = false;
+    dd::Phase4 phase{};
+    // packed gauge fields
+    void *U64 = nullptr, *U32 = nullptr, *U16 = nullptr;
+    void *clov64 = nullptr, *cinv32 = nullptr, *cinv16 = nullptr;
+    // work vectors
+    void *f64[N64] = {}, *f32[N32] = {}, *f16[N16] = {};
+    double *partials = nullptr, *red = nullptr, *red_host = nullptr;
+    int *flag = nullptr;
+    // kernel timing
+    bool timing = false;
+    std::vector<TimerRec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    long long launches[DD_KT_COUNT] = {};
+    double ms[DD_KT_COUNT] = {};
+};
+
+namespace {
+
+dd_status fail(dd_ctx *c, dd_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCK(c, call)                                                                                   \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) return fail((c), DD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+hipEvent_t take_event(dd_ctx *c)
+{
+    if (c->pool_used == c->pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->pool.push_back(e);
+    }
+    return c->pool[c->pool_used++];
+}
+
+// run `launch` and, when timing is on, bracket it with events on the stream
+template <typename F> hipError_t timed(dd_ctx *c, int cls, F &&launch)
+{
+    if (!c->timing) return launch();
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) return launch();
+    (void)hipEventRecord(a, c->stream);
+    hipError_t e = launch();
+    (void)hipEventRecord(b, c->stream);
+    c->recs.push_back({cls, a, b});
+    return e;
+}
+
+hipError_t flush_timing(dd_ctx *c)
+{
+    if (c->recs.empty()) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    for (auto &r : c->recs) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            c->ms[r.cls] += t;
+            c->launches[r.cls] += 1;
+        }
+    }
+    c->recs.clear();
+    c->pool_used = 0;
+    return hipSuccess;
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+size_t spinor_bytes(const Geom &g, int prec)
+{
+    if (prec == DD_F64) return (size_t)g.V * 12 * 16;
+    if (prec == DD_F32) return (size_t)g.V * 12 * 8;
+    return (size_t)g.V * (12 * 4 + 4);
+}
+
+// gamma matrices of the paper's appendix (Dirac representation, gamma_4 diagonal),
+// used here only to form the sigma blocks of the clover setup
+void gamma_table(cplx gm[4][4][4])
+{
+    const cplx I(0, 1);
+    cplx g1[4][4] = {{0, 0, 0, I}, {0, 0, I, 0}, {0, -I, 0, 0}, {-I, 0, 0, 0}};
+    cplx g2[4][4] = {{0, 0, 0, 1}, {0, 0, -1, 0}, {0, -1, 0, 0}, {1, 0, 0, 0}};
+    cplx g3[4][4] = {{0, 0, I, 0}, {0, 0, 0, -I}, {-I, 0, 0, 0}, {0, I, 0, 0}};
+    cplx g4[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, -1, 0}, {0, 0, 0, -1}};
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            gm[0][i][j] = g1[i][j];
+            gm[1][i][j] = g2[i][j];
+            gm[2][i][j] = g3[i][j];
+            gm[3][i][j] = g4[i][j];
+        }
+}
+
+// sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu] rotated by P = [[1,1],[1,-1]]/sqrt2
+// (spin pairs) into the basis where gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4 is
+// diagonal; sigma commutes with gamma_5, so only the two 2x2 diagonal blocks survive
+bool sigma_blocks(dd::SigmaBlocks &sb)
+{
+    cplx gm[4][4][4];
+    gamma_table(gm);
+    const double r = 1.0 / std::sqrt(2.0);
+    double P[4][4] = {{r, 0, r, 0}, {0, r, 0, r}, {r, 0, -r, 0}, {0, r, 0, -r}};
+    int plane = 0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = mu + 1; nu < 4; ++nu, ++plane) {
+            cplx s[4][4], t[4][4], u[4][4];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    cplx c = 0;
+                    for (int k = 0; k < 4; ++k) c += gm[mu][i][k] * gm[nu][k][j] - gm[nu][i][k] * gm[mu][k][j];
+                    s[i][j] = cplx(0, 0.5) * c;
+                }
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    cplx c = 0;
+                    for (int k = 0; k < 4; ++k) c += P[i][k] * s[k][j];
+                    t[i][j] = c;
+                }
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    cplx c = 0;
+                    for (int k = 0; k < 4; ++k) c += t[i][k] * P[k][j];
+                    u[i][j] = c;
+                }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    if (std::abs(u[i][j + 2]) > 1e-12 || std::abs(u[i + 2][j]) > 1e-12) return false;
+                    sb.re[plane][0][i][j] = u[i][j].real();
+                    sb.im[plane][0][i][j] = u[i][j].imag();
+                    sb.re[plane][1][i][j] = u[i + 2][j + 2].real();
+                    sb.im[plane][1][i][j] = u[i + 2][j + 2].imag();
+                }
+        }
+    return true;
+}
+
+// ------------------------------------------------------------------ launch helpers
+
+dd_status k_dirac(dd_ctx *c, void *out, const void *in, int pin, int pout, int pg, int op)
+{
+    dd::DiracArgs a{};
+    a.out = out;
+    a.in = in;
+    a.pin = pin;
+    a.pout = pout;
+    a.pg = pg;
+    a.op = op;
+    a.kappa = c->prm.kappa;
+    a.phase = c->phase;
+    if (pg == 0) {
+        a.links = c->U64;
+        a.clover = c->clov64;
+    } else if (pg == 1) {
+        a.links = c->U32;
+        a.clover = c->cinv32;
+    } else {
+        a.links = c->U16;
+        a.clover = c->cinv16;
+    }
+    int cls = pin == 0 ? DD_KT_DIRAC_F64 : (pin == 1 ? DD_KT_DIRAC_F32 : DD_KT_DIRAC_F16);
+    hipError_t e = timed(c, cls, [&] { return dd::launch_dirac(c->g, c->stream, a); });
+    if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("dirac launch: ") + hipGetErrorString(e));
+    return DD_OK;
+}
+
+// x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s
+dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
+{
+    dd::SapArgs a{};
+    a.b = b;
+    a.s = s;
+    a.x = x;
+    a.prec = prec;
+    a.links = prec == 1 ? c->U32 : c->U16;
+    a.cinv = prec == 1 ? c->cinv32 : c->cinv16;
+    a.n_jac = c->prm.n_jac;
+    a.kappa = c->prm.kappa;
+    a.phase = c->phase;
+    const int E = 0, O = 1;
+    const int n = c->prm.n_sap;
+    auto half = [&](int colour, int flags) -> dd_status {
+        hipError_t e = timed(c, DD_KT_SAP, [&] { return dd::launch_sap_half(c->g, c->stream, a, colour, flags); });
+        if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("sap launch: ") + hipGetErrorString(e));
+        return DD_OK;
+    };
+    dd_status st;
+    for (int i = 0; i < n; ++i) {
+        if ((st = half(E, i == 0 ? dd::SAP_FIRST : dd::SAP_PRE)) != DD_OK) return st;
+        if ((st = half(O, i == 0 ? (dd::SAP_FIRST | dd::SAP_PRE) : dd::SAP_PRE)) != DD_OK) return st;
+    }
+    if ((st = half(E, dd::SAP_TAIL | (n == 0 ? dd::SAP_FIRST : dd::SAP_PRE))) != DD_OK) return st;
+    if ((st = half(O, dd::SAP_TAIL | dd::SAP_PRE | (n == 0 ? dd::SAP_FIRST : 0))) != DD_OK) return st;
+    return DD_OK;
+}
+
+dd_status blas(dd_ctx *c, dd::BlasArgs a)
+{
+    a.partials = c->partials;
+    hipError_t e = timed(c, DD_KT_BLAS, [&] { return dd::launch_blas(c->g, c->stream, a); });
+    if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("vector kernel: ") + hipGetErrorString(e));
+    return DD_OK;
+}
+
+// run a reducing vector kernel and bring its nv sums to the host
+dd_status reduce(dd_ctx *c, dd::BlasArgs a, int nv, double *out)
+{
+    dd_status st = blas(c, a);
+    if (st != DD_OK) return st;
+    HIPCK(c, dd::launch_finalize(c->stream, c->partials, dd::blas_grid(c->g), nv, c->red));
+    HIPCK(c, hipMemcpyAsync(c->red_host, c->red, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < nv; ++k) out[k] = c->red_host[k];
+    return DD_OK;
+}
+
+dd::BlasArgs mkb(int kind, std::initializer_list<void *> v, std::initializer_list<int> p,
+                 std::initializer_list<double> cc = {})
+{
+    dd::BlasArgs a{};
+    a.kind = kind;
+    int i = 0;
+    for (void *x : v) a.v[i++] = x;
+    i = 0;
+    for (int x : p) a.p[i++] = x;
+    i = 0;
+    for (double x : cc) a.c[i++] = x;
+    return a;
+}
+
+dd_status norm2(dd_ctx *c, void *v, int prec, double *out)
+{
+    return reduce(c, mkb(dd::BLAS_NORM2, {v}, {prec}), 1, out);
+}
+
+dd_status copy(dd_ctx *c, void *dst, int pd, void *src, int ps)
+{
+    if (ps == 2 || pd == 2) return blas(c, mkb(dd::BLAS_CONVERT, {src, dst}, {ps, pd}));
+    return blas(c, mkb(dd::BLAS_AXPBY, {src, dst}, {ps, pd}, {1.0, 0.0}));
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+bool is_fin(cplx v) { return std::isfinite(v.real()) && std::isfinite(v.imag()); }
+
+// r = b - D x (FP64) ; returns |r|^2
+dd_status residual64(dd_ctx *c, void *r, void *b, void *x, void *tmp, double *rn2)
+{
+    dd_status st = k_dirac(c, tmp, x, 0, 0, 0, 0);
+    if (st != DD_OK) return st;
+    return reduce(c, mkb(dd::BLAS_SUB_NORM, {r, b, tmp}, {0, 0, 0}), 1, rn2);
+}
+
+// ------------------------------------------------------------------ solvers
+
+struct SolveOut {
+    int iters = 0;
+    double relres = 0;
+    int detail = 0;
+};
+
+// plain BiCGStab (Alg. 5, M = I) on D in FP64; x holds the initial guess.
+// At a recursive exit the true residual is recomputed; if it misses tol the
+// iteration restarts from it.
+dd_status solve_plain64(dd_ctx *c, void *x, void *b, double tol, int maxiter, SolveOut &o)
+{
+    void *r = c->f64[2], *rt = c->f64[3], *p = c->f64[4], *q = c->f64[5], *t = c->f64[6];
+    double bn2;
+    dd_status st = norm2(c, b, 0, &bn2);
+    if (st != DD_OK) return st;
+    if (!is_fin(bn2)) return fail(c, DD_ERR_NONFINITE, "source holds NaN or Inf");
+    if (bn2 == 0.0) {
+        HIPCK(c, hipMemsetAsync(x, 0, spinor_bytes(c->g, DD_F64), c->stream));
+        o.relres = 0;
+        return DD_OK;
+    }
+    int it = 0;
+    for (int restart = 0; restart < 20; ++restart) {
+        double rn2;
+        if ((st = residual64(c, r, b, x, q, &rn2)) != DD_OK) return st;
+        o.relres = std::sqrt(rn2 / bn2);
+        if (o.relres < tol) {
+            o.iters = it;
+            return DD_OK;
+        }
+        if (it >= maxiter) break;
+        if ((st = copy(c, rt, 0, r, 0)) != DD_OK) return st;
+        if ((st = copy(c, p, 0, r, 0)) != DD_OK) return st;
+        cplx rho0 = rn2;
+        bool conv = false;
+        while (it < maxiter) {
+            ++it;
+            if ((st = k_dirac(c, q, p, 0, 0, 0, 0)) != DD_OK) return st;
+            double d[3];
+            if ((st = reduce(c, mkb(dd::BLAS_DOT, {rt, q}, {0, 0}), 2, d)) != DD_OK) return st;
+            cplx rq(d[0], d[1]);
+            if (rq == 0.0 || !is_fin(rq)) {
+                o.iters = it;
+                o.detail = rq == 0.0 ? 1 : 4;
+                return DD_BREAKDOWN;
+            }
+            cplx alpha = rho0 / rq;
+            if ((st = reduce(c, mkb(dd::BLAS_UPDATE1, {x, p, r, q}, {0, 0, 0}, {alpha.real(), alpha.imag()}), 1,
+                             &rn2)) != DD_OK)
+                return st;
+            if (std::sqrt(rn2 / bn2) < tol) {
+                conv = true;
+                break;
+            }
+            if ((st = k_dirac(c, t, r, 0, 0, 0, 0)) != DD_OK) return st;
+            if ((st = reduce(c, mkb(dd::BLAS_DOT_NORM, {t, r}, {0, 0}), 3, d)) != DD_OK) return st;
+            if (d[2] == 0.0 || !is_fin(d[2])) {
+                o.iters = it;
+                o.detail = d[2] == 0.0 ? 2 : 4;
+                return DD_BREAKDOWN;
+            }
+            cplx omega = cplx(d[0], d[1]) / d[2];
+            if ((st = reduce(c, mkb(dd::BLAS_UPDATE2, {x, r, r, t, rt}, {0, 0, 0}, {omega.real(), omega.imag()}), 3,
+                             d)) != DD_OK)
+                return st;
+            rn2 = d[0];
+            cplx rho(d[1], d[2]);
+            if (std::sqrt(rn2 / bn2) < tol) {
+                conv = true;
+                break;
+            }
+            if (omega == 0.0) {
+                o.iters = it;
+                o.detail = 3;
+                return DD_BREAKDOWN;
+            }
+            cplx beta = (alpha / omega) * (rho / rho0);
+            if (!is_fin(beta)) {
+                o.iters = it;
+                o.detail = 4;
+                return DD_BREAKDOWN;
+            }
+            rho0 = rho;
+            if ((st = blas(c, mkb(dd::BLAS_PUPDATE, {p, r, q}, {0, 0, 0},
+                                  {beta.real(), beta.imag(), omega.real(), omega.imag()}))) != DD_OK)
+                return st;
+        }
+        if (!conv) break;
+    }
+    o.iters = it;
+    double rn2;
+    if ((st = residual64(c, r, b, x, q, &rn2)) != DD_OK) return st;
+    o.relres = std::sqrt(rn2 / bn2);
+    return o.relres < tol ? DD_OK : DD_NOT_CONVERGED;
+}
+
+// FP32 BiCGStab on A M_SAP (Alg. 5 with Alg. 1 as right preconditioner) for the
+// source src (FP32, internal); the solution accumulates the preconditioned
+// directions, y += alpha M p + omega M r, which equals M_SAP applied to Alg. 5's
+// iterate when M is linear and stays consistent with the recursive residual
+// when M is computed in rounded FP16.  prec = SAP storage precision (1 or 2).
+dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int maxiter, SolveOut &o)
+{
+    void *r = c->f32[2], *rt = c->f32[3], *p = c->f32[4], *q = c->f32[5], *t = c->f32[6];
+    void *Mp = prec == 1 ? c->f32[7] : c->f16[2];
+    void *Mr = prec == 1 ? c->f32[8] : c->f16[3];
+    void *s = prec == 1 ? c->f32[9] : c->f16[4];
+    void *p16 = c->f16[0], *r16 = c->f16[1];
+    dd_status st;
+    HIPCK(c, hipMemsetAsync(y, 0, spinor_bytes(c->g, DD_F32), c->stream));
+    double bn2;
+    if ((st = norm2(c, src, 1, &bn2)) != DD_OK) return st;
+    if (!is_fin(bn2)) return fail(c, DD_ERR_NONFINITE, "inner source holds NaN or Inf");
+    o.iters = 0;
+    o.relres = 0;
+    if (bn2 == 0.0) return DD_OK;
+    if ((st = copy(c, r, 1, src, 1)) != DD_OK) return st;
+    if ((st = copy(c, p, 1, src, 1)) != DD_OK) return st;
+    if ((st = copy(c, rt, 1, src, 1)) != DD_OK) return st;
+    cplx rho0 = bn2;
+    double rn2 = bn2;
+    auto precond = [&](void *in, void *in16, void *Mout, void *Aout) -> dd_status {
+        dd_status s2;
+        const void *bsrc = in;
+        if (prec == 2) {
+            if ((s2 = copy(c, in16, 2, in, 1)) != DD_OK) return s2;
+            bsrc = in16;
+        }
+        if ((s2 = k_sap(c, prec, bsrc, Mout, s)) != DD_OK) return s2;
+        return k_dirac(c, Aout, Mout, prec, 1, 1, 1);
+    };
+    for (int it = 0; it < maxiter; ++it) {
+        o.iters = it + 1;
+        if ((st = precond(p, p16, Mp, q)) != DD_OK) return st;
+        double d[3];
+        if ((st = reduce(c, mkb(dd::BLAS_DOT, {rt, q}, {1, 1}), 2, d)) != DD_OK) return st;
+        cplx rq(d[0], d[1]);
+        if (rq == 0.0 || !is_fin(rq)) {
+            o.detail = rq == 0.0 ? 1 : 4;
+            o.relres = std::sqrt(rn2 / bn2);
+            return DD_BREAKDOWN;
+        }
+        cplx alpha = rho0 / rq;
+        if ((st = reduce(c, mkb(dd::BLAS_UPDATE1, {y, Mp, r, q}, {1, prec, 1}, {alpha.real(), alpha.imag()}), 1,
+                         &rn2)) != DD_OK)
+            return st;
+        o.relres = std::sqrt(rn2 / bn2);
+        if (o.relres < tol) return DD_OK;
+        if ((st = precond(r, r16, Mr, t)) != DD_OK) return st;
+        if ((st = reduce(c, mkb(dd::BLAS_DOT_NORM, {t, r}, {1, 1}), 3, d)) != DD_OK) return st;
+        if (d[2] == 0.0 || !is_fin(d[2])) {
+            o.detail = d[2] == 0.0 ? 2 : 4;
+            return DD_BREAKDOWN;
+        }
+        cplx omega = cplx(d[0], d[1]) / d[2];
+        if ((st = reduce(c, mkb(dd::BLAS_UPDATE2, {y, Mr, r, t, rt}, {1, prec, 1}, {omega.real(), omega.imag()}), 3,
+                         d)) != DD_OK)
+            return st;
+        rn2 = d[0];
+        cplx rho(d[1], d[2]);
+        o.relres = std::sqrt(rn2 / bn2);
+        if (o.relres < tol) return DD_OK;
+        if (omega == 0.0) {
+            o.detail = 3;
+            return DD_BREAKDOWN;
+        }
+        cplx beta = (alpha / omega) * (rho / rho0);
+        if (!is_fin(beta)) {
+            o.detail = 4;
+            return DD_BREAKDOWN;
+        }
+        rho0 = rho;
+        if ((st = blas(c, mkb(dd::BLAS_PUPDATE, {p, r, q}, {1, 1, 1},
+                              {beta.real(), beta.imag(), omega.real(), omega.imag()}))) != DD_OK)
+            return st;
+    }
+    return DD_NOT_CONVERGED;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
+{
+    if (!prm || !out) return DD_ERR_ARG;
+    *out = nullptr;
+    dd_ctx *c = new (std::nothrow) dd_ctx;
+    if (!c) return DD_ERR_NOMEM;
+    c->prm = *prm;
+    if (c->prm.inner_tol <= 0) c->prm.inner_tol = 1e-6;
+    if (c->prm.inner_maxiter <= 0) c->prm.inner_maxiter = 2000;
+    Geom &g = c->g;
+    long long V = 1;
+    int bvol = 1, nblk = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        int L = prm->dims[mu], b = prm->block[mu];
+        if (L <= 0 || !pow2(b) || b < 2 || b > 16 || L % (2 * b) != 0) {
+            delete c;
+            return DD_ERR_GEOMETRY;
+        }
+        g.L[mu] = L;
+        g.b[mu] = b;
+        g.NB[mu] = L / b;
+        V *= L;
+        bvol *= b;
+        nblk *= L / b;
+    }
+    if (bvol > 1024 || prm->n_sap < 0 || prm->n_jac < 1 || !(prm->kappa >= 0) || !std::isfinite(prm->csw)) {
+        delete c;
+        return bvol > 1024 ? DD_ERR_GEOMETRY : DD_ERR_ARG;
+    }
+    g.bvol = bvol;
+    g.lbvol = ilog2(bvol);
+    g.nblk = nblk;
+    g.V = V;
+    g.sh[0] = 0;
+    for (int mu = 1; mu < 4; ++mu) g.sh[mu] = g.sh[mu - 1] + ilog2(g.b[mu - 1]);
+    g.bstride[0] = 1;
+    for (int mu = 1; mu < 4; ++mu) g.bstride[mu] = g.bstride[mu - 1] * g.NB[mu - 1];
+    for (int mu = 0; mu < 4; ++mu) {
+        c->phase.re[mu] = prm->phase_re[mu];
+        c->phase.im[mu] = prm->phase_im[mu];
+    }
+    c->stream = (hipStream_t)hip_stream;
+
+    auto alloc = [&](void **p, size_t bytes) -> bool { return hipMalloc(p, bytes) == hipSuccess; };
+    bool ok = alloc(&c->U64, (size_t)V * 36 * 16) && alloc(&c->U32, (size_t)V * 36 * 8) &&
+              alloc(&c->U16, (size_t)V * 24 * 4) && alloc(&c->clov64, (size_t)V * 36 * 16) &&
+              alloc(&c->cinv32, (size_t)V * 36 * 8) && alloc(&c->cinv16, (size_t)V * 36 * 4);
+    for (int i = 0; ok && i < N64; ++i) ok = alloc(&c->f64[i], spinor_bytes(g, DD_F64));
+    for (int i = 0; ok && i < N32; ++i) ok = alloc(&c->f32[i], spinor_bytes(g, DD_F32));
+    for (int i = 0; ok && i < N16; ++i) ok = alloc(&c->f16[i], spinor_bytes(g, DD_F16));
+    ok = ok && alloc((void **)&c->partials, dd::MAX_PARTIALS * sizeof(double)) &&
+         alloc((void **)&c->red, 16 * sizeof(double)) && alloc((void **)&c->flag, 4 * sizeof(int)) &&
+         hipHostMalloc((void **)&c->red_host, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        dd_destroy(c);
+        return DD_ERR_NOMEM;
+    }
+    *out = c;
+    return DD_OK;
+}
+
+dd_status dd_destroy(dd_ctx *c)
+{
+    if (!c) return DD_OK;
+    (void)hipStreamSynchronize(c->stream);
+    void *bufs[] = {c->U64, c->U32, c->U16, c->clov64, c->cinv32, c->cinv16, c->partials, c->red, c->flag};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    for (void *p : c->f64)
+        if (p) (void)hipFree(p);
+    for (void *p : c->f32)
+        if (p) (void)hipFree(p);
+    for (void *p : c->f16)
+        if (p) (void)hipFree(p);
+    if (c->red_host) (void)hipHostFree(c->red_host);
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+    return DD_OK;
+}
+
+const char *dd_last_error(const dd_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+dd_status dd_load_gauge(dd_ctx *c, const void *U)
+{
+    if (!c || !U) return fail(c, DD_ERR_ARG, "null argument");
+    HIPCK(c, hipMemsetAsync(c->flag, 0, 4 * sizeof(int), c->stream));
+    HIPCK(c, dd::launch_pack_links(c->g, c->stream, U, c->U64, c->U32, c->U16, c->flag));
+    dd::SigmaBlocks sb{};
+    if (!sigma_blocks(sb)) return fail(c, DD_ERR_ARG, "sigma blocks not block diagonal");
+    HIPCK(c, dd::launch_clover(c->g, c->stream, c->U64, sb, c->prm.kappa * c->prm.csw, c->clov64, c->cinv32,
+                               c->cinv16, c->flag + 1));
+    int fl[2] = {0, 0};
+    HIPCK(c, hipMemcpyAsync(fl, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    c->gauge = false;
+    if (fl[0]) return fail(c, DD_ERR_NONFINITE, "gauge field holds NaN or Inf");
+    if (fl[1]) return fail(c, DD_ERR_CLOVER_NOT_PD, "1 + C is not positive definite at some site");
+    c->gauge = true;
+    return DD_OK;
+}
+
+long long dd_field_bytes(const dd_ctx *c, dd_prec prec)
+{
+    if (!c || prec < DD_F64 || prec > DD_F16) return -1;
+    return (long long)spinor_bytes(c->g, prec);
+}
+
+dd_status dd_pack_spinor(dd_ctx *c, void *dst, const void *src, dd_prec prec)
+{
+    if (!c || !dst || !src || prec < DD_F64 || prec > DD_F16) return fail(c, DD_ERR_ARG, "bad argument");
+    HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, prec, dst, src));
+    return DD_OK;
+}
+
+dd_status dd_unpack_spinor(dd_ctx *c, void *dst, const void *src, dd_prec prec)
+{
+    if (!c || !dst || !src || prec < DD_F64 || prec > DD_F16) return fail(c, DD_ERR_ARG, "bad argument");
+    HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, prec, dst, src));
+    return DD_OK;
+}
+
+static dd_status check_op(dd_ctx *c, dd_prec prec, dd_op op)
+{
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    if (op == DD_OP_A && (prec == DD_F32 || prec == DD_F16)) return DD_OK;
+    if ((op == DD_OP_D || op == DD_OP_DDAG) && prec == DD_F64) return DD_OK;
+    return fail(c, DD_ERR_ARG, "operator not available at this precision (D, D^dagger: FP64; A: FP32, FP16)");
+}
+
+dd_status dirac_apply_packed(dd_ctx *c, void *out, const void *in, dd_prec prec, dd_op op)
+{
+    if (!c || !out || !in) return fail(c, DD_ERR_ARG, "null argument");
+    dd_status st = check_op(c, prec, op);
+    if (st != DD_OK) return st;
+    return k_dirac(c, out, in, prec, prec, prec, op);
+}
+
+dd_status dirac_apply(dd_ctx *c, void *out, const void *in, dd_prec prec, dd_op op)
+{
+    if (!c || !out || !in) return fail(c, DD_ERR_ARG, "null argument");
+    dd_status st = check_op(c, prec, op);
+    if (st != DD_OK) return st;
+    void *ti = c->f64[5], *to = c->f64[6];
+    HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, prec, ti, in));
+    if ((st = k_dirac(c, to, ti, prec, prec, prec, op)) != DD_OK) return st;
+    HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, prec, out, to));
+    return DD_OK;
+}
+
+dd_status sap_precondition(dd_ctx *c, void *x, const void *b, dd_prec prec)
+{
+    if (!c || !x || !b) return fail(c, DD_ERR_ARG, "null argument");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    if (prec != DD_F32 && prec != DD_F16) return fail(c, DD_ERR_ARG, "SAP is available at FP32 and FP16");
+    void *tb = c->f64[5], *tx = c->f64[6], *ts = c->f64[4];
+    HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, prec, tb, b));
+    dd_status st = k_sap(c, prec, tb, tx, ts);
+    if (st != DD_OK) return st;
+    HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, prec, x, tx));
+    return DD_OK;
+}
+
+dd_status bicgstab_solve(dd_ctx *c, void *x_dev, const void *b_dev, double tol, int maxiter, dd_solve_mode mode,
+                         dd_solve_info *info)
+{
+    if (!c || !x_dev || !b_dev) return fail(c, DD_ERR_ARG, "null argument");
+    if (!(tol > 0) || maxiter < 0 || mode < DD_SOLVE_F64_PLAIN || mode > DD_SOLVE_MIXED)
+        return fail(c, DD_ERR_ARG, "bad tolerance, maxiter or mode");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    auto t0 = std::chrono::steady_clock::now();
+    dd_solve_info inf{};
+    void *b = c->f64[0], *x = c->f64[1];
+    HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, b, b_dev));
+    double bn2;
+    dd_status st = norm2(c, b, 0, &bn2);
+    if (st != DD_OK) return st;
+    if (!is_fin(bn2)) return fail(c, DD_ERR_NONFINITE, "source holds NaN or Inf");
+    dd_status res = DD_OK;
+    if (mode == DD_SOLVE_F64_PLAIN) {
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, x, x_dev));
+        SolveOut o;
+        res = solve_plain64(c, x, b, tol, maxiter, o);
+        if (res < 0) return res;
+        inf.iters_outer = 1;
+        inf.iters_inner_total = o.iters;
+        inf.relres_inner_last = o.relres;
+        inf.status_detail = o.detail;
+    } else if (mode == DD_SOLVE_F32_SAP) {
+        void *src = c->f32[0], *y = c->f32[1];
+        if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {src, b, c->cinv32}, {1, 0}, {1.0}))) != DD_OK) return st;
+        SolveOut o;
+        res = solve_sap32(c, 1, src, y, tol, maxiter, o);
+        if (res < 0) return res;
+        if ((st = copy(c, x, 0, y, 1)) != DD_OK) return st;
+        inf.iters_outer = 1;
+        inf.iters_inner_total = o.iters;
+        inf.relres_inner_last = o.relres;
+        inf.status_detail = o.detail;
+    } else {
+        // Alg. 4: x += err * P_DP(A_SP^{-1} R_SP(C_inv r / err)), r = b - D x in FP64
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, x, x_dev));
+        void *r = c->f64[2], *tmp = c->f64[3];
+        void *src = c->f32[0], *y = c->f32[1];
+        double rn2;
+        if ((st = residual64(c, r, b, x, tmp, &rn2)) != DD_OK) return st;
+        double prev = rn2;
+        int stall = 0, outer = 0;
+        res = DD_NOT_CONVERGED;
+        if (bn2 == 0.0) HIPCK(c, hipMemsetAsync(x, 0, spinor_bytes(c->g, DD_F64), c->stream));
+        while (true) {
+            if (bn2 == 0.0 || std::sqrt(rn2 / bn2) < tol) {
+                res = DD_OK;
+                break;
+            }
+            if (outer >= maxiter) break;
+            double err = std::sqrt(rn2);
+            if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {src, r, c->cinv32}, {1, 0}, {1.0 / err}))) != DD_OK) return st;
+            SolveOut o;
+            dd_status si = solve_sap32(c, 2, src, y, c->prm.inner_tol, c->prm.inner_maxiter, o);
+            if (si < 0) return si;
+            inf.iters_inner_total += o.iters;
+            inf.relres_inner_last = o.relres;
+            if ((st = blas(c, mkb(dd::BLAS_AXPBY, {y, x}, {1, 0}, {err, 1.0}))) != DD_OK) return st;
+            if ((st = residual64(c, r, b, x, tmp, &rn2)) != DD_OK) return st;
+            ++outer;
+            if (!is_fin(rn2)) {
+                inf.status_detail = 4;
+                res = DD_BREAKDOWN;
+                break;
+            }
+            stall = rn2 > 0.81 * prev ? stall + 1 : 0;  // |r| fell by less than 10%
+            prev = rn2;
+            if (stall >= 2) {
+                inf.status_detail = 5;
+                res = DD_BREAKDOWN;
+                break;
+            }
+        }
+        inf.iters_outer = outer;
+    }
+    // true FP64 residual of the returned x
+    {
+        double rn2;
+        if ((st = residual64(c, c->f64[2], b, x, c->f64[3], &rn2)) != DD_OK) return st;
+        inf.relres_true = bn2 > 0 ? std::sqrt(rn2 / bn2) : 0.0;
+    }
+    HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F64, x_dev, x));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return res;
+}
+
+dd_status dd_timing_enable(dd_ctx *c, int on)
+{
+    if (!c) return DD_ERR_ARG;
+    HIPCK(c, flush_timing(c));
+    c->timing = on != 0;
+    for (int k = 0; k < DD_KT_COUNT; ++k) {
+        c->launches[k] = 0;
+        c->ms[k] = 0;
+    }
+    return DD_OK;
+}
+
+dd_status dd_timing_query(dd_ctx *c, dd_kernel_class cls, long long *launches, double *ms)
+{
+    if (!c || cls < 0 || cls >= DD_KT_COUNT) return fail(c, DD_ERR_ARG, "bad kernel class");
+    HIPCK(c, flush_timing(c));
+    if (launches) *launches = c->launches[cls];
+    if (ms) *ms = c->ms[cls];
+    return DD_OK;
+}
+
+}  // extern "C"

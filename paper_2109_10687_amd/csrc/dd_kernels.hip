@@ -1,0 +1,939 @@
+// dd_kernels.hip -- gfx950 kernels of the Clover-Wilson quark solver and their
+// host launchers.
+//
+//  * pack / unpack between the canonical layout and the block-major internal
+//    layout (FP64, FP32, per-site-scaled FP16);
+//  * link packing (FP64, FP32 18-real, FP16 12-real) and the clover setup
+//    (four-leaf field strength, 1 + C as two 6x6 Hermitian blocks, Cholesky
+//    inverse) in FP64 -- appendix "Clover-Wilson Dirac operator";
+//  * the full-lattice apply of D = 1 + C - kappa H, A = I - kappa C_inv H
+//    (Sec. 3) and gamma_5 D gamma_5: one thread per site, coalesced
+//    block-major loads, spin-projected hops, FP64 or FP32 arithmetic;
+//  * the SAP half-sweep (Alg. 1 with the Jacobi of Alg. 2): one workgroup per
+//    Schwarz block, the block's links and the current Jacobi iterate staged
+//    in LDS, the cross-block term read from the neighbouring blocks;
+//  * vector updates and reductions of BiCGStab (Alg. 5) with FP64
+//    accumulation: wavefront shuffles, then LDS, then one partial per
+//    workgroup, summed in a fixed order by a one-workgroup kernel.
+#include "dd_device.h"
+#include "dd_launch.h"
+
+namespace dd {
+
+// ============================================================ pack / unpack
+
+// canonical [Lt][Lz][Ly][Lx][3][4] complex double  ->  internal at precision P
+template <int P>
+__global__ void __launch_bounds__(256) k_pack_spinor(Geom g, SpinorField<P> dst, const double2 *src)
+{
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    Site st;
+    decode(g, i, st);
+    long long n = lex_index(g, st);
+    Spinor<double> x;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double2 t = src[n * 12 + c * 4 + a];
+            x.v[a][c] = {t.x, t.y};
+        }
+    dst.store(g, st.l, st.s, x);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_unpack_spinor(Geom g, double2 *dst, SpinorField<P> src)
+{
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    Site st;
+    decode(g, i, st);
+    long long n = lex_index(g, st);
+    Spinor<double> x;
+    src.load(g, st.l, st.s, x);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[n * 12 + c * 4 + a] = make_double2(x.v[a][c].re, x.v[a][c].im);
+}
+
+// canonical links [4][Lt][Lz][Ly][Lx][3][3] -> FP64, FP32 (18 reals) and FP16
+// (rows 0 and 1); flags non-finite entries
+__global__ void __launch_bounds__(256)
+    k_pack_links(Geom g, const double2 *src, double2 *u64, float2 *u32, __half2 *u16, int *bad)
+{
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    Site st;
+    decode(g, i, st);
+    long long n = lex_index(g, st);
+    int nonfinite = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        const double2 *m = src + ((long long)mu * g.V + n) * 9;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            double2 t = m[e];
+            if (!isfinite(t.x) || !isfinite(t.y)) nonfinite = 1;
+            u64[elem(g, st.l, st.s, 36, mu * 9 + e)] = t;
+            u32[elem(g, st.l, st.s, 36, mu * 9 + e)] = make_float2((float)t.x, (float)t.y);
+            if (e < 6) u16[elem(g, st.l, st.s, 24, mu * 6 + e)] = __floats2half2_rn((float)t.x, (float)t.y);
+        }
+    }
+    if (nonfinite) atomicOr(bad, 1);
+}
+
+// ============================================================ clover setup
+
+// site index of a neighbour given as an internal index (re-decoded)
+DD_INL long long step(const Geom &g, long long i, int mu, int dir)
+{
+    Site st;
+    decode(g, i, st);
+    bool w, ib;
+    return neighbour(g, st, mu, dir, w, ib);
+}
+
+DD_INL void load_link64(const Geom &g, const double2 *u, long long i, int mu, Mat3<double> &U)
+{
+    LinkField<0> f{u};
+    f.load(g, (int)(i >> g.lbvol), (int)(i & (g.bvol - 1)), mu, U);
+}
+
+DD_INL void mul3(const Mat3<double> &A, const Mat3<double> &B, Mat3<double> &C)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cx<double> s = {0, 0};
+            for (int k = 0; k < 3; ++k) s = s + A.m[i][k] * B.m[k][j];
+            C.m[i][j] = s;
+        }
+}
+
+DD_INL void dag3(const Mat3<double> &A, Mat3<double> &B)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) B.m[i][j] = conj(A.m[j][i]);
+}
+
+// product of four links, each daggered or not, accumulated into Q
+DD_INL void leaf(const Mat3<double> *M, const int *dg, Mat3<double> &Q)
+{
+    Mat3<double> acc, t, m;
+    if (dg[0]) dag3(M[0], acc); else acc = M[0];
+    for (int k = 1; k < 4; ++k) {
+        if (dg[k]) dag3(M[k], m); else m = M[k];
+        mul3(acc, m, t);
+        acc = t;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Q.m[i][j] = Q.m[i][j] + acc.m[i][j];
+}
+
+// F_{mu nu}(n) = (Q - Q^dagger) / 8 with Q the four counter-clockwise
+// plaquettes of the (mu, nu) plane through n
+DD_INL void field_strength(const Geom &g, const double2 *u, long long n, int mu, int nu, Mat3<double> &F)
+{
+    long long n_pm = step(g, n, mu, +1), n_pn = step(g, n, nu, +1);
+    long long n_mm = step(g, n, mu, -1), n_mn = step(g, n, nu, -1);
+    long long n_mm_pn = step(g, n_mm, nu, +1), n_mm_mn = step(g, n_mm, nu, -1);
+    long long n_pm_mn = step(g, n_pm, nu, -1);
+    Mat3<double> Q;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Q.m[i][j] = {0, 0};
+    Mat3<double> M[4];
+    {
+        load_link64(g, u, n, mu, M[0]); load_link64(g, u, n_pm, nu, M[1]);
+        load_link64(g, u, n_pn, mu, M[2]); load_link64(g, u, n, nu, M[3]);
+        const int dg[4] = {0, 0, 1, 1};
+        leaf(M, dg, Q);
+    }
+    {
+        load_link64(g, u, n, nu, M[0]); load_link64(g, u, n_mm_pn, mu, M[1]);
+        load_link64(g, u, n_mm, nu, M[2]); load_link64(g, u, n_mm, mu, M[3]);
+        const int dg[4] = {0, 1, 1, 0};
+        leaf(M, dg, Q);
+    }
+    {
+        load_link64(g, u, n_mm, mu, M[0]); load_link64(g, u, n_mm_mn, nu, M[1]);
+        load_link64(g, u, n_mm_mn, mu, M[2]); load_link64(g, u, n_mn, nu, M[3]);
+        const int dg[4] = {1, 1, 0, 0};
+        leaf(M, dg, Q);
+    }
+    {
+        load_link64(g, u, n_mn, nu, M[0]); load_link64(g, u, n_mn, mu, M[1]);
+        load_link64(g, u, n_pm_mn, nu, M[2]); load_link64(g, u, n, mu, M[3]);
+        const int dg[4] = {1, 0, 0, 1};
+        leaf(M, dg, Q);
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) F.m[i][j] = 0.125 * (Q.m[i][j] - conj(Q.m[j][i]));
+}
+
+// Cholesky inverse of a Hermitian positive definite 6x6 matrix (full storage);
+// returns false when a pivot is not positive
+DD_INL bool hpd_inverse6(cx<double> (&M)[6][6], cx<double> (&Minv)[6][6])
+{
+    cx<double> L[6][6];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) L[i][j] = {0, 0};
+    for (int j = 0; j < 6; ++j) {
+        double d = M[j][j].re;
+        for (int k = 0; k < j; ++k) d -= norm2(L[j][k]);
+        if (!(d > 0.0)) return false;
+        double ljj = sqrt(d);
+        L[j][j] = {ljj, 0};
+        for (int i = j + 1; i < 6; ++i) {
+            cx<double> s = M[i][j];
+            for (int k = 0; k < j; ++k) s = s - L[i][k] * conj(L[j][k]);
+            L[i][j] = (1.0 / ljj) * s;
+        }
+    }
+    // Linv = L^{-1} (lower triangular) by forward substitution
+    cx<double> Li[6][6];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) Li[i][j] = {0, 0};
+    for (int j = 0; j < 6; ++j) {
+        Li[j][j] = {1.0 / L[j][j].re, 0};
+        for (int i = j + 1; i < 6; ++i) {
+            cx<double> s = {0, 0};
+            for (int k = j; k < i; ++k) s = s + L[i][k] * Li[k][j];
+            Li[i][j] = (-1.0 / L[i][i].re) * s;
+        }
+    }
+    // M^{-1} = Linv^dagger Linv
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            cx<double> s = {0, 0};
+            for (int k = (i > j ? i : j); k < 6; ++k) s = s + cmulc(Li[k][i], Li[k][j]);
+            Minv[i][j] = s;
+        }
+    return true;
+}
+
+template <typename V2> DD_INL V2 mk2(double a, double b);
+template <> DD_INL double2 mk2<double2>(double a, double b) { return make_double2(a, b); }
+template <> DD_INL float2 mk2<float2>(double a, double b) { return make_float2((float)a, (float)b); }
+template <> DD_INL __half2 mk2<__half2>(double a, double b) { return __floats2half2_rn((float)a, (float)b); }
+
+// store a Hermitian 6x6 pair (blocks + and -) scaled by `f` in the clover layout
+template <typename V2>
+DD_INL void store_clov(V2 *dst, const Geom &g, int l, int s, cx<double> (&M)[2][6][6], double f)
+{
+    for (int b = 0; b < 2; ++b) {
+        for (int j = 0; j < 3; ++j)
+            dst[elem(g, l, s, 36, b * 18 + j)] = mk2<V2>(f * M[b][2 * j][2 * j].re, f * M[b][2 * j + 1][2 * j + 1].re);
+        for (int i = 0; i < 6; ++i)
+            for (int j = i + 1; j < 6; ++j) {
+                cx<double> v = M[b][i][j];
+                dst[elem(g, l, s, 36, b * 18 + 3 + upper_index(i, j))] = mk2<V2>(f * v.re, f * v.im);
+            }
+    }
+}
+
+// 1 + C in the gamma_5-diagonal basis is diag(M+, M-) with
+//   M_pm = 1 + i kappa c_SW sum_{mu<nu} sigma^pm_{mu nu} (x) F_{mu nu},
+// sigma^pm the 2x2 diagonal blocks of P sigma_{mu nu} P, P = [[1,1],[1,-1]]/sqrt 2.
+// Stored: N = M/2 (so that 1 + C = Q diag(N+, N-) Q, Q = [[1,1],[1,-1]]) in FP64,
+// and M^{-1}/2 (C_inv = Q diag(M+^{-1}/2, M-^{-1}/2) Q) in FP32 and FP16.
+__global__ void __launch_bounds__(64) k_clover(Geom g, const double2 *u64, SigmaBlocks sig, double kcsw,
+                                               double2 *clov64, float2 *cinv32, __half2 *cinv16, int *bad)
+{
+    long long i = (long long)blockIdx.x * 64 + threadIdx.x;
+    if (i >= g.V) return;
+    int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
+    cx<double> M[2][6][6];
+    for (int b = 0; b < 2; ++b)
+        for (int p = 0; p < 6; ++p)
+            for (int q = 0; q < 6; ++q) M[b][p][q] = {p == q ? 1.0 : 0.0, 0.0};
+    int plane = 0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = mu + 1; nu < 4; ++nu, ++plane) {
+            Mat3<double> F;
+            field_strength(g, u64, i, mu, nu, F);
+            for (int b = 0; b < 2; ++b)
+                for (int s1 = 0; s1 < 2; ++s1)
+                    for (int s2 = 0; s2 < 2; ++s2) {
+                        cx<double> sg = {sig.re[plane][b][s1][s2], sig.im[plane][b][s1][s2]};
+                        if (sg.re == 0.0 && sg.im == 0.0) continue;
+                        cx<double> pre = cx<double>{0.0, kcsw} * sg;  // i kappa c_SW sigma
+                        for (int a = 0; a < 3; ++a)
+                            for (int c = 0; c < 3; ++c)
+                                M[b][s1 * 3 + a][s2 * 3 + c] = M[b][s1 * 3 + a][s2 * 3 + c] + pre * F.m[a][c];
+                    }
+        }
+    store_clov(clov64, g, l, s, M, 0.5);
+    cx<double> Mi[2][6][6];
+    bool ok = hpd_inverse6(M[0], Mi[0]) && hpd_inverse6(M[1], Mi[1]);
+    if (!ok) {
+        atomicOr(bad, 1);
+        for (int b = 0; b < 2; ++b)
+            for (int p = 0; p < 6; ++p)
+                for (int q = 0; q < 6; ++q) Mi[b][p][q] = {0, 0};
+    }
+    store_clov(cinv32, g, l, s, Mi, 0.5);
+    store_clov(cinv16, g, l, s, Mi, 0.5);
+}
+
+// ============================================================ Dirac apply
+
+template <int PIN, int PG> struct Acc { using T = float; };
+template <int PG> struct Acc<0, PG> { using T = double; };
+template <> struct Acc<1, 0> { using T = double; };
+template <> struct Acc<2, 0> { using T = double; };
+
+// out = op(in) on the full lattice, one thread per site; op 0 = D, 1 = A, 2 = D^dagger
+template <int PIN, int POUT, int PG, int OP>
+__global__ void __launch_bounds__(256) k_dirac(Geom g, SpinorField<POUT> out, SpinorField<PIN> in, LinkField<PG> U,
+                                               CloverField<PG> C, Phase4 ph, double kappa)
+{
+    using R = typename Acc<PIN, PG>::T;
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const long long i = (long long)w * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    Site st;
+    decode(g, i, st);
+    Spinor<R> acc;
+    zero(acc);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+        for (int dir = 1; dir >= -1; dir -= 2) {
+            bool wrap, inblk;
+            long long j = neighbour(g, st, mu, dir, wrap, inblk);
+            int lj = (int)(j >> g.lbvol), sj = (int)(j & (g.bvol - 1));
+            Spinor<R> psi;
+            in.load(g, lj, sj, psi);
+            if (OP == 2) gamma5(psi);
+            Mat3<R> W;
+            if (dir > 0)
+                U.load(g, st.l, st.s, mu, W);
+            else
+                U.load(g, lj, sj, mu, W);
+            cx<R> phase = {R(ph.re[mu]), R(dir > 0 ? ph.im[mu] : -ph.im[mu])};
+            hop(mu, dir, W, psi, wrap, phase, acc);
+        }
+    }
+    Spinor<R> x, t, o;
+    in.load(g, st.l, st.s, x);
+    if (OP == 2) gamma5(x);
+    Clov<R> cl;
+    C.load(g, st.l, st.s, cl);
+    const R k = R(kappa);
+    if (OP == 1) {
+        clover_mul(cl, acc, t);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.v[a][c] = x.v[a][c] - k * t.v[a][c];
+    } else {
+        clover_mul(cl, x, t);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.v[a][c] = t.v[a][c] - k * acc.v[a][c];
+        if (OP == 2) gamma5(o);
+    }
+    out.store(g, st.l, st.s, o);
+}
+
+// ============================================================ SAP half-sweep
+
+// where the SAP kernel reads the block's links from: FP16 (12-real) links are
+// staged in LDS (24 elements x bvol half2); FP32 links are read from global
+// memory through the caches, which keeps the workgroup's LDS at 24 KB
+template <int P> struct SapLinks;
+template <> struct SapLinks<1> {
+    static constexpr int E = 0;  // nothing staged
+    using T = float2;
+    LinkField<1> U;
+    DD_INL void stage(T *, const Geom &, int, int) const {}
+    DD_INL void load(const T *, const Geom &g, int l, int s, int mu, Mat3<float> &W) const { U.load(g, l, s, mu, W); }
+};
+template <> struct SapLinks<2> {
+    static constexpr int E = 24;
+    using T = __half2;
+    const __half2 *p;
+    DD_INL void stage(T *lds, const Geom &g, int l, int s) const
+    {
+        for (int e = 0; e < E; ++e) lds[e * g.bvol + s] = p[elem(g, l, s, E, e)];
+    }
+    DD_INL void load(const T *lds, const Geom &g, int, int s, int mu, Mat3<float> &U) const
+    {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                float2 t = __half22float2(lds[(mu * 6 + a * 3 + b) * g.bvol + s]);
+                U.m[a][b] = {t.x, t.y};
+            }
+        su3_row3(U);
+    }
+};
+
+DD_INL void lds_store_spinor(float2 *xs, int bvol, int s, const Spinor<float> &x)
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xs[(a * 3 + c) * bvol + s] = make_float2(x.v[a][c].re, x.v[a][c].im);
+}
+
+DD_INL void lds_load_spinor(const float2 *xs, int bvol, int s, Spinor<float> &x)
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float2 t = xs[(a * 3 + c) * bvol + s];
+            x.v[a][c] = {t.x, t.y};
+        }
+}
+
+// acc = H_in x: the hops that stay inside the block (Dirichlet at the block
+// faces), neighbours from LDS; in-block hops never cross the lattice edge, so
+// they carry no boundary phase
+template <int P>
+DD_INL void inblock_hops(const float2 *xs, const SapLinks<P> &lk, const typename SapLinks<P>::T *ul, const Geom &g,
+                         const Site &st, Spinor<float> &acc)
+{
+    zero(acc);
+    const int bvol = g.bvol;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int stride = 1 << g.sh[mu];
+#pragma unroll
+        for (int dir = 1; dir >= -1; dir -= 2) {
+            int c = st.c[mu] + dir;
+            if (c < 0 || c >= g.b[mu]) continue;
+            int m = st.s + dir * stride;
+            Spinor<float> psi;
+            lds_load_spinor(xs, bvol, m, psi);
+            Mat3<float> W;
+            lk.load(ul, g, st.l, dir > 0 ? st.s : m, mu, W);
+            hop(mu, dir, W, psi, false, cx<float>{1.f, 0.f}, acc);
+        }
+    }
+}
+
+// One half-sweep of Alg. 1 for the blocks of one colour c (E = 0, O = 1):
+//   [PRE]   s_c <- s_c - A_{c c'} x_{c'}     (cross-block hops from the other colour)
+//           x_c  = B_cc s_c                   (Alg. 2: x = s + K x, n_jac times, K = kappa C_inv H_in)
+//   [!TAIL] s_c <- s_c + b_c - A_cc x_c      (A_cc x = x - K x)
+// FIRST takes s_c from b (s = b at the start of Alg. 1).  One workgroup per
+// block, one thread per site; blockDim.x == block volume.
+template <int P>
+__global__ void __launch_bounds__(256) k_sap_half(Geom g, int colour, int flags, SpinorField<P> bsrc,
+                                                  SpinorField<P> sw, SpinorField<P> xw, SapLinks<P> lk,
+                                                  LinkField<P> U, CloverField<P> Ci, Phase4 ph, float kappa,
+                                                  int n_jac)
+{
+    using LT = typename SapLinks<P>::T;
+    extern __shared__ float4 smem_raw[];
+    const int bvol = g.bvol;
+    float2 *xs = reinterpret_cast<float2 *>(smem_raw);
+    LT *ul = reinterpret_cast<LT *>(xs + 12 * bvol);
+
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    Site st;
+    st.l = colour_block(g, colour, w);
+    st.s = threadIdx.x;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) st.c[mu] = (st.s >> g.sh[mu]) & (g.b[mu] - 1);
+    block_coords(g, st.l, st.B);
+
+    lk.stage(ul, g, st.l, st.s);
+
+    Clov<float> cl;
+    Ci.load(g, st.l, st.s, cl);
+    Spinor<float> src;
+    if (flags & SAP_FIRST)
+        bsrc.load(g, st.l, st.s, src);
+    else
+        sw.load(g, st.l, st.s, src);
+
+    Spinor<float> acc, t;
+    if (flags & SAP_PRE) {
+        zero(acc);
+        for (int mu = 0; mu < 4; ++mu) {
+            for (int dir = 1; dir >= -1; dir -= 2) {
+                int c = st.c[mu] + dir;
+                if (c >= 0 && c < g.b[mu]) continue;
+                bool wrap, inblk;
+                long long j = neighbour(g, st, mu, dir, wrap, inblk);
+                int lj = (int)(j >> g.lbvol), sj = (int)(j & (bvol - 1));
+                Spinor<float> psi;
+                xw.load(g, lj, sj, psi);
+                Mat3<float> W;
+                if (dir > 0)
+                    U.load(g, st.l, st.s, mu, W);
+                else
+                    U.load(g, lj, sj, mu, W);
+                cx<float> phase = {(float)ph.re[mu], (float)(dir > 0 ? ph.im[mu] : -ph.im[mu])};
+                hop(mu, dir, W, psi, wrap, phase, acc);
+            }
+        }
+        clover_mul(cl, acc, t);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) src.v[a][c] = src.v[a][c] + kappa * t.v[a][c];
+    }
+
+    Spinor<float> x = src;
+    for (int j = 0; j < n_jac; ++j) {
+        __syncthreads();  // previous readers of xs are done (and links staged)
+        lds_store_spinor(xs, bvol, st.s, x);
+        __syncthreads();
+        inblock_hops<P>(xs, lk, ul, g, st, acc);
+        clover_mul(cl, acc, t);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) x.v[a][c] = src.v[a][c] + kappa * t.v[a][c];
+    }
+    if (!(flags & SAP_TAIL)) {
+        __syncthreads();
+        lds_store_spinor(xs, bvol, st.s, x);
+        __syncthreads();
+        inblock_hops<P>(xs, lk, ul, g, st, acc);
+        clover_mul(cl, acc, t);
+        Spinor<float> b;
+        bsrc.load(g, st.l, st.s, b);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                src.v[a][c] = src.v[a][c] + b.v[a][c] - x.v[a][c] + kappa * t.v[a][c];
+        sw.store(g, st.l, st.s, src);
+    }
+    xw.store(g, st.l, st.s, x);
+}
+
+// ============================================================ vector kernels
+
+template <int P> struct Elem;
+template <> struct Elem<0> {
+    DD_INL static cx<double> get(const SpinorField<0> &f, const Geom &, long long o)
+    {
+        double2 t = f.p[o];
+        return {t.x, t.y};
+    }
+    DD_INL static void put(const SpinorField<0> &f, const Geom &, long long o, cx<double> v)
+    {
+        f.p[o] = make_double2(v.re, v.im);
+    }
+};
+template <> struct Elem<1> {
+    DD_INL static cx<double> get(const SpinorField<1> &f, const Geom &, long long o)
+    {
+        float2 t = f.p[o];
+        return {(double)t.x, (double)t.y};
+    }
+    DD_INL static void put(const SpinorField<1> &f, const Geom &, long long o, cx<double> v)
+    {
+        f.p[o] = make_float2((float)v.re, (float)v.im);
+    }
+};
+template <> struct Elem<2> {  // read only: the scale belongs to the whole site
+    DD_INL static cx<double> get(const SpinorField<2> &f, const Geom &g, long long o)
+    {
+        long long blk12 = o >> g.lbvol;  // l*12 + e
+        long long site = ((blk12 / 12) << g.lbvol) + (o & (g.bvol - 1));
+        float sc = f.scale[site];
+        float2 t = __half22float2(f.p[o]);
+        return {(double)(t.x * sc), (double)(t.y * sc)};
+    }
+};
+
+template <int NV> DD_INL void wg_reduce_store(double (&v)[NV], double *partials)
+{
+    __shared__ double red[NV][BLAS_WG / 64];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double t = 0;
+            for (int q = 0; q < BLAS_WG / 64; ++q) t += red[k][q];
+            partials[(long long)blockIdx.x * NV + k] = t;
+        }
+}
+
+// sum the per-workgroup partials in a fixed order: out[k] = sum_w partials[w*nv + k]
+__global__ void __launch_bounds__(256) k_finalize(const double *partials, int nwg, int nv, double *out)
+{
+    __shared__ double sh[256];
+    for (int k = 0; k < nv; ++k) {
+        double t = 0;
+        for (int w = threadIdx.x; w < nwg; w += 256) t += partials[(long long)w * nv + k];
+        sh[threadIdx.x] = t;
+        __syncthreads();
+        for (int h = 128; h >= 1; h >>= 1) {
+            if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = sh[0];
+        __syncthreads();
+    }
+}
+
+#define GRID_STRIDE(o, N) for (long long o = (long long)blockIdx.x * BLAS_WG + threadIdx.x; o < (N); o += (long long)gridDim.x * BLAS_WG)
+
+// <a|b> (2 values) and, with NV = 3, |a|^2 as the third
+template <int PA, int PB, int NV>
+__global__ void __launch_bounds__(BLAS_WG) k_dot(Geom g, SpinorField<PA> a, SpinorField<PB> b, double *partials)
+{
+    double v[NV] = {};
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        cx<double> x = Elem<PA>::get(a, g, o), y = Elem<PB>::get(b, g, o);
+        cx<double> d = cmulc(x, y);
+        v[0] += d.re;
+        v[1] += d.im;
+        if (NV == 3) v[2] += norm2(x);
+    }
+    wg_reduce_store<NV>(v, partials);
+}
+
+template <int PA>
+__global__ void __launch_bounds__(BLAS_WG) k_norm2(Geom g, SpinorField<PA> a, double *partials)
+{
+    double v[1] = {0};
+    GRID_STRIDE(o, 12 * g.V) v[0] += norm2(Elem<PA>::get(a, g, o));
+    wg_reduce_store<1>(v, partials);
+}
+
+// x += alpha y ; r -= alpha q ; partial |r|^2
+template <int PX, int PY, int PR>
+__global__ void __launch_bounds__(BLAS_WG) k_update1(Geom g, SpinorField<PX> x, SpinorField<PY> y, SpinorField<PR> r,
+                                                     SpinorField<PR> q, double are, double aim, double *partials)
+{
+    double v[1] = {0};
+    const cx<double> al = {are, aim};
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        Elem<PX>::put(x, g, o, Elem<PX>::get(x, g, o) + al * Elem<PY>::get(y, g, o));
+        cx<double> rr = Elem<PR>::get(r, g, o) - al * Elem<PR>::get(q, g, o);
+        Elem<PR>::put(r, g, o, rr);
+        rr = Elem<PR>::get(r, g, o);  // norm of the stored (rounded) value
+        v[0] += norm2(rr);
+    }
+    wg_reduce_store<1>(v, partials);
+}
+
+// x += omega y ; r -= omega t ; partial |r|^2 and <rt|r>
+template <int PX, int PY, int PR>
+__global__ void __launch_bounds__(BLAS_WG) k_update2(Geom g, SpinorField<PX> x, SpinorField<PY> y, SpinorField<PR> r,
+                                                     SpinorField<PR> t, SpinorField<PR> rt, double ore, double oim,
+                                                     double *partials)
+{
+    double v[3] = {0, 0, 0};
+    const cx<double> om = {ore, oim};
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        Elem<PX>::put(x, g, o, Elem<PX>::get(x, g, o) + om * Elem<PY>::get(y, g, o));
+        cx<double> rr = Elem<PR>::get(r, g, o) - om * Elem<PR>::get(t, g, o);
+        Elem<PR>::put(r, g, o, rr);
+        rr = Elem<PR>::get(r, g, o);
+        v[0] += norm2(rr);
+        cx<double> d = cmulc(Elem<PR>::get(rt, g, o), rr);
+        v[1] += d.re;
+        v[2] += d.im;
+    }
+    wg_reduce_store<3>(v, partials);
+}
+
+// p = r + beta (p - omega q)
+template <int PR>
+__global__ void __launch_bounds__(BLAS_WG) k_pupdate(Geom g, SpinorField<PR> p, SpinorField<PR> r, SpinorField<PR> q,
+                                                     double bre, double bim, double ore, double oim)
+{
+    const cx<double> be = {bre, bim}, om = {ore, oim};
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        cx<double> pv = Elem<PR>::get(p, g, o);
+        Elem<PR>::put(p, g, o, Elem<PR>::get(r, g, o) + be * (pv - om * Elem<PR>::get(q, g, o)));
+    }
+}
+
+// y = a (copy with precision conversion; FP16 targets go through a per-site kernel)
+template <int PA, int PY>
+__global__ void __launch_bounds__(BLAS_WG) k_copy(Geom g, SpinorField<PY> y, SpinorField<PA> a)
+{
+    GRID_STRIDE(o, 12 * g.V) Elem<PY>::put(y, g, o, Elem<PA>::get(a, g, o));
+}
+
+// y = alpha a + beta y (real coefficients)
+template <int PA, int PY>
+__global__ void __launch_bounds__(BLAS_WG) k_axpby(Geom g, double alpha, SpinorField<PA> a, double beta, SpinorField<PY> y)
+{
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        cx<double> yv = beta == 0.0 ? cx<double>{0, 0} : Elem<PY>::get(y, g, o);
+        Elem<PY>::put(y, g, o, alpha * Elem<PA>::get(a, g, o) + beta * yv);
+    }
+}
+
+// r = b - a ; partial |r|^2
+template <int P>
+__global__ void __launch_bounds__(BLAS_WG) k_sub_norm(Geom g, SpinorField<P> r, SpinorField<P> b, SpinorField<P> a,
+                                                      double *partials)
+{
+    double v[1] = {0};
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        cx<double> d = Elem<P>::get(b, g, o) - Elem<P>::get(a, g, o);
+        Elem<P>::put(r, g, o, d);
+        v[0] += norm2(d);
+    }
+    wg_reduce_store<1>(v, partials);
+}
+
+// per-site conversion into another storage precision (any target, FP16 included)
+template <int PA, int PY>
+__global__ void __launch_bounds__(256) k_convert(Geom g, SpinorField<PY> y, SpinorField<PA> a)
+{
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
+    Spinor<float> x;
+    a.load(g, l, s, x);
+    y.store(g, l, s, x);
+}
+
+// c = C_inv (scale * r): the inner source of the defect correction, C_inv in FP32
+template <int PR>
+__global__ void __launch_bounds__(256) k_cinv_src(Geom g, SpinorField<1> c, SpinorField<PR> r, CloverField<1> Ci,
+                                                  double scale)
+{
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
+    Spinor<double> x;
+    r.load(g, l, s, x);
+    Spinor<float> xf, o;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) xf.v[a][cc] = {(float)(scale * x.v[a][cc].re), (float)(scale * x.v[a][cc].im)};
+    Clov<float> cl;
+    Ci.load(g, l, s, cl);
+    clover_mul(cl, xf, o);
+    c.store(g, l, s, o);
+}
+
+// ============================================================ host launchers
+
+static inline int grid_sites(long long V, int wg) { return (int)((V + wg - 1) / wg); }
+
+template <int P> static SpinorField<P> sf(void *p, const Geom &g);
+template <> SpinorField<0> sf<0>(void *p, const Geom &) { return SpinorField<0>{(double2 *)p}; }
+template <> SpinorField<1> sf<1>(void *p, const Geom &) { return SpinorField<1>{(float2 *)p}; }
+template <> SpinorField<2> sf<2>(void *p, const Geom &g)
+{
+    return SpinorField<2>{(__half2 *)p, (float *)((char *)p + 12 * g.V * sizeof(__half2))};
+}
+
+#define DISPATCH_P(P, ...)                                    \
+    switch (P) {                                              \
+    case 0: { constexpr int P_ = 0; __VA_ARGS__; } break;     \
+    case 1: { constexpr int P_ = 1; __VA_ARGS__; } break;     \
+    default: { constexpr int P_ = 2; __VA_ARGS__; } break;    \
+    }
+
+hipError_t launch_pack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src)
+{
+    DISPATCH_P(prec, hipLaunchKernelGGL(k_pack_spinor<P_>, dim3(grid_sites(g.V, 256)), dim3(256), 0, st, g,
+                                        sf<P_>(dst, g), (const double2 *)src));
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src)
+{
+    DISPATCH_P(prec, hipLaunchKernelGGL(k_unpack_spinor<P_>, dim3(grid_sites(g.V, 256)), dim3(256), 0, st, g,
+                                        (double2 *)dst, sf<P_>((void *)src, g)));
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_links(const Geom &g, hipStream_t st, const void *src, void *u64, void *u32, void *u16, int *bad)
+{
+    hipLaunchKernelGGL(k_pack_links, dim3(grid_sites(g.V, 256)), dim3(256), 0, st, g, (const double2 *)src,
+                       (double2 *)u64, (float2 *)u32, (__half2 *)u16, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_clover(const Geom &g, hipStream_t st, const void *u64, const SigmaBlocks &sig, double kcsw,
+                         void *clov64, void *cinv32, void *cinv16, int *bad)
+{
+    hipLaunchKernelGGL(k_clover, dim3(grid_sites(g.V, 64)), dim3(64), 0, st, g, (const double2 *)u64, sig, kcsw,
+                       (double2 *)clov64, (float2 *)cinv32, (__half2 *)cinv16, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_dirac(const Geom &g, hipStream_t st, const DiracArgs &a)
+{
+    const int nwg = grid_sites(g.V, 256);
+    const Phase4 ph = a.phase;
+#define DIRAC_LAUNCH(PIN, POUT, PG, OP, CLOV)                                                                   \
+    hipLaunchKernelGGL((k_dirac<PIN, POUT, PG, OP>), dim3(nwg), dim3(256), 0, st, g, sf<POUT>(a.out, g),       \
+                       sf<PIN>((void *)a.in, g), LinkField<PG>{(decltype(LinkField<PG>::p))a.links},            \
+                       CloverField<PG>{(decltype(CloverField<PG>::p))CLOV}, ph, a.kappa)
+    if (a.pin == 0 && a.pout == 0 && a.pg == 0) {
+        if (a.op == 0) DIRAC_LAUNCH(0, 0, 0, 0, a.clover);
+        else if (a.op == 2) DIRAC_LAUNCH(0, 0, 0, 2, a.clover);
+        else return hipErrorInvalidValue;
+    } else if (a.op != 1) {
+        return hipErrorInvalidValue;
+    } else if (a.pin == 1 && a.pout == 1 && a.pg == 1) {
+        DIRAC_LAUNCH(1, 1, 1, 1, a.clover);
+    } else if (a.pin == 2 && a.pout == 1 && a.pg == 1) {
+        DIRAC_LAUNCH(2, 1, 1, 1, a.clover);
+    } else if (a.pin == 2 && a.pout == 2 && a.pg == 2) {
+        DIRAC_LAUNCH(2, 2, 2, 1, a.clover);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef DIRAC_LAUNCH
+    return hipGetLastError();
+}
+
+size_t sap_lds_bytes(const Geom &g, int prec)
+{
+    size_t link = prec == 1 ? 0 : SapLinks<2>::E * sizeof(__half2);
+    return (size_t)g.bvol * (12 * sizeof(float2) + link);
+}
+
+hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags)
+{
+    const int nwg = g.nblk / 2;
+    const size_t lds = sap_lds_bytes(g, a.prec);
+    if (a.prec == 1) {
+        hipLaunchKernelGGL(k_sap_half<1>, dim3(nwg), dim3(g.bvol), lds, st, g, colour, flags, sf<1>((void *)a.b, g),
+                           sf<1>(a.s, g), sf<1>(a.x, g), SapLinks<1>{LinkField<1>{(const float2 *)a.links}},
+                           LinkField<1>{(const float2 *)a.links}, CloverField<1>{(const float2 *)a.cinv}, a.phase,
+                           (float)a.kappa, a.n_jac);
+    } else if (a.prec == 2) {
+        hipLaunchKernelGGL(k_sap_half<2>, dim3(nwg), dim3(g.bvol), lds, st, g, colour, flags, sf<2>((void *)a.b, g),
+                           sf<2>(a.s, g), sf<2>(a.x, g), SapLinks<2>{(const __half2 *)a.links},
+                           LinkField<2>{(const __half2 *)a.links}, CloverField<2>{(const __half2 *)a.cinv}, a.phase,
+                           (float)a.kappa, a.n_jac);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int blas_grid(const Geom &g)
+{
+    long long n = (12 * g.V + BLAS_WG - 1) / BLAS_WG;
+    return (int)(n < BLAS_MAX_WG ? n : BLAS_MAX_WG);
+}
+
+hipError_t launch_finalize(hipStream_t st, const double *partials, int nwg, int nv, double *out)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, nwg, nv, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_blas(const Geom &g, hipStream_t st, const BlasArgs &a)
+{
+    const int nwg = blas_grid(g);
+    const dim3 G(nwg), B(BLAS_WG);
+    switch (a.kind) {
+    case BLAS_DOT:  // <v0|v1>, precisions p0 == p1
+        DISPATCH_P(a.p[0], hipLaunchKernelGGL((k_dot<P_, P_, 2>), G, B, 0, st, g, sf<P_>(a.v[0], g),
+                                              sf<P_>(a.v[1], g), a.partials));
+        break;
+    case BLAS_DOT_NORM:  // <v0|v1>, |v0|^2
+        DISPATCH_P(a.p[0], hipLaunchKernelGGL((k_dot<P_, P_, 3>), G, B, 0, st, g, sf<P_>(a.v[0], g),
+                                              sf<P_>(a.v[1], g), a.partials));
+        break;
+    case BLAS_NORM2:
+        DISPATCH_P(a.p[0], hipLaunchKernelGGL((k_norm2<P_>), G, B, 0, st, g, sf<P_>(a.v[0], g), a.partials));
+        break;
+    case BLAS_UPDATE1:  // v0 += c0 v1 ; v2 -= c0 v3   (p0 = x, p1 = y, p2 = r/q)
+        if (a.p[0] == 0 && a.p[1] == 0 && a.p[2] == 0)
+            hipLaunchKernelGGL((k_update1<0, 0, 0>), G, B, 0, st, g, sf<0>(a.v[0], g), sf<0>(a.v[1], g),
+                               sf<0>(a.v[2], g), sf<0>(a.v[3], g), a.c[0], a.c[1], a.partials);
+        else if (a.p[0] == 1 && a.p[1] == 1 && a.p[2] == 1)
+            hipLaunchKernelGGL((k_update1<1, 1, 1>), G, B, 0, st, g, sf<1>(a.v[0], g), sf<1>(a.v[1], g),
+                               sf<1>(a.v[2], g), sf<1>(a.v[3], g), a.c[0], a.c[1], a.partials);
+        else if (a.p[0] == 1 && a.p[1] == 2 && a.p[2] == 1)
+            hipLaunchKernelGGL((k_update1<1, 2, 1>), G, B, 0, st, g, sf<1>(a.v[0], g), sf<2>(a.v[1], g),
+                               sf<1>(a.v[2], g), sf<1>(a.v[3], g), a.c[0], a.c[1], a.partials);
+        else
+            return hipErrorInvalidValue;
+        break;
+    case BLAS_UPDATE2:  // v0 += c0 v1 ; v2 -= c0 v3 ; <v4|v2>
+        if (a.p[0] == 0 && a.p[1] == 0 && a.p[2] == 0)
+            hipLaunchKernelGGL((k_update2<0, 0, 0>), G, B, 0, st, g, sf<0>(a.v[0], g), sf<0>(a.v[1], g),
+                               sf<0>(a.v[2], g), sf<0>(a.v[3], g), sf<0>(a.v[4], g), a.c[0], a.c[1], a.partials);
+        else if (a.p[0] == 1 && a.p[1] == 1 && a.p[2] == 1)
+            hipLaunchKernelGGL((k_update2<1, 1, 1>), G, B, 0, st, g, sf<1>(a.v[0], g), sf<1>(a.v[1], g),
+                               sf<1>(a.v[2], g), sf<1>(a.v[3], g), sf<1>(a.v[4], g), a.c[0], a.c[1], a.partials);
+        else if (a.p[0] == 1 && a.p[1] == 2 && a.p[2] == 1)
+            hipLaunchKernelGGL((k_update2<1, 2, 1>), G, B, 0, st, g, sf<1>(a.v[0], g), sf<2>(a.v[1], g),
+                               sf<1>(a.v[2], g), sf<1>(a.v[3], g), sf<1>(a.v[4], g), a.c[0], a.c[1], a.partials);
+        else
+            return hipErrorInvalidValue;
+        break;
+    case BLAS_PUPDATE:  // v0 = v1 + c01 (v0 - c23 v2)
+        DISPATCH_P(a.p[0], if (P_ == 2) return hipErrorInvalidValue;
+                   hipLaunchKernelGGL((k_pupdate<P_ == 2 ? 1 : P_>), G, B, 0, st, g, sf<P_ == 2 ? 1 : P_>(a.v[0], g),
+                                      sf<P_ == 2 ? 1 : P_>(a.v[1], g), sf<P_ == 2 ? 1 : P_>(a.v[2], g), a.c[0],
+                                      a.c[1], a.c[2], a.c[3]));
+        break;
+    case BLAS_AXPBY:  // v1 = c0 v0 + c1 v1 (p0 source, p1 target in {0, 1})
+        if (a.p[0] == 1 && a.p[1] == 0)
+            hipLaunchKernelGGL((k_axpby<1, 0>), G, B, 0, st, g, a.c[0], sf<1>(a.v[0], g), a.c[1], sf<0>(a.v[1], g));
+        else if (a.p[0] == 0 && a.p[1] == 0)
+            hipLaunchKernelGGL((k_axpby<0, 0>), G, B, 0, st, g, a.c[0], sf<0>(a.v[0], g), a.c[1], sf<0>(a.v[1], g));
+        else if (a.p[0] == 1 && a.p[1] == 1)
+            hipLaunchKernelGGL((k_axpby<1, 1>), G, B, 0, st, g, a.c[0], sf<1>(a.v[0], g), a.c[1], sf<1>(a.v[1], g));
+        else if (a.p[0] == 0 && a.p[1] == 1)
+            hipLaunchKernelGGL((k_axpby<0, 1>), G, B, 0, st, g, a.c[0], sf<0>(a.v[0], g), a.c[1], sf<1>(a.v[1], g));
+        else
+            return hipErrorInvalidValue;
+        break;
+    case BLAS_SUB_NORM:  // v0 = v1 - v2 ; |v0|^2 (FP64)
+        hipLaunchKernelGGL((k_sub_norm<0>), G, B, 0, st, g, sf<0>(a.v[0], g), sf<0>(a.v[1], g), sf<0>(a.v[2], g),
+                           a.partials);
+        break;
+    case BLAS_CONVERT: {  // v1 = v0 with precisions p0 -> p1 (per site)
+        const dim3 Gs(grid_sites(g.V, 256)), Bs(256);
+        if (a.p[0] == 1 && a.p[1] == 2)
+            hipLaunchKernelGGL((k_convert<1, 2>), Gs, Bs, 0, st, g, sf<2>(a.v[1], g), sf<1>(a.v[0], g));
+        else if (a.p[0] == 2 && a.p[1] == 1)
+            hipLaunchKernelGGL((k_convert<2, 1>), Gs, Bs, 0, st, g, sf<1>(a.v[1], g), sf<2>(a.v[0], g));
+        else if (a.p[0] == 0 && a.p[1] == 1)
+            hipLaunchKernelGGL((k_convert<0, 1>), Gs, Bs, 0, st, g, sf<1>(a.v[1], g), sf<0>(a.v[0], g));
+        else if (a.p[0] == 1 && a.p[1] == 0)
+            hipLaunchKernelGGL((k_convert<1, 0>), Gs, Bs, 0, st, g, sf<0>(a.v[1], g), sf<1>(a.v[0], g));
+        else
+            return hipErrorInvalidValue;
+        break;
+    }
+    case BLAS_CINV_SRC: {  // v0 (FP32) = C_inv (c0 * v1), v1 at precision p1
+        const dim3 Gs(grid_sites(g.V, 256)), Bs(256);
+        if (a.p[1] == 0)
+            hipLaunchKernelGGL((k_cinv_src<0>), Gs, Bs, 0, st, g, sf<1>(a.v[0], g), sf<0>(a.v[1], g),
+                               CloverField<1>{(const float2 *)a.v[2]}, a.c[0]);
+        else
+            return hipErrorInvalidValue;
+        break;
+    }
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dd

@@ -1,0 +1,88 @@
+// dd_launch.h -- host-side interface of the kernels in dd_kernels.hip: plain
+// argument structs and launcher functions used by the solver driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dd_device.h"
+
+namespace dd {
+
+constexpr int BLAS_WG = 256;        // threads per workgroup of the vector kernels
+constexpr int BLAS_MAX_WG = 4096;   // cap on their grid (grid-stride loops beyond it)
+constexpr int MAX_PARTIALS = BLAS_MAX_WG * 4;
+
+// SAP half-sweep flags
+constexpr int SAP_FIRST = 1;  // read s from the source b (s = b at the start of Alg. 1)
+constexpr int SAP_PRE = 2;    // subtract the cross-block term A_{c c'} x_{c'} first
+constexpr int SAP_TAIL = 4;   // tail of Alg. 1: produce x only, leave s alone
+
+struct Phase4 {
+    double re[4], im[4];
+};
+
+// sigma^pm_{mu nu}: the 2x2 diagonal blocks of P sigma_{mu nu} P for the six
+// planes mu < nu, P = [[1, 1], [1, -1]] / sqrt 2 on the spin pairs
+struct SigmaBlocks {
+    double re[6][2][2][2];
+    double im[6][2][2][2];
+};
+
+struct DiracArgs {
+    void *out;
+    const void *in;
+    const void *links;
+    const void *clover;  // 1 + C blocks (op D / D^dagger) or C_inv blocks (op A)
+    int pin, pout, pg;   // precisions: 0 FP64, 1 FP32, 2 FP16
+    int op;              // 0 D, 1 A, 2 D^dagger
+    double kappa;
+    Phase4 phase;
+};
+
+struct SapArgs {
+    const void *b;  // source (storage precision)
+    void *s;        // work vector
+    void *x;        // output M_SAP b
+    const void *links;
+    const void *cinv;
+    int prec;  // 1 FP32 storage, 2 FP16 storage
+    int n_jac;
+    double kappa;
+    Phase4 phase;
+};
+
+enum BlasKind {
+    BLAS_DOT = 0,
+    BLAS_DOT_NORM,
+    BLAS_NORM2,
+    BLAS_UPDATE1,
+    BLAS_UPDATE2,
+    BLAS_PUPDATE,
+    BLAS_AXPBY,
+    BLAS_SUB_NORM,
+    BLAS_CONVERT,
+    BLAS_CINV_SRC,
+};
+
+struct BlasArgs {
+    int kind;
+    void *v[5];
+    int p[5];
+    double c[4];
+    double *partials;
+};
+
+hipError_t launch_pack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src);
+hipError_t launch_unpack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src);
+hipError_t launch_pack_links(const Geom &g, hipStream_t st, const void *src, void *u64, void *u32, void *u16,
+                             int *bad);
+hipError_t launch_clover(const Geom &g, hipStream_t st, const void *u64, const SigmaBlocks &sig, double kcsw,
+                         void *clov64, void *cinv32, void *cinv16, int *bad);
+hipError_t launch_dirac(const Geom &g, hipStream_t st, const DiracArgs &a);
+size_t sap_lds_bytes(const Geom &g, int prec);
+hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
+int blas_grid(const Geom &g);
+hipError_t launch_blas(const Geom &g, hipStream_t st, const BlasArgs &a);
+hipError_t launch_finalize(hipStream_t st, const double *partials, int nwg, int nv, double *out);
+
+}  // namespace dd
