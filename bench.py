@@ -1,0 +1,281 @@
+"""Benchmark: Dirac-apply HBM GB/s and time to a 1e-10 solve, mixed precision
+against plain FP64 BiCGStab, on one MI355X.
+
+Workload (default): 64^3 x 128 lattice, kappa 0.1365, c_SW 1.7, random SU(3)
+links exp(0.3 i H), Gaussian source, SAP with 4^4 blocks, 4 Jacobi sweeps; the
+mixed-precision solver (FP16 SAP, FP32 BiCGStab, FP64 defect correction) to a
+true FP64 relative residual of 1e-10.
+
+A step is one mixed-precision solve of that system from a zero start: every
+part of the path runs in it (FP64 Dirac apply for the outer residual, FP16
+SAP half-sweeps, FP32 Dirac apply on the preconditioned directions, BiCGStab
+vector kernels).  Inputs are drawn on the device before the timed region.
+
+value: algorithmic bytes of all Dirac-apply launches inside the timed steps
+divided by their summed launch time (HIP events on the library's stream).
+The roofline object reports the dominant kernel of a step.  The plain FP64
+BiCGStab solve of the same system runs once, after the timed steps.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_VEC_TFLOPS = 157.3      # MI355X vector FP32 (published)
+FP64_VEC_TFLOPS = 78.6
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dims", default="64,64,64,128", help="Lx,Ly,Lz,Lt")
+    ap.add_argument("--block", default="4,4,4,4")
+    ap.add_argument("--kappa", type=float, default=0.1365)
+    ap.add_argument("--csw", type=float, default=1.7)
+    ap.add_argument("--eps", type=float, default=0.3)
+    ap.add_argument("--n-sap", type=int, default=4)
+    ap.add_argument("--n-jac", type=int, default=4)
+    ap.add_argument("--inner-tol", type=float, default=1e-6)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--seed", type=int, default=2021)
+    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--fp64", choices=["on", "off"], default="on")
+    ap.add_argument("--fp64-maxiter", type=int, default=4000)
+    ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
+    ap.add_argument("--only-apply", action="store_true", help="time the Dirac applies only (profiling runs)")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("dd_kernels.hip", "dd_device.h"):
+        with open(os.path.join(ROOT, "paper_2109_10687_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, launches_bytes):
+    """HBM bytes per launch from committed rocprofv3 counter runs, when they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    rec = t.get(kernel)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def dirac_microbench(dd, solver, b, reps):
+    """Standalone applies on internal-layout fields: FP64 D, FP32 A, FP16 A."""
+    import torch
+    out = {}
+    for name, prec, op in (("f64_D", dd.DD_F64, dd.DD_OP_D), ("f32_A", dd.DD_F32, dd.DD_OP_A),
+                           ("f16_A", dd.DD_F16, dd.DD_OP_A)):
+        fin = solver.pack(b, prec)
+        fout = solver.field(prec)
+        for _ in range(3):
+            solver.apply_packed(fout, fin, op=op, prec=prec)
+        solver.timing(True)
+        for _ in range(reps):
+            solver.apply_packed(fout, fin, op=op, prec=prec)
+        rep = solver.timing_report()
+        solver.timing(False)
+        cls = {"f64_D": "dirac_f64", "f32_A": "dirac_f32", "f16_A": "dirac_f16"}[name]
+        r = rep[cls]
+        ms = r["ms"] / max(r["launches"], 1)
+        out[name] = {"ms": ms, "GBps": r["bytes"] / r["ms"] / 1e6, "GFLOPs": r["flops"] / r["ms"] / 1e6,
+                     "bytes_per_site": r["bytes"] / r["launches"] / solver.params.volume}
+        del fin, fout
+        torch.cuda.synchronize()
+    return out
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle's D apply on a 32^4 sample of the workload (same kappa,
+    c_SW and link recipe), on the host cores; reported in the metric's unit
+    (algorithmic GB/s at 1536 B/site)."""
+    import numpy as np
+    import oracle as O
+    import synth
+    dims = (32, 32, 32, 32)
+    p = O.Params(dims=dims, kappa=0.1365, csw=1.7, block=(4, 4, 4, 4))
+    U = synth.su3_links(dims, 0.3, 5).numpy()
+    C = O.clover_field(p, U)
+    x = synth.gaussian_spinor(dims, 6).numpy()
+    O.dirac_D(p, U, C, x)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        O.dirac_D(p, U, C, x)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > seconds_target or n >= 50:
+            break
+    V = math.prod(dims)
+    cores = os.environ.get("OMP_NUM_THREADS")
+    cores = int(cores) if cores else (len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count())
+    return {"value": round(1536.0 * V * n / el / 1e9, 4), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle D apply on a 32^4 lattice (kappa 0.1365, c_SW 1.7, eps 0.3), {n} applies in "
+                      f"{el:.1f} s; {el / n * 1e3:.0f} ms per apply; clover precomputed"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path runs on one "
+              "MI355X; the multi-GPU decomposition is a design note, not a measured configuration)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2109_10687_amd as dd
+    import synth
+    from paper_2109_10687_amd import flops as F
+
+    dims = tuple(int(v) for v in args.dims.split(","))
+    block = tuple(int(v) for v in args.block.split(","))
+    V = math.prod(dims)
+    params = dd.Params(dims=dims, kappa=args.kappa, csw=args.csw, block=block, n_sap=args.n_sap, n_jac=args.n_jac,
+                       inner_tol=args.inner_tol)
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    log(f"drawing links and source for {dims} on the device")
+    U = synth.su3_links(dims, args.eps, args.seed, device=dev)
+    b = synth.gaussian_spinor(dims, args.seed + 1, device=dev)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.time() - t0:.1f} s; creating the context and loading the gauge field")
+    solver = dd.Solver(params)
+    solver.load_gauge(U)
+    del U
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"setup done at {time.time() - t0:.1f} s")
+
+    micro = dirac_microbench(dd, solver, b, args.apply_reps)
+    for k, v in micro.items():
+        log(f"apply {k}: {v['ms']:.3f} ms, {v['GBps']:.0f} GB/s, {v['GFLOPs']:.0f} GFLOP/s")
+    if args.only_apply:
+        print(json.dumps({"dirac_apply": micro}))
+        return
+
+    # ---- warm-up and timed mixed-precision solves
+    x = solver.new_spinor()
+    for w in range(args.warmup):
+        x, info = solver.solve(b, tol=args.tol, maxiter=50, mode=dd.DD_SOLVE_MIXED)
+        log(f"warm-up solve {w}: {info['status']} {info['seconds']:.2f} s, outer {info['iters_outer']}, "
+            f"inner {info['iters_inner_total']}, true residual {info['relres_true']:.2e}")
+    torch.cuda.synchronize()
+    solver.timing(True)
+    infos = []
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        x, info = solver.solve(b, tol=args.tol, maxiter=50, mode=dd.DD_SOLVE_MIXED)
+        infos.append(info)
+        log(f"step {s}: {info['status']} {info['seconds']:.2f} s, outer {info['iters_outer']}, "
+            f"inner {info['iters_inner_total']}, true residual {info['relres_true']:.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    rep = solver.timing_report()
+    solver.timing(False)
+    ms_step = wall / args.steps * 1e3
+
+    dirac_names = ("dirac_f64", "dirac_f32", "dirac_f16in", "dirac_f16")
+    dbytes = sum(rep[k]["bytes"] for k in dirac_names)
+    dms = sum(rep[k]["ms"] for k in dirac_names)
+    value = dbytes / dms / 1e6 if dms > 0 else 0.0
+    kernels = {k: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps,
+                   "avg_ms": v["ms"] / max(v["launches"], 1),
+                   "GBps": v["bytes"] / v["ms"] / 1e6 if v["ms"] else 0.0,
+                   "GFLOPs": v["flops"] / v["ms"] / 1e6 if v["ms"] else 0.0}
+               for k, v in rep.items() if v["launches"]}
+    dominant = max(rep, key=lambda k: rep[k]["ms"])
+    d = rep[dominant]
+    avg_ms = d["ms"] / d["launches"]
+    if dominant == "sap":
+        # compute-bound once a block is resident: FP32 vector arithmetic
+        achieved = d["flops"] / d["launches"] / (avg_ms * 1e-3) / 1e12
+        roof = {"kernel": "k_sap_half<2>", "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VEC_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VEC_TFLOPS, 4),
+                "bytes_GBps": round(d["bytes"] / d["ms"] / 1e6, 1)}
+    else:
+        achieved = d["bytes"] / d["launches"] / (avg_ms * 1e-3) / 1e9
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roof["avg_launch_ms"] = round(avg_ms, 4)
+    roof["traffic"] = measured_traffic(roof["kernel"], None)
+    # the Dirac apply inside the solve, against the HBM roof
+    dk = max(dirac_names, key=lambda k: rep[k]["ms"])
+    dr = rep[dk]
+    roof_dirac = {"kernel": dk, "bound": "hbm", "achieved": round(dr["bytes"] / dr["ms"] / 1e6, 1),
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dr["bytes"] / dr["ms"] / 1e6 / HBM_PEAK_GBS, 4),
+                  "avg_launch_ms": round(dr["ms"] / dr["launches"], 4),
+                  "bytes_per_site": round(dr["bytes"] / dr["launches"] / V, 1)}
+
+    result = {
+        "metric": "Dirac-apply HBM GB/s; solve time to 1e-10, mixed-prec vs FP64, one GPU",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16/f32/f64",
+        "data": "synthetic: seeded random SU(3) links exp(0.3 i H) and a Gaussian source, drawn on the device",
+        "config": {"workload": f"Clover-Wilson solve {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}",
+                   "dims": list(dims), "block": list(block), "kappa": args.kappa, "csw": args.csw, "eps": args.eps,
+                   "n_sap": args.n_sap, "n_jac": args.n_jac, "tol": args.tol, "inner_tol": args.inner_tol,
+                   "precision": "FP16 SAP / FP32 BiCGStab / FP64 defect correction", "parallelism": "single GPU"},
+        "solve_mixed": {"seconds": round(ms_step / 1e3, 3), "iters_outer": infos[-1]["iters_outer"],
+                        "iters_inner": infos[-1]["iters_inner_total"],
+                        "relres_true": infos[-1]["relres_true"], "status": infos[-1]["status"]},
+        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kernels.items()},
+        "dirac_apply": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in micro.items()},
+        "roofline": roof,
+        "roofline_dirac": roof_dirac,
+    }
+
+    # ---- plain FP64 BiCGStab on the same system (speedup denominator), once
+    if args.fp64 == "on":
+        log(f"plain FP64 BiCGStab, at most {args.fp64_maxiter} iterations")
+        x64, i64 = solver.solve(b, tol=args.tol, maxiter=args.fp64_maxiter, mode=dd.DD_SOLVE_F64_PLAIN)
+        log(f"plain FP64: {i64['status']} {i64['seconds']:.1f} s, {i64['iters_inner_total']} iterations, "
+            f"true residual {i64['relres_true']:.2e}")
+        conv = i64["status"] == "DD_OK"
+        # error of the mixed solution against the FP64 one (relative L2)
+        err = (torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64)).item() if conv else None
+        result["solve_fp64_plain"] = {"seconds": round(i64["seconds"], 3), "iters": i64["iters_inner_total"],
+                                      "relres_true": i64["relres_true"], "status": i64["status"],
+                                      "converged": conv}
+        sp = i64["seconds"] / (ms_step / 1e3)
+        result["speedup_mixed_vs_fp64"] = round(sp, 2) if conv else None
+        if not conv:
+            result["speedup_mixed_vs_fp64_lower_bound"] = round(sp, 2)
+        result["mixed_vs_fp64_solution_relerr"] = err
+        del x64
+
+    if args.cpu_baseline == "on":
+        log("timing the FP64 CPU oracle on a 32^4 sample")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -88,15 +88,17 @@ typedef enum {
 typedef struct {
     int dims[4];        /* Lx, Ly, Lz, Lt                                       */
     int block[4];       /* SAP block extent per direction: a power of two in 2..16,
-                           block volume <= 1024, dims[mu] / block[mu] even         */
+                           block volume <= 256, dims[mu] / block[mu] even          */
     double kappa;       /* hopping parameter                                     */
     double csw;         /* clover coefficient c_SW                               */
     double phase_re[4]; /* boundary phase per direction                          */
     double phase_im[4];
-    int n_sap;          /* loop count of Alg. 1: M = K sum_{j=0}^{n_sap} (1 - A K)^j */
+    int n_sap;          /* loop count of Alg. 1: M = K sum_{j=0}^{n_sap} (1 - A K)^j;
+                           the paper's runs use 4                                   */
     int n_jac;          /* A_EE applications in Alg. 2: B = sum_{j=0}^{n_jac} (1 - A_EE)^j */
     double inner_tol;   /* relative tolerance of each inner FP32 solve in DD_SOLVE_MIXED
-                           (0 = 1e-6, the per-pass reduction Sec. 3 expects)       */
+                           (0 = 1e-6, the per-pass reduction Sec. 3 expects); a pass
+                           whose start is already close to tol stops earlier       */
     int inner_maxiter;  /* iteration cap of each inner solve (0 = 2000)            */
 } dd_params;
 
@@ -116,7 +118,8 @@ typedef struct dd_ctx dd_ctx;
  * vector for all three solve modes (about 4.6 KB per site), binds the stream.
  * hip_stream is a hipStream_t (NULL = default stream).  Geometry rules: each
  * dims[mu] is a multiple of 2*block[mu]; block[mu] is a power of two; the block
- * volume is at most 1024.  Returns DD_ERR_GEOMETRY or DD_ERR_NOMEM on failure. */
+ * volume is at most 256 (one workgroup per block, one thread per site).
+ * Returns DD_ERR_GEOMETRY or DD_ERR_NOMEM on failure. */
 dd_status dd_create(const dd_params *params, void *hip_stream, dd_ctx **out);
 
 /* Free every device buffer the context owns.  NULL is accepted. */
@@ -133,15 +136,17 @@ dd_status dd_load_gauge(dd_ctx *ctx, const void *U_dev);
 /* out = op(in) for canonical spinor fields (device, caller-owned, 24 doubles
  * per site; in and out must not overlap).  The field is packed into the
  * internal layout at precision prec, the operator is applied at that precision
- * (FP16: per-site-scaled FP16 storage, FP32 arithmetic), and the result is
- * unpacked to complex double.  DD_OP_D is available at every precision,
- * DD_OP_A at FP32 and FP16 (and FP64), DD_OP_DDAG at FP64.  Asynchronous. */
+ * (FP16: per-site-scaled FP16 storage, 12-real links and FP16 C_inv, FP32
+ * arithmetic), and the result is unpacked to complex double.  DD_OP_D and
+ * DD_OP_DDAG are available at DD_F64, DD_OP_A at DD_F32 and DD_F16; other
+ * combinations return DD_ERR_ARG.  Asynchronous. */
 dd_status dirac_apply(dd_ctx *ctx, void *out_dev, const void *in_dev, dd_prec prec, dd_op op);
 
 /* x = M_SAP b (Alg. 1 with loop count n_sap, Jacobi count n_jac from the
- * params) for canonical fields, computed with internal storage at precision
- * prec (DD_F32: FP32 spinors/links/C_inv; DD_F16: FP16 storage, FP32
- * arithmetic; DD_F64: FP64 throughout).  Asynchronous. */
+ * params) for canonical fields (device, caller-owned, must not overlap),
+ * computed with internal storage at precision prec: DD_F32 (FP32 spinors,
+ * links and C_inv) or DD_F16 (per-site-scaled FP16 spinors, 12-real FP16
+ * links, FP16 C_inv); arithmetic is FP32 in both.  Asynchronous. */
 dd_status sap_precondition(dd_ctx *ctx, void *x_dev, const void *b_dev, dd_prec prec);
 
 /* Solve D x = b (canonical fields on the device).  On entry x holds the
@@ -175,21 +180,27 @@ dd_status dirac_apply_packed(dd_ctx *ctx, void *out_internal, const void *in_int
 /* ---- kernel timing for roofline reporting -------------------------------- */
 
 typedef enum {
-    DD_KT_DIRAC_F64 = 0,  /* full-lattice Dirac apply, FP64                     */
-    DD_KT_DIRAC_F32 = 1,  /* full-lattice Dirac apply, FP32                     */
-    DD_KT_DIRAC_F16 = 2,  /* full-lattice Dirac apply, FP16 storage             */
-    DD_KT_SAP = 3,        /* SAP half-sweep kernels (all precisions)            */
-    DD_KT_BLAS = 4,       /* vector updates and reductions                      */
-    DD_KT_COUNT = 5
+    DD_KT_DIRAC_F64 = 0,    /* D or D^dagger, FP64 fields                       */
+    DD_KT_DIRAC_F32 = 1,    /* A, FP32 spinors, links and C_inv                 */
+    DD_KT_DIRAC_F16IN = 2,  /* A, FP16 input spinor, FP32 links/C_inv/output    */
+    DD_KT_DIRAC_F16 = 3,    /* A, FP16 spinors, 12-real FP16 links, FP16 C_inv  */
+    DD_KT_SAP = 4,          /* SAP half-sweep kernels (all precisions)           */
+    DD_KT_BLAS = 5,         /* vector updates and reductions                     */
+    DD_KT_COUNT = 6
 } dd_kernel_class;
 
 /* When enabled, every launch of the timed classes is bracketed by HIP events
- * on the context's stream.  Enabling clears the counters. */
+ * on the context's stream.  Enabling (or disabling) clears the counters. */
 dd_status dd_timing_enable(dd_ctx *ctx, int on);
 
-/* Launch count and summed launch time (ms) of one class since enabling;
- * synchronises the stream. */
-dd_status dd_timing_query(dd_ctx *ctx, dd_kernel_class cls, long long *launches, double *ms);
+/* Launch count, summed launch time (ms), and the algorithmic bytes and flops
+ * of those launches for one class since enabling; synchronises the stream.
+ * Algorithmic bytes count every field a launch must read or write once per
+ * site (a link or neighbour spinor used by two sites counts once); flops use
+ * 168 per x/y/z hop, 156 per t hop and 600 per clover multiply.  Any output
+ * pointer may be NULL. */
+dd_status dd_timing_query(dd_ctx *ctx, dd_kernel_class cls, long long *launches, double *ms, double *bytes,
+                          double *flops);
 
 #ifdef __cplusplus
 }

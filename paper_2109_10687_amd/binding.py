@@ -22,7 +22,9 @@ LIB_PATH = os.path.join(HERE, "libddsolve.so")
 DD_F64, DD_F32, DD_F16 = 0, 1, 2
 DD_OP_D, DD_OP_A, DD_OP_DDAG = 0, 1, 2
 DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED = 0, 1, 2
-DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS = range(5)
+DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16IN, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS = range(6)
+KERNEL_CLASSES = {"dirac_f64": DD_KT_DIRAC_F64, "dirac_f32": DD_KT_DIRAC_F32, "dirac_f16in": DD_KT_DIRAC_F16IN,
+                  "dirac_f16": DD_KT_DIRAC_F16, "sap": DD_KT_SAP, "blas": DD_KT_BLAS}
 
 STATUS = {0: "DD_OK", 1: "DD_NOT_CONVERGED", 2: "DD_BREAKDOWN", -1: "DD_ERR_ARG", -2: "DD_ERR_GEOMETRY",
           -3: "DD_ERR_HIP", -4: "DD_ERR_NOMEM", -5: "DD_ERR_NONFINITE", -6: "DD_ERR_CLOVER_NOT_PD",
@@ -77,7 +79,8 @@ def lib():
             "dd_unpack_spinor": (i, [vp, vp, vp, i]),
             "dirac_apply_packed": (i, [vp, vp, vp, i, i]),
             "dd_timing_enable": (i, [vp, i]),
-            "dd_timing_query": (i, [vp, i, ctypes.POINTER(ll), ctypes.POINTER(d)]),
+            "dd_timing_query": (i, [vp, i, ctypes.POINTER(ll), ctypes.POINTER(d), ctypes.POINTER(d),
+                                    ctypes.POINTER(d)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -95,7 +98,7 @@ class Params:
     csw: float
     block: tuple = (4, 4, 4, 4)
     phases: tuple = (1.0, 1.0, 1.0, -1.0)
-    n_sap: int = 2
+    n_sap: int = 4
     n_jac: int = 4
     inner_tol: float = 1e-6
     inner_maxiter: int = 2000
@@ -210,10 +213,12 @@ def dd_timing_enable(ctx, on):
 
 
 def dd_timing_query(ctx, cls):
+    """(launches, ms, algorithmic bytes, flops) of one kernel class since enabling."""
     n = ctypes.c_longlong(0)
-    ms = ctypes.c_double(0)
-    _check(ctx, lib().dd_timing_query(ctx, cls, ctypes.byref(n), ctypes.byref(ms)))
-    return n.value, ms.value
+    ms, by, fl = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    _check(ctx, lib().dd_timing_query(ctx, cls, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                      ctypes.byref(fl)))
+    return n.value, ms.value, by.value, fl.value
 
 
 # ------------------------------------------------------------------ convenience
@@ -278,4 +283,15 @@ class Solver:
 
     def apply_packed(self, out, inp, op=DD_OP_A, prec=DD_F32):
         dirac_apply_packed(self.ctx, out, inp, prec, op)
+        return out
+
+    def timing(self, on=True):
+        dd_timing_enable(self.ctx, on)
+
+    def timing_report(self):
+        """{class: {launches, ms, bytes, flops}} since timing was enabled."""
+        out = {}
+        for name, cls in KERNEL_CLASSES.items():
+            n, ms, by, fl = dd_timing_query(self.ctx, cls)
+            out[name] = {"launches": n, "ms": ms, "bytes": by, "flops": fl}
         return out

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -28,6 +29,7 @@ constexpr int N64 = 7, N32 = 10, N16 = 5;
 struct TimerRec {
     int cls;
     hipEvent_t a, b;
+    double bytes, flops;
 };
 
 }  // namespace
@@ -38,6 +40,7 @@ struct dd_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     bool gauge = false;
+    int verbose = 0;  // DD_VERBOSE=1: one progress line per outer pass and per 100 inner iterations
     dd::Phase4 phase{};
     // packed gauge fields
     void *U64 = nullptr, *U32 = nullptr, *U16 = nullptr;
@@ -52,7 +55,7 @@ struct dd_ctx {
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     long long launches[DD_KT_COUNT] = {};
-    double ms[DD_KT_COUNT] = {};
+    double ms[DD_KT_COUNT] = {}, bytes[DD_KT_COUNT] = {}, flops[DD_KT_COUNT] = {};
 };
 
 namespace {
@@ -79,8 +82,9 @@ hipEvent_t take_event(dd_ctx *c)
     return c->pool[c->pool_used++];
 }
 
-// run `launch` and, when timing is on, bracket it with events on the stream
-template <typename F> hipError_t timed(dd_ctx *c, int cls, F &&launch)
+// run `launch` and, when timing is on, bracket it with events on the stream;
+// bytes and flops are the launch's algorithmic traffic and arithmetic
+template <typename F> hipError_t timed(dd_ctx *c, int cls, double bytes, double flops, F &&launch)
 {
     if (!c->timing) return launch();
     hipEvent_t a = take_event(c), b = take_event(c);
@@ -88,7 +92,7 @@ template <typename F> hipError_t timed(dd_ctx *c, int cls, F &&launch)
     (void)hipEventRecord(a, c->stream);
     hipError_t e = launch();
     (void)hipEventRecord(b, c->stream);
-    c->recs.push_back({cls, a, b});
+    c->recs.push_back({cls, a, b, bytes, flops});
     return e;
 }
 
@@ -102,6 +106,8 @@ hipError_t flush_timing(dd_ctx *c)
         if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
             c->ms[r.cls] += t;
             c->launches[r.cls] += 1;
+            c->bytes[r.cls] += r.bytes;
+            c->flops[r.cls] += r.flops;
         }
     }
     c->recs.clear();
@@ -122,6 +128,27 @@ size_t spinor_bytes(const Geom &g, int prec)
     if (prec == DD_F64) return (size_t)g.V * 12 * 16;
     if (prec == DD_F32) return (size_t)g.V * 12 * 8;
     return (size_t)g.V * (12 * 4 + 4);
+}
+
+// ---- algorithmic bytes and flops per site (each field read or written once)
+double sp_b(int prec) { return prec == 0 ? 192.0 : prec == 1 ? 96.0 : 52.0; }   // spinor (+ FP16 scale)
+double lk_b(int prec) { return prec == 0 ? 144.0 : prec == 1 ? 72.0 : 24.0; }    // one link (FP16: 12 reals)
+double cl_b(int prec) { return prec == 0 ? 576.0 : prec == 1 ? 288.0 : 144.0; }  // clover / C_inv block pair
+const double HOPF[4] = {168, 168, 168, 156};                                      // flops of one hop per direction
+constexpr double CLOVF = 600;                                                      // clover multiply + combine
+
+// hop flops per site that stay inside a block, and those that leave it
+double hops_in(const Geom &g)
+{
+    double f = 0;
+    for (int mu = 0; mu < 4; ++mu) f += 2.0 * (g.b[mu] - 1) / g.b[mu] * HOPF[mu];
+    return f;
+}
+double hops_out(const Geom &g)
+{
+    double f = 0;
+    for (int mu = 0; mu < 4; ++mu) f += 2.0 / g.b[mu] * HOPF[mu];
+    return f;
 }
 
 // gamma matrices of the paper's appendix (Dirac representation, gamma_4 diagonal),
@@ -208,8 +235,11 @@ dd_status k_dirac(dd_ctx *c, void *out, const void *in, int pin, int pout, int p
         a.links = c->U16;
         a.clover = c->cinv16;
     }
-    int cls = pin == 0 ? DD_KT_DIRAC_F64 : (pin == 1 ? DD_KT_DIRAC_F32 : DD_KT_DIRAC_F16);
-    hipError_t e = timed(c, cls, [&] { return dd::launch_dirac(c->g, c->stream, a); });
+    int cls = pg == 0 ? DD_KT_DIRAC_F64 : pg == 2 ? DD_KT_DIRAC_F16 : pin == 2 ? DD_KT_DIRAC_F16IN : DD_KT_DIRAC_F32;
+    const double V = (double)c->g.V;
+    const double bytes = V * (sp_b(pin) + sp_b(pout) + 4 * lk_b(pg) + cl_b(pg));
+    const double flops = V * (hops_in(c->g) + hops_out(c->g) + CLOVF);
+    hipError_t e = timed(c, cls, bytes, flops, [&] { return dd::launch_dirac(c->g, c->stream, a); });
     if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("dirac launch: ") + hipGetErrorString(e));
     return DD_OK;
 }
@@ -229,8 +259,26 @@ dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
     a.phase = c->phase;
     const int E = 0, O = 1;
     const int n = c->prm.n_sap;
+    const Geom &g = c->g;
     auto half = [&](int colour, int flags) -> dd_status {
-        hipError_t e = timed(c, DD_KT_SAP, [&] { return dd::launch_sap_half(c->g, c->stream, a, colour, flags); });
+        // per site of the swept colour: source, links, C_inv, x written; without
+        // TAIL also b read and s written; with PRE the neighbour-block face
+        // spinors and the links that point into the block from outside
+        const bool tail = flags & dd::SAP_TAIL, pre = flags & dd::SAP_PRE, first = flags & dd::SAP_FIRST;
+        double face_sp = 0, face_lk = 0;
+        for (int mu = 0; mu < 4; ++mu) {
+            face_sp += 2.0 / g.b[mu];
+            face_lk += 1.0 / g.b[mu];
+        }
+        double per = sp_b(prec) + 4 * lk_b(prec) + cl_b(prec) + sp_b(prec);
+        if (!tail) per += (first ? 0.0 : sp_b(prec)) + sp_b(prec);
+        if (pre) per += face_sp * sp_b(prec) + face_lk * lk_b(prec);
+        double fl = c->prm.n_jac * (hops_in(g) + CLOVF);
+        if (!tail) fl += hops_in(g) + CLOVF + 48;
+        if (pre) fl += hops_out(g) + CLOVF;
+        const double sites = 0.5 * (double)g.V;
+        hipError_t e = timed(c, DD_KT_SAP, sites * per, sites * fl,
+                             [&] { return dd::launch_sap_half(c->g, c->stream, a, colour, flags); });
         if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("sap launch: ") + hipGetErrorString(e));
         return DD_OK;
     };
@@ -247,7 +295,23 @@ dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
 dd_status blas(dd_ctx *c, dd::BlasArgs a)
 {
     a.partials = c->partials;
-    hipError_t e = timed(c, DD_KT_BLAS, [&] { return dd::launch_blas(c->g, c->stream, a); });
+    // vectors read + written per site, and flops per site
+    double rw = 0, fl = 0;
+    const double P0 = sp_b(a.p[0]), P1 = sp_b(a.p[1]), P2 = sp_b(a.p[2]);
+    switch (a.kind) {
+    case dd::BLAS_DOT: rw = P0 + P1; fl = 96; break;
+    case dd::BLAS_DOT_NORM: rw = P0 + P1; fl = 144; break;
+    case dd::BLAS_NORM2: rw = P0; fl = 48; break;
+    case dd::BLAS_UPDATE1: rw = 2 * P0 + P1 + 3 * P2; fl = 240; break;
+    case dd::BLAS_UPDATE2: rw = 2 * P0 + P1 + 4 * P2; fl = 336; break;
+    case dd::BLAS_PUPDATE: rw = 4 * P0; fl = 192; break;
+    case dd::BLAS_AXPBY: rw = P0 + (a.c[1] != 0.0 ? 2 : 1) * P1; fl = 72; break;
+    case dd::BLAS_SUB_NORM: rw = 3 * P0; fl = 72; break;
+    case dd::BLAS_CONVERT: rw = P0 + P1; break;
+    case dd::BLAS_CINV_SRC: rw = sp_b(1) + P1 + cl_b(1); fl = CLOVF; break;
+    }
+    const double V = (double)c->g.V;
+    hipError_t e = timed(c, DD_KT_BLAS, V * rw, V * fl, [&] { return dd::launch_blas(c->g, c->stream, a); });
     if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("vector kernel: ") + hipGetErrorString(e));
     return DD_OK;
 }
@@ -356,6 +420,10 @@ dd_status solve_plain64(dd_ctx *c, void *x, void *b, double tol, int maxiter, So
                 conv = true;
                 break;
             }
+            if (c->verbose && it % 500 == 0) {
+                std::fprintf(stderr, "[ddsolve] FP64 iteration %d: relative residual %.3e\n", it, std::sqrt(rn2 / bn2));
+                std::fflush(stderr);
+            }
             if ((st = k_dirac(c, t, r, 0, 0, 0, 0)) != DD_OK) return st;
             if ((st = reduce(c, mkb(dd::BLAS_DOT_NORM, {t, r}, {0, 0}), 3, d)) != DD_OK) return st;
             if (d[2] == 0.0 || !is_fin(d[2])) {
@@ -450,6 +518,10 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
             return st;
         o.relres = std::sqrt(rn2 / bn2);
         if (o.relres < tol) return DD_OK;
+        if (c->verbose && (it + 1) % 100 == 0) {
+            std::fprintf(stderr, "[ddsolve] inner iteration %d: relative residual %.3e\n", it + 1, o.relres);
+            std::fflush(stderr);
+        }
         if ((st = precond(r, r16, Mr, t)) != DD_OK) return st;
         if ((st = reduce(c, mkb(dd::BLAS_DOT_NORM, {t, r}, {1, 1}), 3, d)) != DD_OK) return st;
         if (d[2] == 0.0 || !is_fin(d[2])) {
@@ -512,9 +584,9 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
         bvol *= b;
         nblk *= L / b;
     }
-    if (bvol > 1024 || prm->n_sap < 0 || prm->n_jac < 1 || !(prm->kappa >= 0) || !std::isfinite(prm->csw)) {
+    if (bvol > dd::MAX_BLOCK_VOLUME || prm->n_sap < 0 || prm->n_jac < 1 || !(prm->kappa >= 0) || !std::isfinite(prm->csw)) {
         delete c;
-        return bvol > 1024 ? DD_ERR_GEOMETRY : DD_ERR_ARG;
+        return bvol > dd::MAX_BLOCK_VOLUME ? DD_ERR_GEOMETRY : DD_ERR_ARG;
     }
     g.bvol = bvol;
     g.lbvol = ilog2(bvol);
@@ -529,6 +601,7 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
         c->phase.im[mu] = prm->phase_im[mu];
     }
     c->stream = (hipStream_t)hip_stream;
+    if (const char *v = std::getenv("DD_VERBOSE")) c->verbose = std::atoi(v);
 
     auto alloc = [&](void **p, size_t bytes) -> bool { return hipMalloc(p, bytes) == hipSuccess; };
     bool ok = alloc(&c->U64, (size_t)V * 36 * 16) && alloc(&c->U32, (size_t)V * 36 * 8) &&
@@ -705,18 +778,31 @@ dd_status bicgstab_solve(dd_ctx *c, void *x_dev, const void *b_dev, double tol, 
             if (outer >= maxiter) break;
             double err = std::sqrt(rn2);
             if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {src, r, c->cinv32}, {1, 0}, {1.0 / err}))) != DD_OK) return st;
+            // each pass reduces the residual by inner_tol, except that the last
+            // pass stops once the outer target is met (with a factor 2 margin)
+            const double need = 0.5 * tol * std::sqrt(bn2) / err;
+            const double itol = need > c->prm.inner_tol ? (need < 0.1 ? need : 0.1) : c->prm.inner_tol;
             SolveOut o;
-            dd_status si = solve_sap32(c, 2, src, y, c->prm.inner_tol, c->prm.inner_maxiter, o);
+            dd_status si = solve_sap32(c, 2, src, y, itol, c->prm.inner_maxiter, o);
             if (si < 0) return si;
             inf.iters_inner_total += o.iters;
             inf.relres_inner_last = o.relres;
             if ((st = blas(c, mkb(dd::BLAS_AXPBY, {y, x}, {1, 0}, {err, 1.0}))) != DD_OK) return st;
             if ((st = residual64(c, r, b, x, tmp, &rn2)) != DD_OK) return st;
             ++outer;
-            if (!is_fin(rn2)) {
-                inf.status_detail = 4;
+            if (!is_fin(rn2) || rn2 >= prev) {
+                // the correction made the true residual worse (inner solve failed):
+                // take it back, so x stays the best iterate, and stop
+                if ((st = blas(c, mkb(dd::BLAS_AXPBY, {y, x}, {1, 0}, {-err, 1.0}))) != DD_OK) return st;
+                if ((st = residual64(c, r, b, x, tmp, &rn2)) != DD_OK) return st;
+                inf.status_detail = is_fin(rn2) ? 5 : 4;
                 res = DD_BREAKDOWN;
                 break;
+            }
+            if (c->verbose) {
+                std::fprintf(stderr, "[ddsolve] outer pass %d: %d inner iterations (inner tol %.1e, reached %.2e), "
+                             "true residual %.3e\n", outer, o.iters, itol, o.relres, std::sqrt(rn2 / bn2));
+                std::fflush(stderr);
             }
             stall = rn2 > 0.81 * prev ? stall + 1 : 0;  // |r| fell by less than 10%
             prev = rn2;
@@ -748,17 +834,20 @@ dd_status dd_timing_enable(dd_ctx *c, int on)
     c->timing = on != 0;
     for (int k = 0; k < DD_KT_COUNT; ++k) {
         c->launches[k] = 0;
-        c->ms[k] = 0;
+        c->ms[k] = c->bytes[k] = c->flops[k] = 0;
     }
     return DD_OK;
 }
 
-dd_status dd_timing_query(dd_ctx *c, dd_kernel_class cls, long long *launches, double *ms)
+dd_status dd_timing_query(dd_ctx *c, dd_kernel_class cls, long long *launches, double *ms, double *bytes,
+                          double *flops)
 {
     if (!c || cls < 0 || cls >= DD_KT_COUNT) return fail(c, DD_ERR_ARG, "bad kernel class");
     HIPCK(c, flush_timing(c));
     if (launches) *launches = c->launches[cls];
     if (ms) *ms = c->ms[cls];
+    if (bytes) *bytes = c->bytes[cls];
+    if (flops) *flops = c->flops[cls];
     return DD_OK;
 }
 

@@ -11,6 +11,7 @@ namespace dd {
 constexpr int BLAS_WG = 256;        // threads per workgroup of the vector kernels
 constexpr int BLAS_MAX_WG = 4096;   // cap on their grid (grid-stride loops beyond it)
 constexpr int MAX_PARTIALS = BLAS_MAX_WG * 4;
+constexpr int MAX_BLOCK_VOLUME = 256;  // one SAP block per workgroup, one thread per site
 
 // SAP half-sweep flags
 constexpr int SAP_FIRST = 1;  // read s from the source b (s = b at the start of Alg. 1)

@@ -40,6 +40,13 @@ def test_create_rejects_bad_geometry_without_gpu():
         assert e.status == -2
     else:
         raise AssertionError("expected DD_ERR_GEOMETRY")
+    p = dd.Params(dims=(16, 8, 8, 8), kappa=0.12, csw=1.0, block=(8, 4, 4, 4))  # 512 sites > one workgroup
+    try:
+        dd.dd_create(p, stream=0)
+    except dd.DDError as e:
+        assert e.status == -2
+    else:
+        raise AssertionError("expected DD_ERR_GEOMETRY")
     p = dd.Params(dims=(8, 8, 8, 8), kappa=0.12, csw=1.0, block=(4, 3, 4, 4))  # not a power of two
     try:
         dd.dd_create(p, stream=0)
