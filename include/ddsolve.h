@@ -82,7 +82,13 @@ typedef enum {
     /* defect correction (Alg. 4) in FP64 around FP32 SAP-BiCGStab with an FP16
      * preconditioner (per-site-scaled FP16 spinors, 12-real FP16 links, FP16
      * C_inv); tol is the true FP64 relative residual |b - D x| / |b| */
-    DD_SOLVE_MIXED = 2
+    DD_SOLVE_MIXED = 2,
+    /* as DD_SOLVE_MIXED, but the inner FP32 solver is restarted flexible GCR
+     * (cycle length gcr_nkv) right-preconditioned by the FP16 SAP: the flexible
+     * alternative to BiCGStab that Sec. 3 names for a preconditioner that varies
+     * between applications, as a rounded FP16 SAP does.  Each inner iteration
+     * applies M_SAP and A once; the residual never grows. */
+    DD_SOLVE_MIXED_GCR = 3
 } dd_solve_mode;
 
 typedef struct {
@@ -100,6 +106,8 @@ typedef struct {
                            (0 = 1e-6, the per-pass reduction Sec. 3 expects); a pass
                            whose start is already close to tol stops earlier       */
     int inner_maxiter;  /* iteration cap of each inner solve (0 = 2000)            */
+    int gcr_nkv;        /* GCR cycle length for DD_SOLVE_MIXED_GCR, 1..16 (0 = 16);
+                           dd_create allocates gcr_nkv FP32 and gcr_nkv FP16 fields */
 } dd_params;
 
 typedef struct {
@@ -154,7 +162,7 @@ dd_status sap_precondition(dd_ctx *ctx, void *x_dev, const void *b_dev, dd_prec 
  * cold start; a previous solution resumes the solve) and is ignored for
  * DD_SOLVE_F32_SAP; on exit it holds the solution.  maxiter bounds the
  * BiCGStab loop passes of a single-level solve, or the defect-correction
- * passes of DD_SOLVE_MIXED.  Returns DD_OK, DD_NOT_CONVERGED or DD_BREAKDOWN
+ * passes of DD_SOLVE_MIXED and DD_SOLVE_MIXED_GCR.  Returns DD_OK, DD_NOT_CONVERGED or DD_BREAKDOWN
  * (x then holds the best iterate) and fills info (may be NULL).  A source
  * with NaN or Inf returns DD_ERR_NONFINITE without touching x.
  * Synchronises the stream. */

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libddsolve.so")
 
 DD_F64, DD_F32, DD_F16 = 0, 1, 2
 DD_OP_D, DD_OP_A, DD_OP_DDAG = 0, 1, 2
-DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED = 0, 1, 2
+DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED, DD_SOLVE_MIXED_GCR = 0, 1, 2, 3
 DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16IN, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS = range(6)
 KERNEL_CLASSES = {"dirac_f64": DD_KT_DIRAC_F64, "dirac_f32": DD_KT_DIRAC_F32, "dirac_f16in": DD_KT_DIRAC_F16IN,
                   "dirac_f16": DD_KT_DIRAC_F16, "sap": DD_KT_SAP, "blas": DD_KT_BLAS}
@@ -45,7 +45,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("block", ctypes.c_int * 4), ("kappa", ctypes.c_double),
                 ("csw", ctypes.c_double), ("phase_re", ctypes.c_double * 4), ("phase_im", ctypes.c_double * 4),
                 ("n_sap", ctypes.c_int), ("n_jac", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("inner_maxiter", ctypes.c_int)]
+                ("inner_maxiter", ctypes.c_int), ("gcr_nkv", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -102,6 +102,7 @@ class Params:
     n_jac: int = 4
     inner_tol: float = 1e-6
     inner_maxiter: int = 2000
+    gcr_nkv: int = 16
 
     def c(self):
         p = _Params()
@@ -117,6 +118,7 @@ class Params:
         p.n_jac = int(self.n_jac)
         p.inner_tol = float(self.inner_tol)
         p.inner_maxiter = int(self.inner_maxiter)
+        p.gcr_nkv = int(self.gcr_nkv)
         return p
 
     @property

@@ -25,6 +25,7 @@ using cplx = std::complex<double>;
 namespace {
 
 constexpr int N64 = 7, N32 = 10, N16 = 5;
+constexpr int RED_MAX = 2 * dd::GCR_MAX_NKV;  // longest reduction result (doubles)
 
 struct TimerRec {
     int cls;
@@ -47,6 +48,7 @@ struct dd_ctx {
     void *clov64 = nullptr, *cinv32 = nullptr, *cinv16 = nullptr;
     // work vectors
     void *f64[N64] = {}, *f32[N32] = {}, *f16[N16] = {};
+    void *gz[dd::GCR_MAX_NKV] = {}, *gp[dd::GCR_MAX_NKV] = {};  // GCR images (FP32), directions (FP16)
     double *partials = nullptr, *red = nullptr, *red_host = nullptr;
     int *flag = nullptr;
     // kernel timing
@@ -553,6 +555,113 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
     return DD_NOT_CONVERGED;
 }
 
+// bring nv finalized sums of `partials` (nwg workgroups) to the host
+dd_status fetch(dd_ctx *c, int nv, double *out)
+{
+    HIPCK(c, dd::launch_finalize(c->stream, c->partials, dd::blas_grid(c->g), nv, c->red));
+    HIPCK(c, hipMemcpyAsync(c->red_host, c->red, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < nv; ++k) out[k] = c->red_host[k];
+    return DD_OK;
+}
+
+// Restarted flexible GCR on A M (M = FP16 SAP) for the FP32 source src.  Each
+// iteration: p_k = M r (FP16), z_k = A p_k (FP32), z_k orthonormalised against
+// z_0..z_{k-1} (classical Gram-Schmidt, FP64 sums), r -= <z_k|r> z_k.  At the end
+// of a cycle y += sum_k alpha_k p_k with alpha from the triangular relation
+// A p_k = b_k z_k + sum_{j<k} a_jk z_j.  The directions are stored, so M may
+// differ from one application to the next.
+dd_status solve_gcr32(dd_ctx *c, void *src, void *y, double tol, int maxiter, SolveOut &o)
+{
+    const Geom &g = c->g;
+    const int nkv = c->prm.gcr_nkv;
+    void *r = c->f32[2], *r16 = c->f16[1], *s = c->f16[4];
+    const double V = (double)g.V;
+    dd_status st;
+    HIPCK(c, hipMemsetAsync(y, 0, spinor_bytes(g, DD_F32), c->stream));
+    double bn2;
+    if ((st = norm2(c, src, 1, &bn2)) != DD_OK) return st;
+    if (!is_fin(bn2)) return fail(c, DD_ERR_NONFINITE, "inner source holds NaN or Inf");
+    o.iters = 0;
+    o.relres = 0;
+    if (bn2 == 0.0) return DD_OK;
+    if ((st = copy(c, r, 1, src, 1)) != DD_OK) return st;
+    double rn2 = bn2;
+    std::vector<cplx> a((size_t)nkv * nkv), cc(nkv), alpha(nkv);
+    std::vector<double> bk(nkv);
+    bool done = false;
+    while (!done) {
+        int n = 0;
+        for (int k = 0; k < nkv; ++k) {
+            // p_k = M r,  z_k = A p_k
+            if ((st = copy(c, r16, 2, r, 1)) != DD_OK) return st;
+            if ((st = k_sap(c, 2, r16, c->gp[k], s)) != DD_OK) return st;
+            if ((st = k_dirac(c, c->gz[k], c->gp[k], 2, 1, 1, 1)) != DD_OK) return st;
+            dd::VecSet zs{};
+            for (int j = 0; j < k; ++j) zs.v[j] = c->gz[j];
+            double d[2 * dd::GCR_MAX_NKV];
+            if (k > 0) {
+                hipError_t e = timed(c, DD_KT_BLAS, V * 96.0 * (k + 1), V * 96.0 * k,
+                                     [&] { return dd::launch_multidot(g, c->stream, zs, k, c->gz[k], c->partials); });
+                if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("multidot: ") + hipGetErrorString(e));
+                if ((st = fetch(c, 2 * k, d)) != DD_OK) return st;
+                for (int j = 0; j < k; ++j) {
+                    a[(size_t)j * nkv + k] = cplx(d[2 * j], d[2 * j + 1]);
+                    zs.re[j] = d[2 * j];
+                    zs.im[j] = d[2 * j + 1];
+                }
+            }
+            hipError_t e = timed(c, DD_KT_BLAS, V * 96.0 * (k + 3), V * 96.0 * (k + 1), [&] {
+                return dd::launch_gcr_orth(g, c->stream, zs, k, c->gz[k], r, c->partials);
+            });
+            if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("gcr orth: ") + hipGetErrorString(e));
+            if ((st = fetch(c, 3, d)) != DD_OK) return st;
+            if (!(d[0] > 0.0) || !is_fin(d[0])) {
+                o.detail = d[0] == 0.0 ? 2 : 4;
+                done = true;
+                if (k == 0) return DD_BREAKDOWN;
+                break;
+            }
+            bk[k] = std::sqrt(d[0]);
+            cc[k] = cplx(d[1], d[2]) / bk[k];
+            e = timed(c, DD_KT_BLAS, V * 96.0 * 4, V * 96.0, [&] {
+                return dd::launch_gcr_rupdate(g, c->stream, c->gz[k], r, 1.0 / bk[k], cc[k].real(), cc[k].imag(),
+                                              c->partials);
+            });
+            if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("gcr update: ") + hipGetErrorString(e));
+            if ((st = fetch(c, 1, &rn2)) != DD_OK) return st;
+            n = k + 1;
+            ++o.iters;
+            o.relres = std::sqrt(rn2 / bn2);
+            if (c->verbose && o.iters % 100 == 0) {
+                std::fprintf(stderr, "[ddsolve] GCR iteration %d: relative residual %.3e\n", o.iters, o.relres);
+                std::fflush(stderr);
+            }
+            if (o.relres < tol || o.iters >= maxiter) {
+                done = true;
+                break;
+            }
+        }
+        if (n == 0) break;
+        // back substitution: alpha_j = (c_j - sum_{k>j} a_jk alpha_k) / b_j
+        for (int j = n - 1; j >= 0; --j) {
+            cplx t = cc[j];
+            for (int k = j + 1; k < n; ++k) t -= a[(size_t)j * nkv + k] * alpha[k];
+            alpha[j] = t / bk[j];
+        }
+        dd::VecSet ps{};
+        for (int j = 0; j < n; ++j) {
+            ps.v[j] = c->gp[j];
+            ps.re[j] = alpha[j].real();
+            ps.im[j] = alpha[j].imag();
+        }
+        hipError_t e = timed(c, DD_KT_BLAS, V * (52.0 * n + 192.0), V * 96.0 * n,
+                             [&] { return dd::launch_multi_axpy(g, c->stream, ps, n, 2, y); });
+        if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("gcr solution update: ") + hipGetErrorString(e));
+    }
+    return o.relres < tol ? DD_OK : (o.detail ? DD_BREAKDOWN : DD_NOT_CONVERGED);
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -568,6 +677,11 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
     c->prm = *prm;
     if (c->prm.inner_tol <= 0) c->prm.inner_tol = 1e-6;
     if (c->prm.inner_maxiter <= 0) c->prm.inner_maxiter = 2000;
+    if (c->prm.gcr_nkv <= 0) c->prm.gcr_nkv = dd::GCR_MAX_NKV;
+    if (c->prm.gcr_nkv > dd::GCR_MAX_NKV) {
+        delete c;
+        return DD_ERR_ARG;
+    }
     Geom &g = c->g;
     long long V = 1;
     int bvol = 1, nblk = 1;
@@ -610,9 +724,11 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
     for (int i = 0; ok && i < N64; ++i) ok = alloc(&c->f64[i], spinor_bytes(g, DD_F64));
     for (int i = 0; ok && i < N32; ++i) ok = alloc(&c->f32[i], spinor_bytes(g, DD_F32));
     for (int i = 0; ok && i < N16; ++i) ok = alloc(&c->f16[i], spinor_bytes(g, DD_F16));
+    for (int i = 0; ok && i < c->prm.gcr_nkv; ++i)
+        ok = alloc(&c->gz[i], spinor_bytes(g, DD_F32)) && alloc(&c->gp[i], spinor_bytes(g, DD_F16));
     ok = ok && alloc((void **)&c->partials, dd::MAX_PARTIALS * sizeof(double)) &&
-         alloc((void **)&c->red, 16 * sizeof(double)) && alloc((void **)&c->flag, 4 * sizeof(int)) &&
-         hipHostMalloc((void **)&c->red_host, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+         alloc((void **)&c->red, RED_MAX * sizeof(double)) && alloc((void **)&c->flag, 4 * sizeof(int)) &&
+         hipHostMalloc((void **)&c->red_host, RED_MAX * sizeof(double), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         dd_destroy(c);
@@ -634,6 +750,10 @@ dd_status dd_destroy(dd_ctx *c)
     for (void *p : c->f32)
         if (p) (void)hipFree(p);
     for (void *p : c->f16)
+        if (p) (void)hipFree(p);
+    for (void *p : c->gz)
+        if (p) (void)hipFree(p);
+    for (void *p : c->gp)
         if (p) (void)hipFree(p);
     if (c->red_host) (void)hipHostFree(c->red_host);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
@@ -727,7 +847,7 @@ dd_status bicgstab_solve(dd_ctx *c, void *x_dev, const void *b_dev, double tol, 
                          dd_solve_info *info)
 {
     if (!c || !x_dev || !b_dev) return fail(c, DD_ERR_ARG, "null argument");
-    if (!(tol > 0) || maxiter < 0 || mode < DD_SOLVE_F64_PLAIN || mode > DD_SOLVE_MIXED)
+    if (!(tol > 0) || maxiter < 0 || mode < DD_SOLVE_F64_PLAIN || mode > DD_SOLVE_MIXED_GCR)
         return fail(c, DD_ERR_ARG, "bad tolerance, maxiter or mode");
     if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
     auto t0 = std::chrono::steady_clock::now();
@@ -783,7 +903,8 @@ dd_status bicgstab_solve(dd_ctx *c, void *x_dev, const void *b_dev, double tol, 
             const double need = 0.5 * tol * std::sqrt(bn2) / err;
             const double itol = need > c->prm.inner_tol ? (need < 0.1 ? need : 0.1) : c->prm.inner_tol;
             SolveOut o;
-            dd_status si = solve_sap32(c, 2, src, y, itol, c->prm.inner_maxiter, o);
+            dd_status si = mode == DD_SOLVE_MIXED_GCR ? solve_gcr32(c, src, y, itol, c->prm.inner_maxiter, o)
+                                                      : solve_sap32(c, 2, src, y, itol, c->prm.inner_maxiter, o);
             if (si < 0) return si;
             inf.iters_inner_total += o.iters;
             inf.relres_inner_last = o.relres;

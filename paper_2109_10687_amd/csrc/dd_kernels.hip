@@ -339,9 +339,11 @@ __global__ void __launch_bounds__(256) k_dirac(Geom g, SpinorField<POUT> out, Sp
 
 // ============================================================ SAP half-sweep
 
-// where the SAP kernel reads the block's links from: FP16 (12-real) links are
-// staged in LDS (24 elements x bvol half2); FP32 links are read from global
-// memory through the caches, which keeps the workgroup's LDS at 24 KB
+// where the SAP kernel reads the block's links from: the FP16 copy (rows 0 and
+// 1, 24 half2 per site, 24 KB for a 4^4 block) is staged in LDS as is and the
+// third row is rebuilt at each use (staging full 3x3 matrices measured slower:
+// the extra LDS reads cost more than the rebuild); FP32 links are read from
+// global memory through the caches, which keeps that workgroup's LDS at 24 KB
 template <int P> struct SapLinks;
 template <> struct SapLinks<1> {
     static constexpr int E = 0;  // nothing staged
@@ -730,6 +732,129 @@ __global__ void __launch_bounds__(256) k_cinv_src(Geom g, SpinorField<1> c, Spin
     c.store(g, l, s, o);
 }
 
+
+
+// load a spinor from a raw field pointer at precision P
+template <int P> DD_INL void sf_load(void *p, const Geom &g, int l, int s, Spinor<float> &x);
+template <> DD_INL void sf_load<1>(void *p, const Geom &g, int l, int s, Spinor<float> &x)
+{
+    SpinorField<1>{(float2 *)p}.load(g, l, s, x);
+}
+template <> DD_INL void sf_load<2>(void *p, const Geom &g, int l, int s, Spinor<float> &x)
+{
+    SpinorField<2>{(__half2 *)p, (float *)((char *)p + 12 * g.V * sizeof(__half2))}.load(g, l, s, x);
+}
+
+// ------------------------------------------------------------ flexible GCR kernels
+// The k previous images z_j are FP32 fields passed by value (pointer set); the
+// reductions accumulate in FP64 like every other reduction here.
+
+template <int NV> DD_INL void wg_reduce_store_dyn(double (&v)[NV], int nv, double *partials)
+{
+    __shared__ double red[NV][BLAS_WG / 64];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        if (q >= nv) break;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int q = 0; q < nv; ++q) red[q][wave] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < nv; ++q) {
+            double t = 0;
+            for (int w = 0; w < BLAS_WG / 64; ++w) t += red[q][w];
+            partials[(long long)blockIdx.x * nv + q] = t;
+        }
+}
+
+__global__ void __launch_bounds__(BLAS_WG) k_multidot(Geom g, VecSet zs, int k, const float2 *z, double *partials)
+{
+    double v[2 * GCR_MAX_NKV];
+#pragma unroll
+    for (int q = 0; q < 2 * GCR_MAX_NKV; ++q) v[q] = 0;
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        const float2 zo = z[o];
+#pragma unroll
+        for (int j = 0; j < GCR_MAX_NKV; ++j) {
+            if (j >= k) break;
+            const float2 a = ((const float2 *)zs.v[j])[o];
+            v[2 * j] += (double)a.x * zo.x + (double)a.y * zo.y;
+            v[2 * j + 1] += (double)a.x * zo.y - (double)a.y * zo.x;
+        }
+    }
+    wg_reduce_store_dyn<2 * GCR_MAX_NKV>(v, 2 * k, partials);
+}
+
+__global__ void __launch_bounds__(BLAS_WG)
+    k_gcr_orth(Geom g, VecSet zs, int k, float2 *z, const float2 *r, double *partials)
+{
+    double v[3] = {0, 0, 0};
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        float2 zo = z[o];
+        double zr = zo.x, zi = zo.y;
+        for (int j = 0; j < k; ++j) {
+            const float2 a = ((const float2 *)zs.v[j])[o];
+            zr -= zs.re[j] * a.x - zs.im[j] * a.y;
+            zi -= zs.re[j] * a.y + zs.im[j] * a.x;
+        }
+        zo = make_float2((float)zr, (float)zi);
+        z[o] = zo;
+        const float2 ro = r[o];
+        v[0] += (double)zo.x * zo.x + (double)zo.y * zo.y;
+        v[1] += (double)zo.x * ro.x + (double)zo.y * ro.y;
+        v[2] += (double)zo.x * ro.y - (double)zo.y * ro.x;
+    }
+    wg_reduce_store<3>(v, partials);
+}
+
+__global__ void __launch_bounds__(BLAS_WG)
+    k_gcr_rupdate(Geom g, float2 *z, float2 *r, double inv_bn, double cre, double cim, double *partials)
+{
+    double v[1] = {0};
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        float2 zo = z[o];
+        const double zr = zo.x * inv_bn, zi = zo.y * inv_bn;
+        z[o] = make_float2((float)zr, (float)zi);
+        float2 ro = r[o];
+        ro = make_float2((float)(ro.x - (cre * zr - cim * zi)), (float)(ro.y - (cre * zi + cim * zr)));
+        r[o] = ro;
+        v[0] += (double)ro.x * ro.x + (double)ro.y * ro.y;
+    }
+    wg_reduce_store<1>(v, partials);
+}
+
+// y += sum_j coef_j p_j, one thread per site (FP16 p_j carry a per-site scale)
+template <int PP>
+__global__ void __launch_bounds__(256) k_multi_axpy(Geom g, VecSet ps, int k, float2 *y)
+{
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
+    double acc[12][2];
+    for (int e = 0; e < 12; ++e) {
+        float2 t = y[elem(g, l, s, 12, e)];
+        acc[e][0] = t.x;
+        acc[e][1] = t.y;
+    }
+    for (int j = 0; j < k; ++j) {
+        Spinor<float> p;
+        sf_load<PP>(ps.v[j], g, l, s, p);
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) {
+                const int e = a * 3 + c;
+                acc[e][0] += ps.re[j] * p.v[a][c].re - ps.im[j] * p.v[a][c].im;
+                acc[e][1] += ps.re[j] * p.v[a][c].im + ps.im[j] * p.v[a][c].re;
+            }
+    }
+    for (int e = 0; e < 12; ++e) y[elem(g, l, s, 12, e)] = make_float2((float)acc[e][0], (float)acc[e][1]);
+}
+
 // ============================================================ host launchers
 
 static inline int grid_sites(long long V, int wg) { return (int)((V + wg - 1) / wg); }
@@ -933,6 +1058,42 @@ hipError_t launch_blas(const Geom &g, hipStream_t st, const BlasArgs &a)
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_multidot(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *z, double *partials)
+{
+    if (k < 1 || k > GCR_MAX_NKV) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_multidot, dim3(blas_grid(g)), dim3(BLAS_WG), 0, st, g, zs, k, (const float2 *)z, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_gcr_orth(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *z, void *r, double *partials)
+{
+    if (k < 0 || k > GCR_MAX_NKV) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gcr_orth, dim3(blas_grid(g)), dim3(BLAS_WG), 0, st, g, zs, k, (float2 *)z,
+                       (const float2 *)r, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_gcr_rupdate(const Geom &g, hipStream_t st, void *z, void *r, double inv_bn, double cre, double cim,
+                              double *partials)
+{
+    hipLaunchKernelGGL(k_gcr_rupdate, dim3(blas_grid(g)), dim3(BLAS_WG), 0, st, g, (float2 *)z, (float2 *)r, inv_bn,
+                       cre, cim, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(const Geom &g, hipStream_t st, const VecSet &ps, int k, int pp, void *y)
+{
+    if (k < 1 || k > GCR_MAX_NKV) return hipErrorInvalidValue;
+    const dim3 G(grid_sites(g.V, 256)), B(256);
+    if (pp == 2)
+        hipLaunchKernelGGL(k_multi_axpy<2>, G, B, 0, st, g, ps, k, (float2 *)y);
+    else if (pp == 1)
+        hipLaunchKernelGGL(k_multi_axpy<1>, G, B, 0, st, g, ps, k, (float2 *)y);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -10,7 +10,8 @@ namespace dd {
 
 constexpr int BLAS_WG = 256;        // threads per workgroup of the vector kernels
 constexpr int BLAS_MAX_WG = 4096;   // cap on their grid (grid-stride loops beyond it)
-constexpr int MAX_PARTIALS = BLAS_MAX_WG * 4;
+constexpr int GCR_MAX_NKV = 16;     // longest GCR cycle (vectors kept per restart)
+constexpr int MAX_PARTIALS = BLAS_MAX_WG * 2 * GCR_MAX_NKV;
 constexpr int MAX_BLOCK_VOLUME = 256;  // one SAP block per workgroup, one thread per site
 
 // SAP half-sweep flags
@@ -84,6 +85,22 @@ size_t sap_lds_bytes(const Geom &g, int prec);
 hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
 int blas_grid(const Geom &g);
 hipError_t launch_blas(const Geom &g, hipStream_t st, const BlasArgs &a);
+
+// ---- flexible GCR: k directions p_j (FP16 storage) with images z_j (FP32)
+struct VecSet {
+    void *v[GCR_MAX_NKV];
+    double re[GCR_MAX_NKV], im[GCR_MAX_NKV];
+};
+// <z_j | z> for j < k: 2k partial sums per workgroup
+hipError_t launch_multidot(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *z, double *partials);
+// z -= sum_j coef_j z_j (j < k); partials: |z|^2, <z|r>
+hipError_t launch_gcr_orth(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *z, void *r,
+                           double *partials);
+// z *= 1/bn ; r -= c z ; partial |r|^2
+hipError_t launch_gcr_rupdate(const Geom &g, hipStream_t st, void *z, void *r, double inv_bn, double cre, double cim,
+                              double *partials);
+// y (FP32) += sum_j coef_j p_j, p_j at precision pp (FP16 or FP32)
+hipError_t launch_multi_axpy(const Geom &g, hipStream_t st, const VecSet &ps, int k, int pp, void *y);
 hipError_t launch_finalize(hipStream_t st, const double *partials, int nwg, int nv, double *out);
 
 }  // namespace dd

@@ -54,3 +54,13 @@ def test_create_rejects_bad_geometry_without_gpu():
         assert e.status == -2
     else:
         raise AssertionError("expected DD_ERR_GEOMETRY")
+
+
+def test_create_rejects_bad_gcr_cycle_without_gpu():
+    p = dd.Params(dims=(8, 8, 8, 8), kappa=0.12, csw=1.0, gcr_nkv=17)
+    try:
+        dd.dd_create(p, stream=0)
+    except dd.DDError as e:
+        assert e.status == -1
+    else:
+        raise AssertionError("expected DD_ERR_ARG")

@@ -154,11 +154,12 @@ def test_solve_fp32_sap(name):
     assert res < 1e-4
 
 
+@pytest.mark.parametrize("mode", [dd.DD_SOLVE_MIXED, dd.DD_SOLVE_MIXED_GCR])
 @pytest.mark.parametrize("name", ["4^4", "aniso", "8^4"])
-def test_solve_mixed(name):
+def test_solve_mixed(name, mode):
     c = case(name)
     b = c.spinor(9)
-    x, info = c.solver.solve(b.cuda(), tol=1e-10, maxiter=20, mode=dd.DD_SOLVE_MIXED)
+    x, info = c.solver.solve(b.cuda(), tol=1e-10, maxiter=20, mode=mode)
     assert info["status"] == "DD_OK", info
     xn = x.cpu().numpy()
     res = true_relres(c, xn, b.numpy())
