@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--n-sap", type=int, default=4)
     ap.add_argument("--n-jac", type=int, default=4)
     ap.add_argument("--inner-tol", type=float, default=1e-6)
+    ap.add_argument("--sap-fp16-arith", type=int, default=1, help="packed FP16 arithmetic in the FP16 SAP (1) or FP32 (0)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--seed", type=int, default=2021)
     ap.add_argument("--apply-reps", type=int, default=20)
@@ -171,7 +172,7 @@ def main():
     block = tuple(int(v) for v in args.block.split(","))
     V = math.prod(dims)
     params = dd.Params(dims=dims, kappa=args.kappa, csw=args.csw, block=block, n_sap=args.n_sap, n_jac=args.n_jac,
-                       inner_tol=args.inner_tol)
+                       inner_tol=args.inner_tol, sap_fp16_arith=args.sap_fp16_arith)
     dev = torch.device("cuda:0")
     t0 = time.time()
     log(f"drawing links and source for {dims} on the device")
@@ -238,6 +239,8 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
     roof["avg_launch_ms"] = round(avg_ms, 4)
     roof["algorithmic_bytes_per_launch"] = d["bytes"] / d["launches"]
+    if dominant == "sap" and args.sap_fp16_arith:
+        roof["kernel"] = "k_sap_half_pk"
     roof["traffic"] = measured_traffic(roof["kernel"], None)
     # the Dirac apply inside the solve, against the HBM roof
     dk = max(dirac_names, key=lambda k: rep[k]["ms"])
@@ -266,7 +269,8 @@ def main():
                    "kappa_note": "0.1365 is supercritical for this synthetic ensemble at this volume; solve at 0.133",
                    "dims": list(dims), "block": list(block), "kappa": args.kappa, "csw": args.csw, "eps": args.eps,
                    "n_sap": args.n_sap, "n_jac": args.n_jac, "tol": args.tol, "inner_tol": args.inner_tol,
-                   "precision": "FP16 SAP / FP32 BiCGStab / FP64 defect correction", "parallelism": "single GPU"},
+                   "precision": "FP16 SAP / FP32 BiCGStab / FP64 defect correction",
+                   "sap_fp16_arith": args.sap_fp16_arith, "parallelism": "single GPU"},
         "solve_mixed": {"seconds": round(ms_step / 1e3, 3), "iters_outer": infos[-1]["iters_outer"],
                         "iters_inner": infos[-1]["iters_inner_total"],
                         "relres_true": infos[-1]["relres_true"], "status": infos[-1]["status"]},

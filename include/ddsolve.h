@@ -108,6 +108,10 @@ typedef struct {
     int inner_maxiter;  /* iteration cap of each inner solve (0 = 2000)            */
     int gcr_nkv;        /* GCR cycle length for DD_SOLVE_MIXED_GCR, 1..16 (0 = 16);
                            dd_create allocates gcr_nkv FP32 and gcr_nkv FP16 fields */
+    int sap_fp16_arith; /* 1: the FP16-storage SAP (sap_precondition at DD_F16 and the
+                           mixed modes) also does its block-local Jacobi sweeps in
+                           packed FP16 arithmetic, on a source scaled per block to unit
+                           maximum; 0: FP32 arithmetic on FP16 storage              */
 } dd_params;
 
 typedef struct {

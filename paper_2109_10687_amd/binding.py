@@ -45,7 +45,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("block", ctypes.c_int * 4), ("kappa", ctypes.c_double),
                 ("csw", ctypes.c_double), ("phase_re", ctypes.c_double * 4), ("phase_im", ctypes.c_double * 4),
                 ("n_sap", ctypes.c_int), ("n_jac", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("inner_maxiter", ctypes.c_int), ("gcr_nkv", ctypes.c_int)]
+                ("inner_maxiter", ctypes.c_int), ("gcr_nkv", ctypes.c_int), ("sap_fp16_arith", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -103,6 +103,7 @@ class Params:
     inner_tol: float = 1e-6
     inner_maxiter: int = 2000
     gcr_nkv: int = 16
+    sap_fp16_arith: int = 1
 
     def c(self):
         p = _Params()
@@ -119,6 +120,7 @@ class Params:
         p.inner_tol = float(self.inner_tol)
         p.inner_maxiter = int(self.inner_maxiter)
         p.gcr_nkv = int(self.gcr_nkv)
+        p.sap_fp16_arith = int(self.sap_fp16_arith)
         return p
 
     @property

@@ -279,8 +279,11 @@ dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
         if (!tail) fl += hops_in(g) + CLOVF + 48;
         if (pre) fl += hops_out(g) + CLOVF;
         const double sites = 0.5 * (double)g.V;
-        hipError_t e = timed(c, DD_KT_SAP, sites * per, sites * fl,
-                             [&] { return dd::launch_sap_half(c->g, c->stream, a, colour, flags); });
+        const bool pk = prec == 2 && c->prm.sap_fp16_arith;
+        hipError_t e = timed(c, DD_KT_SAP, sites * per, sites * fl, [&] {
+            return pk ? dd::launch_sap_half_pk(c->g, c->stream, a, colour, flags)
+                      : dd::launch_sap_half(c->g, c->stream, a, colour, flags);
+        });
         if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("sap launch: ") + hipGetErrorString(e));
         return DD_OK;
     };

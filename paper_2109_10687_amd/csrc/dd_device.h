@@ -184,6 +184,40 @@ DD_INL int xcd_remap(int w, int n)
     return (w & 7) * (n >> 3) + (w >> 3);
 }
 
+// ------------------------------------------------------------------ streaming access
+// Non-temporal loads and stores for data a kernel touches once (the clover
+// blocks, the Dirac apply's output): they do not displace the spinors and links
+// that neighbouring sites read again from L2.
+typedef double d2nt_t __attribute__((ext_vector_type(2)));
+typedef float f2nt_t __attribute__((ext_vector_type(2)));
+DD_INL double2 ld_stream(const double2 *p)
+{
+    d2nt_t v = __builtin_nontemporal_load((const d2nt_t *)p);
+    return make_double2(v.x, v.y);
+}
+DD_INL float2 ld_stream(const float2 *p)
+{
+    f2nt_t v = __builtin_nontemporal_load((const f2nt_t *)p);
+    return make_float2(v.x, v.y);
+}
+DD_INL __half2 ld_stream(const __half2 *p)
+{
+    unsigned int v = __builtin_nontemporal_load((const unsigned int *)p);
+    return *reinterpret_cast<__half2 *>(&v);
+}
+DD_INL void st_stream(double2 *p, double2 x)
+{
+    d2nt_t v = {x.x, x.y};
+    __builtin_nontemporal_store(v, (d2nt_t *)p);
+}
+DD_INL void st_stream(float2 *p, float2 x)
+{
+    f2nt_t v = {x.x, x.y};
+    __builtin_nontemporal_store(v, (f2nt_t *)p);
+}
+DD_INL void st_stream(__half2 *p, __half2 x) { __builtin_nontemporal_store(*reinterpret_cast<unsigned int *>(&x), (unsigned int *)p); }
+DD_INL void st_stream(float *p, float x) { __builtin_nontemporal_store(x, p); }
+
 // ------------------------------------------------------------------ storage
 // precision tags: 0 = FP64, 1 = FP32, 2 = FP16 (per-site scaled spinors,
 // 12-real links, FP16 clover)
@@ -206,12 +240,18 @@ template <> struct SpinorField<0> {
                 x.v[a][c] = {R(t.x), R(t.y)};
             }
     }
-    template <typename R> DD_INL void store(const Geom &g, int l, int s, const Spinor<R> &x) const
+    template <typename R> DD_INL void store(const Geom &g, int l, int s, const Spinor<R> &x, bool stream = false) const
     {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) p[elem(g, l, s, 12, a * 3 + c)] = make_double2(x.v[a][c].re, x.v[a][c].im);
+            for (int c = 0; c < 3; ++c) {
+                double2 v = make_double2(x.v[a][c].re, x.v[a][c].im);
+                if (stream)
+                    st_stream(&p[elem(g, l, s, 12, a * 3 + c)], v);
+                else
+                    p[elem(g, l, s, 12, a * 3 + c)] = v;
+            }
     }
 };
 
@@ -227,13 +267,18 @@ template <> struct SpinorField<1> {
                 x.v[a][c] = {R(t.x), R(t.y)};
             }
     }
-    template <typename R> DD_INL void store(const Geom &g, int l, int s, const Spinor<R> &x) const
+    template <typename R> DD_INL void store(const Geom &g, int l, int s, const Spinor<R> &x, bool stream = false) const
     {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                p[elem(g, l, s, 12, a * 3 + c)] = make_float2((float)x.v[a][c].re, (float)x.v[a][c].im);
+            for (int c = 0; c < 3; ++c) {
+                float2 v = make_float2((float)x.v[a][c].re, (float)x.v[a][c].im);
+                if (stream)
+                    st_stream(&p[elem(g, l, s, 12, a * 3 + c)], v);
+                else
+                    p[elem(g, l, s, 12, a * 3 + c)] = v;
+            }
     }
 };
 
@@ -251,7 +296,7 @@ template <> struct SpinorField<2> {
                 x.v[a][c] = {R(t.x * sc), R(t.y * sc)};
             }
     }
-    template <typename R> DD_INL void store(const Geom &g, int l, int s, const Spinor<R> &x) const
+    template <typename R> DD_INL void store(const Geom &g, int l, int s, const Spinor<R> &x, bool stream = false) const
     {
         float m = 0.f;
 #pragma unroll
@@ -262,13 +307,20 @@ template <> struct SpinorField<2> {
                 m = fmaxf(m, fabsf((float)x.v[a][c].im));
             }
         float inv = m > 0.f ? 1.0f / m : 0.f;
-        scale[((long long)l << g.lbvol) + s] = m;
+        if (stream)
+            st_stream(&scale[((long long)l << g.lbvol) + s], m);
+        else
+            scale[((long long)l << g.lbvol) + s] = m;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                p[elem(g, l, s, 12, a * 3 + c)] =
-                    __floats2half2_rn((float)x.v[a][c].re * inv, (float)x.v[a][c].im * inv);
+            for (int c = 0; c < 3; ++c) {
+                __half2 v = __floats2half2_rn((float)x.v[a][c].re * inv, (float)x.v[a][c].im * inv);
+                if (stream)
+                    st_stream(&p[elem(g, l, s, 12, a * 3 + c)], v);
+                else
+                    p[elem(g, l, s, 12, a * 3 + c)] = v;
+            }
     }
 };
 
@@ -333,13 +385,13 @@ template <typename R, typename V2> DD_INL void clov_from(const V2 *p, const Geom
     for (int blk = 0; blk < 2; ++blk) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            V2 t = p[elem(g, l, s, 36, blk * 18 + j)];
+            V2 t = ld_stream(&p[elem(g, l, s, 36, blk * 18 + j)]);
             C.d[blk][2 * j] = R(t.x);
             C.d[blk][2 * j + 1] = R(t.y);
         }
 #pragma unroll
         for (int j = 0; j < 15; ++j) {
-            V2 t = p[elem(g, l, s, 36, blk * 18 + 3 + j)];
+            V2 t = ld_stream(&p[elem(g, l, s, 36, blk * 18 + 3 + j)]);
             C.h[blk][j] = {R(t.x), R(t.y)};
         }
     }
@@ -361,13 +413,13 @@ template <> struct CloverField<2> {
         for (int blk = 0; blk < 2; ++blk) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                float2 t = __half22float2(p[elem(g, l, s, 36, blk * 18 + j)]);
+                float2 t = __half22float2(ld_stream(&p[elem(g, l, s, 36, blk * 18 + j)]));
                 C.d[blk][2 * j] = R(t.x);
                 C.d[blk][2 * j + 1] = R(t.y);
             }
 #pragma unroll
             for (int j = 0; j < 15; ++j) {
-                float2 t = __half22float2(p[elem(g, l, s, 36, blk * 18 + 3 + j)]);
+                float2 t = __half22float2(ld_stream(&p[elem(g, l, s, 36, blk * 18 + 3 + j)]));
                 C.h[blk][j] = {R(t.x), R(t.y)};
             }
         }

@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(256) k_dirac(Geom g, SpinorField<POUT> out, Sp
             for (int c = 0; c < 3; ++c) o.v[a][c] = t.v[a][c] - k * acc.v[a][c];
         if (OP == 2) gamma5(o);
     }
-    out.store(g, st.l, st.s, o);
+    out.store(g, st.l, st.s, o, true);
 }
 
 // ============================================================ SAP half-sweep

@@ -83,6 +83,9 @@ hipError_t launch_clover(const Geom &g, hipStream_t st, const void *u64, const S
 hipError_t launch_dirac(const Geom &g, hipStream_t st, const DiracArgs &a);
 size_t sap_lds_bytes(const Geom &g, int prec);
 hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
+// the same half-sweep with FP16 storage and packed FP16 block-local arithmetic
+size_t sap_pk_lds_bytes(const Geom &g);
+hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
 int blas_grid(const Geom &g);
 hipError_t launch_blas(const Geom &g, hipStream_t st, const BlasArgs &a);
 

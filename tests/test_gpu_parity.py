@@ -38,12 +38,13 @@ def rel_max(a, b):
 
 
 class Case:
-    def __init__(self, name, n_sap=2, n_jac=4, seed=101):
+    def __init__(self, name, n_sap=2, n_jac=4, seed=101, fp16_arith=0):
         dims, block, kappa, csw, eps, phases = CASES[name]
         self.name = name
         self.U = synth.su3_links(dims, eps, seed)
         self.op = O.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases, n_sap=n_sap, n_jac=n_jac)
-        self.gp = dd.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases, n_sap=n_sap, n_jac=n_jac)
+        self.gp = dd.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases, n_sap=n_sap, n_jac=n_jac,
+                            sap_fp16_arith=fp16_arith)
         self.orc = O.Oracle(self.op, self.U.numpy())
         self.solver = dd.Solver(self.gp, self.U.cuda())
 
@@ -114,15 +115,18 @@ def test_sap_fp32(name, n_sap):
     assert rel_l2(got, want) < 1e-5
 
 
-@pytest.mark.parametrize("name", ["4^4", "8^4"])
-def test_sap_fp16_storage(name):
-    c = case(name)
+@pytest.mark.parametrize("fp16_arith", [0, 1])
+@pytest.mark.parametrize("name", ["4^4", "aniso", "8^4"])
+def test_sap_fp16_storage(name, fp16_arith):
+    """FP16 storage with FP32 arithmetic, or with packed FP16 block-local
+    arithmetic (one rounding of ~5e-4 per operation on a block-normalised source)."""
+    c = case(name, fp16_arith=fp16_arith)
     b = c.spinor(6)
     got = c.solver.precondition(b.cuda(), prec=dd.DD_F16).cpu().numpy()
     want = c.orc.sap(b.numpy())
     err = rel_l2(got, want)
-    print(f"FP16-storage SAP relative L2 error {err:.3e}")
-    assert err < 2e-2
+    print(f"FP16-storage SAP (fp16 arithmetic {fp16_arith}) relative L2 error {err:.3e}")
+    assert err < (2e-2 if fp16_arith else 1e-2)
 
 
 def true_relres(c, x, b):
@@ -154,10 +158,11 @@ def test_solve_fp32_sap(name):
     assert res < 1e-4
 
 
+@pytest.mark.parametrize("fp16_arith", [0, 1])
 @pytest.mark.parametrize("mode", [dd.DD_SOLVE_MIXED, dd.DD_SOLVE_MIXED_GCR])
 @pytest.mark.parametrize("name", ["4^4", "aniso", "8^4"])
-def test_solve_mixed(name, mode):
-    c = case(name)
+def test_solve_mixed(name, mode, fp16_arith):
+    c = case(name, fp16_arith=fp16_arith)
     b = c.spinor(9)
     x, info = c.solver.solve(b.cuda(), tol=1e-10, maxiter=20, mode=mode)
     assert info["status"] == "DD_OK", info
