@@ -74,7 +74,7 @@ def parse():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dd_kernels.hip", "dd_device.h"):
+    for f in ("dd_kernels.hip", "dd_sap_fp16.hip", "dd_device.h"):
         with open(os.path.join(ROOT, "paper_2109_10687_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
