@@ -62,6 +62,8 @@ def lib():
             "orc_amsap": (None, [P, vp, vp, vp, vp]),
             "orc_bicgstab": (i, [P, vp, vp, vp, i, vp, vp, d, i, pi, pd]),
             "orc_dci": (i, [P, vp, vp, vp, vp, vp, d, d, i, i, i, i, pi, pi, pd]),
+            "orc_force": (None, [P, vp, vp, vp, vp]),
+            "orc_dcsw": (d, [P, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -268,6 +270,71 @@ def dci(p, U, C, Cinv, b, tol=1e-10, inner_tol=1e-6, inner_maxiter=1000, inner_o
                        inner_maxiter, inner_op, int(round_sp), max_outer, ctypes.byref(no), ctypes.byref(ni),
                        ctypes.byref(rr))
     return SolveResult(x, st, ni.value, rr.value, outer=no.value)
+
+
+def gamma5_apply(x):
+    """gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4 on a canonical spinor (spin is the last index)."""
+    g5 = gamma(4)
+    return np.ascontiguousarray(np.einsum("ab,...b->...a", g5, x))
+
+
+def force(p, U, psi, chi):
+    """Link derivative of a loss whose variation is -2 Re <chi| dD psi>: the matrices W_mu(n)
+    with dL = Re sum_{mu,n} tr(dU_mu(n) W_mu(n)); hop term and four-leaf clover term
+    (appendix operator; derivation in oracle.c).  Shape of U."""
+    U, psi, chi = _c128(U), _c128(psi), _c128(chi)
+    W = np.zeros_like(U)
+    cp = p.c()
+    lib().orc_force(ctypes.byref(cp), _ptr(U), _ptr(psi), _ptr(chi), _ptr(W))
+    return W
+
+
+def dcsw(p, C, psi, chi):
+    """dL/dc_SW = -2 Re <chi| (C / c_SW) psi> for the clover field C of the appendix."""
+    C, psi, chi = _c128(C), _c128(psi), _c128(chi)
+    cp = p.c()
+    return lib().orc_dcsw(ctypes.byref(cp), _ptr(C), _ptr(psi), _ptr(chi))
+
+
+def grad_from_force(W):
+    """The gradient dL/dRe U + i dL/dIm U of each link entry, from W: the conjugate transpose."""
+    return np.ascontiguousarray(np.conj(np.swapaxes(W, -1, -2)))
+
+
+def su3_force(U, W):
+    """Traceless Hermitian F_mu(n) with dL = tr(omega F) for U -> exp(i omega) U, omega Hermitian:
+    F = (i/2)(X - X^dagger) with X = U W, trace removed."""
+    X = np.matmul(U, W)
+    F = 0.5j * (X - np.conj(np.swapaxes(X, -1, -2)))
+    tr = np.trace(F, axis1=-2, axis2=-1) / 3.0
+    return F - tr[..., None, None] * np.eye(3)
+
+
+@dataclass
+class LossGrad:
+    loss: float
+    psi: np.ndarray
+    chi: np.ndarray
+    W: np.ndarray
+    dcsw: float
+
+
+def loss_and_force(p, U, phi, tol=1e-13, maxiter=20000):
+    """L = |D^{-1} phi|^2 and its derivatives: psi = D^{-1} phi, chi = D^{-dagger} psi =
+    gamma_5 D^{-1} gamma_5 psi (D^dagger = gamma_5 D gamma_5), then the force bilinear and dL/dc_SW.
+    Both solves are the plain FP64 BiCGStab."""
+    U = _c128(U)
+    C = clover_field(p, U)
+    r1 = bicgstab(p, U, C, None, phi, op=OP_D, tol=tol, maxiter=maxiter)
+    if r1.status != 0:
+        raise RuntimeError(f"oracle solve failed ({r1.status})")
+    psi = r1.x
+    r2 = bicgstab(p, U, C, None, gamma5_apply(psi), op=OP_D, tol=tol, maxiter=maxiter)
+    if r2.status != 0:
+        raise RuntimeError(f"oracle adjoint solve failed ({r2.status})")
+    chi = gamma5_apply(r2.x)
+    L = float(np.vdot(psi, psi).real)
+    return LossGrad(L, psi, chi, force(p, U, psi, chi), dcsw(p, C, psi, chi))
 
 
 class Oracle:

@@ -733,3 +733,131 @@ done:
     free(Dx);
     return status;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Derivative of L = |D^{-1} phi|^2 with respect to the links (fermion force).
+ * With psi = D^{-1} phi and chi = D^{-dagger} psi, dL = -2 Re <chi| dD psi>.
+ * Written as dL = Re sum_links tr(dU_mu(n) W_mu(n)); this function returns W.
+ *   hop part:    W += 2 kappa phase * ( [(1 - gamma_mu) psi(n+mu)] chi(n)^dagger
+ *                                     + ( [(1 + gamma_mu) psi(n)] chi(n+mu)^dagger )^dagger )
+ *   clover part: C = i kappa c_SW sum_{mu<nu} sigma_{mu nu} (x) F_{mu nu} with
+ *                F = (Q - Q^dagger)/8 gives dL = Re sum tr(dQ_{mu nu}(n) Y_{mu nu}(n)),
+ *                Y = (-i kappa c_SW / 4) (Lambda + Lambda^dagger),
+ *                Lambda_{ba} = sum_{alpha beta} sigma[alpha][beta] psi_{b beta} conj(chi_{a alpha});
+ *                a leaf written A U B (U at one position) adds B Y A to W of that
+ *                link, a leaf written A U^dagger B adds (B Y A)^dagger.
+ * The clover part is accumulated by visiting every base site, plane, leaf and
+ * position in turn (sequential: positions of different sites hit the same link). */
+
+static void mat_mul_acc(const cplx *A, const cplx *B, cplx *C) /* C = A B */
+{
+    cplx t[9];
+    mat_mul(A, B, t);
+    memcpy(C, t, sizeof t);
+}
+
+void orc_force(const orc_params *p, const cplx *U, const cplx *psi, const cplx *chi, cplx *W)
+{
+    long V = volume(p);
+    memset(W, 0, (size_t)4 * V * 9 * sizeof(cplx));
+    /* hop part */
+    for (long n = 0; n < V; ++n)
+        for (int mu = 0; mu < 4; ++mu) {
+            long m = shift(p, n, mu, +1);
+            cplx ph = fwd_phase(p, n, mu);
+            cplx Pm[12], Pp[12]; /* (1 - gamma) psi(n+mu), (1 + gamma) psi(n) as [colour][spin] */
+            for (int a = 0; a < 3; ++a)
+                for (int al = 0; al < 4; ++al) {
+                    cplx s1 = 0, s2 = 0;
+                    for (int be = 0; be < 4; ++be) {
+                        cplx g = gam(mu, al, be);
+                        cplx d = (al == be) ? 1.0 : 0.0;
+                        s1 += (d - g) * psi[m * 12 + a * 4 + be];
+                        s2 += (d + g) * psi[n * 12 + a * 4 + be];
+                    }
+                    Pm[a * 4 + al] = s1;
+                    Pp[a * 4 + al] = s2;
+                }
+            cplx *w = W + ((long)mu * V + n) * 9;
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    cplx F = 0, G = 0; /* F_ba, G_ab */
+                    for (int al = 0; al < 4; ++al) {
+                        F += Pm[b * 4 + al] * conj(chi[n * 12 + a * 4 + al]);
+                        G += Pp[a * 4 + al] * conj(chi[m * 12 + b * 4 + al]);
+                    }
+                    /* W_ba += 2 kappa ph (F_ba + conj(G_ab)) */
+                    w[b * 3 + a] += 2.0 * p->kappa * ph * (F + conj(G));
+                }
+        }
+    /* clover part */
+    if (p->csw == 0.0) return;
+    for (long n = 0; n < V; ++n)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                cplx sig[4][4];
+                for (int al = 0; al < 4; ++al)
+                    for (int be = 0; be < 4; ++be) {
+                        cplx c = 0;
+                        for (int k = 0; k < 4; ++k) c += gam(mu, al, k) * gam(nu, k, be) - gam(nu, al, k) * gam(mu, k, be);
+                        sig[al][be] = 0.5 * I * c;
+                    }
+                cplx Lam[9], Y[9];
+                for (int b = 0; b < 3; ++b)
+                    for (int a = 0; a < 3; ++a) {
+                        cplx s = 0;
+                        for (int al = 0; al < 4; ++al)
+                            for (int be = 0; be < 4; ++be) s += sig[al][be] * psi[n * 12 + b * 4 + be] * conj(chi[n * 12 + a * 4 + al]);
+                        Lam[b * 3 + a] = s;
+                    }
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) Y[i * 3 + j] = (-0.25 * I * p->kappa * p->csw) * (Lam[i * 3 + j] + conj(Lam[j * 3 + i]));
+                /* the four leaves of Q_{mu nu}(n), as in clover_Q: (site, direction, daggered) */
+                long n_pm = shift(p, n, mu, +1), n_pn = shift(p, n, nu, +1);
+                long n_mm = shift(p, n, mu, -1), n_mn = shift(p, n, nu, -1);
+                long n_mm_pn = shift(p, n_mm, nu, +1), n_mm_mn = shift(p, n_mm, nu, -1);
+                long n_pm_mn = shift(p, n_pm, nu, -1);
+                const long ls[4][4] = {{n, n_pm, n_pn, n}, {n, n_mm_pn, n_mm, n_mm}, {n_mm, n_mm_mn, n_mm_mn, n_mn},
+                                       {n_mn, n_mn, n_pm_mn, n}};
+                const int ld[4][4] = {{mu, nu, mu, nu}, {nu, mu, nu, mu}, {mu, nu, mu, nu}, {nu, mu, nu, mu}};
+                const int lg[4][4] = {{0, 0, 1, 1}, {0, 1, 1, 0}, {1, 1, 0, 0}, {1, 0, 0, 1}};
+                for (int lf = 0; lf < 4; ++lf) {
+                    cplx M[4][9];
+                    for (int k = 0; k < 4; ++k) {
+                        const cplx *Uk = link(U, V, ld[lf][k], ls[lf][k]);
+                        if (lg[lf][k])
+                            mat_dag(Uk, M[k]);
+                        else
+                            memcpy(M[k], Uk, sizeof M[k]);
+                    }
+                    for (int pos = 0; pos < 4; ++pos) {
+                        cplx A[9], B[9], T[9], R[9];
+                        for (int i = 0; i < 9; ++i) A[i] = B[i] = (i % 4 == 0) ? 1.0 : 0.0;
+                        for (int k = 0; k < pos; ++k) mat_mul_acc(A, M[k], A);
+                        for (int k = pos + 1; k < 4; ++k) mat_mul_acc(B, M[k], B);
+                        mat_mul(B, Y, T);
+                        mat_mul(T, A, R); /* B Y A */
+                        cplx *w = W + ((long)ld[lf][pos] * V + ls[lf][pos]) * 9;
+                        if (lg[lf][pos]) {
+                            for (int i = 0; i < 3; ++i)
+                                for (int j = 0; j < 3; ++j) w[i * 3 + j] += conj(R[j * 3 + i]);
+                        } else {
+                            for (int i = 0; i < 9; ++i) w[i] += R[i];
+                        }
+                    }
+                }
+            }
+}
+
+/* dL/dc_SW = -2 Re <chi| (C / c_SW) psi>, C the clover field (appendix) */
+double orc_dcsw(const orc_params *p, const cplx *C, const cplx *psi, const cplx *chi)
+{
+    long V = volume(p);
+    double s = 0;
+    for (long n = 0; n < V; ++n) {
+        cplx cx[12];
+        mat12_vec(C + n * 144, psi + n * 12, cx);
+        for (int i = 0; i < 12; ++i) s += creal(conj(chi[n * 12 + i]) * cx[i]);
+    }
+    return p->csw != 0.0 ? -2.0 * s / p->csw : 0.0;
+}
