@@ -289,11 +289,12 @@ def force(p, U, psi, chi):
     return W
 
 
-def dcsw(p, C, psi, chi):
-    """dL/dc_SW = -2 Re <chi| (C / c_SW) psi> for the clover field C of the appendix."""
-    C, psi, chi = _c128(C), _c128(psi), _c128(chi)
+def dcsw(p, U, psi, chi):
+    """dL/dc_SW = -2 Re <chi| (C / c_SW) psi> for the clover field C of the appendix (C / c_SW
+    is the clover built with c_SW = 1, so this holds at c_SW = 0 as well)."""
+    U, psi, chi = _c128(U), _c128(psi), _c128(chi)
     cp = p.c()
-    return lib().orc_dcsw(ctypes.byref(cp), _ptr(C), _ptr(psi), _ptr(chi))
+    return lib().orc_dcsw(ctypes.byref(cp), _ptr(U), _ptr(psi), _ptr(chi))
 
 
 def grad_from_force(W):
@@ -334,7 +335,7 @@ def loss_and_force(p, U, phi, tol=1e-13, maxiter=20000):
         raise RuntimeError(f"oracle adjoint solve failed ({r2.status})")
     chi = gamma5_apply(r2.x)
     L = float(np.vdot(psi, psi).real)
-    return LossGrad(L, psi, chi, force(p, U, psi, chi), dcsw(p, C, psi, chi))
+    return LossGrad(L, psi, chi, force(p, U, psi, chi), dcsw(p, U, psi, chi))
 
 
 class Oracle:

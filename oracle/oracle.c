@@ -849,15 +849,20 @@ void orc_force(const orc_params *p, const cplx *U, const cplx *psi, const cplx *
             }
 }
 
-/* dL/dc_SW = -2 Re <chi| (C / c_SW) psi>, C the clover field (appendix) */
-double orc_dcsw(const orc_params *p, const cplx *C, const cplx *psi, const cplx *chi)
+/* dL/dc_SW = -2 Re <chi| (C / c_SW) psi>, C the clover field (appendix); C / c_SW is
+ * the clover block built with c_SW = 1, so the derivative is defined at c_SW = 0 too */
+double orc_dcsw(const orc_params *p, const cplx *U, const cplx *psi, const cplx *chi)
 {
     long V = volume(p);
+    orc_params p1 = *p;
+    p1.csw = 1.0;
     double s = 0;
+    cplx C1[144];
     for (long n = 0; n < V; ++n) {
         cplx cx[12];
-        mat12_vec(C + n * 144, psi + n * 12, cx);
+        clover_site(&p1, U, n, C1);
+        mat12_vec(C1, psi + n * 12, cx);
         for (int i = 0; i < 12; ++i) s += creal(conj(chi[n * 12 + i]) * cx[i]);
     }
-    return p->csw != 0.0 ? -2.0 * s / p->csw : 0.0;
+    return -2.0 * s;
 }

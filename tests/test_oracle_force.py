@@ -140,10 +140,16 @@ def test_loss_gradient_single_links_su3(setup):
         assert abs(got - want) <= 1e-6 * abs(want) + 1e-10 * np.abs(F).max(), (mu, x, y, z, t, got, want)
 
 
-def test_dcsw_finite_difference(setup):
-    p, U, phi, g = setup
+@pytest.mark.parametrize("csw", [0.0, 1.3])
+def test_dcsw_finite_difference(csw):
+    """dL/dc_SW against central differences in c_SW (also at c_SW = 0, where the clover vanishes
+    but its derivative does not)."""
+    p = params(DIMS, csw=csw)
+    U = synth.su3_links(DIMS, 0.5, 21).numpy()
+    phi = synth.gaussian_spinor(DIMS, 22).numpy()
+    g = O.loss_and_force(p, U, phi)
     h = 1e-6
-    pp, pm = params(DIMS, csw=p.csw + h), params(DIMS, csw=p.csw - h)
+    pp, pm = params(DIMS, csw=csw + h), params(DIMS, csw=csw - h)
     # L(csw + h) - L(csw - h) with the differenced solve
     Cp, Cm = O.clover_field(pp, U), O.clover_field(pm, U)
     rm = O.bicgstab(pm, U, Cm, None, phi, op=O.OP_D, tol=1e-14, maxiter=20000)
