@@ -176,6 +176,45 @@ dd_status bicgstab_solve(dd_ctx *ctx, void *x_dev, const void *b_dev, double tol
 /* Text of the last error on this context (never NULL). */
 const char *dd_last_error(const dd_ctx *ctx);
 
+/* ---- differentiation: L = |D^{-1} phi|^2 --------------------------------- */
+
+/* Solve D^dagger x = b, through D^dagger = gamma_5 D gamma_5 (gamma_5 =
+ * gamma_1 gamma_2 gamma_3 gamma_4 in the appendix's basis): y = gamma_5 x solves
+ * D y = gamma_5 b with the solver of bicgstab_solve, and gamma_5 is applied
+ * while the fields are packed and unpacked (no extra memory).  Arguments,
+ * modes, initial guess, tolerance (now on |b - D^dagger x| / |b|), return
+ * values and info are those of bicgstab_solve.  Synchronises the stream. */
+dd_status bicgstab_solve_dagger(dd_ctx *ctx, void *x_dev, const void *b_dev, double tol, int maxiter,
+                                dd_solve_mode mode, dd_solve_info *info);
+
+/* *out = |x|^2 = sum_n sum_{colour, spin} |x|^2 of a canonical spinor field,
+ * accumulated in FP64 in a fixed order (bitwise reproducible).  Synchronises. */
+dd_status dd_spinor_norm2(dd_ctx *ctx, const void *x_dev, double *out);
+
+/* Replace c_SW in the context's parameters.  The clover blocks depend on it,
+ * so the context needs dd_load_gauge before its next operator call
+ * (DD_ERR_STATE until then). */
+dd_status dd_set_csw(dd_ctx *ctx, double csw);
+
+/* Derivatives of the loss L = |psi|^2, psi = D^{-1} phi, given psi and
+ * chi = D^{-dagger} psi (canonical spinors, device, caller-owned): the
+ * variation of L is -2 Re <chi| dD psi>, with D = 1 + C - kappa H of the
+ * appendix and the four-leaf clover built from the loaded gauge field.
+ *   out_dev: canonical [4][Lt][Lz][Ly][Lx][3][3] complex double (caller-owned,
+ *     must not overlap psi or chi).  su3 = 0: per link the gradient
+ *     G = dL/dRe U + i dL/dIm U entry by entry (PyTorch's convention for a
+ *     real function of complex inputs).  su3 = 1: per link the traceless
+ *     Hermitian F with dL = tr(omega F) for U -> exp(i omega) U, omega
+ *     Hermitian (the force projected to su(3)).
+ *   dcsw: host pointer receiving dL/dc_SW = -2 Re <chi| (C / c_SW) psi>, or
+ *     NULL to skip it.
+ * The hop term carries the boundary phases; the clover term differentiates
+ * every leaf through the link (24 per link).  FP64 throughout.  The first
+ * call allocates a work field of 864 bytes per site, kept until dd_destroy
+ * (DD_ERR_NOMEM if that fails).  Uses the context's internal FP64 work
+ * vectors.  Synchronises the stream. */
+dd_status dd_force(dd_ctx *ctx, void *out_dev, double *dcsw, const void *psi_dev, const void *chi_dev, int su3);
+
 /* ---- internal-layout entry points (benchmarks, no pack/unpack) ----------- */
 
 /* Bytes of one internal spinor field at precision prec (FP16 includes the
@@ -198,7 +237,8 @@ typedef enum {
     DD_KT_DIRAC_F16 = 3,    /* A, FP16 spinors, 12-real FP16 links, FP16 C_inv  */
     DD_KT_SAP = 4,          /* SAP half-sweep kernels (all precisions)           */
     DD_KT_BLAS = 5,         /* vector updates and reductions                     */
-    DD_KT_COUNT = 6
+    DD_KT_FORCE = 6,        /* fermion force (dd_force), FP64                    */
+    DD_KT_COUNT = 7
 } dd_kernel_class;
 
 /* When enabled, every launch of the timed classes is bracketed by HIP events

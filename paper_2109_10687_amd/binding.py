@@ -22,9 +22,9 @@ LIB_PATH = os.path.join(HERE, "libddsolve.so")
 DD_F64, DD_F32, DD_F16 = 0, 1, 2
 DD_OP_D, DD_OP_A, DD_OP_DDAG = 0, 1, 2
 DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED, DD_SOLVE_MIXED_GCR = 0, 1, 2, 3
-DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16IN, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS = range(6)
+DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16IN, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS, DD_KT_FORCE = range(7)
 KERNEL_CLASSES = {"dirac_f64": DD_KT_DIRAC_F64, "dirac_f32": DD_KT_DIRAC_F32, "dirac_f16in": DD_KT_DIRAC_F16IN,
-                  "dirac_f16": DD_KT_DIRAC_F16, "sap": DD_KT_SAP, "blas": DD_KT_BLAS}
+                  "dirac_f16": DD_KT_DIRAC_F16, "sap": DD_KT_SAP, "blas": DD_KT_BLAS, "force": DD_KT_FORCE}
 
 STATUS = {0: "DD_OK", 1: "DD_NOT_CONVERGED", 2: "DD_BREAKDOWN", -1: "DD_ERR_ARG", -2: "DD_ERR_GEOMETRY",
           -3: "DD_ERR_HIP", -4: "DD_ERR_NOMEM", -5: "DD_ERR_NONFINITE", -6: "DD_ERR_CLOVER_NOT_PD",
@@ -32,7 +32,8 @@ STATUS = {0: "DD_OK", 1: "DD_NOT_CONVERGED", 2: "DD_BREAKDOWN", -1: "DD_ERR_ARG"
 
 EXPORTS = ["dd_create", "dd_destroy", "dd_load_gauge", "dirac_apply", "sap_precondition", "bicgstab_solve",
            "dd_last_error", "dd_field_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dirac_apply_packed",
-           "dd_timing_enable", "dd_timing_query"]
+           "dd_timing_enable", "dd_timing_query", "bicgstab_solve_dagger", "dd_spinor_norm2", "dd_set_csw",
+           "dd_force"]
 
 
 class DDError(RuntimeError):
@@ -81,6 +82,10 @@ def lib():
             "dd_timing_enable": (i, [vp, i]),
             "dd_timing_query": (i, [vp, i, ctypes.POINTER(ll), ctypes.POINTER(d), ctypes.POINTER(d),
                                     ctypes.POINTER(d)]),
+            "bicgstab_solve_dagger": (i, [vp, vp, vp, d, i, i, ctypes.POINTER(_Info)]),
+            "dd_spinor_norm2": (i, [vp, vp, ctypes.POINTER(d)]),
+            "dd_set_csw": (i, [vp, d]),
+            "dd_force": (i, [vp, vp, ctypes.POINTER(d), vp, vp, i]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -196,6 +201,33 @@ def bicgstab_solve(ctx, x, b, tol, maxiter, mode, shape):
     return st, {k: getattr(info, k) for k, _ in _Info._fields_}
 
 
+def bicgstab_solve_dagger(ctx, x, b, tol, maxiter, mode, shape):
+    sp = shape + (3, 4)
+    info = _Info()
+    st = _check(ctx, lib().bicgstab_solve_dagger(ctx, _c128(x, sp, "x"), _c128(b, sp, "b"), float(tol),
+                                                 int(maxiter), int(mode), ctypes.byref(info)))
+    return st, {k: getattr(info, k) for k, _ in _Info._fields_}
+
+
+def dd_spinor_norm2(ctx, x, shape):
+    out = ctypes.c_double(0)
+    _check(ctx, lib().dd_spinor_norm2(ctx, _c128(x, shape + (3, 4), "x"), ctypes.byref(out)))
+    return out.value
+
+
+def dd_set_csw(ctx, csw):
+    return _check(ctx, lib().dd_set_csw(ctx, float(csw)))
+
+
+def dd_force(ctx, out, psi, chi, su3, shape, want_dcsw=True):
+    """Fills out (gradient W^dagger per link, or the su(3) force); returns dL/dc_SW (None if not asked)."""
+    sp = shape + (3, 4)
+    d = ctypes.c_double(0)
+    _check(ctx, lib().dd_force(ctx, _c128(out, (4,) + shape + (3, 3), "out"), ctypes.byref(d) if want_dcsw else None,
+                               _c128(psi, sp, "psi"), _c128(chi, sp, "chi"), int(su3)))
+    return d.value if want_dcsw else None
+
+
 def dd_field_bytes(ctx, prec):
     return lib().dd_field_bytes(ctx, prec)
 
@@ -233,6 +265,7 @@ class Solver:
     def __init__(self, params, U=None, stream=None):
         self.params = params
         self.shape = params.shape
+        self.gauge_version = 0  # counts dd_load_gauge calls (the autograd backward checks it)
         self.ctx = dd_create(params, stream)
         if U is not None:
             self.load_gauge(U)
@@ -250,6 +283,7 @@ class Solver:
 
     def load_gauge(self, U):
         dd_load_gauge(self.ctx, U, self.shape)
+        self.gauge_version += 1
 
     def new_spinor(self):
         return torch.zeros(self.shape + (3, 4), dtype=torch.complex128, device="cuda")
@@ -269,6 +303,28 @@ class Solver:
         st, info = bicgstab_solve(self.ctx, x, b, tol, maxiter, mode, self.shape)
         info["status"] = STATUS[st]
         return x, info
+
+    def solve_dagger(self, b, tol=1e-10, maxiter=10000, mode=DD_SOLVE_MIXED, x0=None):
+        """x with D^dagger x = b (through D^dagger = gamma_5 D gamma_5)."""
+        x = self.new_spinor() if x0 is None else x0.clone()
+        st, info = bicgstab_solve_dagger(self.ctx, x, b, tol, maxiter, mode, self.shape)
+        info["status"] = STATUS[st]
+        return x, info
+
+    def norm2(self, x):
+        return dd_spinor_norm2(self.ctx, x, self.shape)
+
+    def set_csw(self, csw):
+        """Change c_SW; load the gauge field again before the next operator call."""
+        dd_set_csw(self.ctx, csw)
+        self.params.csw = float(csw)
+
+    def force(self, psi, chi, su3=False, out=None, want_dcsw=True):
+        """(per-link gradient dL/dRe U + i dL/dIm U, or the su(3) force; dL/dc_SW) for
+        L = |psi|^2 with psi = D^{-1} phi and chi = D^{-dagger} psi."""
+        out = torch.empty((4,) + self.shape + (3, 3), dtype=torch.complex128, device="cuda") if out is None else out
+        dcsw = dd_force(self.ctx, out, psi, chi, int(su3), self.shape, want_dcsw)
+        return out, dcsw
 
     def field(self, prec):
         """An internal-layout field buffer for the packed entry points."""

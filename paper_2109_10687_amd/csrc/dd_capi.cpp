@@ -2,7 +2,9 @@
 // gauge loading, the Dirac and SAP entry points, and the solver loops:
 //   plain FP64 BiCGStab on D (Alg. 5 without preconditioner),
 //   FP32 BiCGStab on A M_SAP (Alg. 5 with Alg. 1 as right preconditioner),
-//   FP64 defect correction (Alg. 4) around the FP32 solver with an FP16 SAP.
+//   FP64 defect correction (Alg. 4) around the FP32 solver with an FP16 SAP;
+// the adjoint solve D^dagger x = b through D^dagger = gamma_5 D gamma_5, and the
+// fermion force of L = |D^{-1} phi|^2 (dd_force.hip).
 // Every step of the path runs in the kernels of dd_kernels.hip; this file
 // only sequences launches and evaluates the BiCGStab scalars.
 #include <hip/hip_runtime.h>
@@ -46,6 +48,7 @@ struct dd_ctx {
     // packed gauge fields
     void *U64 = nullptr, *U32 = nullptr, *U16 = nullptr;
     void *clov64 = nullptr, *cinv32 = nullptr, *cinv16 = nullptr;
+    void *yforce = nullptr;  // force work field (54 complex per site), allocated by the first dd_force
     // work vectors
     void *f64[N64] = {}, *f32[N32] = {}, *f16[N16] = {};
     void *gz[dd::GCR_MAX_NKV] = {}, *gp[dd::GCR_MAX_NKV] = {};  // GCR images (FP32), directions (FP16)
@@ -138,6 +141,11 @@ double lk_b(int prec) { return prec == 0 ? 144.0 : prec == 1 ? 72.0 : 24.0; }   
 double cl_b(int prec) { return prec == 0 ? 576.0 : prec == 1 ? 288.0 : 144.0; }  // clover / C_inv block pair
 const double HOPF[4] = {168, 168, 168, 156};                                      // flops of one hop per direction
 constexpr double CLOVF = 600;                                                      // clover multiply + combine
+// fermion force, counted flops (complex multiply 6, add 2; a 3x3 product 198, C += A B 216):
+// per link 6 plaquettes x 1854 + hop outer products 730; per site the Y planes 6 x 400
+// and, for dL/dc_SW, the six field strengths and traces 6 x 2500
+constexpr double FORCE_LINK_FLOPS = 6 * 1854.0 + 730.0;
+constexpr double FORCE_Y_FLOPS = 6 * 400.0, FORCE_DCSW_FLOPS = 6 * 2500.0;
 
 // hop flops per site that stay inside a block, and those that leave it
 double hops_in(const Geom &g)
@@ -745,7 +753,7 @@ dd_status dd_destroy(dd_ctx *c)
 {
     if (!c) return DD_OK;
     (void)hipStreamSynchronize(c->stream);
-    void *bufs[] = {c->U64, c->U32, c->U16, c->clov64, c->cinv32, c->cinv16, c->partials, c->red, c->flag};
+    void *bufs[] = {c->U64, c->U32, c->U16, c->clov64, c->cinv32, c->cinv16, c->yforce, c->partials, c->red, c->flag};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     for (void *p : c->f64)
@@ -846,8 +854,11 @@ dd_status sap_precondition(dd_ctx *c, void *x, const void *b, dd_prec prec)
     return DD_OK;
 }
 
-dd_status bicgstab_solve(dd_ctx *c, void *x_dev, const void *b_dev, double tol, int maxiter, dd_solve_mode mode,
-                         dd_solve_info *info)
+// D x = b, or D^dagger x = b when dagger is set: D^dagger = gamma_5 D gamma_5, so
+// y = gamma_5 x solves D y = gamma_5 b; the gamma_5 is applied while packing b
+// and x and while unpacking the result
+static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double tol, int maxiter, dd_solve_mode mode,
+                             dd_solve_info *info, bool dagger)
 {
     if (!c || !x_dev || !b_dev) return fail(c, DD_ERR_ARG, "null argument");
     if (!(tol > 0) || maxiter < 0 || mode < DD_SOLVE_F64_PLAIN || mode > DD_SOLVE_MIXED_GCR)
@@ -856,14 +867,14 @@ dd_status bicgstab_solve(dd_ctx *c, void *x_dev, const void *b_dev, double tol, 
     auto t0 = std::chrono::steady_clock::now();
     dd_solve_info inf{};
     void *b = c->f64[0], *x = c->f64[1];
-    HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, b, b_dev));
+    HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, b, b_dev, dagger));
     double bn2;
     dd_status st = norm2(c, b, 0, &bn2);
     if (st != DD_OK) return st;
     if (!is_fin(bn2)) return fail(c, DD_ERR_NONFINITE, "source holds NaN or Inf");
     dd_status res = DD_OK;
     if (mode == DD_SOLVE_F64_PLAIN) {
-        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, x, x_dev));
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, x, x_dev, dagger));
         SolveOut o;
         res = solve_plain64(c, x, b, tol, maxiter, o);
         if (res < 0) return res;
@@ -884,7 +895,7 @@ dd_status bicgstab_solve(dd_ctx *c, void *x_dev, const void *b_dev, double tol, 
         inf.status_detail = o.detail;
     } else {
         // Alg. 4: x += err * P_DP(A_SP^{-1} R_SP(C_inv r / err)), r = b - D x in FP64
-        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, x, x_dev));
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, x, x_dev, dagger));
         void *r = c->f64[2], *tmp = c->f64[3];
         void *src = c->f32[0], *y = c->f32[1];
         double rn2;
@@ -944,11 +955,84 @@ dd_status bicgstab_solve(dd_ctx *c, void *x_dev, const void *b_dev, double tol, 
         if ((st = residual64(c, c->f64[2], b, x, c->f64[3], &rn2)) != DD_OK) return st;
         inf.relres_true = bn2 > 0 ? std::sqrt(rn2 / bn2) : 0.0;
     }
-    HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F64, x_dev, x));
+    HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F64, x_dev, x, dagger));
     HIPCK(c, hipStreamSynchronize(c->stream));
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
     return res;
+}
+
+dd_status bicgstab_solve(dd_ctx *c, void *x_dev, const void *b_dev, double tol, int maxiter, dd_solve_mode mode,
+                         dd_solve_info *info)
+{
+    return solve_entry(c, x_dev, b_dev, tol, maxiter, mode, info, false);
+}
+
+dd_status bicgstab_solve_dagger(dd_ctx *c, void *x_dev, const void *b_dev, double tol, int maxiter,
+                                dd_solve_mode mode, dd_solve_info *info)
+{
+    return solve_entry(c, x_dev, b_dev, tol, maxiter, mode, info, true);
+}
+
+dd_status dd_spinor_norm2(dd_ctx *c, const void *x_dev, double *out)
+{
+    if (!c || !x_dev || !out) return fail(c, DD_ERR_ARG, "null argument");
+    void *t = c->f64[5];
+    HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, t, x_dev));
+    return norm2(c, t, 0, out);
+}
+
+dd_status dd_set_csw(dd_ctx *c, double csw)
+{
+    if (!c) return DD_ERR_ARG;
+    if (!std::isfinite(csw)) return fail(c, DD_ERR_ARG, "c_SW must be finite");
+    c->prm.csw = csw;
+    c->gauge = false;  // the clover blocks depend on c_SW: dd_load_gauge again
+    return DD_OK;
+}
+
+dd_status dd_force(dd_ctx *c, void *out_dev, double *dcsw, const void *psi_dev, const void *chi_dev, int su3)
+{
+    if (!c || !out_dev || !psi_dev || !chi_dev) return fail(c, DD_ERR_ARG, "null argument");
+    if (su3 != 0 && su3 != 1) return fail(c, DD_ERR_ARG, "su3 must be 0 or 1");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    const Geom &g = c->g;
+    if (!c->yforce && hipMalloc(&c->yforce, (size_t)g.V * 54 * 16) != hipSuccess) {
+        (void)hipGetLastError();
+        c->yforce = nullptr;
+        return fail(c, DD_ERR_NOMEM, "force work field");
+    }
+    dd::ForceArgs a{};
+    a.psi = c->f64[0];
+    a.chi = c->f64[1];
+    HIPCK(c, dd::launch_pack_spinor(g, c->stream, DD_F64, c->f64[0], psi_dev));
+    HIPCK(c, dd::launch_pack_spinor(g, c->stream, DD_F64, c->f64[1], chi_dev));
+    a.u64 = c->U64;
+    a.y = c->yforce;
+    a.out = out_dev;
+    a.partials = dcsw ? c->partials : nullptr;
+    a.dcsw = c->red;
+    if (!sigma_blocks(a.sig)) return fail(c, DD_ERR_ARG, "sigma blocks not block diagonal");
+    a.kcsw = c->prm.kappa * c->prm.csw;
+    a.kappa = c->prm.kappa;
+    a.phase = c->phase;
+    a.su3 = su3;
+    // per site: psi, chi, four links and the six Y planes read twice over (once
+    // written), the output links written; flops of the hop outer products, the
+    // 24 leaves per link (nine 3x3 products per plaquette) and the dcsw traces
+    const double V = (double)g.V;
+    const double bytes = V * (2 * 192.0 + 4 * 144.0 + 2 * 864.0 + 4 * 144.0 + (dcsw ? 4 * 144.0 : 0.0));
+    const double flops = V * (4 * FORCE_LINK_FLOPS + FORCE_Y_FLOPS + (dcsw ? FORCE_DCSW_FLOPS : 0.0));
+    hipError_t e = timed(c, DD_KT_FORCE, bytes, flops, [&] { return dd::launch_force(g, c->stream, a); });
+    if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("force launch: ") + hipGetErrorString(e));
+    if (dcsw) {
+        HIPCK(c, hipMemcpyAsync(c->red_host, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCK(c, hipStreamSynchronize(c->stream));
+        *dcsw = c->red_host[0];
+    } else {
+        HIPCK(c, hipStreamSynchronize(c->stream));
+    }
+    return DD_OK;
 }
 
 dd_status dd_timing_enable(dd_ctx *c, int on)

@@ -16,15 +16,17 @@
 //    accumulation: wavefront shuffles, then LDS, then one partial per
 //    workgroup, summed in a fixed order by a one-workgroup kernel.
 #include "dd_device.h"
+#include "dd_gauge.h"
 #include "dd_launch.h"
 
 namespace dd {
 
 // ============================================================ pack / unpack
 
-// canonical [Lt][Lz][Ly][Lx][3][4] complex double  ->  internal at precision P
+// canonical [Lt][Lz][Ly][Lx][3][4] complex double  ->  internal at precision P,
+// with gamma_5 applied on the way when g5 is set
 template <int P>
-__global__ void __launch_bounds__(256) k_pack_spinor(Geom g, SpinorField<P> dst, const double2 *src)
+__global__ void __launch_bounds__(256) k_pack_spinor(Geom g, SpinorField<P> dst, const double2 *src, int g5)
 {
     long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= g.V) return;
@@ -39,11 +41,12 @@ __global__ void __launch_bounds__(256) k_pack_spinor(Geom g, SpinorField<P> dst,
             double2 t = src[n * 12 + c * 4 + a];
             x.v[a][c] = {t.x, t.y};
         }
+    if (g5) gamma5(x);
     dst.store(g, st.l, st.s, x);
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) k_unpack_spinor(Geom g, double2 *dst, SpinorField<P> src)
+__global__ void __launch_bounds__(256) k_unpack_spinor(Geom g, double2 *dst, SpinorField<P> src, int g5)
 {
     long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= g.V) return;
@@ -52,6 +55,7 @@ __global__ void __launch_bounds__(256) k_unpack_spinor(Geom g, double2 *dst, Spi
     long long n = lex_index(g, st);
     Spinor<double> x;
     src.load(g, st.l, st.s, x);
+    if (g5) gamma5(x);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -84,91 +88,6 @@ __global__ void __launch_bounds__(256)
 }
 
 // ============================================================ clover setup
-
-// site index of a neighbour given as an internal index (re-decoded)
-DD_INL long long step(const Geom &g, long long i, int mu, int dir)
-{
-    Site st;
-    decode(g, i, st);
-    bool w, ib;
-    return neighbour(g, st, mu, dir, w, ib);
-}
-
-DD_INL void load_link64(const Geom &g, const double2 *u, long long i, int mu, Mat3<double> &U)
-{
-    LinkField<0> f{u};
-    f.load(g, (int)(i >> g.lbvol), (int)(i & (g.bvol - 1)), mu, U);
-}
-
-DD_INL void mul3(const Mat3<double> &A, const Mat3<double> &B, Mat3<double> &C)
-{
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            cx<double> s = {0, 0};
-            for (int k = 0; k < 3; ++k) s = s + A.m[i][k] * B.m[k][j];
-            C.m[i][j] = s;
-        }
-}
-
-DD_INL void dag3(const Mat3<double> &A, Mat3<double> &B)
-{
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) B.m[i][j] = conj(A.m[j][i]);
-}
-
-// product of four links, each daggered or not, accumulated into Q
-DD_INL void leaf(const Mat3<double> *M, const int *dg, Mat3<double> &Q)
-{
-    Mat3<double> acc, t, m;
-    if (dg[0]) dag3(M[0], acc); else acc = M[0];
-    for (int k = 1; k < 4; ++k) {
-        if (dg[k]) dag3(M[k], m); else m = M[k];
-        mul3(acc, m, t);
-        acc = t;
-    }
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Q.m[i][j] = Q.m[i][j] + acc.m[i][j];
-}
-
-// F_{mu nu}(n) = (Q - Q^dagger) / 8 with Q the four counter-clockwise
-// plaquettes of the (mu, nu) plane through n
-DD_INL void field_strength(const Geom &g, const double2 *u, long long n, int mu, int nu, Mat3<double> &F)
-{
-    long long n_pm = step(g, n, mu, +1), n_pn = step(g, n, nu, +1);
-    long long n_mm = step(g, n, mu, -1), n_mn = step(g, n, nu, -1);
-    long long n_mm_pn = step(g, n_mm, nu, +1), n_mm_mn = step(g, n_mm, nu, -1);
-    long long n_pm_mn = step(g, n_pm, nu, -1);
-    Mat3<double> Q;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Q.m[i][j] = {0, 0};
-    Mat3<double> M[4];
-    {
-        load_link64(g, u, n, mu, M[0]); load_link64(g, u, n_pm, nu, M[1]);
-        load_link64(g, u, n_pn, mu, M[2]); load_link64(g, u, n, nu, M[3]);
-        const int dg[4] = {0, 0, 1, 1};
-        leaf(M, dg, Q);
-    }
-    {
-        load_link64(g, u, n, nu, M[0]); load_link64(g, u, n_mm_pn, mu, M[1]);
-        load_link64(g, u, n_mm, nu, M[2]); load_link64(g, u, n_mm, mu, M[3]);
-        const int dg[4] = {0, 1, 1, 0};
-        leaf(M, dg, Q);
-    }
-    {
-        load_link64(g, u, n_mm, mu, M[0]); load_link64(g, u, n_mm_mn, nu, M[1]);
-        load_link64(g, u, n_mm_mn, mu, M[2]); load_link64(g, u, n_mn, nu, M[3]);
-        const int dg[4] = {1, 1, 0, 0};
-        leaf(M, dg, Q);
-    }
-    {
-        load_link64(g, u, n_mn, nu, M[0]); load_link64(g, u, n_mn, mu, M[1]);
-        load_link64(g, u, n_pm_mn, nu, M[2]); load_link64(g, u, n, mu, M[3]);
-        const int dg[4] = {1, 0, 0, 1};
-        leaf(M, dg, Q);
-    }
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) F.m[i][j] = 0.125 * (Q.m[i][j] - conj(Q.m[j][i]));
-}
 
 // Cholesky inverse of a Hermitian positive definite 6x6 matrix (full storage);
 // returns false when a pivot is not positive
@@ -548,27 +467,6 @@ template <> struct Elem<2> {  // read only: the scale belongs to the whole site
     }
 };
 
-template <int NV> DD_INL void wg_reduce_store(double (&v)[NV], double *partials)
-{
-    __shared__ double red[NV][BLAS_WG / 64];
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double t = 0;
-            for (int q = 0; q < BLAS_WG / 64; ++q) t += red[k][q];
-            partials[(long long)blockIdx.x * NV + k] = t;
-        }
-}
-
 // sum the per-workgroup partials in a fixed order: out[k] = sum_w partials[w*nv + k]
 __global__ void __launch_bounds__(256) k_finalize(const double *partials, int nwg, int nv, double *out)
 {
@@ -874,17 +772,17 @@ template <> SpinorField<2> sf<2>(void *p, const Geom &g)
     default: { constexpr int P_ = 2; __VA_ARGS__; } break;    \
     }
 
-hipError_t launch_pack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src)
+hipError_t launch_pack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src, bool g5)
 {
     DISPATCH_P(prec, hipLaunchKernelGGL(k_pack_spinor<P_>, dim3(grid_sites(g.V, 256)), dim3(256), 0, st, g,
-                                        sf<P_>(dst, g), (const double2 *)src));
+                                        sf<P_>(dst, g), (const double2 *)src, (int)g5));
     return hipGetLastError();
 }
 
-hipError_t launch_unpack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src)
+hipError_t launch_unpack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src, bool g5)
 {
     DISPATCH_P(prec, hipLaunchKernelGGL(k_unpack_spinor<P_>, dim3(grid_sites(g.V, 256)), dim3(256), 0, st, g,
-                                        (double2 *)dst, sf<P_>((void *)src, g)));
+                                        (double2 *)dst, sf<P_>((void *)src, g), (int)g5));
     return hipGetLastError();
 }
 
@@ -959,6 +857,12 @@ hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int 
 int blas_grid(const Geom &g)
 {
     long long n = (12 * g.V + BLAS_WG - 1) / BLAS_WG;
+    return (int)(n < BLAS_MAX_WG ? n : BLAS_MAX_WG);
+}
+
+int blas_grid_sites(const Geom &g)
+{
+    long long n = (g.V + BLAS_WG - 1) / BLAS_WG;
     return (int)(n < BLAS_MAX_WG ? n : BLAS_MAX_WG);
 }
 

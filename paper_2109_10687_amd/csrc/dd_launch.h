@@ -74,8 +74,45 @@ struct BlasArgs {
     double *partials;
 };
 
-hipError_t launch_pack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src);
-hipError_t launch_unpack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src);
+struct ForceArgs {
+    const void *psi, *chi;  // FP64 internal-layout spinors
+    const void *u64;        // FP64 links
+    void *y;                // work: 54 complex per site (six planes of 3x3)
+    void *out;              // canonical [4][Lt][Lz][Ly][Lx][3][3] complex double
+    double *partials;       // per-workgroup partial sums of dL/dc_SW (nullptr: skip)
+    double *dcsw;           // device scalar receiving dL/dc_SW
+    SigmaBlocks sig;
+    double kcsw, kappa;
+    Phase4 phase;
+    int su3;  // 0: gradient W^dagger per link; 1: traceless Hermitian su(3) force
+};
+
+// sum of v over the workgroup (BLAS_WG threads): wavefront shuffles, then LDS;
+// thread 0 writes the workgroup's partials[blockIdx.x * NV + k]
+template <int NV> DD_INL void wg_reduce_store(double (&v)[NV], double *partials)
+{
+    __shared__ double red[NV][BLAS_WG / 64];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double t = 0;
+            for (int q = 0; q < BLAS_WG / 64; ++q) t += red[k][q];
+            partials[(long long)blockIdx.x * NV + k] = t;
+        }
+}
+
+// canonical <-> internal spinor copies; g5 = true applies gamma_5 on the way
+hipError_t launch_pack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src, bool g5 = false);
+hipError_t launch_unpack_spinor(const Geom &g, hipStream_t st, int prec, void *dst, const void *src, bool g5 = false);
 hipError_t launch_pack_links(const Geom &g, hipStream_t st, const void *src, void *u64, void *u32, void *u16,
                              int *bad);
 hipError_t launch_clover(const Geom &g, hipStream_t st, const void *u64, const SigmaBlocks &sig, double kcsw,
@@ -87,6 +124,8 @@ hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int 
 size_t sap_pk_lds_bytes(const Geom &g);
 hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
 int blas_grid(const Geom &g);
+// grid of a grid-stride loop over the sites (one thread per site, at most BLAS_MAX_WG workgroups)
+int blas_grid_sites(const Geom &g);
 hipError_t launch_blas(const Geom &g, hipStream_t st, const BlasArgs &a);
 
 // ---- flexible GCR: k directions p_j (FP16 storage) with images z_j (FP32)
@@ -105,5 +144,8 @@ hipError_t launch_gcr_rupdate(const Geom &g, hipStream_t st, void *z, void *r, d
 // y (FP32) += sum_j coef_j p_j, p_j at precision pp (FP16 or FP32)
 hipError_t launch_multi_axpy(const Geom &g, hipStream_t st, const VecSet &ps, int k, int pp, void *y);
 hipError_t launch_finalize(hipStream_t st, const double *partials, int nwg, int nv, double *out);
+
+// fermion force of L = |D^{-1} phi|^2 from psi = D^{-1} phi and chi = D^{-dagger} psi
+hipError_t launch_force(const Geom &g, hipStream_t st, const ForceArgs &a);
 
 }  // namespace dd

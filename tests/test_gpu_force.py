@@ -1,0 +1,157 @@
+"""Parity of the HIP fermion force (dd_force, bicgstab_solve_dagger and the
+torch.autograd.Function around them) with the FP64 CPU oracle and with finite
+differences of the loss L = |D^{-1} phi|^2.
+
+* dd_force on arbitrary psi, chi against the oracle's bilinear (gather form on
+  the GPU, scatter form in the oracle), both output forms and dL/dc_SW;
+* the adjoint solve D^dagger x = b against the oracle;
+* the full gradient (U, phi, c_SW) through autograd against the oracle's,
+  8^4;
+* 16^4 and 24^4: the su(3) force on random links against central finite
+  differences of L in FP64 (eps = 1e-6), each difference computed through the
+  differenced solve  psi(U') - psi(U) = -D(U')^{-1} (D(U') - D(U)) psi(U),
+  whose source is O(eps), so the difference carries no solve noise; and, at
+  24^4, the force bilinear against the oracle on the GPU's psi and chi.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2109_10687_amd as dd
+from paper_2109_10687_amd.autograd import quark_loss
+import synth
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: dims, block, kappa, csw, eps, phases
+    "4^4": ((4, 4, 4, 4), (2, 2, 2, 2), 0.12, 1.0, 0.5, (1, 1, 1, -1)),
+    "aniso": ((8, 4, 16, 8), (4, 2, 4, 2), 0.13, 1.3, 0.4, (1, np.exp(0.3j), 1, np.exp(-0.7j))),
+    "aniso_csw0": ((8, 4, 16, 8), (4, 2, 4, 2), 0.13, 0.0, 0.4, (1, np.exp(0.3j), 1, -1)),
+}
+
+
+def params(name):
+    dims, block, kappa, csw, eps, phases = CASES[name]
+    return (O.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases),
+            dd.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases), eps)
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_force_bilinear_matches_oracle(name):
+    op, gp, eps = params(name)
+    U = synth.su3_links(op.dims, eps, 201)
+    psi = synth.gaussian_spinor(op.dims, 202)
+    chi = synth.gaussian_spinor(op.dims, 203)
+    s = dd.Solver(gp, U.cuda())
+    W = O.force(op, U.numpy(), psi.numpy(), chi.numpy())
+    G, dcsw = s.force(psi.cuda(), chi.cuda(), su3=False)
+    assert rel_max(G.cpu().numpy(), O.grad_from_force(W)) < 1e-12
+    F, _ = s.force(psi.cuda(), chi.cuda(), su3=True, want_dcsw=False)
+    assert rel_max(F.cpu().numpy(), O.su3_force(U.numpy(), W)) < 1e-12
+    want = O.dcsw(op, U.numpy(), psi.numpy(), chi.numpy())
+    assert abs(dcsw - want) < 1e-12 * abs(want)
+    print(f"{name}: force max |G| {np.abs(G.cpu().numpy()).max():.3e}, dL/dc_SW {dcsw:.6e}")
+
+
+def test_dagger_solve_matches_oracle():
+    op, gp, eps = params("aniso")
+    U = synth.su3_links(op.dims, eps, 211)
+    b = synth.gaussian_spinor(op.dims, 212)
+    s = dd.Solver(gp, U.cuda())
+    for mode in (dd.DD_SOLVE_F64_PLAIN, dd.DD_SOLVE_MIXED):
+        x, info = s.solve_dagger(b.cuda(), tol=1e-11, mode=mode)
+        assert info["status"] == "DD_OK", info
+        # residual of D^dagger x = b, with the GPU's own D^dagger apply
+        r = s.apply(x, op=dd.DD_OP_DDAG) - b.cuda()
+        assert float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b.cuda())) < 1e-10
+        # the oracle's D^dagger = gamma_5 D gamma_5
+        orc = O.Oracle(op, U.numpy())
+        xn = x.cpu().numpy()
+        Ddx = O.gamma5_apply(orc.D(O.gamma5_apply(xn)))
+        assert np.linalg.norm(Ddx - b.numpy()) < 1e-10 * np.linalg.norm(b.numpy())
+
+
+def test_autograd_gradient_matches_oracle():
+    dims = (8, 8, 8, 8)
+    op = O.Params(dims=dims, kappa=0.125, csw=1.7, block=(4, 4, 4, 4), phases=(1, 1, 1, -1))
+    gp = dd.Params(dims=dims, kappa=0.125, csw=1.7, block=(4, 4, 4, 4), phases=(1, 1, 1, -1))
+    U = synth.su3_links(dims, 0.3, 221)
+    phi = synth.gaussian_spinor(dims, 222)
+    s = dd.Solver(gp)
+    Ud = U.cuda().requires_grad_(True)
+    phid = phi.cuda().requires_grad_(True)
+    csw = torch.tensor(1.7, dtype=torch.float64, requires_grad=True)
+    L = quark_loss(Ud, phid, csw, s, tol=1e-12)
+    L.backward()
+    ref = O.loss_and_force(op, U.numpy(), phi.numpy())
+    assert abs(L.item() - ref.loss) < 1e-10 * ref.loss
+    assert rel_max(Ud.grad.cpu().numpy(), O.grad_from_force(ref.W)) < 1e-8
+    assert rel_max(phid.grad.cpu().numpy(), 2 * ref.chi) < 1e-8
+    assert abs(csw.grad.item() - ref.dcsw) < 1e-8 * abs(ref.dcsw)
+    print(f"8^4: L = {L.item():.10e}, dL/dc_SW = {csw.grad.item():.10e} (oracle {ref.dcsw:.10e})")
+
+
+def expm_herm(T, t):
+    w, v = np.linalg.eigh(T)
+    return (v * np.exp(1j * t * w)) @ v.conj().T
+
+
+def fd_check(dims, nlinks, seed, kappa=0.125, csw=1.7, eps_links=0.3, check_oracle=False):
+    """Relative errors of the su(3) force on `nlinks` random links against central differences."""
+    gp = dd.Params(dims=dims, kappa=kappa, csw=csw, block=(4, 4, 4, 4), phases=(1, 1, 1, -1))
+    U = synth.su3_links(dims, eps_links, seed).cuda()
+    phi = synth.gaussian_spinor(dims, seed + 1).cuda()
+    base, pert = dd.Solver(gp, U), dd.Solver(gp)
+    psi, info = base.solve(phi, tol=1e-12)
+    assert info["status"] == "DD_OK", info
+    chi, info = base.solve_dagger(psi, tol=1e-12)
+    assert info["status"] == "DD_OK", info
+    F, _ = base.force(psi, chi, su3=True, want_dcsw=False)
+    Fh = F.cpu().numpy()
+    if check_oracle:
+        op = O.Params(dims=dims, kappa=kappa, csw=csw, block=(4, 4, 4, 4), phases=(1, 1, 1, -1))
+        W = O.force(op, U.cpu().numpy(), psi.cpu().numpy(), chi.cpu().numpy())
+        assert rel_max(Fh, O.su3_force(U.cpu().numpy(), W)) < 1e-12
+    D0psi = base.apply(psi, op=dd.DD_OP_D)
+    rng = np.random.default_rng(seed + 2)
+    Lx, Ly, Lz, Lt = dims
+    h = 1e-6
+    errs = []
+    for k in range(nlinks):
+        mu = int(rng.integers(4))
+        x, y, z, t = (int(rng.integers(L)) for L in (Lx, Ly, Lz, Lt))
+        Z = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+        T = 0.5 * (Z + Z.conj().T)
+        T -= np.trace(T) / 3 * np.eye(3)
+        dL = []
+        for sgn in (+1, -1):
+            Up = U.clone()
+            u0 = U[mu, t, z, y, x].cpu().numpy()
+            Up[mu, t, z, y, x] = torch.from_numpy(expm_herm(T, sgn * h) @ u0).cuda()
+            pert.load_gauge(Up)
+            r = pert.apply(psi, op=dd.DD_OP_D) - D0psi
+            d, info = pert.solve(-r, tol=1e-10)
+            assert info["status"] == "DD_OK", info
+            dL.append(float(torch.vdot(d.flatten(), (2 * psi + d).flatten()).real))
+        got = (dL[0] - dL[1]) / (2 * h)
+        want = float(np.trace(T @ Fh[mu, t, z, y, x]).real)
+        errs.append(abs(got - want) / abs(want))
+    return np.array(errs)
+
+
+def test_fd_16x16x16x16_64_links():
+    errs = fd_check((16, 16, 16, 16), 64, 231)
+    print(f"16^4: FD vs su(3) force on 64 links, max rel err {errs.max():.2e}, median {np.median(errs):.2e}")
+    assert errs.max() < 1e-5
+
+
+def test_fd_24x24x24x24_16_links_and_oracle():
+    errs = fd_check((24, 24, 24, 24), 16, 241, check_oracle=True)
+    print(f"24^4: FD vs su(3) force on 16 links, max rel err {errs.max():.2e}, median {np.median(errs):.2e}")
+    assert errs.max() < 1e-5
