@@ -67,6 +67,10 @@ def parse():
     ap.add_argument("--fp64-maxiter", type=int, default=4000)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--only-apply", action="store_true", help="time the Dirac applies only (profiling runs)")
+    ap.add_argument("--force-dims", default="24,24,24,24",
+                    help="lattice of the fermion-force leg (L = |D^-1 phi|^2 and its link derivative); 'off' skips it")
+    ap.add_argument("--force-reps", type=int, default=10)
+    ap.add_argument("--only-force", action="store_true", help="run the fermion-force leg only (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of 4 GiB five times (scale for HBM byte counters) and exit")
     return ap.parse_args()
@@ -119,6 +123,54 @@ def dirac_microbench(dd, solver, b, reps):
     return out
 
 
+def force_bench(dd, args):
+    """The differentiation leg: on its own lattice, psi = D^{-1} phi and chi = D^{-dagger} psi by
+    the mixed-precision solver, then `force_reps` timed dd_force calls (su(3) force and
+    dL/dc_SW, FP64).  The force is compute-heavy (24 leaves per link): it is reported against
+    the FP64 vector peak, with its algorithmic bytes beside."""
+    import torch
+    import synth
+    dims = tuple(int(v) for v in args.force_dims.split(","))
+    V = math.prod(dims)
+    params = dd.Params(dims=dims, kappa=args.kappa, csw=args.csw, block=tuple(int(v) for v in args.block.split(",")),
+                       n_sap=args.n_sap, n_jac=args.n_jac, inner_tol=args.inner_tol,
+                       sap_fp16_arith=args.sap_fp16_arith)
+    U = synth.su3_links(dims, args.eps, args.seed + 7, device="cuda")
+    phi = synth.gaussian_spinor(dims, args.seed + 8, device="cuda")
+    s = dd.Solver(params, U)
+    t0 = time.perf_counter()
+    psi, i1 = s.solve(phi, tol=args.tol, mode=dd.DD_SOLVE_MIXED)
+    chi, i2 = s.solve_dagger(psi, tol=args.tol, mode=dd.DD_SOLVE_MIXED)
+    t_solves = time.perf_counter() - t0
+    F, dcsw = s.force(psi, chi, su3=True)
+    torch.cuda.synchronize()
+    s.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.force_reps):
+        s.force(psi, chi, su3=True, out=F)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r = s.timing_report()["force"]
+    s.timing(False)
+    ms = r["ms"] / r["launches"]
+    tf = r["flops"] / r["ms"] / 1e9
+    out = {"workload": f"fermion force {'x'.join(map(str, dims))}", "dims": list(dims),
+           "forward_solve": {"status": i1["status"], "seconds": round(i1["seconds"], 3), "relres_true": i1["relres_true"]},
+           "adjoint_solve": {"status": i2["status"], "seconds": round(i2["seconds"], 3), "relres_true": i2["relres_true"]},
+           "solves_seconds": round(t_solves, 3), "force_ms": round(ms, 4), "force_wall_ms": round(wall / args.force_reps * 1e3, 4),
+           "dL_dcsw": dcsw, "loss": s.norm2(psi),
+           "roofline": {"kernel": "k_force_y + k_force_w", "bound": "alu", "achieved": round(tf, 3),
+                        "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP64_VEC_TFLOPS, 4),
+                        "bytes_GBps": round(r["bytes"] / r["ms"] / 1e6, 1),
+                        "flops_per_site": r["flops"] / r["launches"] / V,
+                        "algorithmic_bytes_per_site": r["bytes"] / r["launches"] / V}}
+    s.close()
+    del U, phi, psi, chi, F
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle's D apply on a 32^4 sample of the workload (same kappa,
     c_SW and link recipe), on the host cores; reported in the metric's unit
@@ -167,6 +219,16 @@ def main():
 
     import paper_2109_10687_amd as dd
     import synth
+
+    force = None
+    if args.force_dims != "off":
+        log(f"fermion-force leg on {args.force_dims}")
+        force = force_bench(dd, args)
+        log(f"force: {force['force_ms']:.3f} ms per call, {force['roofline']['achieved']:.2f} TFLOP/s FP64, "
+            f"{force['roofline']['bytes_GBps']:.0f} GB/s algorithmic; solves {force['solves_seconds']:.2f} s")
+        if args.only_force:
+            print(json.dumps({"force": force}))
+            return
 
     dims = tuple(int(v) for v in args.dims.split(","))
     block = tuple(int(v) for v in args.block.split(","))
@@ -280,6 +342,8 @@ def main():
         "roofline": roof,
         "roofline_dirac": roof_dirac,
     }
+    if force is not None:
+        result["force"] = force
 
     # ---- plain FP64 BiCGStab on the same system (speedup denominator), once
     if args.fp64 == "on":
