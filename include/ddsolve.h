@@ -215,6 +215,55 @@ dd_status dd_set_csw(dd_ctx *ctx, double csw);
  * vectors.  Synchronises the stream. */
 dd_status dd_force(dd_ctx *ctx, void *out_dev, double *dcsw, const void *psi_dev, const void *chi_dev, int su3);
 
+/* ---- batched right-hand sides ------------------------------------------- */
+
+/* Inner solver of bicgstab_solve_batch: BiCGStab on A M_SAP with the FP32 SAP
+ * of each right-hand side (Alg. 1, 5), or on A alone. */
+typedef enum { DD_BATCH_INNER_SAP = 0, DD_BATCH_INNER_PLAIN = 1 } dd_batch_inner;
+
+/* out_r = op(in_r) for nrhs canonical spinor fields stored one after another
+ * (device, caller-owned, [nrhs][Lt][Lz][Ly][Lx][3][4] complex double, in and
+ * out must not overlap).  DD_F32 / DD_OP_A runs the batched kernel: tiles of
+ * up to 12 right-hand sides share every link and C_inv load, and each hop's
+ * 3x3 link times 3x(2 x 12) half-spinor product runs on the matrix cores
+ * (sixteen sites per wavefront, one 4x4x1 block per site).  The kernel
+ * variant (right-hand sides per pass, workgroup size) is picked by timing
+ * every variant on the first call for each tile size, unless
+ * dd_batch_set_variant forced one.  DD_F64 / DD_OP_D and DD_OP_DDAG apply the
+ * single-field kernel to each right-hand side.  The first call allocates the
+ * batch work fields (kept until dd_destroy; DD_ERR_NOMEM if that fails).
+ * Asynchronous, except for the first call of a tile size, which synchronises
+ * while it times the variants. */
+dd_status dirac_apply_batch(dd_ctx *ctx, void *out_dev, const void *in_dev, int nrhs, dd_prec prec, dd_op op);
+
+/* Force the batched kernel variant (0 .. variants-1), or -1 to let the
+ * autotuner choose (the default). */
+dd_status dd_batch_set_variant(dd_ctx *ctx, int variant);
+
+/* The variant in use for tiles of nrhs (1..12) right-hand sides (-1 before the
+ * first batched call of that size) and the autotuner's times in ms per launch
+ * for the first n_ms variants (0 where not timed); ms may be NULL. */
+dd_status dd_batch_tuning(dd_ctx *ctx, int nrhs, int *variant, double *ms, int n_ms);
+
+/* Name of a batched kernel variant ("?" if out of range). */
+const char *dd_batch_variant_name(int variant);
+
+/* Solve D x_r = b_r for nrhs (1..16) right-hand sides at once (canonical
+ * fields one after another, device, caller-owned; x holds the initial guesses
+ * on entry, zeros for a cold start).  FP64 defect correction (Alg. 4) per
+ * right-hand side around an FP32 BiCGStab that runs all right-hand sides in
+ * lockstep, each with its own scalars and exit, and applies A to all of them
+ * in one batched launch per step; the preconditioner (inner) is the FP32 SAP
+ * of each right-hand side or none.  tol is on each true FP64 residual
+ * |b_r - D x_r| / |b_r|; maxiter bounds the defect-correction passes;
+ * inner_tol and inner_maxiter of the params apply to each inner solve.
+ * info (may be NULL) receives nrhs records.  Returns the worst status over
+ * the right-hand sides (DD_OK < DD_NOT_CONVERGED < DD_BREAKDOWN).  The first
+ * call allocates the batch work fields (about 1.9 KB per site and right-hand
+ * side), kept until dd_destroy.  Synchronises the stream. */
+dd_status bicgstab_solve_batch(dd_ctx *ctx, void *x_dev, const void *b_dev, int nrhs, double tol, int maxiter,
+                               dd_batch_inner inner, dd_solve_info *info);
+
 /* ---- internal-layout entry points (benchmarks, no pack/unpack) ----------- */
 
 /* Bytes of one internal spinor field at precision prec (FP16 includes the
@@ -238,7 +287,8 @@ typedef enum {
     DD_KT_SAP = 4,          /* SAP half-sweep kernels (all precisions)           */
     DD_KT_BLAS = 5,         /* vector updates and reductions                     */
     DD_KT_FORCE = 6,        /* fermion force (dd_force), FP64                    */
-    DD_KT_COUNT = 7
+    DD_KT_DIRAC_MRHS = 7,   /* A on a batch of right-hand sides, matrix cores    */
+    DD_KT_COUNT = 8
 } dd_kernel_class;
 
 /* When enabled, every launch of the timed classes is bracketed by HIP events

@@ -22,9 +22,12 @@ LIB_PATH = os.path.join(HERE, "libddsolve.so")
 DD_F64, DD_F32, DD_F16 = 0, 1, 2
 DD_OP_D, DD_OP_A, DD_OP_DDAG = 0, 1, 2
 DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED, DD_SOLVE_MIXED_GCR = 0, 1, 2, 3
-DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16IN, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS, DD_KT_FORCE = range(7)
+(DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16IN, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS, DD_KT_FORCE,
+ DD_KT_DIRAC_MRHS) = range(8)
 KERNEL_CLASSES = {"dirac_f64": DD_KT_DIRAC_F64, "dirac_f32": DD_KT_DIRAC_F32, "dirac_f16in": DD_KT_DIRAC_F16IN,
-                  "dirac_f16": DD_KT_DIRAC_F16, "sap": DD_KT_SAP, "blas": DD_KT_BLAS, "force": DD_KT_FORCE}
+                  "dirac_f16": DD_KT_DIRAC_F16, "sap": DD_KT_SAP, "blas": DD_KT_BLAS, "force": DD_KT_FORCE,
+                  "dirac_mrhs": DD_KT_DIRAC_MRHS}
+DD_BATCH_INNER_SAP, DD_BATCH_INNER_PLAIN = 0, 1
 
 STATUS = {0: "DD_OK", 1: "DD_NOT_CONVERGED", 2: "DD_BREAKDOWN", -1: "DD_ERR_ARG", -2: "DD_ERR_GEOMETRY",
           -3: "DD_ERR_HIP", -4: "DD_ERR_NOMEM", -5: "DD_ERR_NONFINITE", -6: "DD_ERR_CLOVER_NOT_PD",
@@ -33,7 +36,8 @@ STATUS = {0: "DD_OK", 1: "DD_NOT_CONVERGED", 2: "DD_BREAKDOWN", -1: "DD_ERR_ARG"
 EXPORTS = ["dd_create", "dd_destroy", "dd_load_gauge", "dirac_apply", "sap_precondition", "bicgstab_solve",
            "dd_last_error", "dd_field_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dirac_apply_packed",
            "dd_timing_enable", "dd_timing_query", "bicgstab_solve_dagger", "dd_spinor_norm2", "dd_set_csw",
-           "dd_force"]
+           "dd_force", "dirac_apply_batch", "dd_batch_set_variant", "dd_batch_tuning", "dd_batch_variant_name",
+           "bicgstab_solve_batch"]
 
 
 class DDError(RuntimeError):
@@ -86,6 +90,11 @@ def lib():
             "dd_spinor_norm2": (i, [vp, vp, ctypes.POINTER(d)]),
             "dd_set_csw": (i, [vp, d]),
             "dd_force": (i, [vp, vp, ctypes.POINTER(d), vp, vp, i]),
+            "dirac_apply_batch": (i, [vp, vp, vp, i, i, i]),
+            "dd_batch_set_variant": (i, [vp, i]),
+            "dd_batch_tuning": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(d), i]),
+            "dd_batch_variant_name": (ctypes.c_char_p, [i]),
+            "bicgstab_solve_batch": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(_Info)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -228,6 +237,36 @@ def dd_force(ctx, out, psi, chi, su3, shape, want_dcsw=True):
     return d.value if want_dcsw else None
 
 
+def dirac_apply_batch(ctx, out, inp, nrhs, prec, op, shape):
+    sp = (nrhs,) + shape + (3, 4)
+    return _check(ctx, lib().dirac_apply_batch(ctx, _c128(out, sp, "out"), _c128(inp, sp, "in"), int(nrhs), prec, op))
+
+
+def dd_batch_set_variant(ctx, variant):
+    return _check(ctx, lib().dd_batch_set_variant(ctx, int(variant)))
+
+
+def dd_batch_tuning(ctx, nrhs):
+    """(variant in use, autotuner ms per variant) for tiles of nrhs right-hand sides."""
+    v = ctypes.c_int(-1)
+    n = 8
+    ms = (ctypes.c_double * n)()
+    _check(ctx, lib().dd_batch_tuning(ctx, int(nrhs), ctypes.byref(v), ms, n))
+    return v.value, [m for m in ms]
+
+
+def dd_batch_variant_name(variant):
+    return lib().dd_batch_variant_name(int(variant)).decode()
+
+
+def bicgstab_solve_batch(ctx, x, b, nrhs, tol, maxiter, inner, shape):
+    sp = (nrhs,) + shape + (3, 4)
+    infos = (_Info * nrhs)()
+    st = _check(ctx, lib().bicgstab_solve_batch(ctx, _c128(x, sp, "x"), _c128(b, sp, "b"), int(nrhs), float(tol),
+                                                int(maxiter), int(inner), infos))
+    return st, [{k: getattr(inf, k) for k, _ in _Info._fields_} for inf in infos]
+
+
 def dd_field_bytes(ctx, prec):
     return lib().dd_field_bytes(ctx, prec)
 
@@ -325,6 +364,30 @@ class Solver:
         out = torch.empty((4,) + self.shape + (3, 3), dtype=torch.complex128, device="cuda") if out is None else out
         dcsw = dd_force(self.ctx, out, psi, chi, int(su3), self.shape, want_dcsw)
         return out, dcsw
+
+    def apply_batch(self, xs, op=DD_OP_A, prec=DD_F32, out=None):
+        """op applied to each of xs[r] (shape (nrhs,) + lattice + (3, 4)), one batched launch per 12."""
+        out = torch.empty_like(xs) if out is None else out
+        dirac_apply_batch(self.ctx, out, xs, xs.shape[0], prec, op, self.shape)
+        return out
+
+    def batch_variant(self, variant=-1):
+        """Force the batched kernel variant, or -1 for the autotuner."""
+        dd_batch_set_variant(self.ctx, variant)
+
+    def batch_tuning(self, nrhs):
+        v, ms = dd_batch_tuning(self.ctx, nrhs)
+        n = sum(1 for m in ms if m > 0)
+        return {"variant": v, "name": dd_batch_variant_name(v) if v >= 0 else None,
+                "ms": {dd_batch_variant_name(k): ms[k] for k in range(len(ms)) if ms[k] > 0}, "timed": n}
+
+    def solve_batch(self, bs, tol=1e-10, maxiter=50, inner=DD_BATCH_INNER_SAP, x0=None):
+        """x_r with D x_r = b_r for every r (bs: (nrhs,) + lattice + (3, 4)); returns (x, infos)."""
+        x = torch.zeros_like(bs) if x0 is None else x0.clone()
+        st, infos = bicgstab_solve_batch(self.ctx, x, bs, bs.shape[0], tol, maxiter, inner, self.shape)
+        for inf in infos:
+            inf["status"] = STATUS[0] if inf["relres_true"] < tol else STATUS[st]
+        return x, infos
 
     def field(self, prec):
         """An internal-layout field buffer for the packed entry points."""

@@ -27,7 +27,8 @@ using cplx = std::complex<double>;
 namespace {
 
 constexpr int N64 = 7, N32 = 10, N16 = 5;
-constexpr int RED_MAX = 2 * dd::GCR_MAX_NKV;  // longest reduction result (doubles)
+constexpr int RED_MAX = 64;  // longest reduction result (doubles): GCR cycle, or 3 per batched right-hand side
+constexpr int BATCH_MAX = 16;  // right-hand sides of one batched solve
 
 struct TimerRec {
     int cls;
@@ -49,6 +50,13 @@ struct dd_ctx {
     void *U64 = nullptr, *U32 = nullptr, *U16 = nullptr;
     void *clov64 = nullptr, *cinv32 = nullptr, *cinv16 = nullptr;
     void *yforce = nullptr;  // force work field (54 complex per site), allocated by the first dd_force
+    // batched right-hand sides: contiguous arrays of per-RHS internal fields, allocated by the
+    // first batched call and grown on demand (kinds: see BK_* below)
+    int bcap = 0;
+    std::vector<void *> bk;
+    int mrhs_force = -1;                // multi-RHS kernel variant forced by the caller (-1: autotune)
+    int mrhs_tuned[13] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // per right-hand sides in a tile
+    double mrhs_ms[13][8] = {};         // autotuner timings (ms per launch) per variant
     // work vectors
     void *f64[N64] = {}, *f32[N32] = {}, *f16[N16] = {};
     void *gz[dd::GCR_MAX_NKV] = {}, *gp[dd::GCR_MAX_NKV] = {};  // GCR images (FP32), directions (FP16)
@@ -675,6 +683,290 @@ dd_status solve_gcr32(dd_ctx *c, void *src, void *y, double tol, int maxiter, So
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------------ batched right-hand sides
+
+// kinds of per-RHS fields in the batch buffers (each kind: nrhs fields one after another)
+enum { BK_B64, BK_X64, BK_R64, BK_T64, BK_SRC, BK_Y, BK_R, BK_RT, BK_P, BK_Q, BK_T, BK_MP, BK_MR, BK_S, BK_IN, BK_OUT,
+       BK_COUNT };
+
+int bk_prec(int k) { return k <= BK_T64 ? DD_F64 : DD_F32; }
+
+dd_status batch_alloc(dd_ctx *c, int n)
+{
+    if (n <= c->bcap) return DD_OK;
+    for (void *p : c->bk)
+        if (p) (void)hipFree(p);
+    c->bk.assign(BK_COUNT, nullptr);
+    c->bcap = 0;
+    for (int k = 0; k < BK_COUNT; ++k)
+        if (hipMalloc(&c->bk[k], (size_t)n * spinor_bytes(c->g, bk_prec(k))) != hipSuccess) {
+            (void)hipGetLastError();
+            for (void *&p : c->bk)
+                if (p) {
+                    (void)hipFree(p);
+                    p = nullptr;
+                }
+            return fail(c, DD_ERR_NOMEM, "batch work fields");
+        }
+    c->bcap = n;
+    return DD_OK;
+}
+
+// field r of kind k
+void *bf(dd_ctx *c, int k, int r) { return (char *)c->bk[k] + (size_t)r * spinor_bytes(c->g, bk_prec(k)); }
+
+// run a reducing vector kernel on right-hand side r and leave its nv sums at red[off..]
+dd_status reduce_to(dd_ctx *c, dd::BlasArgs a, int nv, int off)
+{
+    dd_status st = blas(c, a);
+    if (st != DD_OK) return st;
+    HIPCK(c, dd::launch_finalize(c->stream, c->partials, dd::blas_grid(c->g), nv, c->red + off));
+    return DD_OK;
+}
+
+dd_status fetch_red(dd_ctx *c, int n, double *out)
+{
+    HIPCK(c, hipMemcpyAsync(c->red_host, c->red, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n; ++k) out[k] = c->red_host[k];
+    return DD_OK;
+}
+
+// out = A in for n FP32 batched fields (internal layout, contiguous), tiles of up to 12 on the
+// matrix cores; the variant is the caller's, or the autotuner's choice for this tile size
+dd_status mrhs_launch(dd_ctx *c, int v, void *out, const void *in, int n)
+{
+    dd::MrhsArgs a{};
+    a.in = (const float2 *)in;
+    a.out = (float2 *)out;
+    a.u = (const float2 *)c->U32;
+    a.cinv = (const float2 *)c->cinv32;
+    a.nrhs = n;
+    a.kappa = c->prm.kappa;
+    a.phase = c->phase;
+    const double V = (double)c->g.V;
+    const double bytes = V * (n * 2.0 * sp_b(DD_F32) + 4 * lk_b(DD_F32) + cl_b(DD_F32));
+    const double flops = V * n * (hops_in(c->g) + hops_out(c->g) + CLOVF);
+    hipError_t e = timed(c, DD_KT_DIRAC_MRHS, bytes, flops, [&] { return dd::launch_dirac_mrhs(c->g, c->stream, a, v); });
+    if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("multi-RHS dirac launch: ") + hipGetErrorString(e));
+    return DD_OK;
+}
+
+// time every variant on this tile (two warm-up launches, three timed) and keep the fastest
+dd_status mrhs_tune(dd_ctx *c, int n, void *out, const void *in)
+{
+    const int nv = dd::mrhs_variant_count();
+    hipEvent_t e0, e1;
+    HIPCK(c, hipEventCreate(&e0));
+    HIPCK(c, hipEventCreate(&e1));
+    const bool timing = c->timing;
+    c->timing = false;
+    int best = 0;
+    for (int v = 0; v < nv; ++v) {
+        dd_status st;
+        for (int k = 0; k < 2; ++k)
+            if ((st = mrhs_launch(c, v, out, in, n)) != DD_OK) return st;
+        HIPCK(c, hipEventRecord(e0, c->stream));
+        for (int k = 0; k < 3; ++k)
+            if ((st = mrhs_launch(c, v, out, in, n)) != DD_OK) return st;
+        HIPCK(c, hipEventRecord(e1, c->stream));
+        HIPCK(c, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCK(c, hipEventElapsedTime(&ms, e0, e1));
+        c->mrhs_ms[n][v] = ms / 3.0;
+        if (c->mrhs_ms[n][v] < c->mrhs_ms[n][best]) best = v;
+    }
+    c->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->mrhs_tuned[n] = best;
+    return DD_OK;
+}
+
+dd_status k_dirac_mrhs(dd_ctx *c, void *out, const void *in, int n)
+{
+    const size_t fb = spinor_bytes(c->g, DD_F32);
+    for (int r0 = 0; r0 < n; r0 += 12) {
+        const int m = n - r0 < 12 ? n - r0 : 12;
+        void *o = (char *)out + r0 * fb;
+        const void *i = (const char *)in + r0 * fb;
+        int v = c->mrhs_force;
+        if (v < 0) {
+            if (c->mrhs_tuned[m] < 0) {
+                dd_status st = mrhs_tune(c, m, o, i);
+                if (st != DD_OK) return st;
+            }
+            v = c->mrhs_tuned[m];
+        }
+        dd_status st = mrhs_launch(c, v, o, i, m);
+        if (st != DD_OK) return st;
+    }
+    return DD_OK;
+}
+
+struct BRhs {
+    bool active = false;
+    cplx rho0 = 0.0;
+    double bn2 = 0, rn2 = 0, tol = 0;
+    SolveOut o;
+    dd_status st = DD_OK;
+};
+
+// FP32 BiCGStab for n right-hand sides in lockstep (Alg. 5 per right-hand side, each with
+// its own scalars and exit), on A M with M = the FP32 SAP of each right-hand side (sap) or
+// M = I; every A application is one batched launch over all n.  Sources: BK_SRC, solutions:
+// BK_Y (flexible accumulation as in the single right-hand-side solver).
+dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int maxiter)
+{
+    const size_t f32 = spinor_bytes(c->g, DD_F32);
+    dd_status st;
+    HIPCK(c, hipMemsetAsync(c->bk[BK_Y], 0, n * f32, c->stream));
+    for (int r = 0; r < n; ++r)
+        if ((st = reduce_to(c, mkb(dd::BLAS_NORM2, {bf(c, BK_SRC, r)}, {1}), 1, r)) != DD_OK) return st;
+    double red[3 * BATCH_MAX];
+    if ((st = fetch_red(c, n, red)) != DD_OK) return st;
+    int nact = 0;
+    for (int r = 0; r < n; ++r) {
+        BRhs &b = R[r];
+        b.o = SolveOut{};
+        b.bn2 = b.rn2 = red[r];
+        b.rho0 = red[r];
+        b.st = DD_OK;
+        if (!is_fin(red[r])) return fail(c, DD_ERR_NONFINITE, "inner source holds NaN or Inf");
+        b.active = red[r] > 0.0;
+        nact += b.active;
+        if (!b.active) continue;
+        for (int k : {BK_R, BK_P, BK_RT})
+            if ((st = copy(c, bf(c, k, r), 1, bf(c, BK_SRC, r), 1)) != DD_OK) return st;
+    }
+    const int mp = sap ? BK_MP : BK_P, mr = sap ? BK_MR : BK_R;
+    auto precond = [&](int from, int to) -> dd_status {
+        if (!sap) return DD_OK;
+        for (int r = 0; r < n; ++r) {
+            if (!R[r].active) continue;
+            dd_status s2 = k_sap(c, 1, bf(c, from, r), bf(c, to, r), bf(c, BK_S, r));
+            if (s2 != DD_OK) return s2;
+        }
+        return DD_OK;
+    };
+    auto stop = [&](BRhs &b, dd_status s2, int detail) {
+        b.active = false;
+        b.st = s2;
+        b.o.detail = detail;
+        --nact;
+    };
+    for (int it = 0; it < maxiter && nact > 0; ++it) {
+        if ((st = precond(BK_P, BK_MP)) != DD_OK) return st;
+        if ((st = k_dirac_mrhs(c, c->bk[BK_Q], c->bk[mp], n)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r)
+            if (R[r].active &&
+                (st = reduce_to(c, mkb(dd::BLAS_DOT, {bf(c, BK_RT, r), bf(c, BK_Q, r)}, {1, 1}), 2, 2 * r)) != DD_OK)
+                return st;
+        if ((st = fetch_red(c, 2 * n, red)) != DD_OK) return st;
+        std::vector<cplx> alpha(n);
+        for (int r = 0; r < n; ++r) {
+            BRhs &b = R[r];
+            if (!b.active) continue;
+            b.o.iters = it + 1;
+            cplx rq(red[2 * r], red[2 * r + 1]);
+            if (rq == 0.0 || !is_fin(rq)) {
+                stop(b, DD_BREAKDOWN, rq == 0.0 ? 1 : 4);
+                continue;
+            }
+            alpha[r] = b.rho0 / rq;
+            if ((st = reduce_to(c, mkb(dd::BLAS_UPDATE1, {bf(c, BK_Y, r), bf(c, mp, r), bf(c, BK_R, r), bf(c, BK_Q, r)},
+                                       {1, 1, 1}, {alpha[r].real(), alpha[r].imag()}),
+                                1, r)) != DD_OK)
+                return st;
+        }
+        if ((st = fetch_red(c, n, red)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r) {
+            BRhs &b = R[r];
+            if (!b.active) continue;
+            b.rn2 = red[r];
+            b.o.relres = std::sqrt(b.rn2 / b.bn2);
+            if (b.o.relres < b.tol) stop(b, DD_OK, 0);
+        }
+        if (nact == 0) break;
+        if ((st = precond(BK_R, BK_MR)) != DD_OK) return st;
+        if ((st = k_dirac_mrhs(c, c->bk[BK_T], c->bk[mr], n)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r)
+            if (R[r].active &&
+                (st = reduce_to(c, mkb(dd::BLAS_DOT_NORM, {bf(c, BK_T, r), bf(c, BK_R, r)}, {1, 1}), 3, 3 * r)) != DD_OK)
+                return st;
+        if ((st = fetch_red(c, 3 * n, red)) != DD_OK) return st;
+        std::vector<cplx> omega(n);
+        for (int r = 0; r < n; ++r) {
+            BRhs &b = R[r];
+            if (!b.active) continue;
+            const double *d = red + 3 * r;
+            if (d[2] == 0.0 || !is_fin(d[2])) {
+                stop(b, DD_BREAKDOWN, d[2] == 0.0 ? 2 : 4);
+                continue;
+            }
+            omega[r] = cplx(d[0], d[1]) / d[2];
+            if ((st = reduce_to(c, mkb(dd::BLAS_UPDATE2,
+                                       {bf(c, BK_Y, r), bf(c, mr, r), bf(c, BK_R, r), bf(c, BK_T, r), bf(c, BK_RT, r)},
+                                       {1, 1, 1}, {omega[r].real(), omega[r].imag()}),
+                                3, 3 * r)) != DD_OK)
+                return st;
+        }
+        if ((st = fetch_red(c, 3 * n, red)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r) {
+            BRhs &b = R[r];
+            if (!b.active) continue;
+            const double *d = red + 3 * r;
+            b.rn2 = d[0];
+            cplx rho(d[1], d[2]);
+            b.o.relres = std::sqrt(b.rn2 / b.bn2);
+            if (b.o.relres < b.tol) {
+                stop(b, DD_OK, 0);
+                continue;
+            }
+            if (omega[r] == 0.0) {
+                stop(b, DD_BREAKDOWN, 3);
+                continue;
+            }
+            cplx beta = (alpha[r] / omega[r]) * (rho / b.rho0);
+            if (!is_fin(beta)) {
+                stop(b, DD_BREAKDOWN, 4);
+                continue;
+            }
+            b.rho0 = rho;
+            if ((st = blas(c, mkb(dd::BLAS_PUPDATE, {bf(c, BK_P, r), bf(c, BK_R, r), bf(c, BK_Q, r)}, {1, 1, 1},
+                                  {beta.real(), beta.imag(), omega[r].real(), omega[r].imag()}))) != DD_OK)
+                return st;
+        }
+        if (c->verbose && (it + 1) % 100 == 0) {
+            std::fprintf(stderr, "[ddsolve] batched inner iteration %d: %d right-hand sides still running\n", it + 1, nact);
+            std::fflush(stderr);
+        }
+    }
+    for (int r = 0; r < n; ++r)
+        if (R[r].active) {
+            R[r].active = false;
+            R[r].st = DD_NOT_CONVERGED;
+        }
+    return DD_OK;
+}
+
+// r = b - D x for every right-hand side (FP64), |r|^2 into rn2
+dd_status residual64_batch(dd_ctx *c, int n, double *rn2)
+{
+    dd_status st;
+    for (int r = 0; r < n; ++r) {
+        if ((st = k_dirac(c, bf(c, BK_T64, r), bf(c, BK_X64, r), 0, 0, 0, 0)) != DD_OK) return st;
+        if ((st = reduce_to(c, mkb(dd::BLAS_SUB_NORM, {bf(c, BK_R64, r), bf(c, BK_B64, r), bf(c, BK_T64, r)}, {0, 0, 0}), 1,
+                            r)) != DD_OK)
+            return st;
+    }
+    return fetch_red(c, n, rn2);
+}
+
+}  // namespace
+
 // ====================================================================== C ABI
 
 extern "C" {
@@ -765,6 +1057,8 @@ dd_status dd_destroy(dd_ctx *c)
     for (void *p : c->gz)
         if (p) (void)hipFree(p);
     for (void *p : c->gp)
+        if (p) (void)hipFree(p);
+    for (void *p : c->bk)
         if (p) (void)hipFree(p);
     if (c->red_host) (void)hipHostFree(c->red_host);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
@@ -1033,6 +1327,170 @@ dd_status dd_force(dd_ctx *c, void *out_dev, double *dcsw, const void *psi_dev, 
         HIPCK(c, hipStreamSynchronize(c->stream));
     }
     return DD_OK;
+}
+
+dd_status dirac_apply_batch(dd_ctx *c, void *out, const void *in, int nrhs, dd_prec prec, dd_op op)
+{
+    if (!c || !out || !in) return fail(c, DD_ERR_ARG, "null argument");
+    if (nrhs < 1) return fail(c, DD_ERR_ARG, "nrhs must be at least 1");
+    dd_status st = check_op(c, prec, op);
+    if (st != DD_OK) return st;
+    if (prec == DD_F16) return fail(c, DD_ERR_ARG, "batched apply: DD_F64 (D, D^dagger) or DD_F32 (A)");
+    const size_t cb = (size_t)c->g.V * 12 * 16;  // canonical field bytes
+    if (prec == DD_F64) {
+        for (int r = 0; r < nrhs; ++r)
+            if ((st = dirac_apply(c, (char *)out + r * cb, (const char *)in + r * cb, prec, op)) != DD_OK) return st;
+        return DD_OK;
+    }
+    const int tile = nrhs < 12 ? nrhs : 12;
+    if ((st = batch_alloc(c, tile)) != DD_OK) return st;
+    const size_t fb = spinor_bytes(c->g, DD_F32);
+    for (int r0 = 0; r0 < nrhs; r0 += 12) {
+        const int m = nrhs - r0 < 12 ? nrhs - r0 : 12;
+        for (int r = 0; r < m; ++r)
+            HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F32, (char *)c->bk[BK_IN] + r * fb,
+                                            (const char *)in + (r0 + r) * cb));
+        if ((st = k_dirac_mrhs(c, c->bk[BK_OUT], c->bk[BK_IN], m)) != DD_OK) return st;
+        for (int r = 0; r < m; ++r)
+            HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F32, (char *)out + (r0 + r) * cb,
+                                              (char *)c->bk[BK_OUT] + r * fb));
+    }
+    return DD_OK;
+}
+
+dd_status dd_batch_set_variant(dd_ctx *c, int variant)
+{
+    if (!c) return DD_ERR_ARG;
+    if (variant < -1 || variant >= dd::mrhs_variant_count()) return fail(c, DD_ERR_ARG, "no such variant");
+    c->mrhs_force = variant;
+    return DD_OK;
+}
+
+dd_status dd_batch_tuning(dd_ctx *c, int nrhs, int *variant, double *ms, int n_ms)
+{
+    if (!c || nrhs < 1 || nrhs > 12) return fail(c, DD_ERR_ARG, "nrhs must be 1..12");
+    if (variant) *variant = c->mrhs_force >= 0 ? c->mrhs_force : c->mrhs_tuned[nrhs];
+    const int nv = dd::mrhs_variant_count();
+    for (int v = 0; ms && v < n_ms; ++v) ms[v] = v < nv ? c->mrhs_ms[nrhs][v] : 0.0;
+    return DD_OK;
+}
+
+const char *dd_batch_variant_name(int variant) { return dd::mrhs_variant_name(variant); }
+
+dd_status bicgstab_solve_batch(dd_ctx *c, void *x_dev, const void *b_dev, int nrhs, double tol, int maxiter,
+                               dd_batch_inner inner, dd_solve_info *info)
+{
+    if (!c || !x_dev || !b_dev) return fail(c, DD_ERR_ARG, "null argument");
+    if (nrhs < 1 || nrhs > BATCH_MAX) return fail(c, DD_ERR_ARG, "nrhs must be 1..16");
+    if (!(tol > 0) || maxiter < 0 || (inner != DD_BATCH_INNER_SAP && inner != DD_BATCH_INNER_PLAIN))
+        return fail(c, DD_ERR_ARG, "bad tolerance, maxiter or inner solver");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    auto t0 = std::chrono::steady_clock::now();
+    dd_status st = batch_alloc(c, nrhs);
+    if (st != DD_OK) return st;
+    const int n = nrhs;
+    const size_t cb = (size_t)c->g.V * 12 * 16;
+    std::vector<dd_solve_info> inf(n);
+    std::vector<BRhs> R(n);
+    double bn2[BATCH_MAX], rn2[BATCH_MAX], prev[BATCH_MAX];
+    for (int r = 0; r < n; ++r) {
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, bf(c, BK_B64, r), (const char *)b_dev + r * cb));
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, bf(c, BK_X64, r), (const char *)x_dev + r * cb));
+        if ((st = reduce_to(c, mkb(dd::BLAS_NORM2, {bf(c, BK_B64, r)}, {0}), 1, r)) != DD_OK) return st;
+    }
+    if ((st = fetch_red(c, n, bn2)) != DD_OK) return st;
+    for (int r = 0; r < n; ++r)
+        if (!is_fin(bn2[r])) return fail(c, DD_ERR_NONFINITE, "a source holds NaN or Inf");
+    for (int r = 0; r < n; ++r)
+        if (bn2[r] == 0.0) HIPCK(c, hipMemsetAsync(bf(c, BK_X64, r), 0, spinor_bytes(c->g, DD_F64), c->stream));
+    if ((st = residual64_batch(c, n, rn2)) != DD_OK) return st;
+    // per right-hand side: 0 running, 1 converged, 2 stopped (breakdown or stagnation)
+    std::vector<int> state(n, 0);
+    std::vector<int> stall(n, 0);
+    std::vector<dd_status> res(n, DD_NOT_CONVERGED);
+    for (int r = 0; r < n; ++r) prev[r] = rn2[r];
+    const size_t f32 = spinor_bytes(c->g, DD_F32);
+    for (int outer = 0;; ++outer) {
+        int running = 0;
+        for (int r = 0; r < n; ++r) {
+            if (state[r] != 0) continue;
+            if (bn2[r] == 0.0 || std::sqrt(rn2[r] / bn2[r]) < tol) {
+                state[r] = 1;
+                res[r] = DD_OK;
+            } else
+                ++running;
+        }
+        if (running == 0 || outer >= maxiter) break;
+        // inner sources C_inv r / err for the running right-hand sides, zero for the others
+        double err[BATCH_MAX];
+        for (int r = 0; r < n; ++r) {
+            err[r] = std::sqrt(rn2[r]);
+            R[r].tol = 1.0;
+            if (state[r] != 0) {
+                HIPCK(c, hipMemsetAsync(bf(c, BK_SRC, r), 0, f32, c->stream));
+                continue;
+            }
+            if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {bf(c, BK_SRC, r), bf(c, BK_R64, r), c->cinv32}, {1, 0},
+                                  {1.0 / err[r]}))) != DD_OK)
+                return st;
+            const double need = 0.5 * tol * std::sqrt(bn2[r]) / err[r];
+            R[r].tol = need > c->prm.inner_tol ? (need < 0.1 ? need : 0.1) : c->prm.inner_tol;
+        }
+        if ((st = solve_batch32(c, n, inner == DD_BATCH_INNER_SAP, R, c->prm.inner_maxiter)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r) {
+            if (state[r] != 0) continue;
+            inf[r].iters_inner_total += R[r].o.iters;
+            inf[r].relres_inner_last = R[r].o.relres;
+            if ((st = blas(c, mkb(dd::BLAS_AXPBY, {bf(c, BK_Y, r), bf(c, BK_X64, r)}, {1, 0}, {err[r], 1.0}))) != DD_OK)
+                return st;
+        }
+        if ((st = residual64_batch(c, n, rn2)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r) {
+            if (state[r] != 0) continue;
+            inf[r].iters_outer = outer + 1;
+            if (!is_fin(rn2[r]) || rn2[r] >= prev[r]) {
+                // the correction made the true residual worse: take it back and stop this one
+                if ((st = blas(c, mkb(dd::BLAS_AXPBY, {bf(c, BK_Y, r), bf(c, BK_X64, r)}, {1, 0}, {-err[r], 1.0}))) !=
+                    DD_OK)
+                    return st;
+                state[r] = 2;
+                res[r] = DD_BREAKDOWN;
+                inf[r].status_detail = is_fin(rn2[r]) ? 5 : 4;
+                continue;
+            }
+            stall[r] = rn2[r] > 0.81 * prev[r] ? stall[r] + 1 : 0;
+            prev[r] = rn2[r];
+            if (stall[r] >= 2) {
+                state[r] = 2;
+                res[r] = DD_BREAKDOWN;
+                inf[r].status_detail = 5;
+            }
+        }
+        if (c->verbose) {
+            int conv = 0;
+            for (int r = 0; r < n; ++r) conv += state[r] == 1 || (bn2[r] > 0 && std::sqrt(rn2[r] / bn2[r]) < tol);
+            std::fprintf(stderr, "[ddsolve] batched outer pass %d: %d of %d right-hand sides at tolerance\n", outer + 1,
+                         conv, n);
+            std::fflush(stderr);
+        }
+    }
+    // true FP64 residuals of the returned solutions
+    if ((st = residual64_batch(c, n, rn2)) != DD_OK) return st;
+    dd_status worst = DD_OK;
+    for (int r = 0; r < n; ++r) {
+        inf[r].relres_true = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
+        if (res[r] == DD_NOT_CONVERGED && inf[r].relres_true < tol) res[r] = DD_OK;
+        if (res[r] > worst) worst = res[r];
+        HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F64, (char *)x_dev + r * cb, bf(c, BK_X64, r)));
+    }
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < n; ++r) {
+        inf[r].seconds = secs;
+        if (res[r] == DD_BREAKDOWN && inf[r].status_detail == 0) inf[r].status_detail = 4;
+        if (info) info[r] = inf[r];
+    }
+    return worst;
 }
 
 dd_status dd_timing_enable(dd_ctx *c, int on)

@@ -74,6 +74,18 @@ struct BlasArgs {
     double *partials;
 };
 
+// A = I - kappa C_inv H on a batch of FP32 internal-layout spinors (nrhs fields,
+// one after another, 12 V complex apart), FP32 links and C_inv
+struct MrhsArgs {
+    const float2 *in;
+    float2 *out;
+    const float2 *u;     // FP32 links
+    const float2 *cinv;  // FP32 C_inv blocks
+    int nrhs;            // 1..12
+    double kappa;
+    Phase4 phase;
+};
+
 struct ForceArgs {
     const void *psi, *chi;  // FP64 internal-layout spinors
     const void *u64;        // FP64 links
@@ -144,6 +156,11 @@ hipError_t launch_gcr_rupdate(const Geom &g, hipStream_t st, void *z, void *r, d
 // y (FP32) += sum_j coef_j p_j, p_j at precision pp (FP16 or FP32)
 hipError_t launch_multi_axpy(const Geom &g, hipStream_t st, const VecSet &ps, int k, int pp, void *y);
 hipError_t launch_finalize(hipStream_t st, const double *partials, int nwg, int nv, double *out);
+
+// multi right-hand-side A on the matrix cores; variant in [0, mrhs_variant_count())
+int mrhs_variant_count();
+const char *mrhs_variant_name(int v);
+hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, int variant);
 
 // fermion force of L = |D^{-1} phi|^2 from psi = D^{-1} phi and chi = D^{-dagger} psi
 hipError_t launch_force(const Geom &g, hipStream_t st, const ForceArgs &a);

@@ -1,0 +1,284 @@
+// dd_mrhs.hip -- the FP32 operator A = I - kappa C_inv H (Sec. 3) applied to a
+// batch of up to 12 right-hand sides at once, with the link products on the
+// matrix cores.
+//
+// With several right-hand sides, each hop multiplies one 3x3 link by a 3 x 24
+// block of projected half spinors (3 colours x 2 half-spin components x 12
+// right-hand sides).  In real form this is a 6x6 by 6x24 product.  The
+// v_mfma_f32_4x4x1_16b_f32 instruction performs sixteen independent 4x4x1
+// outer-product updates per wavefront, so one wavefront handles sixteen sites
+// at a time, a group of four lanes per site: two 4-row tiles (rows 6 and 7
+// zero), six 4-column tiles, six steps over k.  Nothing is packed
+// block-diagonally, so only the row padding (6 of 8 rows used) is wasted.
+//
+// Lane q of a site's group supplies rows q and q+4 of the link's real form and
+// columns q, q+4, ..., q+20 of the half-spinor block; column c holds
+// right-hand side c/2 and half-spin component c%2, so lanes q and q^1 carry
+// the two half-spin components of the same six right-hand sides.  After each
+// hop a lane adds its component of W h into partial sums of the output spin
+// components it touches (its own, and the lower-half components that its
+// half-spin component feeds); one exchange between the lane pair at the end
+// completes the lower half, and a second exchange gives each lane the full
+// chiral 6-vector for the clover block C_inv.
+//
+// Batched fields: nrhs FP32 internal-layout spinors, one after another
+// (stride 12 V complex).  Right-hand sides beyond nrhs in the last tile are
+// neither read nor written.
+#include "dd_device.h"
+#include "dd_launch.h"
+
+namespace dd {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+namespace {
+
+struct Cf {
+    float re, im;
+};
+DD_INL Cf cadd(Cf a, Cf b) { return {a.re + b.re, a.im + b.im}; }
+DD_INL Cf cmul(Cf a, Cf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+DD_INL Cf cmulc_(Cf a, Cf b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }  // conj(a) b
+DD_INL Cf ld2(const float2 *p)
+{
+    float2 t = *p;
+    return {t.x, t.y};
+}
+DD_INL Cf shfl1(Cf a) { return {__shfl_xor(a.re, 1, 64), __shfl_xor(a.im, 1, 64)}; }
+
+}  // namespace
+
+// NTP: column tiles per pass (6 = all twelve right-hand sides in one pass,
+// 3 = six per pass, two passes).  WGS: threads per workgroup.
+template <int NTP, int WGS>
+__global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
+{
+    constexpr int NPASS = 6 / NTP;
+    const int nwg = gridDim.x;
+    const int w = xcd_remap(blockIdx.x, nwg);
+    const int lane = threadIdx.x & 63;
+    const int q = lane & 3, s = q & 1;
+    const long long i = (long long)w * (WGS / 4) + (threadIdx.x >> 2);  // site of this lane's group
+    if (i >= g.V) return;                                              // whole groups leave together
+    Site st;
+    decode(g, i, st);
+    const long long RS = 12 * g.V;  // stride between right-hand sides (complex)
+    const float kap = (float)a.kappa;
+
+#pragma unroll 1
+    for (int pass = 0; pass < NPASS; ++pass) {
+        // this lane's right-hand sides: rhs(nt) = 2 (pass*NTP + nt) + (q >> 1)
+        int rhs[NTP];
+        bool on[NTP];
+#pragma unroll
+        for (int nt = 0; nt < NTP; ++nt) {
+            rhs[nt] = 2 * (pass * NTP + nt) + (q >> 1);
+            on[nt] = rhs[nt] < a.nrhs;
+        }
+        // partial sums: P0 = spin component s, P2 / P3 = components 2 / 3
+        Cf P0[NTP][3], P2[NTP][3], P3[NTP][3];
+#pragma unroll
+        for (int nt = 0; nt < NTP; ++nt)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) P0[nt][c] = P2[nt][c] = P3[nt][c] = {0.f, 0.f};
+
+        // hops one at a time: the unrolled form keeps every hop's operands live and spills
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll 1
+            for (int dir = 1; dir >= -1; dir -= 2) {
+                bool wrap, inblk;
+                const long long j = neighbour(g, st, mu, dir, wrap, inblk);
+                const int lj = (int)(j >> g.lbvol), sj = (int)(j & (g.bvol - 1));
+                // ---- A: rows q and q+4 of the real form of W (U forward, U^dagger backward)
+                float A[2][6];
+                {
+                    const int ll = dir > 0 ? st.l : lj, ss = dir > 0 ? st.s : sj;
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) {
+                        const int r = q + 4 * mt;
+                        if (r < 6) {
+                            const int rr = r % 3;
+                            const bool rim = r >= 3;
+#pragma unroll
+                            for (int kk = 0; kk < 3; ++kk) {
+                                // W[rr][kk]: U[rr][kk] or conj(U[kk][rr])
+                                const int e = dir > 0 ? rr * 3 + kk : kk * 3 + rr;
+                                Cf u = ld2(&a.u[elem(g, ll, ss, 36, mu * 9 + e)]);
+                                if (dir < 0) u.im = -u.im;
+                                // real form [[Re, -Im], [Im, Re]]
+                                A[mt][kk] = rim ? u.im : u.re;
+                                A[mt][kk + 3] = rim ? u.re : -u.im;
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < 6; ++k) A[mt][k] = 0.f;
+                        }
+                    }
+                }
+                // ---- B: this lane's half-spin component s of the projected neighbour spinor
+                // h_s = psi_{i1} + f * psi_{i2} (spin projection of (1 - dir gamma_mu))
+                int i1, i2;
+                Cf f1 = {1.f, 0.f}, f2 = {0.f, 0.f};
+                const float sr = (float)dir;
+                if (mu == 0) {
+                    i1 = s;
+                    i2 = 3 - s;
+                    f2 = {0.f, -sr};
+                } else if (mu == 1) {
+                    i1 = s;
+                    i2 = 3 - s;
+                    f2 = {s ? sr : -sr, 0.f};
+                } else if (mu == 2) {
+                    i1 = s;
+                    i2 = 2 + s;
+                    f2 = {0.f, s ? sr : -sr};
+                } else {
+                    i1 = (dir > 0 ? 2 : 0) + s;
+                    i2 = i1;
+                    f1 = {2.f, 0.f};
+                }
+                float B[NTP][6];
+#pragma unroll
+                for (int nt = 0; nt < NTP; ++nt) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        Cf h = {0.f, 0.f};
+                        if (on[nt]) {
+                            const float2 *base = a.in + rhs[nt] * RS;
+                            Cf p1 = ld2(&base[elem(g, lj, sj, 12, i1 * 3 + c)]);
+                            h = cmul(f1, p1);
+                            if (mu < 3) {
+                                Cf p2 = ld2(&base[elem(g, lj, sj, 12, i2 * 3 + c)]);
+                                h = cadd(h, cmul(f2, p2));
+                            }
+                        }
+                        B[nt][c] = h.re;
+                        B[nt][c + 3] = h.im;
+                    }
+                }
+                // ---- C = A B on the matrix cores: per column tile, two row tiles, six k steps
+                f4_t C[NTP][2];
+#pragma unroll
+                for (int nt = 0; nt < NTP; ++nt)
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) {
+                        f4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(A[mt][k], B[nt][k], acc, 0, 0, 0);
+                        C[nt][mt] = acc;
+                    }
+                // ---- reconstruct: k_s[colour] = (Re: rows 0..2, Im: rows 3..5) of column (nt, q)
+                Cf ph = {1.f, 0.f};
+                if (wrap) ph = {(float)a.phase.re[mu], (float)(dir > 0 ? a.phase.im[mu] : -a.phase.im[mu])};
+                // factors into P0, P2, P3 for this (mu, dir, s)
+                Cf g0 = {1.f, 0.f}, g2 = {0.f, 0.f}, g3 = {0.f, 0.f};
+                if (mu == 0) {
+                    if (s == 0) g3 = {0.f, sr}; else g2 = {0.f, sr};
+                } else if (mu == 1) {
+                    if (s == 0) g3 = {-sr, 0.f}; else g2 = {sr, 0.f};
+                } else if (mu == 2) {
+                    if (s == 0) g2 = {0.f, sr}; else g3 = {0.f, -sr};
+                } else {
+                    if (dir > 0) {
+                        g0 = {0.f, 0.f};
+                        if (s == 0) g2 = {1.f, 0.f}; else g3 = {1.f, 0.f};
+                    }
+                }
+#pragma unroll
+                for (int nt = 0; nt < NTP; ++nt) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        Cf k = {C[nt][0][c], c == 0 ? C[nt][0][3] : C[nt][1][c - 1]};
+                        k = cmul(ph, k);
+                        P0[nt][c] = cadd(P0[nt][c], cmul(g0, k));
+                        P2[nt][c] = cadd(P2[nt][c], cmul(g2, k));
+                        P3[nt][c] = cadd(P3[nt][c], cmul(g3, k));
+                    }
+                }
+            }
+        }
+        // ---- epilogue per column tile: complete the lower components across the lane
+        // pair (lane s then owns spins s and s+2), form the chiral vectors
+        // u = H_a + H_{a+2}, u2 = H_a - H_{a+2} (lane s holds a = s, its partner the
+        // other half), apply rows 3s..3s+2 of the two C_inv blocks, out = in - kappa C_inv H
+#pragma unroll
+        for (int nt = 0; nt < NTP; ++nt) {
+            Cf U1[3], U2[3], V1[3], V2[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Cf send = s == 0 ? P3[nt][c] : P2[nt][c];
+                Cf recv = shfl1(send);
+                Cf h = P0[nt][c];
+                Cf h2 = s == 0 ? cadd(P2[nt][c], recv) : cadd(P3[nt][c], recv);
+                U1[c] = cadd(h, h2);
+                U2[c] = {h.re - h2.re, h.im - h2.im};
+                V1[c] = shfl1(U1[c]);
+                V2[c] = shfl1(U2[c]);
+            }
+            if (!on[nt]) continue;
+            float2 *ob = a.out + rhs[nt] * RS;
+            const float2 *ib = a.in + rhs[nt] * RS;
+#pragma unroll
+            for (int rr = 0; rr < 3; ++rr) {
+                const int r = 3 * s + rr;
+                Cf w1 = {0.f, 0.f}, w2 = {0.f, 0.f};
+#pragma unroll
+                for (int cc = 0; cc < 6; ++cc) {
+                    // entry (r, cc) of N+ (block 0) and N- (block 1): Hermitian, stored as the
+                    // real diagonal (pairs) and the upper triangle
+                    Cf np, nm;
+                    if (cc == r) {
+                        float2 d0 = a.cinv[elem(g, st.l, st.s, 36, r / 2)];
+                        float2 d1 = a.cinv[elem(g, st.l, st.s, 36, 18 + r / 2)];
+                        np = {(r & 1) ? d0.y : d0.x, 0.f};
+                        nm = {(r & 1) ? d1.y : d1.x, 0.f};
+                    } else {
+                        const int ui = cc > r ? upper_index(r, cc) : upper_index(cc, r);
+                        np = ld2(&a.cinv[elem(g, st.l, st.s, 36, 3 + ui)]);
+                        nm = ld2(&a.cinv[elem(g, st.l, st.s, 36, 18 + 3 + ui)]);
+                        if (cc < r) {
+                            np.im = -np.im;
+                            nm.im = -nm.im;
+                        }
+                    }
+                    // the chiral 6-vector: entries 0..2 belong to lane s = 0, 3..5 to s = 1
+                    const bool mine = (cc < 3) == (s == 0);
+                    const int c3 = cc % 3;
+                    w1 = cadd(w1, cmul(np, mine ? U1[c3] : V1[c3]));
+                    w2 = cadd(w2, cmul(nm, mine ? U2[c3] : V2[c3]));
+                }
+                // (C_inv H)_s = w1 + w2, (C_inv H)_{s+2} = w1 - w2
+                Cf xs = ld2(&ib[elem(g, st.l, st.s, 12, s * 3 + rr)]);
+                Cf xs2 = ld2(&ib[elem(g, st.l, st.s, 12, (s + 2) * 3 + rr)]);
+                ob[elem(g, st.l, st.s, 12, s * 3 + rr)] =
+                    make_float2(xs.re - kap * (w1.re + w2.re), xs.im - kap * (w1.im + w2.im));
+                ob[elem(g, st.l, st.s, 12, (s + 2) * 3 + rr)] =
+                    make_float2(xs2.re - kap * (w1.re - w2.re), xs2.im - kap * (w1.im - w2.im));
+            }
+        }
+    }
+}
+
+int mrhs_variant_count() { return 4; }
+
+const char *mrhs_variant_name(int v)
+{
+    static const char *names[] = {"mfma4x4x1 12 rhs/pass, 64-thread workgroups", "mfma4x4x1 12 rhs/pass, 256-thread workgroups",
+                                  "mfma4x4x1 6 rhs/pass, 64-thread workgroups", "mfma4x4x1 6 rhs/pass, 256-thread workgroups"};
+    return (v >= 0 && v < 4) ? names[v] : "?";
+}
+
+hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, int variant)
+{
+    auto grid = [&](int wgs) { return dim3((unsigned)((g.V * 4 + wgs - 1) / wgs)); };
+    switch (variant) {
+    case 0: hipLaunchKernelGGL((k_dirac_mrhs<6, 64>), grid(64), dim3(64), 0, st, g, a); break;
+    case 1: hipLaunchKernelGGL((k_dirac_mrhs<6, 256>), grid(256), dim3(256), 0, st, g, a); break;
+    case 2: hipLaunchKernelGGL((k_dirac_mrhs<3, 64>), grid(64), dim3(64), 0, st, g, a); break;
+    default: hipLaunchKernelGGL((k_dirac_mrhs<3, 256>), grid(256), dim3(256), 0, st, g, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dd
