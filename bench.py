@@ -71,6 +71,9 @@ def parse():
                     help="lattice of the fermion-force leg (L = |D^-1 phi|^2 and its link derivative); 'off' skips it")
     ap.add_argument("--force-reps", type=int, default=10)
     ap.add_argument("--only-force", action="store_true", help="run the fermion-force leg only (profiling runs)")
+    ap.add_argument("--batch-dims", default="32,32,32,64",
+                    help="lattice of the batched leg (12 spin-colour point sources); 'off' skips it")
+    ap.add_argument("--only-batch", action="store_true", help="run the batched leg only (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of 4 GiB five times (scale for HBM byte counters) and exit")
     return ap.parse_args()
@@ -171,6 +174,81 @@ def force_bench(dd, args):
     return out
 
 
+def batch_bench(dd, args, reps=10):
+    """The batched leg: the 12 spin-colour point sources at the origin on their own lattice.
+    (1) The FP32 operator A on all 12 at once (matrix-core kernel, autotuned variant) against 12
+    single right-hand-side FP32 applies; (2) the batched mixed-precision solve to 1e-10 (lockstep
+    FP32 BiCGStab with the FP16 SAP of each right-hand side, FP64 defect correction) against 12
+    single right-hand-side mixed solves (FP16 SAP) one after another."""
+    import torch
+    import synth
+    dims = tuple(int(v) for v in args.batch_dims.split(","))
+    V = math.prod(dims)
+    params = dd.Params(dims=dims, kappa=args.kappa, csw=args.csw, block=tuple(int(v) for v in args.block.split(",")),
+                       n_sap=args.n_sap, n_jac=args.n_jac, inner_tol=args.inner_tol,
+                       sap_fp16_arith=args.sap_fp16_arith)
+    U = synth.su3_links(dims, args.eps, args.seed + 11, device="cuda")
+    s = dd.Solver(params, U)
+    bs = torch.stack([synth.point_source(dims, c, sp, device="cuda") for c in range(3) for sp in range(4)])
+    n = bs.shape[0]
+    out = {"workload": f"12 point sources {'x'.join(map(str, dims))}", "dims": list(dims), "nrhs": n}
+    # (1) operator: batched (tuned on the first call) against single right-hand sides
+    ys = s.apply_batch(bs, op=dd.DD_OP_A, prec=dd.DD_F32)
+    tune = s.batch_tuning(12)
+    s.timing(True)
+    for _ in range(reps):
+        s.apply_batch(bs, op=dd.DD_OP_A, prec=dd.DD_F32, out=ys)
+    r = s.timing_report()["dirac_mrhs"]
+    s.timing(False)
+    fin = s.pack(bs[0], dd.DD_F32)
+    fout = s.field(dd.DD_F32)
+    s.apply_packed(fout, fin, op=dd.DD_OP_A, prec=dd.DD_F32)
+    s.timing(True)
+    for _ in range(reps):
+        s.apply_packed(fout, fin, op=dd.DD_OP_A, prec=dd.DD_F32)
+    r1 = s.timing_report()["dirac_f32"]
+    s.timing(False)
+    ms_b = r["ms"] / r["launches"]
+    ms_1 = r1["ms"] / r1["launches"]
+    out["apply"] = {"batched_ms": round(ms_b, 4), "single_ms": round(ms_1, 4), "single_x12_ms": round(12 * ms_1, 4),
+                    "speedup_vs_12_single": round(12 * ms_1 / ms_b, 2),
+                    "batched_GBps": round(r["bytes"] / r["ms"] / 1e6, 1),
+                    "batched_TFLOPs": round(r["flops"] / r["ms"] / 1e9, 3),
+                    "bytes_per_site": r["bytes"] / r["launches"] / V, "flops_per_site": r["flops"] / r["launches"] / V,
+                    "variant": tune["name"], "autotuner_ms": tune["ms"]}
+    out["roofline"] = {"kernel": "k_dirac_mrhs", "bound": "hbm", "achieved": out["apply"]["batched_GBps"],
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(out["apply"]["batched_GBps"] / HBM_PEAK_GBS, 4),
+                       "mfma_fp32_TFLOPs": out["apply"]["batched_TFLOPs"], "mfma_fp32_peak": 157.3}
+    del fin, fout, ys
+    # (2) solves
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xb, infos = s.solve_batch(bs, tol=args.tol, inner=dd.DD_BATCH_INNER_SAP)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    singles = []
+    for k in range(n):
+        x1, i1 = s.solve(bs[k], tol=args.tol, mode=dd.DD_SOLVE_MIXED)
+        singles.append(i1)
+        if k == 0:
+            err0 = (torch.linalg.vector_norm(xb[0] - x1) / torch.linalg.vector_norm(x1)).item()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter() - t0
+    out["solve"] = {"batched_seconds": round(tb, 3), "batched_status": sorted({i["status"] for i in infos}),
+                    "batched_max_relres_true": max(i["relres_true"] for i in infos),
+                    "batched_outer": max(i["iters_outer"] for i in infos),
+                    "batched_inner_max": max(i["iters_inner_total"] for i in infos),
+                    "single_x12_seconds": round(t1, 3), "single_status": sorted({i["status"] for i in singles}),
+                    "single_max_relres_true": max(i["relres_true"] for i in singles),
+                    "batched_vs_single_solution_relerr_rhs0": err0}
+    s.close()
+    del U, bs, xb
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle's D apply on a 32^4 sample of the workload (same kappa,
     c_SW and link recipe), on the host cores; reported in the metric's unit
@@ -228,6 +306,17 @@ def main():
             f"{force['roofline']['bytes_GBps']:.0f} GB/s algorithmic; solves {force['solves_seconds']:.2f} s")
         if args.only_force:
             print(json.dumps({"force": force}))
+            return
+
+    batch = None
+    if args.batch_dims != "off":
+        log(f"batched leg on {args.batch_dims}")
+        batch = batch_bench(dd, args)
+        log(f"batched A: {batch['apply']['batched_ms']:.3f} ms for 12 right-hand sides vs "
+            f"{batch['apply']['single_x12_ms']:.3f} ms for 12 single ({batch['apply']['variant']}); batched solve "
+            f"{batch['solve']['batched_seconds']:.2f} s vs 12 single solves {batch['solve']['single_x12_seconds']:.2f} s")
+        if args.only_batch:
+            print(json.dumps({"batch": batch}))
             return
 
     dims = tuple(int(v) for v in args.dims.split(","))
@@ -344,6 +433,8 @@ def main():
     }
     if force is not None:
         result["force"] = force
+    if batch is not None:
+        result["batch"] = batch
 
     # ---- plain FP64 BiCGStab on the same system (speedup denominator), once
     if args.fp64 == "on":

@@ -217,8 +217,9 @@ dd_status dd_force(dd_ctx *ctx, void *out_dev, double *dcsw, const void *psi_dev
 
 /* ---- batched right-hand sides ------------------------------------------- */
 
-/* Inner solver of bicgstab_solve_batch: BiCGStab on A M_SAP with the FP32 SAP
- * of each right-hand side (Alg. 1, 5), or on A alone. */
+/* Inner solver of bicgstab_solve_batch: BiCGStab on A M_SAP with the SAP of
+ * each right-hand side (Alg. 1, 5; FP16 storage, as in DD_SOLVE_MIXED), or on
+ * A alone. */
 typedef enum { DD_BATCH_INNER_SAP = 0, DD_BATCH_INNER_PLAIN = 1 } dd_batch_inner;
 
 /* out_r = op(in_r) for nrhs canonical spinor fields stored one after another
@@ -253,13 +254,13 @@ const char *dd_batch_variant_name(int variant);
  * on entry, zeros for a cold start).  FP64 defect correction (Alg. 4) per
  * right-hand side around an FP32 BiCGStab that runs all right-hand sides in
  * lockstep, each with its own scalars and exit, and applies A to all of them
- * in one batched launch per step; the preconditioner (inner) is the FP32 SAP
- * of each right-hand side or none.  tol is on each true FP64 residual
+ * in one batched launch per step; the preconditioner (inner) is the SAP of
+ * each right-hand side (FP16 storage) or none.  tol is on each true FP64 residual
  * |b_r - D x_r| / |b_r|; maxiter bounds the defect-correction passes;
  * inner_tol and inner_maxiter of the params apply to each inner solve.
  * info (may be NULL) receives nrhs records.  Returns the worst status over
  * the right-hand sides (DD_OK < DD_NOT_CONVERGED < DD_BREAKDOWN).  The first
- * call allocates the batch work fields (about 1.9 KB per site and right-hand
+ * call allocates the batch work fields (about 1.8 KB per site and right-hand
  * side), kept until dd_destroy.  Synchronises the stream. */
 dd_status bicgstab_solve_batch(dd_ctx *ctx, void *x_dev, const void *b_dev, int nrhs, double tol, int maxiter,
                                dd_batch_inner inner, dd_solve_info *info);

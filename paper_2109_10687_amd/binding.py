@@ -249,7 +249,7 @@ def dd_batch_set_variant(ctx, variant):
 def dd_batch_tuning(ctx, nrhs):
     """(variant in use, autotuner ms per variant) for tiles of nrhs right-hand sides."""
     v = ctypes.c_int(-1)
-    n = 8
+    n = 16
     ms = (ctypes.c_double * n)()
     _check(ctx, lib().dd_batch_tuning(ctx, int(nrhs), ctypes.byref(v), ms, n))
     return v.value, [m for m in ms]

@@ -56,7 +56,7 @@ struct dd_ctx {
     std::vector<void *> bk;
     int mrhs_force = -1;                // multi-RHS kernel variant forced by the caller (-1: autotune)
     int mrhs_tuned[13] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // per right-hand sides in a tile
-    double mrhs_ms[13][8] = {};         // autotuner timings (ms per launch) per variant
+    double mrhs_ms[13][16] = {};         // autotuner timings (ms per launch) per variant
     // work vectors
     void *f64[N64] = {}, *f32[N32] = {}, *f16[N16] = {};
     void *gz[dd::GCR_MAX_NKV] = {}, *gp[dd::GCR_MAX_NKV] = {};  // GCR images (FP32), directions (FP16)
@@ -688,7 +688,7 @@ namespace {
 // ------------------------------------------------------------------ batched right-hand sides
 
 // kinds of per-RHS fields in the batch buffers (each kind: nrhs fields one after another)
-enum { BK_B64, BK_X64, BK_R64, BK_T64, BK_SRC, BK_Y, BK_R, BK_RT, BK_P, BK_Q, BK_T, BK_MP, BK_MR, BK_S, BK_IN, BK_OUT,
+enum { BK_B64, BK_X64, BK_R64, BK_T64, BK_SRC, BK_Y, BK_R, BK_RT, BK_P, BK_Q, BK_T, BK_MP, BK_MR, BK_IN, BK_OUT,
        BK_COUNT };
 
 int bk_prec(int k) { return k <= BK_T64 ? DD_F64 : DD_F32; }
@@ -815,8 +815,8 @@ struct BRhs {
 };
 
 // FP32 BiCGStab for n right-hand sides in lockstep (Alg. 5 per right-hand side, each with
-// its own scalars and exit), on A M with M = the FP32 SAP of each right-hand side (sap) or
-// M = I; every A application is one batched launch over all n.  Sources: BK_SRC, solutions:
+// its own scalars and exit), on A M with M = the FP16-storage SAP of each right-hand side
+// (sap) or M = I; every A application is one batched launch over all n.  Sources: BK_SRC, solutions:
 // BK_Y (flexible accumulation as in the single right-hand-side solver).
 dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int maxiter)
 {
@@ -842,12 +842,17 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
             if ((st = copy(c, bf(c, k, r), 1, bf(c, BK_SRC, r), 1)) != DD_OK) return st;
     }
     const int mp = sap ? BK_MP : BK_P, mr = sap ? BK_MR : BK_R;
+    // M = the FP16-storage SAP of each right-hand side (as in the single right-hand-side
+    // mixed solver), its output widened to FP32 for the batched A
     auto precond = [&](int from, int to) -> dd_status {
         if (!sap) return DD_OK;
+        void *in16 = c->f16[0], *out16 = c->f16[2], *s16 = c->f16[4];
         for (int r = 0; r < n; ++r) {
             if (!R[r].active) continue;
-            dd_status s2 = k_sap(c, 1, bf(c, from, r), bf(c, to, r), bf(c, BK_S, r));
-            if (s2 != DD_OK) return s2;
+            dd_status s2;
+            if ((s2 = copy(c, in16, 2, bf(c, from, r), 1)) != DD_OK) return s2;
+            if ((s2 = k_sap(c, 2, in16, out16, s16)) != DD_OK) return s2;
+            if ((s2 = copy(c, bf(c, to, r), 1, out16, 2)) != DD_OK) return s2;
         }
         return DD_OK;
     };

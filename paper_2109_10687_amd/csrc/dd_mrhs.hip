@@ -23,7 +23,7 @@
 //
 // Batched fields: nrhs FP32 internal-layout spinors, one after another
 // (stride 12 V complex).  Right-hand sides beyond nrhs in the last tile are
-// neither read nor written.
+// never written (their lanes read the last right-hand side instead).
 #include "dd_device.h"
 #include "dd_launch.h"
 
@@ -48,8 +48,8 @@ DD_INL Cf shfl1(Cf a) { return {__shfl_xor(a.re, 1, 64), __shfl_xor(a.im, 1, 64)
 
 }  // namespace
 
-// NTP: column tiles per pass (6 = all twelve right-hand sides in one pass,
-// 3 = six per pass, two passes).  WGS: threads per workgroup.
+// NTP: column tiles per pass (a lane carries NTP right-hand sides per pass; the
+// group of four lanes 2 NTP; 6 passes / NTP cover twelve).  WGS: threads per workgroup.
 template <int NTP, int WGS>
 __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
 {
@@ -68,12 +68,15 @@ __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
 #pragma unroll 1
     for (int pass = 0; pass < NPASS; ++pass) {
         // this lane's right-hand sides: rhs(nt) = 2 (pass*NTP + nt) + (q >> 1)
-        int rhs[NTP];
+        // (a right-hand side beyond nrhs reads the last one and is not stored: every
+        // load stays unconditional, so no branch splits the loads of a hop)
+        int rhs[NTP], rld[NTP];
         bool on[NTP];
 #pragma unroll
         for (int nt = 0; nt < NTP; ++nt) {
             rhs[nt] = 2 * (pass * NTP + nt) + (q >> 1);
             on[nt] = rhs[nt] < a.nrhs;
+            rld[nt] = on[nt] ? rhs[nt] : a.nrhs - 1;
         }
         // partial sums: P0 = spin component s, P2 / P3 = components 2 / 3
         Cf P0[NTP][3], P2[NTP][3], P3[NTP][3];
@@ -96,23 +99,19 @@ __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
                     const int ll = dir > 0 ? st.l : lj, ss = dir > 0 ? st.s : sj;
 #pragma unroll
                     for (int mt = 0; mt < 2; ++mt) {
-                        const int r = q + 4 * mt;
-                        if (r < 6) {
-                            const int rr = r % 3;
-                            const bool rim = r >= 3;
+                        const int r = q + 4 * mt;  // rows 6 and 7 are padding: loaded from row 0, zeroed
+                        const bool pad = r >= 6;
+                        const int rr = pad ? 0 : r % 3;
+                        const bool rim = r >= 3;
 #pragma unroll
-                            for (int kk = 0; kk < 3; ++kk) {
-                                // W[rr][kk]: U[rr][kk] or conj(U[kk][rr])
-                                const int e = dir > 0 ? rr * 3 + kk : kk * 3 + rr;
-                                Cf u = ld2(&a.u[elem(g, ll, ss, 36, mu * 9 + e)]);
-                                if (dir < 0) u.im = -u.im;
-                                // real form [[Re, -Im], [Im, Re]]
-                                A[mt][kk] = rim ? u.im : u.re;
-                                A[mt][kk + 3] = rim ? u.re : -u.im;
-                            }
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < 6; ++k) A[mt][k] = 0.f;
+                        for (int kk = 0; kk < 3; ++kk) {
+                            // W[rr][kk]: U[rr][kk] or conj(U[kk][rr])
+                            const int e = dir > 0 ? rr * 3 + kk : kk * 3 + rr;
+                            Cf u = ld2(&a.u[elem(g, ll, ss, 36, mu * 9 + e)]);
+                            if (dir < 0) u.im = -u.im;
+                            // real form [[Re, -Im], [Im, Re]]
+                            A[mt][kk] = pad ? 0.f : (rim ? u.im : u.re);
+                            A[mt][kk + 3] = pad ? 0.f : (rim ? u.re : -u.im);
                         }
                     }
                 }
@@ -143,16 +142,10 @@ __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
                 for (int nt = 0; nt < NTP; ++nt) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        Cf h = {0.f, 0.f};
-                        if (on[nt]) {
-                            const float2 *base = a.in + rhs[nt] * RS;
-                            Cf p1 = ld2(&base[elem(g, lj, sj, 12, i1 * 3 + c)]);
-                            h = cmul(f1, p1);
-                            if (mu < 3) {
-                                Cf p2 = ld2(&base[elem(g, lj, sj, 12, i2 * 3 + c)]);
-                                h = cadd(h, cmul(f2, p2));
-                            }
-                        }
+                        const float2 *base = a.in + rld[nt] * RS;
+                        Cf p1 = ld2(&base[elem(g, lj, sj, 12, i1 * 3 + c)]);
+                        Cf p2 = ld2(&base[elem(g, lj, sj, 12, i2 * 3 + c)]);  // i2 = i1 for mu = 3 (f2 = 0)
+                        Cf h = cadd(cmul(f1, p1), cmul(f2, p2));
                         B[nt][c] = h.re;
                         B[nt][c + 3] = h.im;
                     }
@@ -216,9 +209,8 @@ __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
                 V1[c] = shfl1(U1[c]);
                 V2[c] = shfl1(U2[c]);
             }
-            if (!on[nt]) continue;
-            float2 *ob = a.out + rhs[nt] * RS;
-            const float2 *ib = a.in + rhs[nt] * RS;
+            float2 *ob = a.out + rld[nt] * RS;
+            const float2 *ib = a.in + rld[nt] * RS;
 #pragma unroll
             for (int rr = 0; rr < 3; ++rr) {
                 const int r = 3 * s + rr;
@@ -227,21 +219,15 @@ __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
                 for (int cc = 0; cc < 6; ++cc) {
                     // entry (r, cc) of N+ (block 0) and N- (block 1): Hermitian, stored as the
                     // real diagonal (pairs) and the upper triangle
-                    Cf np, nm;
-                    if (cc == r) {
-                        float2 d0 = a.cinv[elem(g, st.l, st.s, 36, r / 2)];
-                        float2 d1 = a.cinv[elem(g, st.l, st.s, 36, 18 + r / 2)];
-                        np = {(r & 1) ? d0.y : d0.x, 0.f};
-                        nm = {(r & 1) ? d1.y : d1.x, 0.f};
-                    } else {
-                        const int ui = cc > r ? upper_index(r, cc) : upper_index(cc, r);
-                        np = ld2(&a.cinv[elem(g, st.l, st.s, 36, 3 + ui)]);
-                        nm = ld2(&a.cinv[elem(g, st.l, st.s, 36, 18 + 3 + ui)]);
-                        if (cc < r) {
-                            np.im = -np.im;
-                            nm.im = -nm.im;
-                        }
-                    }
+                    // (one unconditional load per block: the element index and the
+                    // interpretation are selected, not branched on)
+                    const bool dg = cc == r;
+                    const int e = dg ? r / 2 : 3 + (cc > r ? upper_index(r, cc) : upper_index(cc, r));
+                    const float2 t0 = a.cinv[elem(g, st.l, st.s, 36, e)];
+                    const float2 t1 = a.cinv[elem(g, st.l, st.s, 36, 18 + e)];
+                    const float cj = cc < r ? -1.f : 1.f;
+                    Cf np = dg ? Cf{(r & 1) ? t0.y : t0.x, 0.f} : Cf{t0.x, cj * t0.y};
+                    Cf nm = dg ? Cf{(r & 1) ? t1.y : t1.x, 0.f} : Cf{t1.x, cj * t1.y};
                     // the chiral 6-vector: entries 0..2 belong to lane s = 0, 3..5 to s = 1
                     const bool mine = (cc < 3) == (s == 0);
                     const int c3 = cc % 3;
@@ -251,32 +237,108 @@ __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
                 // (C_inv H)_s = w1 + w2, (C_inv H)_{s+2} = w1 - w2
                 Cf xs = ld2(&ib[elem(g, st.l, st.s, 12, s * 3 + rr)]);
                 Cf xs2 = ld2(&ib[elem(g, st.l, st.s, 12, (s + 2) * 3 + rr)]);
-                ob[elem(g, st.l, st.s, 12, s * 3 + rr)] =
-                    make_float2(xs.re - kap * (w1.re + w2.re), xs.im - kap * (w1.im + w2.im));
-                ob[elem(g, st.l, st.s, 12, (s + 2) * 3 + rr)] =
-                    make_float2(xs2.re - kap * (w1.re - w2.re), xs2.im - kap * (w1.im - w2.im));
+                if (on[nt]) {
+                    ob[elem(g, st.l, st.s, 12, s * 3 + rr)] =
+                        make_float2(xs.re - kap * (w1.re + w2.re), xs.im - kap * (w1.im + w2.im));
+                    ob[elem(g, st.l, st.s, 12, (s + 2) * 3 + rr)] =
+                        make_float2(xs2.re - kap * (w1.re - w2.re), xs2.im - kap * (w1.im - w2.im));
+                }
             }
         }
     }
 }
 
-int mrhs_variant_count() { return 4; }
+// The vector alternative for the autotuner: one thread per (site, right-hand side),
+// the twelve workgroups of a block's right-hand sides launched back to back on the
+// same XCD, so the block's links and C_inv come from HBM once and from L2 for the
+// other right-hand sides (loaded with ordinary, cached loads for that reason).
+__global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom g, MrhsArgs a)
+{
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = w / a.nrhs, r = w - blk * a.nrhs;
+    const long long i = (long long)blk * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    Site st;
+    decode(g, i, st);
+    const long long RS = 12 * g.V;
+    SpinorField<1> in{(float2 *)(a.in + r * RS)}, out{a.out + r * RS};
+    LinkField<1> U{a.u};
+    Spinor<float> acc;
+    zero(acc);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+        for (int dir = 1; dir >= -1; dir -= 2) {
+            bool wrap, inblk;
+            const long long j = neighbour(g, st, mu, dir, wrap, inblk);
+            const int lj = (int)(j >> g.lbvol), sj = (int)(j & (g.bvol - 1));
+            Spinor<float> psi;
+            in.load(g, lj, sj, psi);
+            Mat3<float> W;
+            if (dir > 0)
+                U.load(g, st.l, st.s, mu, W);
+            else
+                U.load(g, lj, sj, mu, W);
+            cx<float> phase = {(float)a.phase.re[mu], (float)(dir > 0 ? a.phase.im[mu] : -a.phase.im[mu])};
+            hop(mu, dir, W, psi, wrap, phase, acc);
+        }
+    }
+    Clov<float> cl;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            float2 t = a.cinv[elem(g, st.l, st.s, 36, b * 18 + jj)];
+            cl.d[b][2 * jj] = t.x;
+            cl.d[b][2 * jj + 1] = t.y;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 15; ++jj) {
+            float2 t = a.cinv[elem(g, st.l, st.s, 36, b * 18 + 3 + jj)];
+            cl.h[b][jj] = {t.x, t.y};
+        }
+    }
+    Spinor<float> x, t, o;
+    in.load(g, st.l, st.s, x);
+    clover_mul(cl, acc, t);
+#pragma unroll
+    for (int aa = 0; aa < 4; ++aa)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o.v[aa][c] = x.v[aa][c] - (float)a.kappa * t.v[aa][c];
+    out.store(g, st.l, st.s, o, true);
+}
+
+// variants 0-7: column tiles per pass (1, 2, 3 or 6: 2, 4, 6 or 12 right-hand sides per
+// pass) x workgroup size (64 or 256 threads); variant 8: the vector kernel above.  Fewer right-hand sides per pass
+// need fewer registers, so more wavefronts hide the load latency, at the price of
+// reading the links and C_inv once per pass.
+int mrhs_variant_count() { return 9; }
 
 const char *mrhs_variant_name(int v)
 {
-    static const char *names[] = {"mfma4x4x1 12 rhs/pass, 64-thread workgroups", "mfma4x4x1 12 rhs/pass, 256-thread workgroups",
-                                  "mfma4x4x1 6 rhs/pass, 64-thread workgroups", "mfma4x4x1 6 rhs/pass, 256-thread workgroups"};
-    return (v >= 0 && v < 4) ? names[v] : "?";
+    static const char *names[] = {"mfma4x4x1 2 rhs/pass, 64-thread wg",  "mfma4x4x1 2 rhs/pass, 256-thread wg",
+                                  "mfma4x4x1 4 rhs/pass, 64-thread wg",  "mfma4x4x1 4 rhs/pass, 256-thread wg",
+                                  "mfma4x4x1 6 rhs/pass, 64-thread wg",  "mfma4x4x1 6 rhs/pass, 256-thread wg",
+                                  "mfma4x4x1 12 rhs/pass, 64-thread wg", "mfma4x4x1 12 rhs/pass, 256-thread wg",
+                                  "vector, one thread per site and rhs, rhs-interleaved workgroups"};
+    return (v >= 0 && v < 9) ? names[v] : "?";
 }
 
 hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, int variant)
 {
     auto grid = [&](int wgs) { return dim3((unsigned)((g.V * 4 + wgs - 1) / wgs)); };
     switch (variant) {
-    case 0: hipLaunchKernelGGL((k_dirac_mrhs<6, 64>), grid(64), dim3(64), 0, st, g, a); break;
-    case 1: hipLaunchKernelGGL((k_dirac_mrhs<6, 256>), grid(256), dim3(256), 0, st, g, a); break;
-    case 2: hipLaunchKernelGGL((k_dirac_mrhs<3, 64>), grid(64), dim3(64), 0, st, g, a); break;
-    default: hipLaunchKernelGGL((k_dirac_mrhs<3, 256>), grid(256), dim3(256), 0, st, g, a); break;
+    case 0: hipLaunchKernelGGL((k_dirac_mrhs<1, 64>), grid(64), dim3(64), 0, st, g, a); break;
+    case 1: hipLaunchKernelGGL((k_dirac_mrhs<1, 256>), grid(256), dim3(256), 0, st, g, a); break;
+    case 2: hipLaunchKernelGGL((k_dirac_mrhs<2, 64>), grid(64), dim3(64), 0, st, g, a); break;
+    case 3: hipLaunchKernelGGL((k_dirac_mrhs<2, 256>), grid(256), dim3(256), 0, st, g, a); break;
+    case 4: hipLaunchKernelGGL((k_dirac_mrhs<3, 64>), grid(64), dim3(64), 0, st, g, a); break;
+    case 5: hipLaunchKernelGGL((k_dirac_mrhs<3, 256>), grid(256), dim3(256), 0, st, g, a); break;
+    case 6: hipLaunchKernelGGL((k_dirac_mrhs<6, 64>), grid(64), dim3(64), 0, st, g, a); break;
+    case 7: hipLaunchKernelGGL((k_dirac_mrhs<6, 256>), grid(256), dim3(256), 0, st, g, a); break;
+    default:
+        hipLaunchKernelGGL(k_dirac_rhs_vec, dim3((unsigned)((g.V + 255) / 256 * a.nrhs)), dim3(256), 0, st, g, a);
+        break;
     }
     return hipGetLastError();
 }
