@@ -265,6 +265,42 @@ const char *dd_batch_variant_name(int variant);
 dd_status bicgstab_solve_batch(dd_ctx *ctx, void *x_dev, const void *b_dev, int nrhs, double tol, int maxiter,
                                dd_batch_inner inner, dd_solve_info *info);
 
+/* ---- several lattices ---------------------------------------------------- */
+
+/* A set of independent lattices (sizes, blocks, kappa, c_SW and phases of their
+ * own, each with its own gauge field) whose FP32 operator A is applied to all of
+ * them in one persistent launch: the work items are (lattice, 256-site chunk)
+ * pairs taken from a global counter, so uneven lattices fill the chip together. */
+typedef struct dd_multi dd_multi;
+
+/* params: nlat (1..64) parameter sets, each checked as by dd_create (every
+ * lattice gets a context of its own, with its fields and work vectors). */
+dd_status dd_multi_create(const dd_params *params, int nlat, void *hip_stream, dd_multi **out);
+dd_status dd_multi_destroy(dd_multi *m);
+const char *dd_multi_last_error(const dd_multi *m);
+
+/* The context of lattice lat (owned by m: do not destroy it; its timers hold the
+ * multi-lattice launches for lattice 0), or NULL. */
+dd_ctx *dd_multi_context(dd_multi *m, int lat);
+
+/* Load lattice lat's gauge field, as dd_load_gauge. */
+dd_status dd_multi_load_gauge(dd_multi *m, int lat, const void *U_dev);
+
+/* out[k] = A_k in[k] for every lattice k (canonical fields of each lattice's
+ * size, device, caller-owned, must not overlap), FP32, in one launch of the
+ * multi-lattice kernel.  Synchronises the stream. */
+dd_status dirac_apply_multi(dd_multi *m, void *const *out_dev, const void *const *in_dev);
+
+/* Solve D_k x_k = b_k on every lattice to the true FP64 relative residual tol:
+ * the mixed-precision solver of DD_SOLVE_MIXED (FP64 defect correction, FP32
+ * BiCGStab on A M_SAP with the FP16 SAP) run for all lattices in lockstep,
+ * each with its own scalars and exit, every A application of a step one
+ * multi-lattice launch.  x holds the initial guesses (zeros for a cold start).
+ * info (may be NULL) receives nlat records; returns the worst status.
+ * Synchronises the stream. */
+dd_status bicgstab_solve_multi(dd_multi *m, void *const *x_dev, const void *const *b_dev, double tol, int maxiter,
+                               dd_solve_info *info);
+
 /* ---- internal-layout entry points (benchmarks, no pack/unpack) ----------- */
 
 /* Bytes of one internal spinor field at precision prec (FP16 includes the
@@ -289,7 +325,9 @@ typedef enum {
     DD_KT_BLAS = 5,         /* vector updates and reductions                     */
     DD_KT_FORCE = 6,        /* fermion force (dd_force), FP64                    */
     DD_KT_DIRAC_MRHS = 7,   /* A on a batch of right-hand sides, matrix cores    */
-    DD_KT_COUNT = 8
+    DD_KT_DIRAC_MULTI = 8,  /* A on several lattices in one launch (timers of the
+                               first lattice's context)                          */
+    DD_KT_COUNT = 9
 } dd_kernel_class;
 
 /* When enabled, every launch of the timed classes is bracketed by HIP events

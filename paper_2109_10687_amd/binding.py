@@ -23,10 +23,10 @@ DD_F64, DD_F32, DD_F16 = 0, 1, 2
 DD_OP_D, DD_OP_A, DD_OP_DDAG = 0, 1, 2
 DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED, DD_SOLVE_MIXED_GCR = 0, 1, 2, 3
 (DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16IN, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS, DD_KT_FORCE,
- DD_KT_DIRAC_MRHS) = range(8)
+ DD_KT_DIRAC_MRHS, DD_KT_DIRAC_MULTI) = range(9)
 KERNEL_CLASSES = {"dirac_f64": DD_KT_DIRAC_F64, "dirac_f32": DD_KT_DIRAC_F32, "dirac_f16in": DD_KT_DIRAC_F16IN,
                   "dirac_f16": DD_KT_DIRAC_F16, "sap": DD_KT_SAP, "blas": DD_KT_BLAS, "force": DD_KT_FORCE,
-                  "dirac_mrhs": DD_KT_DIRAC_MRHS}
+                  "dirac_mrhs": DD_KT_DIRAC_MRHS, "dirac_multi": DD_KT_DIRAC_MULTI}
 DD_BATCH_INNER_SAP, DD_BATCH_INNER_PLAIN = 0, 1
 
 STATUS = {0: "DD_OK", 1: "DD_NOT_CONVERGED", 2: "DD_BREAKDOWN", -1: "DD_ERR_ARG", -2: "DD_ERR_GEOMETRY",
@@ -37,7 +37,8 @@ EXPORTS = ["dd_create", "dd_destroy", "dd_load_gauge", "dirac_apply", "sap_preco
            "dd_last_error", "dd_field_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dirac_apply_packed",
            "dd_timing_enable", "dd_timing_query", "bicgstab_solve_dagger", "dd_spinor_norm2", "dd_set_csw",
            "dd_force", "dirac_apply_batch", "dd_batch_set_variant", "dd_batch_tuning", "dd_batch_variant_name",
-           "bicgstab_solve_batch"]
+           "bicgstab_solve_batch", "dd_multi_create", "dd_multi_destroy", "dd_multi_last_error", "dd_multi_context",
+           "dd_multi_load_gauge", "dirac_apply_multi", "bicgstab_solve_multi"]
 
 
 class DDError(RuntimeError):
@@ -95,6 +96,13 @@ def lib():
             "dd_batch_tuning": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(d), i]),
             "dd_batch_variant_name": (ctypes.c_char_p, [i]),
             "bicgstab_solve_batch": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(_Info)]),
+            "dd_multi_create": (i, [ctypes.POINTER(_Params), i, vp, ctypes.POINTER(vp)]),
+            "dd_multi_destroy": (i, [vp]),
+            "dd_multi_last_error": (ctypes.c_char_p, [vp]),
+            "dd_multi_context": (vp, [vp, i]),
+            "dd_multi_load_gauge": (i, [vp, i, vp]),
+            "dirac_apply_multi": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+            "bicgstab_solve_multi": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), d, i, ctypes.POINTER(_Info)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -418,3 +426,74 @@ class Solver:
             n, ms, by, fl = dd_timing_query(self.ctx, cls)
             out[name] = {"launches": n, "ms": ms, "bytes": by, "flops": fl}
         return out
+
+
+class Multi:
+    """Several independent lattices whose FP32 operator runs in one persistent launch
+    (dd_multi_*): load a gauge field per lattice, apply A to all, or solve all in lockstep."""
+
+    def __init__(self, params_list, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        self.params = list(params_list)
+        self.shapes = [p.shape for p in self.params]
+        arr = (_Params * len(self.params))(*[p.c() for p in self.params])
+        out = ctypes.c_void_p()
+        st = lib().dd_multi_create(arr, len(self.params), h, ctypes.byref(out))
+        if st < 0:
+            raise DDError(st, "dd_multi_create failed")
+        self.m = out
+
+    def _check(self, st):
+        if st < 0:
+            raise DDError(st, lib().dd_multi_last_error(self.m).decode())
+        return st
+
+    def close(self):
+        if self.m:
+            lib().dd_multi_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def context(self, k):
+        return ctypes.c_void_p(lib().dd_multi_context(self.m, k))
+
+    def load_gauge(self, k, U):
+        self._check(lib().dd_multi_load_gauge(self.m, k, _c128(U, (4,) + self.shapes[k] + (3, 3), "gauge field")))
+
+    def _ptrs(self, ts, what):
+        return (ctypes.c_void_p * len(ts))(*[_c128(t, sh + (3, 4), what) for t, sh in zip(ts, self.shapes)])
+
+    def apply(self, xs):
+        """[A_k x_k] for every lattice, FP32, one launch."""
+        outs = [torch.empty_like(x) for x in xs]
+        self._check(lib().dirac_apply_multi(self.m, self._ptrs(outs, "out"), self._ptrs(xs, "in")))
+        return outs
+
+    def solve(self, bs, tol=1e-10, maxiter=50, x0=None):
+        xs = [torch.zeros_like(b) for b in bs] if x0 is None else [x.clone() for x in x0]
+        infos = (_Info * len(bs))()
+        st = self._check(lib().bicgstab_solve_multi(self.m, self._ptrs(xs, "x"), self._ptrs(bs, "b"), float(tol),
+                                                    int(maxiter), infos))
+        out = [{k: getattr(inf, k) for k, _ in _Info._fields_} for inf in infos]
+        for o in out:
+            o["status"] = STATUS[0] if o["relres_true"] < tol else STATUS[st]
+        return xs, out
+
+    def timing(self, on=True):
+        dd_timing_enable(self.context(0), on)
+
+    def timing_report(self):
+        """{class: {launches, ms, bytes, flops}} of lattice 0's context (it times the multi-lattice launches)."""
+        out = {}
+        for name, cls in KERNEL_CLASSES.items():
+            n, ms, by, fl = dd_timing_query(self.context(0), cls)
+            out[name] = {"launches": n, "ms": ms, "bytes": by, "flops": fl}
+        return out
+

@@ -196,20 +196,25 @@ __global__ void __launch_bounds__(64) k_clover(Geom g, const double2 *u64, Sigma
 
 // ============================================================ Dirac apply
 
+template <int P> DD_INL SpinorField<P> sf_at(void *p, const Geom &g);
+template <> DD_INL SpinorField<1> sf_at<1>(void *p, const Geom &) { return SpinorField<1>{(float2 *)p}; }
+template <> DD_INL SpinorField<2> sf_at<2>(void *p, const Geom &g)
+{
+    return SpinorField<2>{(__half2 *)p, (float *)((char *)p + 12 * g.V * sizeof(__half2))};
+}
+
 template <int PIN, int PG> struct Acc { using T = float; };
 template <int PG> struct Acc<0, PG> { using T = double; };
 template <> struct Acc<1, 0> { using T = double; };
 template <> struct Acc<2, 0> { using T = double; };
 
 // out = op(in) on the full lattice, one thread per site; op 0 = D, 1 = A, 2 = D^dagger
+// out(i) = op(in)(i) for one site i
 template <int PIN, int POUT, int PG, int OP>
-__global__ void __launch_bounds__(256) k_dirac(Geom g, SpinorField<POUT> out, SpinorField<PIN> in, LinkField<PG> U,
-                                               CloverField<PG> C, Phase4 ph, double kappa)
+DD_INL void dirac_site(const Geom &g, const SpinorField<POUT> &out, const SpinorField<PIN> &in, const LinkField<PG> &U,
+                       const CloverField<PG> &C, const Phase4 &ph, double kappa, long long i)
 {
     using R = typename Acc<PIN, PG>::T;
-    const int w = xcd_remap(blockIdx.x, gridDim.x);
-    const long long i = (long long)w * 256 + threadIdx.x;
-    if (i >= g.V) return;
     Site st;
     decode(g, i, st);
     Spinor<R> acc;
@@ -254,6 +259,45 @@ __global__ void __launch_bounds__(256) k_dirac(Geom g, SpinorField<POUT> out, Sp
         if (OP == 2) gamma5(o);
     }
     out.store(g, st.l, st.s, o, true);
+}
+
+template <int PIN, int POUT, int PG, int OP>
+__global__ void __launch_bounds__(256) k_dirac(Geom g, SpinorField<POUT> out, SpinorField<PIN> in, LinkField<PG> U,
+                                               CloverField<PG> C, Phase4 ph, double kappa)
+{
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const long long i = (long long)w * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    dirac_site<PIN, POUT, PG, OP>(g, out, in, U, C, ph, kappa, i);
+}
+
+// A = I - kappa C_inv H (FP32 links and C_inv, FP32 output, input at precision PIN) on
+// several lattices in one persistent launch: the work items are (lattice, 256-site
+// chunk) pairs numbered lattice by lattice; each workgroup takes the next item from
+// a global counter until none is left, so lattices of uneven size share the chip
+// without a launch (or an idle tail) per lattice.  Every workgroup leaves once the
+// counter passes the item count.
+template <int PIN>
+__global__ void __launch_bounds__(256) k_dirac_multi(const LatDesc *desc, int nlat, int total, int *counter)
+{
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= total) break;
+        int lat = 0;
+        while (lat + 1 < nlat && item >= desc[lat + 1].item0) ++lat;
+        const LatDesc &d = desc[lat];
+        const long long i = (long long)(item - d.item0) * 256 + threadIdx.x;
+        if (i < d.g.V) {
+            SpinorField<PIN> in = sf_at<PIN>((void *)d.in, d.g);
+            SpinorField<1> out{(float2 *)d.out};
+            dirac_site<PIN, 1, 1, 1>(d.g, out, in, LinkField<1>{(const float2 *)d.u},
+                                     CloverField<1>{(const float2 *)d.cinv}, d.phase, d.kappa, i);
+        }
+    }
 }
 
 // ============================================================ SAP half-sweep
@@ -825,6 +869,18 @@ hipError_t launch_dirac(const Geom &g, hipStream_t st, const DiracArgs &a)
         return hipErrorInvalidValue;
     }
 #undef DIRAC_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_dirac_multi(hipStream_t st, const LatDesc *desc_dev, int nlat, int total, int pin, int *counter)
+{
+    hipError_t e = hipMemsetAsync(counter, 0, sizeof(int), st);
+    if (e != hipSuccess) return e;
+    const int nwg = total < 2048 ? total : 2048;
+    if (pin == 2)
+        hipLaunchKernelGGL(k_dirac_multi<2>, dim3(nwg), dim3(256), 0, st, desc_dev, nlat, total, counter);
+    else
+        hipLaunchKernelGGL(k_dirac_multi<1>, dim3(nwg), dim3(256), 0, st, desc_dev, nlat, total, counter);
     return hipGetLastError();
 }
 

@@ -86,6 +86,19 @@ struct MrhsArgs {
     Phase4 phase;
 };
 
+// one lattice of a multi-lattice launch: A = I - kappa C_inv H with FP32 links and
+// C_inv, input at the launch's precision, FP32 output
+struct LatDesc {
+    Geom g;
+    const void *in;
+    void *out;
+    const void *u;     // FP32 links
+    const void *cinv;  // FP32 C_inv
+    Phase4 phase;
+    double kappa;
+    int item0;  // first work item (256-site chunk) of this lattice
+};
+
 struct ForceArgs {
     const void *psi, *chi;  // FP64 internal-layout spinors
     const void *u64;        // FP64 links
@@ -156,6 +169,10 @@ hipError_t launch_gcr_rupdate(const Geom &g, hipStream_t st, void *z, void *r, d
 // y (FP32) += sum_j coef_j p_j, p_j at precision pp (FP16 or FP32)
 hipError_t launch_multi_axpy(const Geom &g, hipStream_t st, const VecSet &ps, int k, int pp, void *y);
 hipError_t launch_finalize(hipStream_t st, const double *partials, int nwg, int nv, double *out);
+
+// A on several lattices in one persistent launch (work queue over (lattice, chunk)
+// items, desc_dev in device memory, counter: one device int, cleared here)
+hipError_t launch_dirac_multi(hipStream_t st, const LatDesc *desc_dev, int nlat, int total, int pin, int *counter);
 
 // multi right-hand-side A on the matrix cores; variant in [0, mrhs_variant_count())
 int mrhs_variant_count();

@@ -98,3 +98,64 @@ def test_solve_batch_point_sources_match_oracle(inner):
           f"{[i['iters_outer'] for i in infos]}, inner {[i['iters_inner_total'] for i in infos]}, "
           f"{infos[0]['seconds']:.2f} s")
     s2.close()
+
+
+# ---------------------------------------------------------------- several lattices in one launch
+
+# the uneven set of eight lattices (two each of 8^4, 12^4, 16^4, 16^3 x 32), each with its own
+# links, kappa and boundary phases; 12^4 takes 2^4 blocks (12 / 4 blocks per direction is odd)
+MULTI = [((8, 8, 8, 8), (4, 4, 4, 4), 0.125, 1.7, (1, 1, 1, -1)),
+         ((8, 8, 8, 8), (4, 4, 4, 4), 0.12, 1.5, (1, np.exp(0.4j), 1, -1)),
+         ((12, 12, 12, 12), (2, 2, 2, 2), 0.125, 1.7, (1, 1, 1, -1)),
+         ((12, 12, 12, 12), (2, 2, 2, 2), 0.122, 1.0, (-1, 1, 1, np.exp(0.2j))),
+         ((16, 16, 16, 16), (4, 4, 4, 4), 0.125, 1.7, (1, 1, 1, -1)),
+         ((16, 16, 16, 16), (4, 4, 4, 4), 0.12, 1.7, (1, 1, np.exp(-0.3j), -1)),
+         ((16, 16, 16, 32), (4, 4, 4, 4), 0.125, 1.7, (1, 1, 1, -1)),
+         ((16, 16, 16, 32), (4, 4, 4, 4), 0.124, 1.3, (1, 1, 1, -1))]
+
+
+def multi_setup():
+    if "multi" not in _cache:
+        ops, gps, Us = [], [], []
+        for k, (dims, block, kappa, csw, phases) in enumerate(MULTI):
+            ops.append(O.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases))
+            gps.append(dd.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases))
+            Us.append(synth.su3_links(dims, 0.3, 400 + k))
+        m = dd.Multi(gps)
+        for k, U in enumerate(Us):
+            m.load_gauge(k, U.cuda())
+        _cache["multi"] = (ops, gps, Us, m)
+    return _cache["multi"]
+
+
+def test_apply_multi_matches_oracle():
+    ops, gps, Us, m = multi_setup()
+    xs = [synth.gaussian_spinor(p.dims, 410 + k) for k, p in enumerate(ops)]
+    outs = m.apply([x.cuda() for x in xs])
+    for k, (p, U, x, o) in enumerate(zip(ops, Us, xs, outs)):
+        want = O.dirac_A(p, U.numpy(), O.clover_inverse(p, O.clover_field(p, U.numpy())), x.numpy())
+        assert rel_l2(o.cpu().numpy(), want) < 1e-6, k
+    # the one-launch result equals the lattice's own FP32 apply to rounding
+    s = dd.Solver(gps[2], Us[2].cuda())
+    one = s.apply(xs[2].cuda(), op=dd.DD_OP_A, prec=dd.DD_F32)
+    assert rel_l2(outs[2].cpu().numpy(), one.cpu().numpy()) < 1e-6
+    s.close()
+
+
+def test_solve_multi_matches_oracle():
+    ops, gps, Us, m = multi_setup()
+    bs = [synth.gaussian_spinor(p.dims, 420 + k) for k, p in enumerate(ops)]
+    xs, infos = m.solve([b.cuda() for b in bs], tol=1e-10)
+    for k, (p, U, b, x, inf) in enumerate(zip(ops, Us, bs, xs, infos)):
+        assert inf["status"] == "DD_OK" and inf["relres_true"] < 1e-10, (k, inf)
+        orc = O.Oracle(p, U.numpy())
+        xn = x.cpu().numpy()
+        # the oracle's residual of the GPU solution on every lattice
+        res = np.linalg.norm(orc.D(xn) - b.numpy()) / np.linalg.norm(b.numpy())
+        assert res < 1e-10, (k, res)
+        if p.volume <= 12 ** 4:  # the oracle's own solve where it takes seconds
+            ref = orc.solve(b.numpy(), tol=1e-12)
+            assert ref.status == 0
+            assert rel_l2(xn, ref.x) < 1e-8, k
+    print("multi-lattice solve: outer", [i["iters_outer"] for i in infos], "inner",
+          [i["iters_inner_total"] for i in infos], f"{infos[0]['seconds']:.2f} s")
