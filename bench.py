@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--batch-dims", default="32,32,32,64",
                     help="lattice of the batched leg (12 spin-colour point sources); 'off' skips it")
     ap.add_argument("--only-batch", action="store_true", help="run the batched leg only (profiling runs)")
+    ap.add_argument("--multi", choices=["on", "off"], default="on",
+                    help="the multi-lattice leg: 8^4, 12^4, 16^4, 16^3x32, two each, in one launch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of 4 GiB five times (scale for HBM byte counters) and exit")
     return ap.parse_args()
@@ -249,6 +251,76 @@ def batch_bench(dd, args, reps=10):
     return out
 
 
+MULTI_SET = [((8, 8, 8, 8), (4, 4, 4, 4)), ((12, 12, 12, 12), (2, 2, 2, 2)), ((16, 16, 16, 16), (4, 4, 4, 4)),
+             ((16, 16, 16, 32), (4, 4, 4, 4))]
+
+
+def multi_bench(dd, args, reps=20):
+    """The multi-lattice leg: eight independent lattices (two each of MULTI_SET, own links),
+    A on all of them in one persistent launch against one launch per lattice, and the lockstep
+    mixed-precision solve of all eight against eight solves one after another."""
+    import torch
+    import synth
+    params, Us = [], []
+    for k in range(8):
+        dims, block = MULTI_SET[k // 2]
+        params.append(dd.Params(dims=dims, kappa=args.kappa, csw=args.csw, block=block, n_sap=args.n_sap,
+                                n_jac=args.n_jac, inner_tol=args.inner_tol, sap_fp16_arith=args.sap_fp16_arith))
+        Us.append(synth.su3_links(dims, args.eps, args.seed + 20 + k, device="cuda"))
+    m = dd.Multi(params)
+    singles = [dd.Solver(p, U) for p, U in zip(params, Us)]
+    for k, U in enumerate(Us):
+        m.load_gauge(k, U)
+    bs = [synth.gaussian_spinor(p.dims, args.seed + 40 + k, device="cuda") for k, p in enumerate(params)]
+    V = sum(math.prod(p.dims) for p in params)
+    m.apply(bs)
+    m.timing(True)
+    for _ in range(reps):
+        m.apply(bs)
+    r = m.timing_report()["dirac_multi"]
+    m.timing(False)
+    # one launch per lattice, internal layout, the same FP32 operator
+    fins = [s.pack(b, dd.DD_F32) for s, b in zip(singles, bs)]
+    fouts = [s.field(dd.DD_F32) for s in singles]
+    for s, fi, fo in zip(singles, fins, fouts):
+        s.apply_packed(fo, fi, op=dd.DD_OP_A, prec=dd.DD_F32)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        for s, fi, fo in zip(singles, fins, fouts):
+            s.apply_packed(fo, fi, op=dd.DD_OP_A, prec=dd.DD_F32)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_seq = ev0.elapsed_time(ev1) / reps
+    ms_multi = r["ms"] / r["launches"]
+    out = {"workload": "8 lattices: 8^4, 12^4, 16^4, 16^3x32, two each", "sites": V,
+           "apply": {"one_launch_ms": round(ms_multi, 4), "eight_launches_ms": round(ms_seq, 4),
+                     "one_launch_GBps": round(r["bytes"] / r["ms"] / 1e6, 1),
+                     "speedup": round(ms_seq / ms_multi, 2)}}
+    del fins, fouts
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, infos = m.solve(bs, tol=args.tol)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    seq = [s.solve(b, tol=args.tol, mode=dd.DD_SOLVE_MIXED)[1] for s, b in zip(singles, bs)]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out["solve"] = {"lockstep_seconds": round(tm, 4), "sequential_seconds": round(ts, 4),
+                    "lockstep_status": sorted({i["status"] for i in infos}),
+                    "lockstep_max_relres_true": max(i["relres_true"] for i in infos),
+                    "sequential_status": sorted({i["status"] for i in seq})}
+    for s in singles:
+        s.close()
+    m.close()
+    del Us, bs, xs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle's D apply on a 32^4 sample of the workload (same kappa,
     c_SW and link recipe), on the host cores; reported in the metric's unit
@@ -318,6 +390,14 @@ def main():
         if args.only_batch:
             print(json.dumps({"batch": batch}))
             return
+
+    multi = None
+    if args.multi == "on" and not args.only_apply:
+        log("multi-lattice leg")
+        multi = multi_bench(dd, args)
+        log(f"multi-lattice A: {multi['apply']['one_launch_ms']:.3f} ms in one launch vs "
+            f"{multi['apply']['eight_launches_ms']:.3f} ms in eight; lockstep solve {multi['solve']['lockstep_seconds']:.3f} s "
+            f"vs {multi['solve']['sequential_seconds']:.3f} s")
 
     dims = tuple(int(v) for v in args.dims.split(","))
     block = tuple(int(v) for v in args.block.split(","))
@@ -435,6 +515,8 @@ def main():
         result["force"] = force
     if batch is not None:
         result["batch"] = batch
+    if multi is not None:
+        result["multi"] = multi
 
     # ---- plain FP64 BiCGStab on the same system (speedup denominator), once
     if args.fp64 == "on":
