@@ -261,6 +261,9 @@ DD_INL void inblock_pair(const uint4 *xs, const h2 *ul, const Geom &g, const Sit
     }
 }
 
+// log2 of the block extent in direction nu
+DD_INL int log2b(const Geom &g, int nu) { return (nu < 3 ? g.sh[nu + 1] : g.lbvol) - g.sh[nu]; }
+
 // One half-sweep with FP16 arithmetic in the block-local part; same flags and
 // result (up to FP16 rounding) as k_sap_half<2>.
 __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int flags, SpinorField<2> bsrc,
@@ -281,8 +284,109 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int fla
     for (int mu = 0; mu < 4; ++mu) st.c[mu] = (st.s >> g.sh[mu]) & (g.b[mu] - 1);
     block_coords(g, st.l, st.B);
 
-    // stage the block's links as full 3x3 FP16 matrices
     const LinkField<2> U16{u16};
+    Clov<float> cl;
+    Ci.load(g, st.l, st.s, cl);
+
+    Spinor<float> src;
+    if (flags & SAP_FIRST)
+        bsrc.load(g, st.l, st.s, src);
+    else
+        sw.load(g, st.l, st.s, src);
+
+    if (flags & SAP_PRE) {  // s_c += kappa C_inv (cross-block hops of x_{c'}), FP32
+        // Each (direction, side, face site) hop once, spread evenly over the workgroup: a
+        // per-site loop would run all eight hop bodies in every wavefront with most lanes
+        // idle.  The hops' half spinors are parked in LDS (the link staging area, not in
+        // use yet) and summed per site afterwards.
+        float2 *fb = reinterpret_cast<float2 *>(ul);  // [6][P] complex
+        int off[9];
+        off[0] = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) off[q + 1] = off[q] + bvol / g.b[q >> 1];
+        const int P = off[8];
+        for (int p = threadIdx.x; p < P; p += bvol) {
+            int q = 0;
+            while (q < 7 && p >= off[q + 1]) ++q;
+            const int mu = q >> 1, dir = (q & 1) ? -1 : 1;
+            int kk = p - off[q];
+            Site fs;
+            fs.l = st.l;
+            fs.s = 0;
+#pragma unroll
+            for (int nu = 0; nu < 4; ++nu) {
+                fs.B[nu] = st.B[nu];
+                if (nu == mu) {
+                    fs.c[nu] = dir > 0 ? g.b[nu] - 1 : 0;
+                } else {
+                    fs.c[nu] = kk & (g.b[nu] - 1);
+                    kk >>= log2b(g, nu);
+                }
+                fs.s += fs.c[nu] << g.sh[nu];
+            }
+            bool wrap, inblk;
+            const long long j = neighbour(g, fs, mu, dir, wrap, inblk);
+            const int lj = (int)(j >> g.lbvol), sj = (int)(j & (bvol - 1));
+            Spinor<float> psi;
+            xw.load(g, lj, sj, psi);
+            Mat3<float> W;
+            if (dir > 0)
+                U16.load(g, st.l, fs.s, mu, W);
+            else
+                U16.load(g, lj, sj, mu, W);
+            Half<float> h, k;
+            project(mu, dir, psi, h);
+            mat_half(W, dir < 0, h, k);
+            if (wrap) {
+                const cx<float> phase = {(float)ph.re[mu], (float)(dir > 0 ? ph.im[mu] : -ph.im[mu])};
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) k.v[a][c] = k.v[a][c] * phase;
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) fb[(a * 3 + c) * P + p] = make_float2(k.v[a][c].re, k.v[a][c].im);
+        }
+        __syncthreads();
+        Spinor<float> acc, t;
+        zero(acc);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+            for (int dir = 1; dir >= -1; dir -= 2) {
+                const int c = st.c[mu] + dir;
+                if (c >= 0 && c < g.b[mu]) continue;
+                // index of this site on the face: the other three coordinates in order
+                int kk = 0, w8 = 0;
+#pragma unroll
+                for (int nu = 0; nu < 4; ++nu) {
+                    if (nu == mu) continue;
+                    kk += st.c[nu] << w8;
+                    w8 += log2b(g, nu);
+                }
+                const int p = off[2 * mu + (dir > 0 ? 0 : 1)] + kk;
+                Half<float> k;
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const float2 v = fb[(a * 3 + cc) * P + p];
+                        k.v[a][cc] = {v.x, v.y};
+                    }
+                reconstruct(mu, dir, k, acc);
+            }
+        }
+        clover_mul(cl, acc, t);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) src.v[a][c] = src.v[a][c] + kappa * t.v[a][c];
+        __syncthreads();  // the face buffer is about to become the link staging area
+    }
+
+    // stage the block's links as full 3x3 FP16 matrices
     for (int mu = 0; mu < 4; ++mu) {
         Mat3<float> U;
         U16.load(g, st.l, st.s, mu, U);
@@ -293,47 +397,7 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int fla
     }
 
     ClovPair CP;
-    {
-        Clov<float> cl;
-        Ci.load(g, st.l, st.s, cl);
-        clov_pairs(cl, CP);
-    }
-
-    Spinor<float> src;
-    if (flags & SAP_FIRST)
-        bsrc.load(g, st.l, st.s, src);
-    else
-        sw.load(g, st.l, st.s, src);
-
-    if (flags & SAP_PRE) {  // s_c += kappa C_inv (cross-block hops of x_{c'}), FP32
-        Spinor<float> acc, t;
-        zero(acc);
-        for (int mu = 0; mu < 4; ++mu) {
-            for (int dir = 1; dir >= -1; dir -= 2) {
-                const int c = st.c[mu] + dir;
-                if (c >= 0 && c < g.b[mu]) continue;
-                bool wrap, inblk;
-                const long long j = neighbour(g, st, mu, dir, wrap, inblk);
-                const int lj = (int)(j >> g.lbvol), sj = (int)(j & (bvol - 1));
-                Spinor<float> psi;
-                xw.load(g, lj, sj, psi);
-                Mat3<float> W;
-                if (dir > 0)
-                    U16.load(g, st.l, st.s, mu, W);
-                else
-                    U16.load(g, lj, sj, mu, W);
-                const cx<float> phase = {(float)ph.re[mu], (float)(dir > 0 ? ph.im[mu] : -ph.im[mu])};
-                hop(mu, dir, W, psi, wrap, phase, acc);
-            }
-        }
-        Clov<float> cl;
-        Ci.load(g, st.l, st.s, cl);
-        clover_mul(cl, acc, t);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) src.v[a][c] = src.v[a][c] + kappa * t.v[a][c];
-    }
+    clov_pairs(cl, CP);
 
     // block normalisation: scale the source to max |component| = 1
     float m = 0.f;
@@ -389,7 +453,15 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int fla
     xw.store(g, st.l, st.s, xf);
 }
 
-size_t sap_pk_lds_bytes(const Geom &g) { return (size_t)g.bvol * (3 * sizeof(uint4) + 36 * sizeof(__half2)); }
+size_t sap_pk_lds_bytes(const Geom &g)
+{
+    // the Jacobi iterate, then the larger of the link staging area and the face buffer of
+    // the cross-block prologue (6 FP32 complex per face hop)
+    size_t faces = 0;
+    for (int mu = 0; mu < 4; ++mu) faces += 2 * (size_t)(g.bvol / g.b[mu]);
+    const size_t links = (size_t)g.bvol * 36 * sizeof(__half2), fbuf = faces * 6 * sizeof(float2);
+    return (size_t)g.bvol * 3 * sizeof(uint4) + (links > fbuf ? links : fbuf);
+}
 
 hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags)
 {
