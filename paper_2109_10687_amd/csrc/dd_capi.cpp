@@ -1763,7 +1763,7 @@ dd_status dd_multi_create(const dd_params *params, int nlat, void *hip_stream, d
 dd_status dd_multi_destroy(dd_multi *m)
 {
     if (!m) return DD_OK;
-    (void)hipStreamSynchronize(m->stream);
+    if (!m->L.empty()) (void)hipStreamSynchronize(m->stream);  // no device call when nothing was created
     for (dd_ctx *c : m->L) dd_destroy(c);
     if (m->counter) (void)hipFree(m->counter);
     if (m->desc_dev) (void)hipFree(m->desc_dev);

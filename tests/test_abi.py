@@ -64,3 +64,44 @@ def test_create_rejects_bad_gcr_cycle_without_gpu():
         assert e.status == -1
     else:
         raise AssertionError("expected DD_ERR_ARG")
+
+
+def test_new_entry_points_reject_null_handles_without_gpu():
+    L = dd.lib()
+    vp = ctypes.c_void_p
+    null = vp(0)
+    d = ctypes.c_double(0)
+    info = dd.binding._Info()
+    assert L.dirac_apply_batch(null, null, null, 12, dd.DD_F32, dd.DD_OP_A) == -1
+    assert L.bicgstab_solve_batch(null, null, null, 12, 1e-10, 10, 0, ctypes.byref(info)) == -1
+    assert L.bicgstab_solve_dagger(null, null, null, 1e-10, 10, dd.DD_SOLVE_MIXED, ctypes.byref(info)) == -1
+    assert L.dd_force(null, null, ctypes.byref(d), null, null, 0) == -1
+    assert L.dd_spinor_norm2(null, null, ctypes.byref(d)) == -1
+    assert L.dd_set_csw(null, 1.0) == -1
+    assert L.dd_batch_set_variant(null, 0) == -1
+    assert L.dd_batch_tuning(null, 12, None, None, 0) == -1
+    assert L.dirac_apply_multi(null, None, None) == -1
+    assert L.bicgstab_solve_multi(null, None, None, 1e-10, 10, None) == -1
+    assert L.dd_multi_load_gauge(null, 0, null) == -1
+    assert L.dd_multi_context(null, 0) is None
+    assert L.dd_multi_last_error(null) == b"null handle"
+    assert L.dd_destroy(null) == 0 and L.dd_multi_destroy(null) == 0
+
+
+def test_batch_variant_names():
+    names = [dd.dd_batch_variant_name(v) for v in range(9)]
+    assert all(n and n != "?" for n in names) and len(set(names)) == 9
+    assert any("mfma" in n for n in names) and any("vector" in n for n in names)
+    assert dd.dd_batch_variant_name(-1) == "?" and dd.dd_batch_variant_name(9) == "?"
+
+
+def test_multi_create_checks_every_lattice_without_gpu():
+    ok = dd.Params(dims=(8, 8, 8, 8), kappa=0.12, csw=1.0, block=(4, 4, 4, 4))
+    bad = dd.Params(dims=(8, 8, 8, 6), kappa=0.12, csw=1.0, block=(4, 4, 4, 4))
+    L = dd.lib()
+    out = ctypes.c_void_p()
+    arr = (dd.binding._Params * 1)(bad.c())
+    assert L.dd_multi_create(arr, 1, None, ctypes.byref(out)) == -2 and not out.value
+    assert L.dd_multi_create(arr, 0, None, ctypes.byref(out)) == -1
+    arr2 = (dd.binding._Params * 2)(bad.c(), ok.c())
+    assert L.dd_multi_create(arr2, 2, None, ctypes.byref(out)) == -2 and not out.value
