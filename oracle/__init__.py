@@ -63,6 +63,7 @@ def lib():
             "orc_bicgstab": (i, [P, vp, vp, vp, i, vp, vp, d, i, pi, pd]),
             "orc_dci": (i, [P, vp, vp, vp, vp, vp, d, d, i, i, i, i, pi, pi, pd]),
             "orc_force": (None, [P, vp, vp, vp, vp]),
+            "orc_dirac_A_sites": (i, [P, vp, vp, vp, lg, vp]),
             "orc_dcsw": (d, [P, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
@@ -192,6 +193,19 @@ def dirac_D_sites(p, U, x, sites):
     y = np.zeros((len(sites), 3, 4), dtype=np.complex128)
     cp = p.c()
     lib().orc_dirac_D_sites(ctypes.byref(cp), _ptr(U), _ptr(x), _ptr(sites), len(sites), _ptr(y))
+    return y
+
+
+def dirac_A_sites(p, U, x, sites):
+    """(A x)(n) = x(n) - kappa C_inv(n) (H x)(n) at the listed lexicographic sites (Sec. 3), with
+    the clover and its inverse built on the fly; shape (len(sites), 3, 4)."""
+    U, x = _c128(U), _c128(x)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    y = np.zeros((len(sites), 3, 4), dtype=np.complex128)
+    cp = p.c()
+    bad = lib().orc_dirac_A_sites(ctypes.byref(cp), _ptr(U), _ptr(x), _ptr(sites), len(sites), _ptr(y))
+    if bad:
+        raise ValueError(f"1 + C singular at {bad} listed sites")
     return y
 
 

@@ -451,6 +451,27 @@ void orc_dirac_D_sites(const orc_params *p, const cplx *U, const cplx *x, const 
     }
 }
 
+/* (A x)(n) = x(n) - kappa C_inv(n) (H x)(n) at a list of sites (Sec. 3), the clover
+ * of each listed site built on the fly and inverted there (Gauss-Jordan, as
+ * orc_clover_inverse); returns the number of sites where 1 + C was singular. */
+int orc_dirac_A_sites(const orc_params *p, const cplx *U, const cplx *x, const long *sites, long ns, cplx *y)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) if (ns >= 64) reduction(+ : bad)
+    for (long k = 0; k < ns; ++k) {
+        long n = sites[k];
+        cplx C[144], Ci[144], hx[12], t[12];
+        clover_site(p, U, n, C);
+        for (int i = 0; i < 12; ++i) C[i * 12 + i] += 1.0;
+        if (invert12(C, Ci)) ++bad;
+        for (int i = 0; i < 12; ++i) hx[i] = 0;
+        hop_site(p, U, x, n, PART_ALL, 1.0, hx);
+        mat12_vec(Ci, hx, t);
+        for (int i = 0; i < 12; ++i) y[k * 12 + i] = x[n * 12 + i] - p->kappa * t[i];
+    }
+    return bad;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Schwarz block pieces of A (Sec. 3, 2x2 block form):
  *   part IN : y(n) = x(n) - kappa C_inv(n) sum_{hops inside n's block} ...   = (A_cc x)(n)

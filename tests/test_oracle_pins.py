@@ -291,6 +291,14 @@ def test_D_sites_matches_full(cfg1):
     np.testing.assert_allclose(got, full[sites], atol=1e-14)
 
 
+def test_A_sites_matches_full(cfg1):
+    x = synth.gaussian_spinor(cfg1.p.dims, 5).numpy()
+    full = cfg1.A(x).reshape(-1, 3, 4)
+    sites = np.array([0, 1, 17, 128, 200, 255])
+    got = O.dirac_A_sites(cfg1.p, cfg1.U, x, sites)
+    np.testing.assert_allclose(got, full[sites], atol=1e-13)
+
+
 def test_block_pieces_are_blocks_of_A(cfg1, dense_cfg1):
     """A_EE, A_OO keep in-block hops, A_EO, A_OE cross-block hops: they are the
     four blocks of A in the E/O ordering (Sec. 3), and A_EE never couples
