@@ -89,3 +89,57 @@ def test_full_size_mixed_solve(full):
     rel = np.linalg.norm(r) / np.linalg.norm(bs)
     print(f"oracle residual on {len(sites)} sampled sites: {rel:.2e}")
     assert rel < 1e-8
+
+
+def lattice_samples(dims, n_random=40, seed=11):
+    Lx, Ly, Lz, Lt = dims
+    pts = {(0, 0, 0, 0), (Lx - 1, Ly - 1, Lz - 1, Lt - 1), (Lx - 1, 0, Lz - 1, 0), (0, Ly - 1, 0, Lt - 1)}
+    rng = np.random.default_rng(seed)
+    for _ in range(n_random):
+        pts.add(tuple(int(rng.integers(L)) for L in dims))
+    return np.array(sorted(x + Lx * (y + Ly * (z + Lz * t)) for x, y, z, t in pts), dtype=np.int64)
+
+
+def test_32x32x32x32_fp32_sap_solve_at_kappa_0_1365():
+    """The 32^4 configuration: FP32 SAP-preconditioned BiCGStab (4^4 blocks, N_JAC = 4, N_SAP = 4)
+    at kappa 0.1365, c_SW 1.7, to the single-precision tolerance 1e-6 of Alg. 5."""
+    dims = (32, 32, 32, 32)
+    U = synth.su3_links(dims, 0.3, 33, device="cuda")
+    b = synth.gaussian_spinor(dims, 34, device="cuda")
+    gp = dd.Params(dims=dims, kappa=0.1365, csw=1.7, block=(4, 4, 4, 4), n_sap=4, n_jac=4)
+    op = O.Params(dims=dims, kappa=0.1365, csw=1.7, block=(4, 4, 4, 4))
+    s = dd.Solver(gp, U)
+    x, info = s.solve(b, tol=1e-6, maxiter=2000, mode=dd.DD_SOLVE_F32_SAP)
+    print(f"32^4 FP32 SAP solve at kappa 0.1365: {info}")
+    assert info["status"] == "DD_OK" and info["relres_inner_last"] < 1e-6
+    sites = lattice_samples(dims)
+    idx = torch.from_numpy(sites).cuda()
+    bs = b.reshape(-1, 3, 4)[idx].cpu().numpy()
+    r = bs - O.dirac_D_sites(op, U.cpu().numpy(), x.cpu().numpy(), sites)
+    rel = np.linalg.norm(r) / np.linalg.norm(bs)
+    print(f"true residual {info['relres_true']:.2e}; oracle residual on {len(sites)} sampled sites {rel:.2e}")
+    assert info["relres_true"] < 1e-5 and rel < 1e-5
+    s.close()
+
+
+def test_32x32x32x64_twelve_point_sources_batched():
+    """The batched configuration: the 12 spin-colour point sources at the origin on 32^3 x 64 in one
+    batched solve to 1e-10; the oracle's residual on sampled sites for every right-hand side."""
+    dims = (32, 32, 32, 64)
+    U = synth.su3_links(dims, 0.3, 2021 + 11, device="cuda")
+    gp = dd.Params(dims=dims, kappa=0.133, csw=1.7, block=(4, 4, 4, 4), n_sap=4, n_jac=4)
+    op = O.Params(dims=dims, kappa=0.133, csw=1.7, block=(4, 4, 4, 4))
+    s = dd.Solver(gp, U)
+    bs = torch.stack([synth.point_source(dims, c, sp, device="cuda") for c in range(3) for sp in range(4)])
+    x, infos = s.solve_batch(bs, tol=1e-10)
+    assert all(i["status"] == "DD_OK" and i["relres_true"] < 1e-10 for i in infos), infos
+    sites = np.concatenate([[0], lattice_samples(dims, n_random=24)])
+    idx = torch.from_numpy(sites).cuda()
+    Uh = U.cpu().numpy()
+    for r in range(12):
+        bsr = bs[r].reshape(-1, 3, 4)[idx].cpu().numpy()
+        res = bsr - O.dirac_D_sites(op, Uh, x[r].cpu().numpy(), sites)
+        assert np.linalg.norm(res) < 1e-9 * np.linalg.norm(bs[r].cpu().numpy()), r
+    print("32^3x64 batched point sources: outer", [i["iters_outer"] for i in infos], "inner",
+          [i["iters_inner_total"] for i in infos])
+    s.close()
