@@ -46,6 +46,12 @@
 #ifndef DDSOLVE_H
 #define DDSOLVE_H
 
+/* the library is built with hidden visibility; the declarations below are its
+ * only exported symbols */
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility push(default)
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -345,6 +351,10 @@ dd_status dd_timing_query(dd_ctx *ctx, dd_kernel_class cls, long long *launches,
 
 #ifdef __cplusplus
 }
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility pop
 #endif
 
 #endif /* DDSOLVE_H */

@@ -11,11 +11,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddsolve.so")
-SOURCES = ["dd_kernels.hip", "dd_sap_fp16.hip", "dd_force.hip", "dd_mrhs.hip", "dd_capi.cpp"]
+SOURCES = ["dd_kernels.hip", "dd_sap_fp16.hip", "dd_force.hip", "dd_mrhs.hip",
+           "dd_ops.cpp", "dd_solvers.cpp", "dd_batch.cpp", "dd_capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
+         "-Wall", "-Wno-unused-function", "-Xarch_host", "-fvisibility=hidden", "-I", os.path.join(HERE, "..", "include")]
 
 
 def _run(cmd, verbose):

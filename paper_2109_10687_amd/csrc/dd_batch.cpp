@@ -1,0 +1,867 @@
+// dd_batch.cpp -- batched right-hand sides (one launch of the multi-RHS A for
+// all of them, each with its own BiCGStab scalars) and several lattices in one
+// work-queue launch: the internals and their C entry points.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+
+#include "dd_host.h"
+
+using namespace ddh;
+
+namespace ddh {
+
+dd_status batch_alloc(dd_ctx *c, int n)
+{
+    if (n <= c->bcap) return DD_OK;
+    for (void *p : c->bk)
+        if (p) (void)hipFree(p);
+    c->bk.assign(BK_COUNT, nullptr);
+    c->bcap = 0;
+    for (int k = 0; k < BK_COUNT; ++k)
+        if (hipMalloc(&c->bk[k], (size_t)n * spinor_bytes(c->g, bk_prec(k))) != hipSuccess) {
+            (void)hipGetLastError();
+            for (void *&p : c->bk)
+                if (p) {
+                    (void)hipFree(p);
+                    p = nullptr;
+                }
+            return fail(c, DD_ERR_NOMEM, "batch work fields");
+        }
+    c->bcap = n;
+    return DD_OK;
+}
+
+// field r of kind k
+void *bf(dd_ctx *c, int k, int r) { return (char *)c->bk[k] + (size_t)r * spinor_bytes(c->g, bk_prec(k)); }
+
+// run a reducing vector kernel on right-hand side r and leave its nv sums at red[off..]
+dd_status reduce_to(dd_ctx *c, dd::BlasArgs a, int nv, int off)
+{
+    dd_status st = blas(c, a);
+    if (st != DD_OK) return st;
+    HIPCK(c, dd::launch_finalize(c->stream, c->partials, dd::blas_grid(c->g), nv, c->red + off));
+    return DD_OK;
+}
+
+dd_status fetch_red(dd_ctx *c, int n, double *out)
+{
+    HIPCK(c, hipMemcpyAsync(c->red_host, c->red, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n; ++k) out[k] = c->red_host[k];
+    return DD_OK;
+}
+
+// out = A in for n FP32 batched fields (internal layout, contiguous), tiles of up to 12 on the
+// matrix cores; the variant is the caller's, or the autotuner's choice for this tile size
+dd_status mrhs_launch(dd_ctx *c, int v, void *out, const void *in, int n)
+{
+    dd::MrhsArgs a{};
+    a.in = (const float2 *)in;
+    a.out = (float2 *)out;
+    a.u = (const float2 *)c->U32;
+    a.cinv = (const float2 *)c->cinv32;
+    a.nrhs = n;
+    a.kappa = c->prm.kappa;
+    a.phase = c->phase;
+    const double V = (double)c->g.V;
+    const double bytes = V * (n * 2.0 * sp_b(DD_F32) + 4 * lk_b(DD_F32) + cl_b(DD_F32));
+    const double flops = V * n * (hops_in(c->g) + hops_out(c->g) + CLOVF);
+    hipError_t e = timed(c, DD_KT_DIRAC_MRHS, bytes, flops, [&] { return dd::launch_dirac_mrhs(c->g, c->stream, a, v); });
+    if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("multi-RHS dirac launch: ") + hipGetErrorString(e));
+    return DD_OK;
+}
+
+// time every variant on this tile (two warm-up launches, three timed) and keep the fastest
+dd_status mrhs_tune(dd_ctx *c, int n, void *out, const void *in)
+{
+    const int nv = dd::mrhs_variant_count();
+    hipEvent_t e0, e1;
+    HIPCK(c, hipEventCreate(&e0));
+    HIPCK(c, hipEventCreate(&e1));
+    const bool timing = c->timing;
+    c->timing = false;
+    int best = 0;
+    for (int v = 0; v < nv; ++v) {
+        dd_status st;
+        for (int k = 0; k < 2; ++k)
+            if ((st = mrhs_launch(c, v, out, in, n)) != DD_OK) return st;
+        HIPCK(c, hipEventRecord(e0, c->stream));
+        for (int k = 0; k < 3; ++k)
+            if ((st = mrhs_launch(c, v, out, in, n)) != DD_OK) return st;
+        HIPCK(c, hipEventRecord(e1, c->stream));
+        HIPCK(c, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCK(c, hipEventElapsedTime(&ms, e0, e1));
+        c->mrhs_ms[n][v] = ms / 3.0;
+        if (c->mrhs_ms[n][v] < c->mrhs_ms[n][best]) best = v;
+    }
+    c->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->mrhs_tuned[n] = best;
+    return DD_OK;
+}
+
+dd_status k_dirac_mrhs(dd_ctx *c, void *out, const void *in, int n)
+{
+    const size_t fb = spinor_bytes(c->g, DD_F32);
+    for (int r0 = 0; r0 < n; r0 += 12) {
+        const int m = n - r0 < 12 ? n - r0 : 12;
+        void *o = (char *)out + r0 * fb;
+        const void *i = (const char *)in + r0 * fb;
+        int v = c->mrhs_force;
+        if (v < 0) {
+            if (c->mrhs_tuned[m] < 0) {
+                dd_status st = mrhs_tune(c, m, o, i);
+                if (st != DD_OK) return st;
+            }
+            v = c->mrhs_tuned[m];
+        }
+        dd_status st = mrhs_launch(c, v, o, i, m);
+        if (st != DD_OK) return st;
+    }
+    return DD_OK;
+}
+
+
+
+// FP32 BiCGStab for n right-hand sides in lockstep (Alg. 5 per right-hand side, each with
+// its own scalars and exit), on A M with M = the FP16-storage SAP of each right-hand side
+// (sap) or M = I; every A application is one batched launch over all n.  Sources: BK_SRC, solutions:
+// BK_Y (flexible accumulation as in the single right-hand-side solver).
+dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int maxiter)
+{
+    const size_t f32 = spinor_bytes(c->g, DD_F32);
+    dd_status st;
+    HIPCK(c, hipMemsetAsync(c->bk[BK_Y], 0, n * f32, c->stream));
+    for (int r = 0; r < n; ++r)
+        if ((st = reduce_to(c, mkb(dd::BLAS_NORM2, {bf(c, BK_SRC, r)}, {1}), 1, r)) != DD_OK) return st;
+    double red[3 * BATCH_MAX];
+    if ((st = fetch_red(c, n, red)) != DD_OK) return st;
+    int nact = 0;
+    for (int r = 0; r < n; ++r) {
+        BRhs &b = R[r];
+        b.o = SolveOut{};
+        b.bn2 = b.rn2 = red[r];
+        b.rho0 = red[r];
+        b.st = DD_OK;
+        if (!is_fin(red[r])) return fail(c, DD_ERR_NONFINITE, "inner source holds NaN or Inf");
+        b.active = red[r] > 0.0;
+        nact += b.active;
+        if (!b.active) continue;
+        for (int k : {BK_R, BK_P, BK_RT})
+            if ((st = copy(c, bf(c, k, r), 1, bf(c, BK_SRC, r), 1)) != DD_OK) return st;
+    }
+    const int mp = sap ? BK_MP : BK_P, mr = sap ? BK_MR : BK_R;
+    // M = the FP16-storage SAP of each right-hand side (as in the single right-hand-side
+    // mixed solver), its output widened to FP32 for the batched A
+    auto precond = [&](int from, int to) -> dd_status {
+        if (!sap) return DD_OK;
+        void *in16 = c->f16[0], *out16 = c->f16[2], *s16 = c->f16[4];
+        for (int r = 0; r < n; ++r) {
+            if (!R[r].active) continue;
+            dd_status s2;
+            if ((s2 = copy(c, in16, 2, bf(c, from, r), 1)) != DD_OK) return s2;
+            if ((s2 = k_sap(c, 2, in16, out16, s16)) != DD_OK) return s2;
+            if ((s2 = copy(c, bf(c, to, r), 1, out16, 2)) != DD_OK) return s2;
+        }
+        return DD_OK;
+    };
+    auto stop = [&](BRhs &b, dd_status s2, int detail) {
+        b.active = false;
+        b.st = s2;
+        b.o.detail = detail;
+        --nact;
+    };
+    for (int it = 0; it < maxiter && nact > 0; ++it) {
+        if ((st = precond(BK_P, BK_MP)) != DD_OK) return st;
+        if ((st = k_dirac_mrhs(c, c->bk[BK_Q], c->bk[mp], n)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r)
+            if (R[r].active &&
+                (st = reduce_to(c, mkb(dd::BLAS_DOT, {bf(c, BK_RT, r), bf(c, BK_Q, r)}, {1, 1}), 2, 2 * r)) != DD_OK)
+                return st;
+        if ((st = fetch_red(c, 2 * n, red)) != DD_OK) return st;
+        std::vector<cplx> alpha(n);
+        for (int r = 0; r < n; ++r) {
+            BRhs &b = R[r];
+            if (!b.active) continue;
+            b.o.iters = it + 1;
+            cplx rq(red[2 * r], red[2 * r + 1]);
+            if (rq == 0.0 || !is_fin(rq)) {
+                stop(b, DD_BREAKDOWN, rq == 0.0 ? 1 : 4);
+                continue;
+            }
+            alpha[r] = b.rho0 / rq;
+            if ((st = reduce_to(c, mkb(dd::BLAS_UPDATE1, {bf(c, BK_Y, r), bf(c, mp, r), bf(c, BK_R, r), bf(c, BK_Q, r)},
+                                       {1, 1, 1}, {alpha[r].real(), alpha[r].imag()}),
+                                1, r)) != DD_OK)
+                return st;
+        }
+        if ((st = fetch_red(c, n, red)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r) {
+            BRhs &b = R[r];
+            if (!b.active) continue;
+            b.rn2 = red[r];
+            b.o.relres = std::sqrt(b.rn2 / b.bn2);
+            if (b.o.relres < b.tol) stop(b, DD_OK, 0);
+        }
+        if (nact == 0) break;
+        if ((st = precond(BK_R, BK_MR)) != DD_OK) return st;
+        if ((st = k_dirac_mrhs(c, c->bk[BK_T], c->bk[mr], n)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r)
+            if (R[r].active &&
+                (st = reduce_to(c, mkb(dd::BLAS_DOT_NORM, {bf(c, BK_T, r), bf(c, BK_R, r)}, {1, 1}), 3, 3 * r)) != DD_OK)
+                return st;
+        if ((st = fetch_red(c, 3 * n, red)) != DD_OK) return st;
+        std::vector<cplx> omega(n);
+        for (int r = 0; r < n; ++r) {
+            BRhs &b = R[r];
+            if (!b.active) continue;
+            const double *d = red + 3 * r;
+            if (d[2] == 0.0 || !is_fin(d[2])) {
+                stop(b, DD_BREAKDOWN, d[2] == 0.0 ? 2 : 4);
+                continue;
+            }
+            omega[r] = cplx(d[0], d[1]) / d[2];
+            if ((st = reduce_to(c, mkb(dd::BLAS_UPDATE2,
+                                       {bf(c, BK_Y, r), bf(c, mr, r), bf(c, BK_R, r), bf(c, BK_T, r), bf(c, BK_RT, r)},
+                                       {1, 1, 1}, {omega[r].real(), omega[r].imag()}),
+                                3, 3 * r)) != DD_OK)
+                return st;
+        }
+        if ((st = fetch_red(c, 3 * n, red)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r) {
+            BRhs &b = R[r];
+            if (!b.active) continue;
+            const double *d = red + 3 * r;
+            b.rn2 = d[0];
+            cplx rho(d[1], d[2]);
+            b.o.relres = std::sqrt(b.rn2 / b.bn2);
+            if (b.o.relres < b.tol) {
+                stop(b, DD_OK, 0);
+                continue;
+            }
+            if (omega[r] == 0.0) {
+                stop(b, DD_BREAKDOWN, 3);
+                continue;
+            }
+            cplx beta = (alpha[r] / omega[r]) * (rho / b.rho0);
+            if (!is_fin(beta)) {
+                stop(b, DD_BREAKDOWN, 4);
+                continue;
+            }
+            b.rho0 = rho;
+            if ((st = blas(c, mkb(dd::BLAS_PUPDATE, {bf(c, BK_P, r), bf(c, BK_R, r), bf(c, BK_Q, r)}, {1, 1, 1},
+                                  {beta.real(), beta.imag(), omega[r].real(), omega[r].imag()}))) != DD_OK)
+                return st;
+        }
+        if (c->verbose && (it + 1) % 100 == 0) {
+            std::fprintf(stderr, "[ddsolve] batched inner iteration %d: %d right-hand sides still running\n", it + 1, nact);
+            std::fflush(stderr);
+        }
+    }
+    for (int r = 0; r < n; ++r)
+        if (R[r].active) {
+            R[r].active = false;
+            R[r].st = DD_NOT_CONVERGED;
+        }
+    return DD_OK;
+}
+
+// r = b - D x for every right-hand side (FP64), |r|^2 into rn2
+dd_status residual64_batch(dd_ctx *c, int n, double *rn2)
+{
+    dd_status st;
+    for (int r = 0; r < n; ++r) {
+        if ((st = k_dirac(c, bf(c, BK_T64, r), bf(c, BK_X64, r), 0, 0, 0, 0)) != DD_OK) return st;
+        if ((st = reduce_to(c, mkb(dd::BLAS_SUB_NORM, {bf(c, BK_R64, r), bf(c, BK_B64, r), bf(c, BK_T64, r)}, {0, 0, 0}), 1,
+                            r)) != DD_OK)
+            return st;
+    }
+    return fetch_red(c, n, rn2);
+}
+
+
+}  // namespace ddh
+
+namespace {
+
+// a lattice's own failure, reported on the multi-lattice handle
+dd_status lat_fail(dd_multi *m, int k, dd_status s)
+{
+    if (s < 0) m->err = "lattice " + std::to_string(k) + ": " + m->L[k]->err;
+    return s;
+}
+
+void fill_desc(dd_multi *m, dd::LatDesc *d, const std::vector<const void *> &in, const std::vector<void *> &out)
+{
+    int item = 0;
+    for (size_t k = 0; k < m->L.size(); ++k) {
+        dd_ctx *c = m->L[k];
+        d[k].g = c->g;
+        d[k].in = in[k];
+        d[k].out = out[k];
+        d[k].u = c->U32;
+        d[k].cinv = c->cinv32;
+        d[k].phase = c->phase;
+        d[k].kappa = c->prm.kappa;
+        d[k].item0 = item;
+        item += (int)((c->g.V + 255) / 256);
+    }
+}
+
+// one launch of A over every lattice with descriptor table t (0 caller, 1 A Mp, 2 A Mr)
+dd_status multi_launch(dd_multi *m, int t, int pin)
+{
+    const int n = (int)m->L.size();
+    double bytes = 0, flops = 0;
+    for (dd_ctx *c : m->L) {
+        const double V = (double)c->g.V;
+        bytes += V * (sp_b(pin) + sp_b(DD_F32) + 4 * lk_b(DD_F32) + cl_b(DD_F32));
+        flops += V * (hops_in(c->g) + hops_out(c->g) + CLOVF);
+    }
+    dd_ctx *c0 = m->L[0];  // the timers of the first lattice's context hold the multi-lattice launches
+    hipError_t e = timed(c0, DD_KT_DIRAC_MULTI, bytes, flops, [&] {
+        return dd::launch_dirac_multi(m->stream, m->desc_dev + t * n, n, m->total, pin, m->counter);
+    });
+    if (e != hipSuccess) return mfail(m, DD_ERR_HIP, std::string("multi-lattice dirac launch: ") + hipGetErrorString(e));
+    return DD_OK;
+}
+
+// bring the first nv reduction results of every lattice's context to the host (one sync)
+dd_status multi_fetch(dd_multi *m, int nv, std::vector<std::array<double, 3>> &out)
+{
+    for (dd_ctx *c : m->L)
+        MHIPCK(m, hipMemcpyAsync(c->red_host, c->red, nv * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    MHIPCK(m, hipStreamSynchronize(m->stream));
+    for (size_t k = 0; k < m->L.size(); ++k)
+        for (int v = 0; v < nv; ++v) out[k][v] = m->L[k]->red_host[v];
+    return DD_OK;
+}
+
+// the inner FP32 BiCGStab of every lattice in lockstep (Alg. 5 on A M_SAP with the FP16
+// SAP of each lattice, as in the single-lattice mixed solver, flexible accumulation):
+// per lattice its own fields and scalars, the A applications of a step as one launch
+dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
+{
+    const int n = (int)m->L.size();
+    dd_status st;
+    std::vector<std::array<double, 3>> red(n);
+    // fields per lattice (as in solve_sap32 with FP16 SAP storage)
+    auto F = [&](int k, int which) -> void * {
+        dd_ctx *c = m->L[k];
+        switch (which) {
+        case 0: return c->f32[0];  // src
+        case 1: return c->f32[1];  // y
+        case 2: return c->f32[2];  // r
+        case 3: return c->f32[3];  // rt
+        case 4: return c->f32[4];  // p
+        case 5: return c->f32[5];  // q
+        case 6: return c->f32[6];  // t
+        case 7: return c->f16[2];  // M p
+        case 8: return c->f16[3];  // M r
+        case 9: return c->f16[4];  // SAP work
+        case 10: return c->f16[0]; // p in FP16
+        default: return c->f16[1]; // r in FP16
+        }
+    };
+    int nact = 0;
+    for (int k = 0; k < n; ++k) {
+        dd_ctx *c = m->L[k];
+        MHIPCK(m, hipMemsetAsync(F(k, 1), 0, spinor_bytes(c->g, DD_F32), m->stream));
+        if ((st = reduce_to(c, mkb(dd::BLAS_NORM2, {F(k, 0)}, {1}), 1, 0)) != DD_OK) return lat_fail(m, k, st);
+    }
+    if ((st = multi_fetch(m, 1, red)) != DD_OK) return st;
+    for (int k = 0; k < n; ++k) {
+        BRhs &b = R[k];
+        b.o = SolveOut{};
+        b.bn2 = b.rn2 = red[k][0];
+        b.rho0 = red[k][0];
+        b.st = DD_OK;
+        if (!is_fin(red[k][0])) return mfail(m, DD_ERR_NONFINITE, "inner source holds NaN or Inf");
+        b.active = red[k][0] > 0.0;
+        nact += b.active;
+        if (!b.active) continue;
+        dd_ctx *c = m->L[k];
+        for (int w : {2, 4, 3})
+            if ((st = copy(c, F(k, w), 1, F(k, 0), 1)) != DD_OK) return lat_fail(m, k, st);
+    }
+    auto precond = [&](int from, int from16, int to) -> dd_status {
+        for (int k = 0; k < n; ++k) {
+            if (!R[k].active) continue;
+            dd_ctx *c = m->L[k];
+            dd_status s2;
+            if ((s2 = copy(c, F(k, from16), 2, F(k, from), 1)) != DD_OK) return lat_fail(m, k, s2);
+            if ((s2 = k_sap(c, 2, F(k, from16), F(k, to), F(k, 9))) != DD_OK) return lat_fail(m, k, s2);
+        }
+        return DD_OK;
+    };
+    auto stop = [&](BRhs &b, dd_status s2, int detail) {
+        b.active = false;
+        b.st = s2;
+        b.o.detail = detail;
+        --nact;
+    };
+    std::vector<cplx> alpha(n), omega(n);
+    for (int it = 0; it < maxiter && nact > 0; ++it) {
+        if ((st = precond(4, 10, 7)) != DD_OK) return st;
+        if ((st = multi_launch(m, 1, 2)) != DD_OK) return st;  // q = A M p, every lattice
+        for (int k = 0; k < n; ++k)
+            if (R[k].active && (st = reduce_to(m->L[k], mkb(dd::BLAS_DOT, {F(k, 3), F(k, 5)}, {1, 1}), 2, 0)) != DD_OK)
+                return lat_fail(m, k, st);
+        if ((st = multi_fetch(m, 2, red)) != DD_OK) return st;
+        for (int k = 0; k < n; ++k) {
+            BRhs &b = R[k];
+            if (!b.active) continue;
+            b.o.iters = it + 1;
+            cplx rq(red[k][0], red[k][1]);
+            if (rq == 0.0 || !is_fin(rq)) {
+                stop(b, DD_BREAKDOWN, rq == 0.0 ? 1 : 4);
+                continue;
+            }
+            alpha[k] = b.rho0 / rq;
+            if ((st = reduce_to(m->L[k], mkb(dd::BLAS_UPDATE1, {F(k, 1), F(k, 7), F(k, 2), F(k, 5)}, {1, 2, 1},
+                                             {alpha[k].real(), alpha[k].imag()}),
+                                1, 0)) != DD_OK)
+                return lat_fail(m, k, st);
+        }
+        if ((st = multi_fetch(m, 1, red)) != DD_OK) return st;
+        for (int k = 0; k < n; ++k) {
+            BRhs &b = R[k];
+            if (!b.active) continue;
+            b.rn2 = red[k][0];
+            b.o.relres = std::sqrt(b.rn2 / b.bn2);
+            if (b.o.relres < b.tol) stop(b, DD_OK, 0);
+        }
+        if (nact == 0) break;
+        if ((st = precond(2, 11, 8)) != DD_OK) return st;
+        if ((st = multi_launch(m, 2, 2)) != DD_OK) return st;  // t = A M r, every lattice
+        for (int k = 0; k < n; ++k)
+            if (R[k].active &&
+                (st = reduce_to(m->L[k], mkb(dd::BLAS_DOT_NORM, {F(k, 6), F(k, 2)}, {1, 1}), 3, 0)) != DD_OK)
+                return lat_fail(m, k, st);
+        if ((st = multi_fetch(m, 3, red)) != DD_OK) return st;
+        for (int k = 0; k < n; ++k) {
+            BRhs &b = R[k];
+            if (!b.active) continue;
+            const double *d = red[k].data();
+            if (d[2] == 0.0 || !is_fin(d[2])) {
+                stop(b, DD_BREAKDOWN, d[2] == 0.0 ? 2 : 4);
+                continue;
+            }
+            omega[k] = cplx(d[0], d[1]) / d[2];
+            if ((st = reduce_to(m->L[k], mkb(dd::BLAS_UPDATE2, {F(k, 1), F(k, 8), F(k, 2), F(k, 6), F(k, 3)}, {1, 2, 1},
+                                             {omega[k].real(), omega[k].imag()}),
+                                3, 0)) != DD_OK)
+                return lat_fail(m, k, st);
+        }
+        if ((st = multi_fetch(m, 3, red)) != DD_OK) return st;
+        for (int k = 0; k < n; ++k) {
+            BRhs &b = R[k];
+            if (!b.active) continue;
+            const double *d = red[k].data();
+            b.rn2 = d[0];
+            cplx rho(d[1], d[2]);
+            b.o.relres = std::sqrt(b.rn2 / b.bn2);
+            if (b.o.relres < b.tol) {
+                stop(b, DD_OK, 0);
+                continue;
+            }
+            if (omega[k] == 0.0) {
+                stop(b, DD_BREAKDOWN, 3);
+                continue;
+            }
+            cplx beta = (alpha[k] / omega[k]) * (rho / b.rho0);
+            if (!is_fin(beta)) {
+                stop(b, DD_BREAKDOWN, 4);
+                continue;
+            }
+            b.rho0 = rho;
+            if ((st = blas(m->L[k], mkb(dd::BLAS_PUPDATE, {F(k, 4), F(k, 2), F(k, 5)}, {1, 1, 1},
+                                        {beta.real(), beta.imag(), omega[k].real(), omega[k].imag()}))) != DD_OK)
+                return lat_fail(m, k, st);
+        }
+    }
+    for (int k = 0; k < n; ++k)
+        if (R[k].active) {
+            R[k].active = false;
+            R[k].st = DD_NOT_CONVERGED;
+        }
+    return DD_OK;
+}
+
+
+
+}  // namespace
+
+extern "C" {
+
+dd_status dirac_apply_batch(dd_ctx *c, void *out, const void *in, int nrhs, dd_prec prec, dd_op op)
+{
+    if (!c || !out || !in) return fail(c, DD_ERR_ARG, "null argument");
+    if (nrhs < 1) return fail(c, DD_ERR_ARG, "nrhs must be at least 1");
+    dd_status st = check_op(c, prec, op);
+    if (st != DD_OK) return st;
+    if (prec == DD_F16) return fail(c, DD_ERR_ARG, "batched apply: DD_F64 (D, D^dagger) or DD_F32 (A)");
+    const size_t cb = (size_t)c->g.V * 12 * 16;  // canonical field bytes
+    if (prec == DD_F64) {
+        for (int r = 0; r < nrhs; ++r)
+            if ((st = dirac_apply(c, (char *)out + r * cb, (const char *)in + r * cb, prec, op)) != DD_OK) return st;
+        return DD_OK;
+    }
+    const int tile = nrhs < 12 ? nrhs : 12;
+    if ((st = batch_alloc(c, tile)) != DD_OK) return st;
+    const size_t fb = spinor_bytes(c->g, DD_F32);
+    for (int r0 = 0; r0 < nrhs; r0 += 12) {
+        const int m = nrhs - r0 < 12 ? nrhs - r0 : 12;
+        for (int r = 0; r < m; ++r)
+            HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F32, (char *)c->bk[BK_IN] + r * fb,
+                                            (const char *)in + (r0 + r) * cb));
+        if ((st = k_dirac_mrhs(c, c->bk[BK_OUT], c->bk[BK_IN], m)) != DD_OK) return st;
+        for (int r = 0; r < m; ++r)
+            HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F32, (char *)out + (r0 + r) * cb,
+                                              (char *)c->bk[BK_OUT] + r * fb));
+    }
+    return DD_OK;
+}
+
+dd_status dd_batch_set_variant(dd_ctx *c, int variant)
+{
+    if (!c) return DD_ERR_ARG;
+    if (variant < -1 || variant >= dd::mrhs_variant_count()) return fail(c, DD_ERR_ARG, "no such variant");
+    c->mrhs_force = variant;
+    return DD_OK;
+}
+
+dd_status dd_batch_tuning(dd_ctx *c, int nrhs, int *variant, double *ms, int n_ms)
+{
+    if (!c || nrhs < 1 || nrhs > 12) return fail(c, DD_ERR_ARG, "nrhs must be 1..12");
+    if (variant) *variant = c->mrhs_force >= 0 ? c->mrhs_force : c->mrhs_tuned[nrhs];
+    const int nv = dd::mrhs_variant_count();
+    for (int v = 0; ms && v < n_ms; ++v) ms[v] = v < nv ? c->mrhs_ms[nrhs][v] : 0.0;
+    return DD_OK;
+}
+
+const char *dd_batch_variant_name(int variant) { return dd::mrhs_variant_name(variant); }
+
+dd_status bicgstab_solve_batch(dd_ctx *c, void *x_dev, const void *b_dev, int nrhs, double tol, int maxiter,
+                               dd_batch_inner inner, dd_solve_info *info)
+{
+    if (!c || !x_dev || !b_dev) return fail(c, DD_ERR_ARG, "null argument");
+    if (nrhs < 1 || nrhs > BATCH_MAX) return fail(c, DD_ERR_ARG, "nrhs must be 1..16");
+    if (!(tol > 0) || maxiter < 0 || (inner != DD_BATCH_INNER_SAP && inner != DD_BATCH_INNER_PLAIN))
+        return fail(c, DD_ERR_ARG, "bad tolerance, maxiter or inner solver");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    auto t0 = std::chrono::steady_clock::now();
+    dd_status st = batch_alloc(c, nrhs);
+    if (st != DD_OK) return st;
+    const int n = nrhs;
+    const size_t cb = (size_t)c->g.V * 12 * 16;
+    std::vector<dd_solve_info> inf(n);
+    std::vector<BRhs> R(n);
+    double bn2[BATCH_MAX], rn2[BATCH_MAX], prev[BATCH_MAX];
+    for (int r = 0; r < n; ++r) {
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, bf(c, BK_B64, r), (const char *)b_dev + r * cb));
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, bf(c, BK_X64, r), (const char *)x_dev + r * cb));
+        if ((st = reduce_to(c, mkb(dd::BLAS_NORM2, {bf(c, BK_B64, r)}, {0}), 1, r)) != DD_OK) return st;
+    }
+    if ((st = fetch_red(c, n, bn2)) != DD_OK) return st;
+    for (int r = 0; r < n; ++r)
+        if (!is_fin(bn2[r])) return fail(c, DD_ERR_NONFINITE, "a source holds NaN or Inf");
+    for (int r = 0; r < n; ++r)
+        if (bn2[r] == 0.0) HIPCK(c, hipMemsetAsync(bf(c, BK_X64, r), 0, spinor_bytes(c->g, DD_F64), c->stream));
+    if ((st = residual64_batch(c, n, rn2)) != DD_OK) return st;
+    // per right-hand side: 0 running, 1 converged, 2 stopped (breakdown or stagnation)
+    std::vector<int> state(n, 0);
+    std::vector<int> stall(n, 0);
+    std::vector<dd_status> res(n, DD_NOT_CONVERGED);
+    for (int r = 0; r < n; ++r) prev[r] = rn2[r];
+    const size_t f32 = spinor_bytes(c->g, DD_F32);
+    for (int outer = 0;; ++outer) {
+        int running = 0;
+        for (int r = 0; r < n; ++r) {
+            if (state[r] != 0) continue;
+            if (bn2[r] == 0.0 || std::sqrt(rn2[r] / bn2[r]) < tol) {
+                state[r] = 1;
+                res[r] = DD_OK;
+            } else
+                ++running;
+        }
+        if (running == 0 || outer >= maxiter) break;
+        // inner sources C_inv r / err for the running right-hand sides, zero for the others
+        double err[BATCH_MAX];
+        for (int r = 0; r < n; ++r) {
+            err[r] = std::sqrt(rn2[r]);
+            R[r].tol = 1.0;
+            if (state[r] != 0) {
+                HIPCK(c, hipMemsetAsync(bf(c, BK_SRC, r), 0, f32, c->stream));
+                continue;
+            }
+            if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {bf(c, BK_SRC, r), bf(c, BK_R64, r), c->cinv32}, {1, 0},
+                                  {1.0 / err[r]}))) != DD_OK)
+                return st;
+            const double need = 0.5 * tol * std::sqrt(bn2[r]) / err[r];
+            R[r].tol = need > c->prm.inner_tol ? (need < 0.1 ? need : 0.1) : c->prm.inner_tol;
+        }
+        if ((st = solve_batch32(c, n, inner == DD_BATCH_INNER_SAP, R, c->prm.inner_maxiter)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r) {
+            if (state[r] != 0) continue;
+            inf[r].iters_inner_total += R[r].o.iters;
+            inf[r].relres_inner_last = R[r].o.relres;
+            if ((st = blas(c, mkb(dd::BLAS_AXPBY, {bf(c, BK_Y, r), bf(c, BK_X64, r)}, {1, 0}, {err[r], 1.0}))) != DD_OK)
+                return st;
+        }
+        if ((st = residual64_batch(c, n, rn2)) != DD_OK) return st;
+        for (int r = 0; r < n; ++r) {
+            if (state[r] != 0) continue;
+            inf[r].iters_outer = outer + 1;
+            if (!is_fin(rn2[r]) || rn2[r] >= prev[r]) {
+                // the correction made the true residual worse: take it back and stop this one
+                if ((st = blas(c, mkb(dd::BLAS_AXPBY, {bf(c, BK_Y, r), bf(c, BK_X64, r)}, {1, 0}, {-err[r], 1.0}))) !=
+                    DD_OK)
+                    return st;
+                state[r] = 2;
+                res[r] = DD_BREAKDOWN;
+                inf[r].status_detail = is_fin(rn2[r]) ? 5 : 4;
+                continue;
+            }
+            stall[r] = rn2[r] > 0.81 * prev[r] ? stall[r] + 1 : 0;
+            prev[r] = rn2[r];
+            if (stall[r] >= 2) {
+                state[r] = 2;
+                res[r] = DD_BREAKDOWN;
+                inf[r].status_detail = 5;
+            }
+        }
+        if (c->verbose) {
+            int conv = 0;
+            for (int r = 0; r < n; ++r) conv += state[r] == 1 || (bn2[r] > 0 && std::sqrt(rn2[r] / bn2[r]) < tol);
+            std::fprintf(stderr, "[ddsolve] batched outer pass %d: %d of %d right-hand sides at tolerance\n", outer + 1,
+                         conv, n);
+            std::fflush(stderr);
+        }
+    }
+    // true FP64 residuals of the returned solutions
+    if ((st = residual64_batch(c, n, rn2)) != DD_OK) return st;
+    dd_status worst = DD_OK;
+    for (int r = 0; r < n; ++r) {
+        inf[r].relres_true = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
+        if (res[r] == DD_NOT_CONVERGED && inf[r].relres_true < tol) res[r] = DD_OK;
+        if (res[r] > worst) worst = res[r];
+        HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F64, (char *)x_dev + r * cb, bf(c, BK_X64, r)));
+    }
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < n; ++r) {
+        inf[r].seconds = secs;
+        if (res[r] == DD_BREAKDOWN && inf[r].status_detail == 0) inf[r].status_detail = 4;
+        if (info) info[r] = inf[r];
+    }
+    return worst;
+}
+
+dd_status dd_multi_create(const dd_params *params, int nlat, void *hip_stream, dd_multi **out)
+{
+    if (!params || !out || nlat < 1 || nlat > 64) return DD_ERR_ARG;
+    *out = nullptr;
+    dd_multi *m = new (std::nothrow) dd_multi;
+    if (!m) return DD_ERR_NOMEM;
+    m->stream = (hipStream_t)hip_stream;
+    for (int k = 0; k < nlat; ++k) {
+        dd_ctx *c = nullptr;
+        dd_status st = dd_create(&params[k], hip_stream, &c);
+        if (st != DD_OK) {
+            dd_multi_destroy(m);
+            return st;
+        }
+        m->L.push_back(c);
+        m->total += (int)((c->g.V + 255) / 256);
+    }
+    bool ok = hipMalloc((void **)&m->counter, sizeof(int)) == hipSuccess &&
+              hipMalloc((void **)&m->desc_dev, 3 * nlat * sizeof(dd::LatDesc)) == hipSuccess &&
+              hipHostMalloc((void **)&m->desc_host, 3 * nlat * sizeof(dd::LatDesc), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        dd_multi_destroy(m);
+        return DD_ERR_NOMEM;
+    }
+    *out = m;
+    return DD_OK;
+}
+
+dd_status dd_multi_destroy(dd_multi *m)
+{
+    if (!m) return DD_OK;
+    if (!m->L.empty()) (void)hipStreamSynchronize(m->stream);  // no device call when nothing was created
+    for (dd_ctx *c : m->L) dd_destroy(c);
+    if (m->counter) (void)hipFree(m->counter);
+    if (m->desc_dev) (void)hipFree(m->desc_dev);
+    if (m->desc_host) (void)hipHostFree(m->desc_host);
+    delete m;
+    return DD_OK;
+}
+
+const char *dd_multi_last_error(const dd_multi *m) { return m ? m->err.c_str() : "null handle"; }
+
+dd_ctx *dd_multi_context(dd_multi *m, int lat)
+{
+    if (!m || lat < 0 || lat >= (int)m->L.size()) return nullptr;
+    return m->L[lat];
+}
+
+dd_status dd_multi_load_gauge(dd_multi *m, int lat, const void *U)
+{
+    if (!m || lat < 0 || lat >= (int)m->L.size()) return mfail(m, DD_ERR_ARG, "no such lattice");
+    return lat_fail(m, lat, dd_load_gauge(m->L[lat], U));
+}
+
+static dd_status multi_ready(dd_multi *m)
+{
+    for (size_t k = 0; k < m->L.size(); ++k)
+        if (!m->L[k]->gauge) return mfail(m, DD_ERR_STATE, "lattice " + std::to_string(k) + ": no gauge field loaded");
+    return DD_OK;
+}
+
+dd_status dirac_apply_multi(dd_multi *m, void *const *out, const void *const *in)
+{
+    if (!m || !out || !in) return mfail(m, DD_ERR_ARG, "null argument");
+    const int n = (int)m->L.size();
+    for (int k = 0; k < n; ++k)
+        if (!out[k] || !in[k]) return mfail(m, DD_ERR_ARG, "null field");
+    dd_status st = multi_ready(m);
+    if (st != DD_OK) return st;
+    std::vector<const void *> vin(n);
+    std::vector<void *> vout(n);
+    for (int k = 0; k < n; ++k) {
+        dd_ctx *c = m->L[k];
+        vin[k] = c->f32[7];
+        vout[k] = c->f32[8];
+        MHIPCK(m, dd::launch_pack_spinor(c->g, m->stream, DD_F32, c->f32[7], in[k]));
+    }
+    fill_desc(m, m->desc_host, vin, vout);
+    MHIPCK(m, hipMemcpyAsync(m->desc_dev, m->desc_host, n * sizeof(dd::LatDesc), hipMemcpyHostToDevice, m->stream));
+    if ((st = multi_launch(m, 0, 1)) != DD_OK) return st;
+    for (int k = 0; k < n; ++k)
+        MHIPCK(m, dd::launch_unpack_spinor(m->L[k]->g, m->stream, DD_F32, out[k], m->L[k]->f32[8]));
+    MHIPCK(m, hipStreamSynchronize(m->stream));  // the staging table is reused by the next call
+    return DD_OK;
+}
+
+dd_status bicgstab_solve_multi(dd_multi *m, void *const *x_dev, const void *const *b_dev, double tol, int maxiter,
+                               dd_solve_info *info)
+{
+    if (!m || !x_dev || !b_dev) return mfail(m, DD_ERR_ARG, "null argument");
+    if (!(tol > 0) || maxiter < 0) return mfail(m, DD_ERR_ARG, "bad tolerance or maxiter");
+    const int n = (int)m->L.size();
+    for (int k = 0; k < n; ++k)
+        if (!x_dev[k] || !b_dev[k]) return mfail(m, DD_ERR_ARG, "null field");
+    dd_status st = multi_ready(m);
+    if (st != DD_OK) return st;
+    auto t0 = std::chrono::steady_clock::now();
+    // descriptor tables of the two A applications of a BiCGStab step: M p -> q, M r -> t
+    {
+        std::vector<const void *> i1(n), i2(n);
+        std::vector<void *> o1(n), o2(n);
+        for (int k = 0; k < n; ++k) {
+            dd_ctx *c = m->L[k];
+            i1[k] = c->f16[2];
+            o1[k] = c->f32[5];
+            i2[k] = c->f16[3];
+            o2[k] = c->f32[6];
+        }
+        fill_desc(m, m->desc_host + n, i1, o1);
+        fill_desc(m, m->desc_host + 2 * n, i2, o2);
+        MHIPCK(m, hipMemcpyAsync(m->desc_dev + n, m->desc_host + n, 2 * n * sizeof(dd::LatDesc), hipMemcpyHostToDevice,
+                                 m->stream));
+        MHIPCK(m, hipStreamSynchronize(m->stream));
+    }
+    std::vector<dd_solve_info> inf(n);
+    std::vector<BRhs> R(n);
+    std::vector<double> bn2(n), rn2(n), prev(n);
+    std::vector<int> state(n, 0), stall(n, 0);
+    std::vector<dd_status> res(n, DD_NOT_CONVERGED);
+    for (int k = 0; k < n; ++k) {
+        dd_ctx *c = m->L[k];
+        MHIPCK(m, dd::launch_pack_spinor(c->g, m->stream, DD_F64, c->f64[0], b_dev[k]));
+        MHIPCK(m, dd::launch_pack_spinor(c->g, m->stream, DD_F64, c->f64[1], x_dev[k]));
+        if ((st = norm2(c, c->f64[0], 0, &bn2[k])) != DD_OK) return lat_fail(m, k, st);
+        if (!is_fin(bn2[k])) return mfail(m, DD_ERR_NONFINITE, "a source holds NaN or Inf");
+        if (bn2[k] == 0.0) MHIPCK(m, hipMemsetAsync(c->f64[1], 0, spinor_bytes(c->g, DD_F64), m->stream));
+        if ((st = residual64(c, c->f64[2], c->f64[0], c->f64[1], c->f64[3], &rn2[k])) != DD_OK) return lat_fail(m, k, st);
+        prev[k] = rn2[k];
+    }
+    for (int outer = 0;; ++outer) {
+        int running = 0;
+        for (int k = 0; k < n; ++k) {
+            if (state[k] != 0) continue;
+            if (bn2[k] == 0.0 || std::sqrt(rn2[k] / bn2[k]) < tol) {
+                state[k] = 1;
+                res[k] = DD_OK;
+            } else
+                ++running;
+        }
+        if (running == 0 || outer >= maxiter) break;
+        std::vector<double> err(n);
+        for (int k = 0; k < n; ++k) {
+            dd_ctx *c = m->L[k];
+            err[k] = std::sqrt(rn2[k]);
+            R[k].tol = 1.0;
+            if (state[k] != 0) {
+                MHIPCK(m, hipMemsetAsync(c->f32[0], 0, spinor_bytes(c->g, DD_F32), m->stream));
+                continue;
+            }
+            if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {c->f32[0], c->f64[2], c->cinv32}, {1, 0}, {1.0 / err[k]}))) != DD_OK)
+                return lat_fail(m, k, st);
+            const double need = 0.5 * tol * std::sqrt(bn2[k]) / err[k];
+            R[k].tol = need > c->prm.inner_tol ? (need < 0.1 ? need : 0.1) : c->prm.inner_tol;
+        }
+        if ((st = solve_multi32(m, R, m->L[0]->prm.inner_maxiter)) != DD_OK) return st;
+        for (int k = 0; k < n; ++k) {
+            if (state[k] != 0) continue;
+            dd_ctx *c = m->L[k];
+            inf[k].iters_inner_total += R[k].o.iters;
+            inf[k].relres_inner_last = R[k].o.relres;
+            if ((st = blas(c, mkb(dd::BLAS_AXPBY, {c->f32[1], c->f64[1]}, {1, 0}, {err[k], 1.0}))) != DD_OK)
+                return lat_fail(m, k, st);
+            if ((st = residual64(c, c->f64[2], c->f64[0], c->f64[1], c->f64[3], &rn2[k])) != DD_OK)
+                return lat_fail(m, k, st);
+            inf[k].iters_outer = outer + 1;
+            if (!is_fin(rn2[k]) || rn2[k] >= prev[k]) {
+                if ((st = blas(c, mkb(dd::BLAS_AXPBY, {c->f32[1], c->f64[1]}, {1, 0}, {-err[k], 1.0}))) != DD_OK)
+                    return lat_fail(m, k, st);
+                state[k] = 2;
+                res[k] = DD_BREAKDOWN;
+                inf[k].status_detail = is_fin(rn2[k]) ? 5 : 4;
+                continue;
+            }
+            stall[k] = rn2[k] > 0.81 * prev[k] ? stall[k] + 1 : 0;
+            prev[k] = rn2[k];
+            if (stall[k] >= 2) {
+                state[k] = 2;
+                res[k] = DD_BREAKDOWN;
+                inf[k].status_detail = 5;
+            }
+        }
+    }
+    dd_status worst = DD_OK;
+    for (int k = 0; k < n; ++k) {
+        dd_ctx *c = m->L[k];
+        if ((st = residual64(c, c->f64[2], c->f64[0], c->f64[1], c->f64[3], &rn2[k])) != DD_OK) return lat_fail(m, k, st);
+        inf[k].relres_true = bn2[k] > 0 ? std::sqrt(rn2[k] / bn2[k]) : 0.0;
+        if (res[k] == DD_NOT_CONVERGED && inf[k].relres_true < tol) res[k] = DD_OK;
+        if (res[k] > worst) worst = res[k];
+        MHIPCK(m, dd::launch_unpack_spinor(c->g, m->stream, DD_F64, x_dev[k], c->f64[1]));
+    }
+    MHIPCK(m, hipStreamSynchronize(m->stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int k = 0; k < n; ++k) {
+        inf[k].seconds = secs;
+        if (res[k] == DD_BREAKDOWN && inf[k].status_detail == 0) inf[k].status_detail = 4;
+        if (info) info[k] = inf[k];
+    }
+    return worst;
+}
+
+
+}  // extern "C"

@@ -44,7 +44,7 @@ def sample_sites(n_random=96, seed=7):
     return np.array(lex, dtype=np.int64)
 
 
-@pytest.fixture(scope="module")
+@pytest.fixture(scope="class")
 def full():
     dev = torch.device("cuda:0")
     U = synth.su3_links(DIMS, 0.3, SEED, device=dev)
@@ -56,39 +56,47 @@ def full():
     Uh = U.cpu().numpy()
     del U
     torch.cuda.empty_cache()
-    yield op, s, Uh, b, sample_sites()
+    held = [op, s, Uh, b, sample_sites()]
+    del b
+    yield held
+    # the benchmark lattice's fields take about half of the device memory: release them
+    # (and torch's cached blocks) before the other lattices of this file
     s.close()
+    held.clear()
+    torch.cuda.empty_cache()
 
 
-def test_full_size_dirac_applies_on_sampled_sites(full):
-    op, s, Uh, b, sites = full
-    x = synth.gaussian_spinor(DIMS, SEED + 5, device="cuda")
-    xh = x.cpu().numpy()
-    d64 = s.apply(x, op=dd.DD_OP_D, prec=dd.DD_F64).reshape(-1, 3, 4)[torch.from_numpy(sites).cuda()].cpu().numpy()
-    want = O.dirac_D_sites(op, Uh, xh, sites)
-    assert np.abs(d64 - want).max() < 1e-13 * np.abs(want).max()
-    wantA = O.dirac_A_sites(op, Uh, xh, sites)
-    idx = torch.from_numpy(sites).cuda()
-    a32 = s.apply(x, op=dd.DD_OP_A, prec=dd.DD_F32).reshape(-1, 3, 4)[idx].cpu().numpy()
-    a16 = s.apply(x, op=dd.DD_OP_A, prec=dd.DD_F16).reshape(-1, 3, 4)[idx].cpu().numpy()
-    e32 = np.linalg.norm(a32 - wantA) / np.linalg.norm(wantA)
-    e16 = np.linalg.norm(a16 - wantA) / np.linalg.norm(wantA)
-    print(f"64^3x128, {len(sites)} sampled sites: FP32 A rel. error {e32:.2e}, FP16-storage A {e16:.2e}")
-    assert e32 < 1e-6
-    assert e16 < 3e-3
+class TestBenchmarkLattice:
+    """The 64^3 x 128 lattice; its solver lives for the two tests of this class only."""
 
+    def test_full_size_dirac_applies_on_sampled_sites(self, full):
+        op, s, Uh, b, sites = full
+        x = synth.gaussian_spinor(DIMS, SEED + 5, device="cuda")
+        xh = x.cpu().numpy()
+        d64 = s.apply(x, op=dd.DD_OP_D, prec=dd.DD_F64).reshape(-1, 3, 4)[torch.from_numpy(sites).cuda()].cpu().numpy()
+        want = O.dirac_D_sites(op, Uh, xh, sites)
+        assert np.abs(d64 - want).max() < 1e-13 * np.abs(want).max()
+        wantA = O.dirac_A_sites(op, Uh, xh, sites)
+        idx = torch.from_numpy(sites).cuda()
+        a32 = s.apply(x, op=dd.DD_OP_A, prec=dd.DD_F32).reshape(-1, 3, 4)[idx].cpu().numpy()
+        a16 = s.apply(x, op=dd.DD_OP_A, prec=dd.DD_F16).reshape(-1, 3, 4)[idx].cpu().numpy()
+        e32 = np.linalg.norm(a32 - wantA) / np.linalg.norm(wantA)
+        e16 = np.linalg.norm(a16 - wantA) / np.linalg.norm(wantA)
+        print(f"64^3x128, {len(sites)} sampled sites: FP32 A rel. error {e32:.2e}, FP16-storage A {e16:.2e}")
+        assert e32 < 1e-6
+        assert e16 < 3e-3
 
-def test_full_size_mixed_solve(full):
-    op, s, Uh, b, sites = full
-    x, info = s.solve(b, tol=1e-10, maxiter=50, mode=dd.DD_SOLVE_MIXED)
-    print(f"64^3x128 mixed solve: {info}")
-    assert info["status"] == "DD_OK" and info["relres_true"] < 1e-10
-    idx = torch.from_numpy(sites).cuda()
-    bs = b.reshape(-1, 3, 4)[idx].cpu().numpy()
-    r = bs - O.dirac_D_sites(op, Uh, x.cpu().numpy(), sites)
-    rel = np.linalg.norm(r) / np.linalg.norm(bs)
-    print(f"oracle residual on {len(sites)} sampled sites: {rel:.2e}")
-    assert rel < 1e-8
+    def test_full_size_mixed_solve(self, full):
+        op, s, Uh, b, sites = full
+        x, info = s.solve(b, tol=1e-10, maxiter=50, mode=dd.DD_SOLVE_MIXED)
+        print(f"64^3x128 mixed solve: {info}")
+        assert info["status"] == "DD_OK" and info["relres_true"] < 1e-10
+        idx = torch.from_numpy(sites).cuda()
+        bs = b.reshape(-1, 3, 4)[idx].cpu().numpy()
+        r = bs - O.dirac_D_sites(op, Uh, x.cpu().numpy(), sites)
+        rel = np.linalg.norm(r) / np.linalg.norm(bs)
+        print(f"oracle residual on {len(sites)} sampled sites: {rel:.2e}")
+        assert rel < 1e-8
 
 
 def lattice_samples(dims, n_random=40, seed=11):
