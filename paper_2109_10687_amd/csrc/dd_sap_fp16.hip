@@ -1,5 +1,5 @@
 // dd_sap_fp16.hip -- SAP half-sweep (Alg. 1 with the Jacobi of Alg. 2) with
-// FP16 storage and packed FP16 arithmetic for the block-local sweeps.
+// FP16 storage and packed FP16 arithmetic.
 //
 // The block-local work of a half-sweep is N_JAC + 1 applications of
 // K = kappa C_inv H_in, all inside one workgroup.  Here every spinor is kept in
@@ -9,12 +9,19 @@
 // a link entry, broadcast to both halves, multiplies both spins of the half
 // spinor in one packed FMA: a hop's two 3x3 complex products take 36 packed
 // FMAs.  The clover block (two 6x6 Hermitian blocks in the gamma_5-diagonal
-// basis) is rearranged once per launch into pair coefficients,
+// basis) is rearranged once per launch, straight from its FP16 storage, into
+// pair coefficients,
 //   w_pair[c] = sum_c' A[c][c'] (.) z_pair[c'] + B[c][c'] (.) swap(z_pair[c']).
-// FP16 range: the block's source is scaled by 1 / max|component| before the
-// sweeps (the sweeps are linear) and the result is scaled back in FP32.  The
-// cross-block prologue (A_{c c'} x_{c'}, the previous half-sweep's output read
-// from the neighbouring blocks) and the final s update stay in FP32.
+// The cross-block term of Alg. 1 (the neighbouring blocks' x_{c'} hopping into
+// the block) is computed in packed FP16 too, one face hop per thread, and is not
+// multiplied by C_inv on its own: with h = H_{c c'} x_{c'} the updated source is
+// s_c + kappa C_inv h, and every Jacobi step x <- s_c + kappa C_inv (H_in x + h)
+// carries h inside the clover product it already does; the first step, from
+// x = 0, yields the updated source itself.  The face hops are summed per site in
+// FP32 (each neighbour has its own storage scale).  FP16 range: the block's
+// source and h are scaled by 1 / max|component| before the sweeps (the sweeps
+// are linear) and the result is scaled back in FP32; the final s update of
+// Alg. 1 is evaluated in FP32.
 #include "dd_device.h"
 #include "dd_launch.h"
 
@@ -45,6 +52,16 @@ DD_INL void zero(SpH &s)
     for (int c = 0; c < 3; ++c) s.u[c] = s.l[c] = PC{zero2(), zero2()};
 }
 
+// a += b, pair form
+DD_INL void add_pair(SpH &a, const SpH &b)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a.u[c] = PC{add2(a.u[c].re, b.u[c].re), add2(a.u[c].im, b.u[c].im)};
+        a.l[c] = PC{add2(a.l[c].re, b.l[c].re), add2(a.l[c].im, b.l[c].im)};
+    }
+}
+
 // k = W h for a half spinor in pair form; W = U (dag = false) or U^dagger.
 // U[a][b] holds (re, im) in one half2.
 DD_INL void mat_pair(const h2 (&U)[3][3], bool dag, const PC (&h)[3], PC (&k)[3])
@@ -65,12 +82,11 @@ DD_INL void mat_pair(const h2 (&U)[3][3], bool dag, const PC (&h)[3], PC (&k)[3]
     }
 }
 
-// acc += (1 - s gamma_mu) W psi, pair form, for the gamma matrices of the appendix
-DD_INL void hop_pair(int mu, int s, const h2 (&U)[3][3], const SpH &p, SpH &acc)
+// half spinor (h0, h1) of (1 - s gamma_mu) p, pair form, for the gamma matrices of the appendix
+DD_INL void proj_pair(int mu, int s, const SpH &p, PC (&h)[3])
 {
     const h2 S = __float2half2_rn((float)s);                      // (s, s)
     const h2 Cm = __floats2half2_rn(-(float)s, (float)s);         // (-s, s)
-    PC h[3], k[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         if (mu == 0) {  // (h0, h1) = (psi0, psi1) - s i (psi3, psi2)
@@ -88,8 +104,13 @@ DD_INL void hop_pair(int mu, int s, const h2 (&U)[3][3], const SpH &p, SpH &acc)
             h[c].im = add2(q.im, q.im);
         }
     }
-    mat_pair(U, s < 0, h, k);
-    const h2 Cp = __floats2half2_rn((float)s, -(float)s);  // (s, -s)
+}
+
+// acc += (1 - s gamma_mu) rebuilt from k = W h, pair form
+DD_INL void recon_pair(int mu, int s, const PC (&k)[3], SpH &acc)
+{
+    const h2 S = __float2half2_rn((float)s);                      // (s, s)
+    const h2 Cp = __floats2half2_rn((float)s, -(float)s);         // (s, -s)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         if (mu == 3) {
@@ -113,32 +134,51 @@ DD_INL void hop_pair(int mu, int s, const h2 (&U)[3][3], const SpH &p, SpH &acc)
     }
 }
 
+// acc += (1 - s gamma_mu) W psi, pair form
+DD_INL void hop_pair(int mu, int s, const h2 (&U)[3][3], const SpH &p, SpH &acc)
+{
+    PC h[3], k[3];
+    proj_pair(mu, s, p, h);
+    mat_pair(U, s < 0, h, k);
+    recon_pair(mu, s, k, acc);
+}
+
 // clover block in pair form: for each chiral block, A[c][c'] and B[c][c']
 struct ClovPair {
     PC A[2][3][3], B[2][3][3];
 };
 
-// element (i, j) of the Hermitian 6x6 block blk
-DD_INL cx<float> herm_elem(const Clov<float> &C, int blk, int i, int j)
+// entry (i, j) of a Hermitian 6x6 block as an (re, im) half2, from its stored
+// diagonal pairs dg and upper entries up
+DD_INL h2 herm_h2(const h2 (&dg)[3], const h2 (&up)[15], int i, int j)
 {
-    if (i == j) return {C.d[blk][i], 0.f};
-    if (i < j) return C.h[blk][upper_index(i, j)];
-    return conj(C.h[blk][upper_index(j, i)]);
+    if (i == j) return __halves2half2((i & 1) ? __high2half(dg[i >> 1]) : __low2half(dg[i >> 1]), __float2half(0.f));
+    if (i < j) return up[upper_index(i, j)];
+    const h2 v = up[upper_index(j, i)];
+    return __halves2half2(__low2half(v), __hneg(__high2half(v)));
 }
 
-DD_INL PC pair_of(cx<float> a, cx<float> b) { return PC{__floats2half2_rn(a.re, b.re), __floats2half2_rn(a.im, b.im)}; }
-
-DD_INL void clov_pairs(const Clov<float> &C, ClovPair &P)
+// the pair coefficients of the site's FP16 C_inv (no FP32 round trip: the entries are
+// only regrouped)
+DD_INL void clov_pairs_ld(const CloverField<2> &Ci, const Geom &g, int l, int s, ClovPair &P)
 {
 #pragma unroll
-    for (int blk = 0; blk < 2; ++blk)
+    for (int blk = 0; blk < 2; ++blk) {
+        h2 dg[3], up[15];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dg[j] = ld_stream(&Ci.p[elem(g, l, s, 36, blk * 18 + j)]);
+#pragma unroll
+        for (int j = 0; j < 15; ++j) up[j] = ld_stream(&Ci.p[elem(g, l, s, 36, blk * 18 + 3 + j)]);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                P.A[blk][c][d] = pair_of(herm_elem(C, blk, c, d), herm_elem(C, blk, 3 + c, 3 + d));
-                P.B[blk][c][d] = pair_of(herm_elem(C, blk, c, 3 + d), herm_elem(C, blk, 3 + c, d));
+                const h2 a = herm_h2(dg, up, c, d), b = herm_h2(dg, up, 3 + c, 3 + d);
+                const h2 e = herm_h2(dg, up, c, 3 + d), f = herm_h2(dg, up, 3 + c, d);
+                P.A[blk][c][d] = PC{__lows2half2(a, b), __highs2half2(a, b)};
+                P.B[blk][c][d] = PC{__lows2half2(e, f), __highs2half2(e, f)};
             }
+    }
 }
 
 // (a (.) z): complex product lane by lane, accumulated into r
@@ -167,7 +207,12 @@ DD_INL void clover_pair(const ClovPair &P, const SpH &in, SpH &out)
             PC r{zero2(), zero2()};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                cmac_pair(P.A[blk][c][d], z[blk][d], r);
+                if (d == c) {  // a diagonal entry of the Hermitian block: real in both lanes
+                    r.re = fma2(P.A[blk][c][d].re, z[blk][d].re, r.re);
+                    r.im = fma2(P.A[blk][c][d].re, z[blk][d].im, r.im);
+                } else {
+                    cmac_pair(P.A[blk][c][d], z[blk][d], r);
+                }
                 cmac_pair(P.B[blk][c][d], PC{swp(z[blk][d].re), swp(z[blk][d].im)}, r);
             }
             w[blk][c] = r;
@@ -201,6 +246,53 @@ DD_INL void from_pair(const SpH &p, float sc, Spinor<float> &x)
         x.v[1][c] = {sc * ur.y, sc * ui.y};
         x.v[2][c] = {sc * lr.x, sc * li.x};
         x.v[3][c] = {sc * lr.y, sc * li.y};
+    }
+}
+
+// one site of an FP16-storage spinor in pair form, as stored (relative to the
+// site's scale); returns the scale
+DD_INL float load_pair(const SpinorField<2> &f, const Geom &g, int l, int s, SpH &p)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const h2 a0 = f.p[elem(g, l, s, 12, c)], a1 = f.p[elem(g, l, s, 12, 3 + c)];
+        const h2 a2 = f.p[elem(g, l, s, 12, 6 + c)], a3 = f.p[elem(g, l, s, 12, 9 + c)];
+        p.u[c] = PC{__lows2half2(a0, a1), __highs2half2(a0, a1)};
+        p.l[c] = PC{__lows2half2(a2, a3), __highs2half2(a2, a3)};
+    }
+    return f.scale[((long long)l << g.lbvol) + s];
+}
+
+// pair form times an FP32 factor, rounded once per component
+DD_INL void scale_pair(const SpH &a, float f, SpH &r)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float2 ur = __half22float2(a.u[c].re), ui = __half22float2(a.u[c].im);
+        const float2 lr = __half22float2(a.l[c].re), li = __half22float2(a.l[c].im);
+        r.u[c] = PC{__floats2half2_rn(f * ur.x, f * ur.y), __floats2half2_rn(f * ui.x, f * ui.y)};
+        r.l[c] = PC{__floats2half2_rn(f * lr.x, f * lr.y), __floats2half2_rn(f * li.x, f * li.y)};
+    }
+}
+
+// an FP16 link as a 3x3 of (re, im) half2: rows 0 and 1 as stored, row 2 =
+// conj(row0 x row1) evaluated in FP32 and rounded once
+DD_INL void load_link_pair(const __half2 *u16, const Geom &g, int l, int s, int mu, h2 (&U)[3][3])
+{
+    cx<float> r[2][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            U[a][b] = u16[elem(g, l, s, 24, mu * 6 + a * 3 + b)];
+            const float2 t = __half22float2(U[a][b]);
+            r[a][b] = {t.x, t.y};
+        }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+        const cx<float> v = conj(r[0][b1] * r[1][b2] - r[0][b2] * r[1][b1]);
+        U[2][b] = __floats2half2_rn(v.re, v.im);
     }
 }
 
@@ -261,11 +353,25 @@ DD_INL void inblock_pair(const uint4 *xs, const h2 *ul, const Geom &g, const Sit
     }
 }
 
+// a[mu] for a lane-varying mu, as selects
+DD_INL int pick4(int mu, int a0, int a1, int a2, int a3) { return mu == 0 ? a0 : mu == 1 ? a1 : mu == 2 ? a2 : a3; }
+
 // log2 of the block extent in direction nu
 DD_INL int log2b(const Geom &g, int nu) { return (nu < 3 ? g.sh[nu + 1] : g.lbvol) - g.sh[nu]; }
 
-// One half-sweep with FP16 arithmetic in the block-local part; same flags and
-// result (up to FP16 rounding) as k_sap_half<2>.
+// first face hop of face q = 2 mu + side (side 0: the +mu face, 1: the -mu face);
+// faces are numbered in that order, face q holds bvol / b[mu] hops
+DD_INL int face_offset(const Geom &g, int mu, int side)
+{
+    int o = 0;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu)
+        if (nu < mu) o += 2 * (g.bvol >> log2b(g, nu));
+    return o + side * (g.bvol >> log2b(g, mu));
+}
+
+// One half-sweep with FP16 arithmetic; same flags and result (up to FP16
+// rounding) as k_sap_half<2>.
 __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int flags, SpinorField<2> bsrc,
                                                      SpinorField<2> sw, SpinorField<2> xw, const __half2 *u16,
                                                      CloverField<2> Ci, Phase4 ph, float kappa, int n_jac)
@@ -284,127 +390,139 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int fla
     for (int mu = 0; mu < 4; ++mu) st.c[mu] = (st.s >> g.sh[mu]) & (g.b[mu] - 1);
     block_coords(g, st.l, st.B);
 
-    const LinkField<2> U16{u16};
-    Clov<float> cl;
-    Ci.load(g, st.l, st.s, cl);
+    // s_c as stored: pair form relative to the site scale ssc
+    SpH sraw;
+    const float ssc = load_pair((flags & SAP_FIRST) ? bsrc : sw, g, st.l, st.s, sraw);
 
-    Spinor<float> src;
-    if (flags & SAP_FIRST)
-        bsrc.load(g, st.l, st.s, src);
-    else
-        sw.load(g, st.l, st.s, src);
-
-    if (flags & SAP_PRE) {  // s_c += kappa C_inv (cross-block hops of x_{c'}), FP32
-        // Each (direction, side, face site) hop once, spread evenly over the workgroup: a
+    // h = H_{c c'} x_{c'} at this site: the hops from the neighbouring blocks
+    const bool pre = (flags & SAP_PRE) != 0;
+    Spinor<float> hc;
+    zero(hc);
+    if (pre) {
+        // Each (direction, side, face site) hop once, spread evenly over the workgroup (a
         // per-site loop would run all eight hop bodies in every wavefront with most lanes
-        // idle.  The hops' half spinors are parked in LDS (the link staging area, not in
-        // use yet) and summed per site afterwards.
-        float2 *fb = reinterpret_cast<float2 *>(ul);  // [6][P] complex
-        int off[9];
-        off[0] = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) off[q + 1] = off[q] + bvol / g.b[q >> 1];
-        const int P = off[8];
+        // idle).  The hop results, relative to the neighbour's storage scale, and the
+        // scales are parked in LDS (the link staging area, not in use yet) and summed per
+        // site afterwards.
+        const int P = face_offset(g, 3, 1) + (bvol >> log2b(g, 3));  // all face hops
+        const bool equal_faces = g.b[0] == g.b[1] && g.b[1] == g.b[2] && g.b[2] == g.b[3];
+        const int lnf = g.lbvol - log2b(g, 0);                       // log2 of hops per face
+        h2 *fk = ul;                                           // [6][P] half2
+        float *fsc = reinterpret_cast<float *>(fk + 6 * P);    // [P]
         for (int p = threadIdx.x; p < P; p += bvol) {
-            int q = 0;
-            while (q < 7 && p >= off[q + 1]) ++q;
-            const int mu = q >> 1, dir = (q & 1) ? -1 : 1;
-            int kk = p - off[q];
-            Site fs;
-            fs.l = st.l;
-            fs.s = 0;
+            int q = 0, base = 0;
+            if (equal_faces) {  // hypercubic block: face q holds hops q * nf ... q * nf + nf - 1
+                q = p >> lnf;
+                base = q << lnf;
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < 7; ++qq) {
+                    const int n = bvol >> log2b(g, qq >> 1);
+                    if (q == qq && p >= base + n) {
+                        base += n;
+                        q = qq + 1;
+                    }
+                }
+            }
+            const int mu = q >> 1, side = q & 1, dir = side ? -1 : 1;
+            // the face site (c_mu on the face, the other three in-block coordinates from
+            // the hop's index in order) and its neighbour on the opposite face of the next
+            // block in direction dir; selects instead of indexing by the lane's mu keep the
+            // site arrays in registers
+            const int bm = pick4(mu, g.b[0], g.b[1], g.b[2], g.b[3]);
+            const int shm = pick4(mu, g.sh[0], g.sh[1], g.sh[2], g.sh[3]);
+            const int Bm = pick4(mu, st.B[0], st.B[1], st.B[2], st.B[3]);
+            const int NBm = pick4(mu, g.NB[0], g.NB[1], g.NB[2], g.NB[3]);
+            const int bsm = pick4(mu, g.bstride[0], g.bstride[1], g.bstride[2], g.bstride[3]);
+            int kk = p - base;
+            int fsite = (side ? 0 : bm - 1) << shm;
 #pragma unroll
             for (int nu = 0; nu < 4; ++nu) {
-                fs.B[nu] = st.B[nu];
-                if (nu == mu) {
-                    fs.c[nu] = dir > 0 ? g.b[nu] - 1 : 0;
-                } else {
-                    fs.c[nu] = kk & (g.b[nu] - 1);
-                    kk >>= log2b(g, nu);
-                }
-                fs.s += fs.c[nu] << g.sh[nu];
+                if (nu == mu) continue;
+                fsite += (kk & (g.b[nu] - 1)) << g.sh[nu];
+                kk >>= log2b(g, nu);
             }
-            bool wrap, inblk;
-            const long long j = neighbour(g, fs, mu, dir, wrap, inblk);
-            const int lj = (int)(j >> g.lbvol), sj = (int)(j & (bvol - 1));
-            Spinor<float> psi;
-            xw.load(g, lj, sj, psi);
-            Mat3<float> W;
-            if (dir > 0)
-                U16.load(g, st.l, fs.s, mu, W);
-            else
-                U16.load(g, lj, sj, mu, W);
-            Half<float> h, k;
-            project(mu, dir, psi, h);
-            mat_half(W, dir < 0, h, k);
-            if (wrap) {
-                const cx<float> phase = {(float)ph.re[mu], (float)(dir > 0 ? ph.im[mu] : -ph.im[mu])};
+            int lj = st.l + dir * bsm;
+            if (Bm + dir < 0)
+                lj += NBm * bsm;
+            else if (Bm + dir >= NBm)
+                lj -= NBm * bsm;
+            const int sj = fsite - dir * ((bm - 1) << shm);
+            SpH ps;
+            const float scj = load_pair(xw, g, lj, sj, ps);
+            h2 U[3][3];  // U_mu at the face site (forward) or at its neighbour (backward)
+            load_link_pair(u16, g, dir > 0 ? st.l : lj, dir > 0 ? fsite : sj, mu, U);
+            PC h[3], k[3];
+            proj_pair(mu, dir, ps, h);
+            mat_pair(U, dir < 0, h, k);
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) k.v[a][c] = k.v[a][c] * phase;
+            for (int c = 0; c < 3; ++c) {
+                fk[(2 * c) * P + p] = k[c].re;
+                fk[(2 * c + 1) * P + p] = k[c].im;
             }
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) fb[(a * 3 + c) * P + p] = make_float2(k.v[a][c].re, k.v[a][c].im);
+            fsc[p] = scj;
         }
         __syncthreads();
-        Spinor<float> acc, t;
-        zero(acc);
+        // per site: at most one face per direction (blocks are at least 2 wide)
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
+            const int c = st.c[mu];
+            const bool hi = c == g.b[mu] - 1;
+            if (c != 0 && !hi) continue;
+            const int dir = hi ? 1 : -1;
+            int kk = 0, w8 = 0;
 #pragma unroll
-            for (int dir = 1; dir >= -1; dir -= 2) {
-                const int c = st.c[mu] + dir;
-                if (c >= 0 && c < g.b[mu]) continue;
-                // index of this site on the face: the other three coordinates in order
-                int kk = 0, w8 = 0;
+            for (int nu = 0; nu < 4; ++nu) {
+                if (nu == mu) continue;
+                kk += st.c[nu] << w8;
+                w8 += log2b(g, nu);
+            }
+            const int p = face_offset(g, mu, hi ? 0 : 1) + kk;
+            const float scj = fsc[p];
+            Half<float> k;
 #pragma unroll
-                for (int nu = 0; nu < 4; ++nu) {
-                    if (nu == mu) continue;
-                    kk += st.c[nu] << w8;
-                    w8 += log2b(g, nu);
-                }
-                const int p = off[2 * mu + (dir > 0 ? 0 : 1)] + kk;
-                Half<float> k;
+            for (int cc = 0; cc < 3; ++cc) {
+                const float2 re = __half22float2(fk[(2 * cc) * P + p]), im = __half22float2(fk[(2 * cc + 1) * P + p]);
+                k.v[0][cc] = {scj * re.x, scj * im.x};
+                k.v[1][cc] = {scj * re.y, scj * im.y};
+            }
+            if (hi ? st.B[mu] == g.NB[mu] - 1 : st.B[mu] == 0) {  // the hop crosses the lattice edge
+                const cx<float> phase = {(float)ph.re[mu], (float)(hi ? ph.im[mu] : -ph.im[mu])};
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) {
-                        const float2 v = fb[(a * 3 + cc) * P + p];
-                        k.v[a][cc] = {v.x, v.y};
-                    }
-                reconstruct(mu, dir, k, acc);
+                    for (int cc = 0; cc < 3; ++cc) k.v[a][cc] = k.v[a][cc] * phase;
             }
+            if (mu < 3)
+                reconstruct(mu, dir, k, hc);
+            else if (hi)
+                reconstruct(3, 1, k, hc);
+            else
+                reconstruct(3, -1, k, hc);
         }
-        clover_mul(cl, acc, t);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) src.v[a][c] = src.v[a][c] + kappa * t.v[a][c];
         __syncthreads();  // the face buffer is about to become the link staging area
     }
 
     // stage the block's links as full 3x3 FP16 matrices
     for (int mu = 0; mu < 4; ++mu) {
-        Mat3<float> U;
-        U16.load(g, st.l, st.s, mu, U);
+        h2 U[3][3];
+        load_link_pair(u16, g, st.l, st.s, mu, U);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) ul[(mu * 9 + a * 3 + b) * bvol + st.s] = __floats2half2_rn(U.m[a][b].re, U.m[a][b].im);
+            for (int b = 0; b < 3; ++b) ul[(mu * 9 + a * 3 + b) * bvol + st.s] = U[a][b];
     }
 
     ClovPair CP;
-    clov_pairs(cl, CP);
+    clov_pairs_ld(Ci, g, st.l, st.s, CP);
 
-    // block normalisation: scale the source to max |component| = 1
-    float m = 0.f;
+    // block normalisation: scale s_c and h to max |component| <= 1 (a stored FP16
+    // spinor has max |component| = 1 relative to its scale)
+    float m = ssc;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(src.v[a][c].re), fabsf(src.v[a][c].im)));
+        for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(hc.v[a][c].re), fabsf(hc.v[a][c].im)));
     const int wv = bvol < 64 ? bvol : 64;  // lanes of this workgroup in one wavefront
     for (int off = wv / 2; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, wv));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
@@ -413,15 +531,29 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int fla
     for (int q = 0; q < (bvol + 63) / 64; ++q) m = fmaxf(m, wmax[q]);
     const float sc = m > 0.f ? 1.f / m : 0.f;
 
-    SpH sh, x, acc, t;
-    to_pair(src, sc, sh);
-    x = sh;
+    SpH sh, hp, x, acc, t;
+    scale_pair(sraw, ssc * sc, sh);
+    to_pair(hc, sc, hp);
     const h2 K = __float2half2_rn(kappa);
+    // x_0 = s_c + kappa C_inv h: one Jacobi step from x = 0
+    if (pre) {
+        clover_pair(CP, hp, t);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x.u[c].re = fma2(K, t.u[c].re, sh.u[c].re);
+            x.u[c].im = fma2(K, t.u[c].im, sh.u[c].im);
+            x.l[c].re = fma2(K, t.l[c].re, sh.l[c].re);
+            x.l[c].im = fma2(K, t.l[c].im, sh.l[c].im);
+        }
+    } else {
+        x = sh;
+    }
     for (int j = 0; j < n_jac; ++j) {
         __syncthreads();
         lds_put(xs, bvol, st.s, x);
         __syncthreads();
         inblock_pair(xs, ul, g, st, acc);
+        if (pre) add_pair(acc, hp);
         clover_pair(CP, acc, t);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -435,13 +567,16 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int fla
     Spinor<float> xf;
     from_pair(x, inv, xf);
     if (!(flags & SAP_TAIL)) {
+        // s_c <- s_c + b_c - x_c + kappa C_inv (H_in x_c + h)
         __syncthreads();
         lds_put(xs, bvol, st.s, x);
         __syncthreads();
         inblock_pair(xs, ul, g, st, acc);
+        if (pre) add_pair(acc, hp);
         clover_pair(CP, acc, t);
-        Spinor<float> tf, b;
+        Spinor<float> tf, b, src;
         from_pair(t, inv, tf);
+        from_pair(sraw, ssc, src);
         bsrc.load(g, st.l, st.s, b);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -456,10 +591,10 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int fla
 size_t sap_pk_lds_bytes(const Geom &g)
 {
     // the Jacobi iterate, then the larger of the link staging area and the face buffer of
-    // the cross-block prologue (6 FP32 complex per face hop)
+    // the cross-block hops (6 half2 and one FP32 scale per face hop)
     size_t faces = 0;
     for (int mu = 0; mu < 4; ++mu) faces += 2 * (size_t)(g.bvol / g.b[mu]);
-    const size_t links = (size_t)g.bvol * 36 * sizeof(__half2), fbuf = faces * 6 * sizeof(float2);
+    const size_t links = (size_t)g.bvol * 36 * sizeof(__half2), fbuf = faces * (6 * sizeof(__half2) + sizeof(float));
     return (size_t)g.bvol * 3 * sizeof(uint4) + (links > fbuf ? links : fbuf);
 }
 
