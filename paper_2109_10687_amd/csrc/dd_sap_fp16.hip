@@ -52,16 +52,6 @@ DD_INL void zero(SpH &s)
     for (int c = 0; c < 3; ++c) s.u[c] = s.l[c] = PC{zero2(), zero2()};
 }
 
-// a += b, pair form
-DD_INL void add_pair(SpH &a, const SpH &b)
-{
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        a.u[c] = PC{add2(a.u[c].re, b.u[c].re), add2(a.u[c].im, b.u[c].im)};
-        a.l[c] = PC{add2(a.l[c].re, b.l[c].re), add2(a.l[c].im, b.l[c].im)};
-    }
-}
-
 // k = W h for a half spinor in pair form; W = U (dag = false) or U^dagger.
 // U[a][b] holds (re, im) in one half2.
 DD_INL void mat_pair(const h2 (&U)[3][3], bool dag, const PC (&h)[3], PC (&k)[3])
@@ -143,23 +133,23 @@ DD_INL void hop_pair(int mu, int s, const h2 (&U)[3][3], const SpH &p, SpH &acc)
     recon_pair(mu, s, k, acc);
 }
 
-// clover block in pair form: for each chiral block, A[c][c'] and B[c][c']
+// clover block in pair form.  For chiral block blk with Hermitian 6x6 entries H,
+//   A[c][d] = (H(c, d), H(3+c, 3+d)),  B[c][d] = (H(c, 3+d), H(3+c, d))   (lane 0, lane 1)
+// and w_pair[c] = sum_d A[c][d] (.) z_pair[d] + B[c][d] (.) swap(z_pair[d]).  Hermiticity
+// fixes half of them: A[d][c] = conj(A[c][d]) lane by lane, A[c][c] is real, and
+// B[d][c] = conj(swap(B[c][d])), B[c][c] = (w, conj w) with w = H(c, 3+c).  Only the
+// diagonal and the upper entries are kept (36 registers instead of 72).
 struct ClovPair {
-    PC A[2][3][3], B[2][3][3];
+    h2 Ad[2][3];  // real parts of A[c][c]
+    PC Au[2][3];  // A[0][1], A[0][2], A[1][2]
+    h2 Bd[2][3];  // w = H(c, 3+c) as (re, im)
+    PC Bu[2][3];  // B[0][1], B[0][2], B[1][2]
 };
 
-// entry (i, j) of a Hermitian 6x6 block as an (re, im) half2, from its stored
-// diagonal pairs dg and upper entries up
-DD_INL h2 herm_h2(const h2 (&dg)[3], const h2 (&up)[15], int i, int j)
-{
-    if (i == j) return __halves2half2((i & 1) ? __high2half(dg[i >> 1]) : __low2half(dg[i >> 1]), __float2half(0.f));
-    if (i < j) return up[upper_index(i, j)];
-    const h2 v = up[upper_index(j, i)];
-    return __halves2half2(__low2half(v), __hneg(__high2half(v)));
-}
+DD_INL int upper3(int c, int d) { return c + d - 1; }  // (0,1) -> 0, (0,2) -> 1, (1,2) -> 2
 
-// the pair coefficients of the site's FP16 C_inv (no FP32 round trip: the entries are
-// only regrouped)
+// the pair coefficients of the site's FP16 C_inv (the stored entries are only
+// regrouped: no rounding)
 DD_INL void clov_pairs_ld(const CloverField<2> &Ci, const Geom &g, int l, int s, ClovPair &P)
 {
 #pragma unroll
@@ -169,14 +159,21 @@ DD_INL void clov_pairs_ld(const CloverField<2> &Ci, const Geom &g, int l, int s,
         for (int j = 0; j < 3; ++j) dg[j] = ld_stream(&Ci.p[elem(g, l, s, 36, blk * 18 + j)]);
 #pragma unroll
         for (int j = 0; j < 15; ++j) up[j] = ld_stream(&Ci.p[elem(g, l, s, 36, blk * 18 + 3 + j)]);
+        auto diag = [&](int i) { return (i & 1) ? __high2half(dg[i >> 1]) : __low2half(dg[i >> 1]); };
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            P.Ad[blk][c] = __halves2half2(diag(c), diag(3 + c));
+            P.Bd[blk][c] = up[upper_index(c, 3 + c)];
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const h2 a = herm_h2(dg, up, c, d), b = herm_h2(dg, up, 3 + c, 3 + d);
-                const h2 e = herm_h2(dg, up, c, 3 + d), f = herm_h2(dg, up, 3 + c, d);
-                P.A[blk][c][d] = PC{__lows2half2(a, b), __highs2half2(a, b)};
-                P.B[blk][c][d] = PC{__lows2half2(e, f), __highs2half2(e, f)};
+            for (int d = c + 1; d < 3; ++d) {
+                const h2 a = up[upper_index(c, d)], b = up[upper_index(3 + c, 3 + d)];
+                P.Au[blk][upper3(c, d)] = PC{__lows2half2(a, b), __highs2half2(a, b)};
+                // B[c][d] = (H(c, 3+d), conj H(d, 3+c))
+                const h2 e = up[upper_index(c, 3 + d)], f = up[upper_index(d, 3 + c)];
+                P.Bu[blk][upper3(c, d)] = PC{__lows2half2(e, f), __halves2half2(__high2half(e), __hneg(__high2half(f)))};
             }
     }
 }
@@ -188,6 +185,15 @@ DD_INL void cmac_pair(const PC &a, const PC &z, PC &r)
     r.re = fma2(neg2(a.im), z.im, r.re);
     r.im = fma2(a.re, z.im, r.im);
     r.im = fma2(a.im, z.re, r.im);
+}
+
+// r += conj(a) (.) z lane by lane
+DD_INL void cmac_pair_conj(const PC &a, const PC &z, PC &r)
+{
+    r.re = fma2(a.re, z.re, r.re);
+    r.re = fma2(a.im, z.im, r.re);
+    r.im = fma2(a.re, z.im, r.im);
+    r.im = fma2(neg2(a.im), z.re, r.im);
 }
 
 // out = Q diag(N+, N-) Q in, pair form (Q = [[1, 1], [1, -1]] on the spin pairs)
@@ -207,13 +213,22 @@ DD_INL void clover_pair(const ClovPair &P, const SpH &in, SpH &out)
             PC r{zero2(), zero2()};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                if (d == c) {  // a diagonal entry of the Hermitian block: real in both lanes
-                    r.re = fma2(P.A[blk][c][d].re, z[blk][d].re, r.re);
-                    r.im = fma2(P.A[blk][c][d].re, z[blk][d].im, r.im);
+                const PC &zd = z[blk][d];
+                const PC zs{swp(zd.re), swp(zd.im)};
+                if (d == c) {
+                    // A[c][c] real; B[c][c] = (w, conj w): re pair (w.re, w.re), im pair (w.im, -w.im)
+                    const h2 wb = P.Bd[blk][c];
+                    r.re = fma2(P.Ad[blk][c], zd.re, r.re);
+                    r.im = fma2(P.Ad[blk][c], zd.im, r.im);
+                    cmac_pair(PC{lo2(wb), __halves2half2(__high2half(wb), __hneg(__high2half(wb)))}, zs, r);
+                } else if (d > c) {
+                    cmac_pair(P.Au[blk][upper3(c, d)], zd, r);
+                    cmac_pair(P.Bu[blk][upper3(c, d)], zs, r);
                 } else {
-                    cmac_pair(P.A[blk][c][d], z[blk][d], r);
+                    cmac_pair_conj(P.Au[blk][upper3(d, c)], zd, r);
+                    const PC &b = P.Bu[blk][upper3(d, c)];
+                    cmac_pair_conj(PC{swp(b.re), swp(b.im)}, zs, r);
                 }
-                cmac_pair(P.B[blk][c][d], PC{swp(z[blk][d].re), swp(z[blk][d].im)}, r);
             }
             w[blk][c] = r;
         }
@@ -276,23 +291,43 @@ DD_INL void scale_pair(const SpH &a, float f, SpH &r)
 }
 
 // an FP16 link as a 3x3 of (re, im) half2: rows 0 and 1 as stored, row 2 =
-// conj(row0 x row1) evaluated in FP32 and rounded once
+// conj(row0 x row1) accumulated in FP32 from the FP16 entries (mixed-precision
+// FMAs) and rounded once
 DD_INL void load_link_pair(const __half2 *u16, const Geom &g, int l, int s, int mu, h2 (&U)[3][3])
 {
-    cx<float> r[2][3];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            U[a][b] = u16[elem(g, l, s, 24, mu * 6 + a * 3 + b)];
-            const float2 t = __half22float2(U[a][b]);
-            r[a][b] = {t.x, t.y};
-        }
+        for (int b = 0; b < 3; ++b) U[a][b] = u16[elem(g, l, s, 24, mu * 6 + a * 3 + b)];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
-        const cx<float> v = conj(r[0][b1] * r[1][b2] - r[0][b2] * r[1][b1]);
-        U[2][b] = __floats2half2_rn(v.re, v.im);
+        const h2 p = U[0][b1], q = U[1][b2], r = U[0][b2], t = U[1][b1];  // conj(p q - r t)
+        const float pr = __low2float(p), pi = __high2float(p), qr = __low2float(q), qi = __high2float(q);
+        const float rr = __low2float(r), ri = __high2float(r), tr = __low2float(t), ti = __high2float(t);
+        const float re = pr * qr - pi * qi - rr * tr + ri * ti;
+        const float im = pr * qi + pi * qr - rr * ti - ri * tr;
+        U[2][b] = __floats2half2_rn(re, -im);
+    }
+}
+
+// o = fa a + fb b + fx x + ft t, component by component, accumulated in FP32 from the
+// FP16 pair-form inputs
+DD_INL void combine_pair(const SpH &a, float fa, const SpH &b, float fb, const SpH &x, float fx, const SpH &t,
+                         float ft, Spinor<float> &o)
+{
+    auto lo = [&](h2 A, h2 B, h2 X, h2 T) {
+        return fa * __low2float(A) + fb * __low2float(B) + fx * __low2float(X) + ft * __low2float(T);
+    };
+    auto hi = [&](h2 A, h2 B, h2 X, h2 T) {
+        return fa * __high2float(A) + fb * __high2float(B) + fx * __high2float(X) + ft * __high2float(T);
+    };
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        o.v[0][c] = {lo(a.u[c].re, b.u[c].re, x.u[c].re, t.u[c].re), lo(a.u[c].im, b.u[c].im, x.u[c].im, t.u[c].im)};
+        o.v[1][c] = {hi(a.u[c].re, b.u[c].re, x.u[c].re, t.u[c].re), hi(a.u[c].im, b.u[c].im, x.u[c].im, t.u[c].im)};
+        o.v[2][c] = {lo(a.l[c].re, b.l[c].re, x.l[c].re, t.l[c].re), lo(a.l[c].im, b.l[c].im, x.l[c].im, t.l[c].im)};
+        o.v[3][c] = {hi(a.l[c].re, b.l[c].re, x.l[c].re, t.l[c].re), hi(a.l[c].im, b.l[c].im, x.l[c].im, t.l[c].im)};
     }
 }
 
@@ -331,11 +366,11 @@ DD_INL void lds_link(const h2 *ul, int bvol, int s, int mu, h2 (&U)[3][3])
         for (int b = 0; b < 3; ++b) U[a][b] = ul[(mu * 9 + a * 3 + b) * bvol + s];
 }
 
-// acc = H_in x in pair form (hops inside the block, Dirichlet at its faces)
-DD_INL void inblock_pair(const uint4 *xs, const h2 *ul, const Geom &g, const Site &st, SpH &acc)
+// acc = H_in x in pair form (hops inside the block, Dirichlet at its faces); bvol is
+// the block volume (a compile-time constant where the kernel is specialised for it)
+DD_INL void inblock_pair(const uint4 *xs, const h2 *ul, const Geom &g, int bvol, const Site &st, SpH &acc)
 {
     zero(acc);
-    const int bvol = g.bvol;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         const int stride = 1 << g.sh[mu];
@@ -371,12 +406,28 @@ DD_INL int face_offset(const Geom &g, int mu, int side)
 }
 
 // One half-sweep with FP16 arithmetic; same flags and result (up to FP16
-// rounding) as k_sap_half<2>.
-__global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int flags, SpinorField<2> bsrc,
+// rounding) as k_sap_half<2>.  B > 0 fixes the block shape to B^4 at compile time:
+// the block extents, in-block strides and the block volume become constants, so
+// every LDS offset of the sweeps is an immediate instead of a register and the
+// face-hop index arithmetic folds; B = 0 takes the shape from the geometry.
+template <int B>
+__global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int flags, SpinorField<2> bsrc,
                                                      SpinorField<2> sw, SpinorField<2> xw, const __half2 *u16,
                                                      CloverField<2> Ci, Phase4 ph, float kappa, int n_jac)
 {
     extern __shared__ uint4 smem_pk[];
+    Geom g = gin;
+    if (B > 0) {
+        constexpr int lb = B == 2 ? 1 : B == 4 ? 2 : 3;
+        static_assert(B == 0 || B == 2 || B == 4 || B == 8, "block side");
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            g.b[mu] = B;
+            g.sh[mu] = mu * lb;
+        }
+        g.bvol = B * B * B * B;
+        g.lbvol = 4 * lb;
+    }
     const int bvol = g.bvol;
     uint4 *xs = smem_pk;                                    // 3 x bvol uint4
     h2 *ul = reinterpret_cast<h2 *>(xs + 3 * bvol);         // 36 x bvol half2
@@ -531,59 +582,53 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom g, int colour, int fla
     for (int q = 0; q < (bvol + 63) / 64; ++q) m = fmaxf(m, wmax[q]);
     const float sc = m > 0.f ? 1.f / m : 0.f;
 
-    SpH sh, hp, x, acc, t;
-    scale_pair(sraw, ssc * sc, sh);
-    to_pair(hc, sc, hp);
+    // x0 = s_c + kappa C_inv h (normalised): the first Jacobi step from x = 0; every later
+    // step is x <- x0 + kappa C_inv H_in x
+    SpH x0, x, acc, t;
+    scale_pair(sraw, ssc * sc, x0);
     const h2 K = __float2half2_rn(kappa);
-    // x_0 = s_c + kappa C_inv h: one Jacobi step from x = 0
     if (pre) {
+        SpH hp;
+        to_pair(hc, sc, hp);
         clover_pair(CP, hp, t);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            x.u[c].re = fma2(K, t.u[c].re, sh.u[c].re);
-            x.u[c].im = fma2(K, t.u[c].im, sh.u[c].im);
-            x.l[c].re = fma2(K, t.l[c].re, sh.l[c].re);
-            x.l[c].im = fma2(K, t.l[c].im, sh.l[c].im);
+            x0.u[c].re = fma2(K, t.u[c].re, x0.u[c].re);
+            x0.u[c].im = fma2(K, t.u[c].im, x0.u[c].im);
+            x0.l[c].re = fma2(K, t.l[c].re, x0.l[c].re);
+            x0.l[c].im = fma2(K, t.l[c].im, x0.l[c].im);
         }
-    } else {
-        x = sh;
     }
+    x = x0;
     for (int j = 0; j < n_jac; ++j) {
         __syncthreads();
         lds_put(xs, bvol, st.s, x);
         __syncthreads();
-        inblock_pair(xs, ul, g, st, acc);
-        if (pre) add_pair(acc, hp);
+        inblock_pair(xs, ul, g, bvol, st, acc);
         clover_pair(CP, acc, t);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            x.u[c].re = fma2(K, t.u[c].re, sh.u[c].re);
-            x.u[c].im = fma2(K, t.u[c].im, sh.u[c].im);
-            x.l[c].re = fma2(K, t.l[c].re, sh.l[c].re);
-            x.l[c].im = fma2(K, t.l[c].im, sh.l[c].im);
+            x.u[c].re = fma2(K, t.u[c].re, x0.u[c].re);
+            x.u[c].im = fma2(K, t.u[c].im, x0.u[c].im);
+            x.l[c].re = fma2(K, t.l[c].re, x0.l[c].re);
+            x.l[c].im = fma2(K, t.l[c].im, x0.l[c].im);
         }
     }
     const float inv = m;  // undo the normalisation
     Spinor<float> xf;
     from_pair(x, inv, xf);
     if (!(flags & SAP_TAIL)) {
-        // s_c <- s_c + b_c - x_c + kappa C_inv (H_in x_c + h)
+        // s_c <- (s_c + kappa C_inv h) + b_c - x_c + kappa C_inv H_in x_c, in FP32
         __syncthreads();
         lds_put(xs, bvol, st.s, x);
         __syncthreads();
-        inblock_pair(xs, ul, g, st, acc);
-        if (pre) add_pair(acc, hp);
+        inblock_pair(xs, ul, g, bvol, st, acc);
         clover_pair(CP, acc, t);
-        Spinor<float> tf, b, src;
-        from_pair(t, inv, tf);
-        from_pair(sraw, ssc, src);
-        bsrc.load(g, st.l, st.s, b);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                src.v[a][c] = src.v[a][c] + b.v[a][c] - xf.v[a][c] + kappa * tf.v[a][c];
-        sw.store(g, st.l, st.s, src);
+        SpH braw;
+        const float sb = load_pair(bsrc, g, st.l, st.s, braw);
+        Spinor<float> snew;
+        combine_pair(x0, inv, braw, sb, x, -inv, t, kappa * inv, snew);
+        sw.store(g, st.l, st.s, snew);
     }
     xw.store(g, st.l, st.s, xf);
 }
@@ -604,7 +649,9 @@ hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, i
     auto sfh = [&](void *p) {
         return SpinorField<2>{(__half2 *)p, (float *)((char *)p + 12 * g.V * sizeof(__half2))};
     };
-    hipLaunchKernelGGL(k_sap_half_pk, dim3(g.nblk / 2), dim3(g.bvol), sap_pk_lds_bytes(g), st, g, colour, flags,
+    const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
+    auto kern = cube4 ? k_sap_half_pk<4> : k_sap_half_pk<0>;
+    hipLaunchKernelGGL(kern, dim3(g.nblk / 2), dim3(g.bvol), sap_pk_lds_bytes(g), st, g, colour, flags,
                        sfh((void *)a.b), sfh(a.s), sfh(a.x), (const __half2 *)a.links,
                        CloverField<2>{(const __half2 *)a.cinv}, a.phase, (float)a.kappa, a.n_jac);
     return hipGetLastError();
