@@ -331,6 +331,37 @@ DD_INL void combine_pair(const SpH &a, float fa, const SpH &b, float fb, const S
     }
 }
 
+// acc += f (1 - s gamma_mu) rebuilt from the pair-form half spinor k, accumulated in
+// FP32 straight from the FP16 parts (mixed-precision FMAs)
+DD_INL void recon_mix(int mu, int s, const PC (&k)[3], float f, Spinor<float> &acc)
+{
+    const float fs = s > 0 ? f : -f;
+    auto add = [](cx<float> &a, float fr, float fi) { a = {a.re + fr, a.im + fi}; };
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float r0 = __low2float(k[c].re), r1 = __high2float(k[c].re);
+        const float i0 = __low2float(k[c].im), i1 = __high2float(k[c].im);
+        if (mu == 3) {
+            const int o = s > 0 ? 2 : 0;
+            add(acc.v[o][c], f * r0, f * i0);
+            add(acc.v[o + 1][c], f * r1, f * i1);
+            continue;
+        }
+        add(acc.v[0][c], f * r0, f * i0);
+        add(acc.v[1][c], f * r1, f * i1);
+        if (mu == 0) {  // (acc2, acc3) += s i (k1, k0)
+            add(acc.v[2][c], -fs * i1, fs * r1);
+            add(acc.v[3][c], -fs * i0, fs * r0);
+        } else if (mu == 1) {  // (acc2, acc3) += s (k1, -k0)
+            add(acc.v[2][c], fs * r1, fs * i1);
+            add(acc.v[3][c], -fs * r0, -fs * i0);
+        } else {  // (acc2, acc3) += s i (k0, -k1)
+            add(acc.v[2][c], -fs * i0, fs * r0);
+            add(acc.v[3][c], fs * i1, -fs * r1);
+        }
+    }
+}
+
 // LDS: the Jacobi iterate as 3 x uint4 per site (one colour: u.re, u.im, l.re, l.im)
 DD_INL void lds_put(uint4 *xs, int bvol, int s, const SpH &p)
 {
@@ -388,9 +419,6 @@ DD_INL void inblock_pair(const uint4 *xs, const h2 *ul, const Geom &g, int bvol,
     }
 }
 
-// a[mu] for a lane-varying mu, as selects
-DD_INL int pick4(int mu, int a0, int a1, int a2, int a3) { return mu == 0 ? a0 : mu == 1 ? a1 : mu == 2 ? a2 : a3; }
-
 // log2 of the block extent in direction nu
 DD_INL int log2b(const Geom &g, int nu) { return (nu < 3 ? g.sh[nu + 1] : g.lbvol) - g.sh[nu]; }
 
@@ -403,6 +431,44 @@ DD_INL int face_offset(const Geom &g, int mu, int side)
     for (int nu = 0; nu < 4; ++nu)
         if (nu < mu) o += 2 * (g.bvol >> log2b(g, nu));
     return o + side * (g.bvol >> log2b(g, mu));
+}
+
+// One face hop of the block st.l in direction MU, side DIR (kk: the hop's index on the
+// face, the other three in-block coordinates in order): the neighbouring block's
+// spinor at the opposite face, spin-projected and multiplied by U (forward) or
+// U^dagger (backward), parked in LDS (pair form, relative to the neighbour's storage
+// scale) with that scale
+template <int MU, int DIR>
+DD_INL void face_hop(const Geom &g, const Site &st, int kk, int p, int P, const SpinorField<2> &xw, const __half2 *u16,
+                     h2 *fk, float *fsc)
+{
+    const int bm = g.b[MU], shm = g.sh[MU];
+    int fsite = (DIR > 0 ? bm - 1 : 0) << shm;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == MU) continue;
+        fsite += (kk & (g.b[nu] - 1)) << g.sh[nu];
+        kk >>= log2b(g, nu);
+    }
+    int lj = st.l + DIR * g.bstride[MU];
+    if (st.B[MU] + DIR < 0)
+        lj += g.NB[MU] * g.bstride[MU];
+    else if (st.B[MU] + DIR >= g.NB[MU])
+        lj -= g.NB[MU] * g.bstride[MU];
+    const int sj = fsite - DIR * ((bm - 1) << shm);
+    SpH ps;
+    const float scj = load_pair(xw, g, lj, sj, ps);
+    h2 U[3][3];  // U_mu at the face site (forward) or at its neighbour (backward)
+    load_link_pair(u16, g, DIR > 0 ? st.l : lj, DIR > 0 ? fsite : sj, MU, U);
+    PC h[3], k[3];
+    proj_pair(MU, DIR, ps, h);
+    mat_pair(U, DIR < 0, h, k);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        fk[(2 * c) * P + p] = k[c].re;
+        fk[(2 * c + 1) * P + p] = k[c].im;
+    }
+    fsc[p] = scj;
 }
 
 // One half-sweep with FP16 arithmetic; same flags and result (up to FP16
@@ -475,43 +541,17 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
                     }
                 }
             }
-            const int mu = q >> 1, side = q & 1, dir = side ? -1 : 1;
-            // the face site (c_mu on the face, the other three in-block coordinates from
-            // the hop's index in order) and its neighbour on the opposite face of the next
-            // block in direction dir; selects instead of indexing by the lane's mu keep the
-            // site arrays in registers
-            const int bm = pick4(mu, g.b[0], g.b[1], g.b[2], g.b[3]);
-            const int shm = pick4(mu, g.sh[0], g.sh[1], g.sh[2], g.sh[3]);
-            const int Bm = pick4(mu, st.B[0], st.B[1], st.B[2], st.B[3]);
-            const int NBm = pick4(mu, g.NB[0], g.NB[1], g.NB[2], g.NB[3]);
-            const int bsm = pick4(mu, g.bstride[0], g.bstride[1], g.bstride[2], g.bstride[3]);
-            int kk = p - base;
-            int fsite = (side ? 0 : bm - 1) << shm;
-#pragma unroll
-            for (int nu = 0; nu < 4; ++nu) {
-                if (nu == mu) continue;
-                fsite += (kk & (g.b[nu] - 1)) << g.sh[nu];
-                kk >>= log2b(g, nu);
+            const int kk = p - base;
+            switch (q) {  // faces in order +x, -x, +y, -y, +z, -z, +t, -t
+            case 0: face_hop<0, 1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
+            case 1: face_hop<0, -1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
+            case 2: face_hop<1, 1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
+            case 3: face_hop<1, -1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
+            case 4: face_hop<2, 1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
+            case 5: face_hop<2, -1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
+            case 6: face_hop<3, 1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
+            default: face_hop<3, -1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
             }
-            int lj = st.l + dir * bsm;
-            if (Bm + dir < 0)
-                lj += NBm * bsm;
-            else if (Bm + dir >= NBm)
-                lj -= NBm * bsm;
-            const int sj = fsite - dir * ((bm - 1) << shm);
-            SpH ps;
-            const float scj = load_pair(xw, g, lj, sj, ps);
-            h2 U[3][3];  // U_mu at the face site (forward) or at its neighbour (backward)
-            load_link_pair(u16, g, dir > 0 ? st.l : lj, dir > 0 ? fsite : sj, mu, U);
-            PC h[3], k[3];
-            proj_pair(mu, dir, ps, h);
-            mat_pair(U, dir < 0, h, k);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                fk[(2 * c) * P + p] = k[c].re;
-                fk[(2 * c + 1) * P + p] = k[c].im;
-            }
-            fsc[p] = scj;
         }
         __syncthreads();
         // per site: at most one face per direction (blocks are at least 2 wide)
@@ -529,27 +569,22 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
                 w8 += log2b(g, nu);
             }
             const int p = face_offset(g, mu, hi ? 0 : 1) + kk;
-            const float scj = fsc[p];
-            Half<float> k;
+            PC k[3];
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
-                const float2 re = __half22float2(fk[(2 * cc) * P + p]), im = __half22float2(fk[(2 * cc + 1) * P + p]);
-                k.v[0][cc] = {scj * re.x, scj * im.x};
-                k.v[1][cc] = {scj * re.y, scj * im.y};
-            }
+            for (int cc = 0; cc < 3; ++cc) k[cc] = PC{fk[(2 * cc) * P + p], fk[(2 * cc + 1) * P + p]};
             if (hi ? st.B[mu] == g.NB[mu] - 1 : st.B[mu] == 0) {  // the hop crosses the lattice edge
-                const cx<float> phase = {(float)ph.re[mu], (float)(hi ? ph.im[mu] : -ph.im[mu])};
+                const h2 pr = __float2half2_rn((float)ph.re[mu]);
+                const h2 pi = __float2half2_rn((float)(hi ? ph.im[mu] : -ph.im[mu]));
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) k.v[a][cc] = k.v[a][cc] * phase;
+                for (int cc = 0; cc < 3; ++cc)
+                    k[cc] = PC{fma2(pr, k[cc].re, mul2(neg2(pi), k[cc].im)), fma2(pr, k[cc].im, mul2(pi, k[cc].re))};
             }
             if (mu < 3)
-                reconstruct(mu, dir, k, hc);
-            else if (hi)
-                reconstruct(3, 1, k, hc);
+                recon_mix(mu, dir, k, fsc[p], hc);
+            else if (hi)  // the spin pair that gamma_4 keeps depends on the side
+                recon_mix(3, 1, k, fsc[p], hc);
             else
-                reconstruct(3, -1, k, hc);
+                recon_mix(3, -1, k, fsc[p], hc);
         }
         __syncthreads();  // the face buffer is about to become the link staging area
     }
