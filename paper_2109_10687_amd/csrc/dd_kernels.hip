@@ -620,6 +620,91 @@ __global__ void __launch_bounds__(BLAS_WG) k_pupdate(Geom g, SpinorField<PR> p, 
     }
 }
 
+// Fused updates of the mixed-precision BiCGStab (FP32 vectors, FP16-storage SAP
+// inputs and outputs): the FP16 copy of r or p that the next SAP application reads
+// is written by the update that produces the vector, one site per thread (the FP16
+// storage scale belongs to the whole site), instead of by a separate conversion
+// pass that reads the vector again.  The grid is the vector kernels' grid, so the
+// partial sums line up with the finalising reduction.
+#define SITE_STRIDE(i) for (long long i = (long long)blockIdx.x * BLAS_WG + threadIdx.x; i < g.V; i += (long long)gridDim.x * BLAS_WG)
+
+// r -= alpha q ; partial |r|^2 ; r16 = r
+__global__ void __launch_bounds__(BLAS_WG) k_update1_h(Geom g, SpinorField<1> r, SpinorField<1> q, SpinorField<2> r16,
+                                                       double are, double aim, double *partials)
+{
+    double v[1] = {0};
+    const cx<double> al = {are, aim};
+    SITE_STRIDE(i)
+    {
+        const int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
+        Spinor<float> rs;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long long o = elem(g, l, s, 12, a * 3 + c);
+                const cx<double> rr = Elem<1>::get(r, g, o) - al * Elem<1>::get(q, g, o);
+                Elem<1>::put(r, g, o, rr);
+                rs.v[a][c] = {(float)rr.re, (float)rr.im};  // the stored (rounded) value
+                v[0] += norm2(cx<double>{(double)rs.v[a][c].re, (double)rs.v[a][c].im});
+            }
+        r16.store(g, l, s, rs);
+    }
+    wg_reduce_store<1>(v, partials);
+}
+
+// x += alpha y1 + omega y2 ; r -= omega t ; partial |r|^2 and <rt|r>
+template <int PY>
+__global__ void __launch_bounds__(BLAS_WG) k_update2_mm(Geom g, SpinorField<1> x, SpinorField<PY> y1, SpinorField<PY> y2,
+                                                        SpinorField<1> r, SpinorField<1> t, SpinorField<1> rt,
+                                                        double are, double aim, double ore, double oim, double *partials)
+{
+    double v[3] = {0, 0, 0};
+    const cx<double> al = {are, aim}, om = {ore, oim};
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        Elem<1>::put(x, g, o, Elem<1>::get(x, g, o) + al * Elem<PY>::get(y1, g, o) + om * Elem<PY>::get(y2, g, o));
+        cx<double> rr = Elem<1>::get(r, g, o) - om * Elem<1>::get(t, g, o);
+        Elem<1>::put(r, g, o, rr);
+        rr = Elem<1>::get(r, g, o);
+        v[0] += norm2(rr);
+        const cx<double> d = cmulc(Elem<1>::get(rt, g, o), rr);
+        v[1] += d.re;
+        v[2] += d.im;
+    }
+    wg_reduce_store<3>(v, partials);
+}
+
+// p = r + beta (p - omega q) ; p16 = p
+__global__ void __launch_bounds__(BLAS_WG) k_pupdate_h(Geom g, SpinorField<1> p, SpinorField<1> r, SpinorField<1> q,
+                                                       SpinorField<2> p16, double bre, double bim, double ore, double oim)
+{
+    const cx<double> be = {bre, bim}, om = {ore, oim};
+    SITE_STRIDE(i)
+    {
+        const int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
+        Spinor<float> ps;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long long o = elem(g, l, s, 12, a * 3 + c);
+                const cx<double> pv = Elem<1>::get(r, g, o) + be * (Elem<1>::get(p, g, o) - om * Elem<1>::get(q, g, o));
+                Elem<1>::put(p, g, o, pv);
+                ps.v[a][c] = {(float)pv.re, (float)pv.im};
+            }
+        p16.store(g, l, s, ps);
+    }
+}
+
+// x += alpha y (complex alpha)
+template <int PY>
+__global__ void __launch_bounds__(BLAS_WG) k_caxpy(Geom g, SpinorField<1> x, SpinorField<PY> y, double are, double aim)
+{
+    const cx<double> al = {are, aim};
+    GRID_STRIDE(o, 12 * g.V) Elem<1>::put(x, g, o, Elem<1>::get(x, g, o) + al * Elem<PY>::get(y, g, o));
+}
+
 // y = a (copy with precision conversion; FP16 targets go through a per-site kernel)
 template <int PA, int PY>
 __global__ void __launch_bounds__(BLAS_WG) k_copy(Geom g, SpinorField<PY> y, SpinorField<PA> a)
@@ -1031,6 +1116,34 @@ hipError_t launch_blas(const Geom &g, hipStream_t st, const BlasArgs &a)
             return hipErrorInvalidValue;
         break;
     }
+    case BLAS_UPDATE1_H:  // r -= c01 q ; |r|^2 ; v2 = r (FP16)
+        hipLaunchKernelGGL(k_update1_h, G, B, 0, st, g, sf<1>(a.v[0], g), sf<1>(a.v[1], g), sf<2>(a.v[2], g), a.c[0],
+                           a.c[1], a.partials);
+        break;
+    case BLAS_UPDATE2_MM:  // y += c01 v1 + c23 v2 ; r -= c23 t ; |r|^2, <rt|r>
+        if (a.p[1] == 2)
+            hipLaunchKernelGGL((k_update2_mm<2>), G, B, 0, st, g, sf<1>(a.v[0], g), sf<2>(a.v[1], g), sf<2>(a.v[2], g),
+                               sf<1>(a.v[3], g), sf<1>(a.v[4], g), sf<1>(a.v[5], g), a.c[0], a.c[1], a.c[2], a.c[3],
+                               a.partials);
+        else if (a.p[1] == 1)
+            hipLaunchKernelGGL((k_update2_mm<1>), G, B, 0, st, g, sf<1>(a.v[0], g), sf<1>(a.v[1], g), sf<1>(a.v[2], g),
+                               sf<1>(a.v[3], g), sf<1>(a.v[4], g), sf<1>(a.v[5], g), a.c[0], a.c[1], a.c[2], a.c[3],
+                               a.partials);
+        else
+            return hipErrorInvalidValue;
+        break;
+    case BLAS_PUPDATE_H:  // p = r + c01 (p - c23 q) ; v3 = p (FP16)
+        hipLaunchKernelGGL(k_pupdate_h, G, B, 0, st, g, sf<1>(a.v[0], g), sf<1>(a.v[1], g), sf<1>(a.v[2], g),
+                           sf<2>(a.v[3], g), a.c[0], a.c[1], a.c[2], a.c[3]);
+        break;
+    case BLAS_CAXPY:  // v0 += c01 v1
+        if (a.p[1] == 2)
+            hipLaunchKernelGGL((k_caxpy<2>), G, B, 0, st, g, sf<1>(a.v[0], g), sf<2>(a.v[1], g), a.c[0], a.c[1]);
+        else if (a.p[1] == 1)
+            hipLaunchKernelGGL((k_caxpy<1>), G, B, 0, st, g, sf<1>(a.v[0], g), sf<1>(a.v[1], g), a.c[0], a.c[1]);
+        else
+            return hipErrorInvalidValue;
+        break;
     default:
         return hipErrorInvalidValue;
     }

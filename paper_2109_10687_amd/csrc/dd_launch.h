@@ -64,12 +64,16 @@ enum BlasKind {
     BLAS_SUB_NORM,
     BLAS_CONVERT,
     BLAS_CINV_SRC,
+    BLAS_UPDATE1_H,  // FP32 r -= c01 q ; |r|^2 ; v2 = r in FP16 storage (the next SAP input)
+    BLAS_UPDATE2_MM, // FP32 y += c01 v1 + c23 v2 (FP16 v1, v2) ; r -= c23 t ; |r|^2, <rt|r>
+    BLAS_PUPDATE_H,  // FP32 p = r + c01 (p - c23 q) ; v3 = p in FP16 storage
+    BLAS_CAXPY,      // v0 += c01 v1 (FP32 v0, v1 at precision p1)
 };
 
 struct BlasArgs {
     int kind;
-    void *v[5];
-    int p[5];
+    void *v[6];
+    int p[6];
     double c[4];
     double *partials;
 };

@@ -214,6 +214,10 @@ dd_status blas(dd_ctx *c, dd::BlasArgs a)
     case dd::BLAS_SUB_NORM: rw = 3 * P0; fl = 72; break;
     case dd::BLAS_CONVERT: rw = P0 + P1; break;
     case dd::BLAS_CINV_SRC: rw = sp_b(1) + P1 + cl_b(1); fl = CLOVF; break;
+    case dd::BLAS_UPDATE1_H: rw = 3 * sp_b(1) + sp_b(2); fl = 144; break;                 // r r/w, q, r16 written
+    case dd::BLAS_UPDATE2_MM: rw = 4 * sp_b(1) + 2 * P1 + 2 * sp_b(1); fl = 432; break;  // y, r r/w; Mp, Mr; t, rt
+    case dd::BLAS_PUPDATE_H: rw = 4 * sp_b(1) + sp_b(2); fl = 192; break;                 // p r/w, r, q, p16 written
+    case dd::BLAS_CAXPY: rw = 2 * sp_b(1) + P1; fl = 96; break;
     }
     const double V = (double)c->g.V;
     hipError_t e = timed(c, DD_KT_BLAS, V * rw, V * fl, [&] { return dd::launch_blas(c->g, c->stream, a); });

@@ -113,6 +113,9 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
     void *Mr = prec == 1 ? c->f32[8] : c->f16[3];
     void *s = prec == 1 ? c->f32[9] : c->f16[4];
     void *p16 = c->f16[0], *r16 = c->f16[1];
+    // FP16 SAP: the updates that produce r and p also write their FP16 copies (the SAP's
+    // inputs), and y takes alpha Mp + omega Mr in one pass per iteration
+    const bool fused = prec == 2;
     dd_status st;
     HIPCK(c, hipMemsetAsync(y, 0, spinor_bytes(c->g, DD_F32), c->stream));
     double bn2;
@@ -124,17 +127,24 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
     if ((st = copy(c, r, 1, src, 1)) != DD_OK) return st;
     if ((st = copy(c, p, 1, src, 1)) != DD_OK) return st;
     if ((st = copy(c, rt, 1, src, 1)) != DD_OK) return st;
+    if (fused && (st = copy(c, p16, 2, src, 1)) != DD_OK) return st;
     cplx rho0 = bn2;
     double rn2 = bn2;
     auto precond = [&](void *in, void *in16, void *Mout, void *Aout) -> dd_status {
         dd_status s2;
         const void *bsrc = in;
         if (prec == 2) {
-            if ((s2 = copy(c, in16, 2, in, 1)) != DD_OK) return s2;
+            if (!fused && (s2 = copy(c, in16, 2, in, 1)) != DD_OK) return s2;
             bsrc = in16;
         }
         if ((s2 = k_sap(c, prec, bsrc, Mout, s)) != DD_OK) return s2;
         return k_dirac(c, Aout, Mout, prec, 1, 1, 1);
+    };
+    cplx alpha = 0.0;
+    // with the fused updates y lacks alpha Mp between the two half steps: add it on an exit there
+    auto settle_y = [&]() -> dd_status {
+        if (!fused) return DD_OK;
+        return blas(c, mkb(dd::BLAS_CAXPY, {y, Mp}, {1, prec}, {alpha.real(), alpha.imag()}));
     };
     for (int it = 0; it < maxiter; ++it) {
         o.iters = it + 1;
@@ -147,12 +157,14 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
             o.relres = std::sqrt(rn2 / bn2);
             return DD_BREAKDOWN;
         }
-        cplx alpha = rho0 / rq;
-        if ((st = reduce(c, mkb(dd::BLAS_UPDATE1, {y, Mp, r, q}, {1, prec, 1}, {alpha.real(), alpha.imag()}), 1,
-                         &rn2)) != DD_OK)
-            return st;
+        alpha = rho0 / rq;
+        if (fused)
+            st = reduce(c, mkb(dd::BLAS_UPDATE1_H, {r, q, r16}, {1, 1, 2}, {alpha.real(), alpha.imag()}), 1, &rn2);
+        else
+            st = reduce(c, mkb(dd::BLAS_UPDATE1, {y, Mp, r, q}, {1, prec, 1}, {alpha.real(), alpha.imag()}), 1, &rn2);
+        if (st != DD_OK) return st;
         o.relres = std::sqrt(rn2 / bn2);
-        if (o.relres < tol) return DD_OK;
+        if (o.relres < tol) return settle_y();
         if (c->verbose && (it + 1) % 100 == 0) {
             std::fprintf(stderr, "[ddsolve] inner iteration %d: relative residual %.3e\n", it + 1, o.relres);
             std::fflush(stderr);
@@ -161,12 +173,17 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
         if ((st = reduce(c, mkb(dd::BLAS_DOT_NORM, {t, r}, {1, 1}), 3, d)) != DD_OK) return st;
         if (d[2] == 0.0 || !is_fin(d[2])) {
             o.detail = d[2] == 0.0 ? 2 : 4;
+            if ((st = settle_y()) != DD_OK) return st;
             return DD_BREAKDOWN;
         }
         cplx omega = cplx(d[0], d[1]) / d[2];
-        if ((st = reduce(c, mkb(dd::BLAS_UPDATE2, {y, Mr, r, t, rt}, {1, prec, 1}, {omega.real(), omega.imag()}), 3,
-                         d)) != DD_OK)
-            return st;
+        if (fused)
+            st = reduce(c, mkb(dd::BLAS_UPDATE2_MM, {y, Mp, Mr, r, t, rt}, {1, prec, 1, 1, 1, 1},
+                               {alpha.real(), alpha.imag(), omega.real(), omega.imag()}),
+                        3, d);
+        else
+            st = reduce(c, mkb(dd::BLAS_UPDATE2, {y, Mr, r, t, rt}, {1, prec, 1}, {omega.real(), omega.imag()}), 3, d);
+        if (st != DD_OK) return st;
         rn2 = d[0];
         cplx rho(d[1], d[2]);
         o.relres = std::sqrt(rn2 / bn2);
@@ -181,9 +198,12 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
             return DD_BREAKDOWN;
         }
         rho0 = rho;
-        if ((st = blas(c, mkb(dd::BLAS_PUPDATE, {p, r, q}, {1, 1, 1},
-                              {beta.real(), beta.imag(), omega.real(), omega.imag()}))) != DD_OK)
-            return st;
+        if (fused)
+            st = blas(c, mkb(dd::BLAS_PUPDATE_H, {p, r, q, p16}, {1, 1, 1, 2},
+                             {beta.real(), beta.imag(), omega.real(), omega.imag()}));
+        else
+            st = blas(c, mkb(dd::BLAS_PUPDATE, {p, r, q}, {1, 1, 1}, {beta.real(), beta.imag(), omega.real(), omega.imag()}));
+        if (st != DD_OK) return st;
     }
     return DD_NOT_CONVERGED;
 }
