@@ -52,12 +52,14 @@ dd_status fetch_red(dd_ctx *c, int n, double *out)
     return DD_OK;
 }
 
-// out = A in for n FP32 batched fields (internal layout, contiguous), tiles of up to 12 on the
-// matrix cores; the variant is the caller's, or the autotuner's choice for this tile size
-dd_status mrhs_launch(dd_ctx *c, int v, void *out, const void *in, int n)
+// out = A in for n batched fields (internal layout, contiguous) at input precision pin (FP32,
+// or FP16 storage), FP32 output; FP32 inputs run the variant v
+dd_status mrhs_launch(dd_ctx *c, int v, void *out, const void *in, int n, int pin = DD_F32)
 {
     dd::MrhsArgs a{};
     a.in = (const float2 *)in;
+    a.in16 = in;
+    a.pin = pin;
     a.out = (float2 *)out;
     a.u = (const float2 *)c->U32;
     a.cinv = (const float2 *)c->cinv32;
@@ -65,7 +67,7 @@ dd_status mrhs_launch(dd_ctx *c, int v, void *out, const void *in, int n)
     a.kappa = c->prm.kappa;
     a.phase = c->phase;
     const double V = (double)c->g.V;
-    const double bytes = V * (n * 2.0 * sp_b(DD_F32) + 4 * lk_b(DD_F32) + cl_b(DD_F32));
+    const double bytes = V * (n * (sp_b(pin) + sp_b(DD_F32)) + 4 * lk_b(DD_F32) + cl_b(DD_F32));
     const double flops = V * n * (hops_in(c->g) + hops_out(c->g) + CLOVF);
     hipError_t e = timed(c, DD_KT_DIRAC_MRHS, bytes, flops, [&] { return dd::launch_dirac_mrhs(c->g, c->stream, a, v); });
     if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("multi-RHS dirac launch: ") + hipGetErrorString(e));
@@ -103,13 +105,18 @@ dd_status mrhs_tune(dd_ctx *c, int n, void *out, const void *in)
     return DD_OK;
 }
 
-dd_status k_dirac_mrhs(dd_ctx *c, void *out, const void *in, int n)
+dd_status k_dirac_mrhs(dd_ctx *c, void *out, const void *in, int n, int pin)
 {
-    const size_t fb = spinor_bytes(c->g, DD_F32);
+    const size_t fb = spinor_bytes(c->g, DD_F32), fi = spinor_bytes(c->g, pin);
     for (int r0 = 0; r0 < n; r0 += 12) {
         const int m = n - r0 < 12 ? n - r0 : 12;
         void *o = (char *)out + r0 * fb;
-        const void *i = (const char *)in + r0 * fb;
+        const void *i = (const char *)in + r0 * fi;
+        if (pin == DD_F16) {  // FP16 inputs: the vector kernel, no autotuning
+            dd_status st = mrhs_launch(c, 8, o, i, m, DD_F16);
+            if (st != DD_OK) return st;
+            continue;
+        }
         int v = c->mrhs_force;
         if (v < 0) {
             if (c->mrhs_tuned[m] < 0) {
@@ -152,21 +159,27 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
         if (!b.active) continue;
         for (int k : {BK_R, BK_P, BK_RT})
             if ((st = copy(c, bf(c, k, r), 1, bf(c, BK_SRC, r), 1)) != DD_OK) return st;
+        if (sap && (st = copy(c, bf(c, BK_P16, r), 2, bf(c, BK_SRC, r), 1)) != DD_OK) return st;
     }
-    const int mp = sap ? BK_MP : BK_P, mr = sap ? BK_MR : BK_R;
+    const int mp = sap ? BK_MP16 : BK_P, mr = sap ? BK_MR16 : BK_R;
     // M = the FP16-storage SAP of each right-hand side (as in the single right-hand-side
-    // mixed solver), its output widened to FP32 for the batched A
-    auto precond = [&](int from, int to) -> dd_status {
+    // mixed solver), reading the FP16 copies of r and p that the updates write and writing
+    // FP16 fields that the batched A reads as they are
+    auto precond = [&](int from16, int to16) -> dd_status {
         if (!sap) return DD_OK;
-        void *in16 = c->f16[0], *out16 = c->f16[2], *s16 = c->f16[4];
+        void *s16 = c->f16[4];
         for (int r = 0; r < n; ++r) {
             if (!R[r].active) continue;
             dd_status s2;
-            if ((s2 = copy(c, in16, 2, bf(c, from, r), 1)) != DD_OK) return s2;
-            if ((s2 = k_sap(c, 2, in16, out16, s16)) != DD_OK) return s2;
-            if ((s2 = copy(c, bf(c, to, r), 1, out16, 2)) != DD_OK) return s2;
+            if ((s2 = k_sap(c, 2, bf(c, from16, r), bf(c, to16, r), s16)) != DD_OK) return s2;
         }
         return DD_OK;
+    };
+    // with the SAP, y takes alpha Mp + omega Mr in one pass; a right-hand side that stops
+    // between the two half steps gets its alpha Mp here
+    auto settle_y = [&](int r, cplx al) -> dd_status {
+        if (!sap) return DD_OK;
+        return blas(c, mkb(dd::BLAS_CAXPY, {bf(c, BK_Y, r), bf(c, BK_MP16, r)}, {1, 2}, {al.real(), al.imag()}));
     };
     auto stop = [&](BRhs &b, dd_status s2, int detail) {
         b.active = false;
@@ -175,8 +188,8 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
         --nact;
     };
     for (int it = 0; it < maxiter && nact > 0; ++it) {
-        if ((st = precond(BK_P, BK_MP)) != DD_OK) return st;
-        if ((st = k_dirac_mrhs(c, c->bk[BK_Q], c->bk[mp], n)) != DD_OK) return st;
+        if ((st = precond(BK_P16, BK_MP16)) != DD_OK) return st;
+        if ((st = k_dirac_mrhs(c, c->bk[BK_Q], c->bk[mp], n, sap ? DD_F16 : DD_F32)) != DD_OK) return st;
         for (int r = 0; r < n; ++r)
             if (R[r].active &&
                 (st = reduce_to(c, mkb(dd::BLAS_DOT, {bf(c, BK_RT, r), bf(c, BK_Q, r)}, {1, 1}), 2, 2 * r)) != DD_OK)
@@ -193,10 +206,15 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
                 continue;
             }
             alpha[r] = b.rho0 / rq;
-            if ((st = reduce_to(c, mkb(dd::BLAS_UPDATE1, {bf(c, BK_Y, r), bf(c, mp, r), bf(c, BK_R, r), bf(c, BK_Q, r)},
-                                       {1, 1, 1}, {alpha[r].real(), alpha[r].imag()}),
-                                1, r)) != DD_OK)
-                return st;
+            if (sap)
+                st = reduce_to(c, mkb(dd::BLAS_UPDATE1_H, {bf(c, BK_R, r), bf(c, BK_Q, r), bf(c, BK_R16, r)}, {1, 1, 2},
+                                      {alpha[r].real(), alpha[r].imag()}),
+                               1, r);
+            else
+                st = reduce_to(c, mkb(dd::BLAS_UPDATE1, {bf(c, BK_Y, r), bf(c, mp, r), bf(c, BK_R, r), bf(c, BK_Q, r)},
+                                      {1, 1, 1}, {alpha[r].real(), alpha[r].imag()}),
+                               1, r);
+            if (st != DD_OK) return st;
         }
         if ((st = fetch_red(c, n, red)) != DD_OK) return st;
         for (int r = 0; r < n; ++r) {
@@ -204,11 +222,14 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
             if (!b.active) continue;
             b.rn2 = red[r];
             b.o.relres = std::sqrt(b.rn2 / b.bn2);
-            if (b.o.relres < b.tol) stop(b, DD_OK, 0);
+            if (b.o.relres < b.tol) {
+                if ((st = settle_y(r, alpha[r])) != DD_OK) return st;
+                stop(b, DD_OK, 0);
+            }
         }
         if (nact == 0) break;
-        if ((st = precond(BK_R, BK_MR)) != DD_OK) return st;
-        if ((st = k_dirac_mrhs(c, c->bk[BK_T], c->bk[mr], n)) != DD_OK) return st;
+        if ((st = precond(BK_R16, BK_MR16)) != DD_OK) return st;
+        if ((st = k_dirac_mrhs(c, c->bk[BK_T], c->bk[mr], n, sap ? DD_F16 : DD_F32)) != DD_OK) return st;
         for (int r = 0; r < n; ++r)
             if (R[r].active &&
                 (st = reduce_to(c, mkb(dd::BLAS_DOT_NORM, {bf(c, BK_T, r), bf(c, BK_R, r)}, {1, 1}), 3, 3 * r)) != DD_OK)
@@ -220,15 +241,24 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
             if (!b.active) continue;
             const double *d = red + 3 * r;
             if (d[2] == 0.0 || !is_fin(d[2])) {
+                if ((st = settle_y(r, alpha[r])) != DD_OK) return st;
                 stop(b, DD_BREAKDOWN, d[2] == 0.0 ? 2 : 4);
                 continue;
             }
             omega[r] = cplx(d[0], d[1]) / d[2];
-            if ((st = reduce_to(c, mkb(dd::BLAS_UPDATE2,
-                                       {bf(c, BK_Y, r), bf(c, mr, r), bf(c, BK_R, r), bf(c, BK_T, r), bf(c, BK_RT, r)},
-                                       {1, 1, 1}, {omega[r].real(), omega[r].imag()}),
-                                3, 3 * r)) != DD_OK)
-                return st;
+            if (sap)
+                st = reduce_to(c, mkb(dd::BLAS_UPDATE2_MM,
+                                      {bf(c, BK_Y, r), bf(c, BK_MP16, r), bf(c, BK_MR16, r), bf(c, BK_R, r),
+                                       bf(c, BK_T, r), bf(c, BK_RT, r)},
+                                      {1, 2, 2, 1, 1, 1},
+                                      {alpha[r].real(), alpha[r].imag(), omega[r].real(), omega[r].imag()}),
+                               3, 3 * r);
+            else
+                st = reduce_to(c, mkb(dd::BLAS_UPDATE2,
+                                      {bf(c, BK_Y, r), bf(c, mr, r), bf(c, BK_R, r), bf(c, BK_T, r), bf(c, BK_RT, r)},
+                                      {1, 1, 1}, {omega[r].real(), omega[r].imag()}),
+                               3, 3 * r);
+            if (st != DD_OK) return st;
         }
         if ((st = fetch_red(c, 3 * n, red)) != DD_OK) return st;
         for (int r = 0; r < n; ++r) {
@@ -252,9 +282,13 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
                 continue;
             }
             b.rho0 = rho;
-            if ((st = blas(c, mkb(dd::BLAS_PUPDATE, {bf(c, BK_P, r), bf(c, BK_R, r), bf(c, BK_Q, r)}, {1, 1, 1},
-                                  {beta.real(), beta.imag(), omega[r].real(), omega[r].imag()}))) != DD_OK)
-                return st;
+            if (sap)
+                st = blas(c, mkb(dd::BLAS_PUPDATE_H, {bf(c, BK_P, r), bf(c, BK_R, r), bf(c, BK_Q, r), bf(c, BK_P16, r)},
+                                 {1, 1, 1, 2}, {beta.real(), beta.imag(), omega[r].real(), omega[r].imag()}));
+            else
+                st = blas(c, mkb(dd::BLAS_PUPDATE, {bf(c, BK_P, r), bf(c, BK_R, r), bf(c, BK_Q, r)}, {1, 1, 1},
+                                 {beta.real(), beta.imag(), omega[r].real(), omega[r].imag()}));
+            if (st != DD_OK) return st;
         }
         if (c->verbose && (it + 1) % 100 == 0) {
             std::fprintf(stderr, "[ddsolve] batched inner iteration %d: %d right-hand sides still running\n", it + 1, nact);
@@ -518,7 +552,7 @@ dd_status dirac_apply_batch(dd_ctx *c, void *out, const void *in, int nrhs, dd_p
         for (int r = 0; r < m; ++r)
             HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F32, (char *)c->bk[BK_IN] + r * fb,
                                             (const char *)in + (r0 + r) * cb));
-        if ((st = k_dirac_mrhs(c, c->bk[BK_OUT], c->bk[BK_IN], m)) != DD_OK) return st;
+        if ((st = k_dirac_mrhs(c, c->bk[BK_OUT], c->bk[BK_IN], m, DD_F32)) != DD_OK) return st;
         for (int r = 0; r < m; ++r)
             HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F32, (char *)out + (r0 + r) * cb,
                                               (char *)c->bk[BK_OUT] + r * fb));

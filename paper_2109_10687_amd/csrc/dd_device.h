@@ -175,6 +175,27 @@ DD_INL long long elem(const Geom &g, int l, int s, int E, int e)
     return (((long long)l * E + e) << g.lbvol) + s;
 }
 
+// The geometry with the block shape fixed to B^4 at compile time (B = 2, 4, 8):
+// block extents, in-block strides and the block volume become constants, so the
+// compiler folds the in-block index arithmetic and turns offsets into immediates.
+// B = 0 keeps the run-time shape.
+template <int B> DD_INL Geom fixed_shape(const Geom &gin)
+{
+    static_assert(B == 0 || B == 2 || B == 4 || B == 8, "block side");
+    Geom g = gin;
+    if (B > 0) {
+        constexpr int lb = B == 2 ? 1 : B == 4 ? 2 : 3;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            g.b[mu] = B;
+            g.sh[mu] = mu * lb;
+        }
+        g.bvol = B * B * B * B;
+        g.lbvol = 4 * lb;
+    }
+    return g;
+}
+
 // workgroup id -> work item, spreading consecutive items over one XCD: the
 // hardware deals workgroups round-robin to the 8 XCDs, so item
 // (w % 8) * (n / 8) + w / 8 keeps neighbouring items on the same L2.

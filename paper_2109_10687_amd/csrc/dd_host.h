@@ -196,10 +196,10 @@ dd_status solve_gcr32(dd_ctx *c, void *src, void *y, double tol, int maxiter, So
 // ---- dd_batch.cpp: batched right-hand sides and several lattices
 
 // kinds of per-RHS fields in the batch buffers (each kind: nrhs fields one after another)
-enum { BK_B64, BK_X64, BK_R64, BK_T64, BK_SRC, BK_Y, BK_R, BK_RT, BK_P, BK_Q, BK_T, BK_MP, BK_MR, BK_IN, BK_OUT,
-       BK_COUNT };
+enum { BK_B64, BK_X64, BK_R64, BK_T64, BK_SRC, BK_Y, BK_R, BK_RT, BK_P, BK_Q, BK_T, BK_IN, BK_OUT,
+       BK_R16, BK_P16, BK_MP16, BK_MR16, BK_COUNT };
 
-inline int bk_prec(int k) { return k <= BK_T64 ? DD_F64 : DD_F32; }
+inline int bk_prec(int k) { return k <= BK_T64 ? DD_F64 : k >= BK_R16 ? DD_F16 : DD_F32; }
 
 dd_status batch_alloc(dd_ctx *c, int n);
 // field r of kind k
@@ -207,8 +207,9 @@ void *bf(dd_ctx *c, int k, int r);
 // run a reducing vector kernel on right-hand side r and leave its nv sums at red[off..]
 dd_status reduce_to(dd_ctx *c, dd::BlasArgs a, int nv, int off);
 dd_status fetch_red(dd_ctx *c, int n, double *out);
-// out = A in for n FP32 batched fields, in tiles of up to 12
-dd_status k_dirac_mrhs(dd_ctx *c, void *out, const void *in, int n);
+// out = A in for n batched fields at input precision pin (DD_F32 or DD_F16), FP32 output,
+// in tiles of up to 12
+dd_status k_dirac_mrhs(dd_ctx *c, void *out, const void *in, int n, int pin);
 
 struct BRhs {
     bool active = false;

@@ -266,17 +266,7 @@ template <int PIN, int POUT, int PG, int OP, int B>
 __global__ void __launch_bounds__(256) k_dirac(Geom gin, SpinorField<POUT> out, SpinorField<PIN> in, LinkField<PG> U,
                                                CloverField<PG> C, Phase4 ph, double kappa)
 {
-    Geom g = gin;
-    if (B > 0) {  // block shape B^4 known at compile time
-        constexpr int lb = B == 2 ? 1 : B == 4 ? 2 : 3;
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            g.b[mu] = B;
-            g.sh[mu] = mu * lb;
-        }
-        g.bvol = B * B * B * B;
-        g.lbvol = 4 * lb;
-    }
+    const Geom g = fixed_shape<B>(gin);
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     const long long i = (long long)w * 256 + threadIdx.x;
     if (i >= g.V) return;

@@ -81,7 +81,9 @@ struct BlasArgs {
 // A = I - kappa C_inv H on a batch of FP32 internal-layout spinors (nrhs fields,
 // one after another, 12 V complex apart), FP32 links and C_inv
 struct MrhsArgs {
-    const float2 *in;
+    const float2 *in;    // FP32 inputs (pin 1)
+    const void *in16;    // FP16-storage inputs (pin 2): nrhs fields of 12 V half2 + V scales, one after another
+    int pin;             // 1 or 2; FP16 inputs run the vector kernel only
     float2 *out;
     const float2 *u;     // FP32 links
     const float2 *cinv;  // FP32 C_inv blocks

@@ -50,9 +50,11 @@ DD_INL Cf shfl1(Cf a) { return {__shfl_xor(a.re, 1, 64), __shfl_xor(a.im, 1, 64)
 
 // NTP: column tiles per pass (a lane carries NTP right-hand sides per pass; the
 // group of four lanes 2 NTP; 6 passes / NTP cover twelve).  WGS: threads per workgroup.
-template <int NTP, int WGS>
-__global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
+// BS: block side when the block shape is fixed at compile time (0: taken from the geometry).
+template <int NTP, int WGS, int BS>
+__global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom gin, MrhsArgs a)
 {
+    const Geom g = fixed_shape<BS>(gin);
     constexpr int NPASS = 6 / NTP;
     const int nwg = gridDim.x;
     const int w = xcd_remap(blockIdx.x, nwg);
@@ -252,8 +254,11 @@ __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom g, MrhsArgs a)
 // the twelve workgroups of a block's right-hand sides launched back to back on the
 // same XCD, so the block's links and C_inv come from HBM once and from L2 for the
 // other right-hand sides (loaded with ordinary, cached loads for that reason).
-__global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom g, MrhsArgs a)
+// PIN: input storage precision (1 FP32, 2 FP16 with per-site scales).
+template <int B, int PIN>
+__global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom gin, MrhsArgs a)
 {
+    const Geom g = fixed_shape<B>(gin);
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     const int blk = w / a.nrhs, r = w - blk * a.nrhs;
     const long long i = (long long)blk * 256 + threadIdx.x;
@@ -261,7 +266,14 @@ __global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom g, MrhsArgs a)
     Site st;
     decode(g, i, st);
     const long long RS = 12 * g.V;
-    SpinorField<1> in{(float2 *)(a.in + r * RS)}, out{a.out + r * RS};
+    SpinorField<1> out{a.out + r * RS};
+    SpinorField<PIN> in;
+    if constexpr (PIN == 1) {
+        in = SpinorField<1>{(float2 *)(a.in + r * RS)};
+    } else {
+        __half2 *h = (__half2 *)((char *)a.in16 + r * g.V * (12 * sizeof(__half2) + sizeof(float)));
+        in = SpinorField<2>{h, (float *)(h + RS)};
+    }
     LinkField<1> U{a.u};
     Spinor<float> acc;
     zero(acc);
@@ -327,18 +339,35 @@ const char *mrhs_variant_name(int v)
 hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, int variant)
 {
     auto grid = [&](int wgs) { return dim3((unsigned)((g.V * 4 + wgs - 1) / wgs)); };
+    // the vector kernel runs with the block shape fixed at compile time for 4^4 blocks (fewer
+    // registers); the matrix-core kernels' registers are their accumulators, they stay generic
+    const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
+    if (a.pin == 2) {  // FP16-storage inputs: the vector kernel
+        const dim3 G((unsigned)((g.V + 255) / 256 * a.nrhs)), T(256);
+        if (cube4)
+            hipLaunchKernelGGL((k_dirac_rhs_vec<4, 2>), G, T, 0, st, g, a);
+        else
+            hipLaunchKernelGGL((k_dirac_rhs_vec<0, 2>), G, T, 0, st, g, a);
+        return hipGetLastError();
+    }
+    if (a.pin != 1) return hipErrorInvalidValue;
     switch (variant) {
-    case 0: hipLaunchKernelGGL((k_dirac_mrhs<1, 64>), grid(64), dim3(64), 0, st, g, a); break;
-    case 1: hipLaunchKernelGGL((k_dirac_mrhs<1, 256>), grid(256), dim3(256), 0, st, g, a); break;
-    case 2: hipLaunchKernelGGL((k_dirac_mrhs<2, 64>), grid(64), dim3(64), 0, st, g, a); break;
-    case 3: hipLaunchKernelGGL((k_dirac_mrhs<2, 256>), grid(256), dim3(256), 0, st, g, a); break;
-    case 4: hipLaunchKernelGGL((k_dirac_mrhs<3, 64>), grid(64), dim3(64), 0, st, g, a); break;
-    case 5: hipLaunchKernelGGL((k_dirac_mrhs<3, 256>), grid(256), dim3(256), 0, st, g, a); break;
-    case 6: hipLaunchKernelGGL((k_dirac_mrhs<6, 64>), grid(64), dim3(64), 0, st, g, a); break;
-    case 7: hipLaunchKernelGGL((k_dirac_mrhs<6, 256>), grid(256), dim3(256), 0, st, g, a); break;
-    default:
-        hipLaunchKernelGGL(k_dirac_rhs_vec, dim3((unsigned)((g.V + 255) / 256 * a.nrhs)), dim3(256), 0, st, g, a);
+    case 0: hipLaunchKernelGGL((k_dirac_mrhs<1, 64, 0>), grid(64), dim3(64), 0, st, g, a); break;
+    case 1: hipLaunchKernelGGL((k_dirac_mrhs<1, 256, 0>), grid(256), dim3(256), 0, st, g, a); break;
+    case 2: hipLaunchKernelGGL((k_dirac_mrhs<2, 64, 0>), grid(64), dim3(64), 0, st, g, a); break;
+    case 3: hipLaunchKernelGGL((k_dirac_mrhs<2, 256, 0>), grid(256), dim3(256), 0, st, g, a); break;
+    case 4: hipLaunchKernelGGL((k_dirac_mrhs<3, 64, 0>), grid(64), dim3(64), 0, st, g, a); break;
+    case 5: hipLaunchKernelGGL((k_dirac_mrhs<3, 256, 0>), grid(256), dim3(256), 0, st, g, a); break;
+    case 6: hipLaunchKernelGGL((k_dirac_mrhs<6, 64, 0>), grid(64), dim3(64), 0, st, g, a); break;
+    case 7: hipLaunchKernelGGL((k_dirac_mrhs<6, 256, 0>), grid(256), dim3(256), 0, st, g, a); break;
+    default: {
+        const dim3 G((unsigned)((g.V + 255) / 256 * a.nrhs)), T(256);
+        if (cube4)
+            hipLaunchKernelGGL((k_dirac_rhs_vec<4, 1>), G, T, 0, st, g, a);
+        else
+            hipLaunchKernelGGL((k_dirac_rhs_vec<0, 1>), G, T, 0, st, g, a);
         break;
+    }
     }
     return hipGetLastError();
 }

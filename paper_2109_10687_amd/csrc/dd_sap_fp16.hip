@@ -482,18 +482,7 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
                                                      CloverField<2> Ci, Phase4 ph, float kappa, int n_jac)
 {
     extern __shared__ uint4 smem_pk[];
-    Geom g = gin;
-    if (B > 0) {
-        constexpr int lb = B == 2 ? 1 : B == 4 ? 2 : 3;
-        static_assert(B == 0 || B == 2 || B == 4 || B == 8, "block side");
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            g.b[mu] = B;
-            g.sh[mu] = mu * lb;
-        }
-        g.bvol = B * B * B * B;
-        g.lbvol = 4 * lb;
-    }
+    const Geom g = fixed_shape<B>(gin);
     const int bvol = g.bvol;
     uint4 *xs = smem_pk;                                    // 3 x bvol uint4
     h2 *ul = reinterpret_cast<h2 *>(xs + 3 * bvol);         // 36 x bvol half2
