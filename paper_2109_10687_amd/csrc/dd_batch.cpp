@@ -401,6 +401,7 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
         }
     };
     int nact = 0;
+    std::vector<cplx> alpha(n), omega(n);
     for (int k = 0; k < n; ++k) {
         dd_ctx *c = m->L[k];
         MHIPCK(m, hipMemsetAsync(F(k, 1), 0, spinor_bytes(c->g, DD_F32), m->stream));
@@ -420,16 +421,20 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
         dd_ctx *c = m->L[k];
         for (int w : {2, 4, 3})
             if ((st = copy(c, F(k, w), 1, F(k, 0), 1)) != DD_OK) return lat_fail(m, k, st);
+        if ((st = copy(c, F(k, 10), 2, F(k, 0), 1)) != DD_OK) return lat_fail(m, k, st);
     }
-    auto precond = [&](int from, int from16, int to) -> dd_status {
+    // the FP16 SAP of each lattice reads the FP16 copies of p and r that the fused updates
+    // write (as in solve_sap32); y takes alpha Mp + omega Mr in one pass
+    auto precond = [&](int from16, int to) -> dd_status {
         for (int k = 0; k < n; ++k) {
             if (!R[k].active) continue;
-            dd_ctx *c = m->L[k];
             dd_status s2;
-            if ((s2 = copy(c, F(k, from16), 2, F(k, from), 1)) != DD_OK) return lat_fail(m, k, s2);
-            if ((s2 = k_sap(c, 2, F(k, from16), F(k, to), F(k, 9))) != DD_OK) return lat_fail(m, k, s2);
+            if ((s2 = k_sap(m->L[k], 2, F(k, from16), F(k, to), F(k, 9))) != DD_OK) return lat_fail(m, k, s2);
         }
         return DD_OK;
+    };
+    auto settle_y = [&](int k) -> dd_status {  // a lattice stopping between the half steps gets its alpha Mp
+        return blas(m->L[k], mkb(dd::BLAS_CAXPY, {F(k, 1), F(k, 7)}, {1, 2}, {alpha[k].real(), alpha[k].imag()}));
     };
     auto stop = [&](BRhs &b, dd_status s2, int detail) {
         b.active = false;
@@ -437,9 +442,8 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
         b.o.detail = detail;
         --nact;
     };
-    std::vector<cplx> alpha(n), omega(n);
     for (int it = 0; it < maxiter && nact > 0; ++it) {
-        if ((st = precond(4, 10, 7)) != DD_OK) return st;
+        if ((st = precond(10, 7)) != DD_OK) return st;
         if ((st = multi_launch(m, 1, 2)) != DD_OK) return st;  // q = A M p, every lattice
         for (int k = 0; k < n; ++k)
             if (R[k].active && (st = reduce_to(m->L[k], mkb(dd::BLAS_DOT, {F(k, 3), F(k, 5)}, {1, 1}), 2, 0)) != DD_OK)
@@ -455,7 +459,7 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
                 continue;
             }
             alpha[k] = b.rho0 / rq;
-            if ((st = reduce_to(m->L[k], mkb(dd::BLAS_UPDATE1, {F(k, 1), F(k, 7), F(k, 2), F(k, 5)}, {1, 2, 1},
+            if ((st = reduce_to(m->L[k], mkb(dd::BLAS_UPDATE1_H, {F(k, 2), F(k, 5), F(k, 11)}, {1, 1, 2},
                                              {alpha[k].real(), alpha[k].imag()}),
                                 1, 0)) != DD_OK)
                 return lat_fail(m, k, st);
@@ -466,10 +470,13 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
             if (!b.active) continue;
             b.rn2 = red[k][0];
             b.o.relres = std::sqrt(b.rn2 / b.bn2);
-            if (b.o.relres < b.tol) stop(b, DD_OK, 0);
+            if (b.o.relres < b.tol) {
+                if ((st = settle_y(k)) != DD_OK) return lat_fail(m, k, st);
+                stop(b, DD_OK, 0);
+            }
         }
         if (nact == 0) break;
-        if ((st = precond(2, 11, 8)) != DD_OK) return st;
+        if ((st = precond(11, 8)) != DD_OK) return st;
         if ((st = multi_launch(m, 2, 2)) != DD_OK) return st;  // t = A M r, every lattice
         for (int k = 0; k < n; ++k)
             if (R[k].active &&
@@ -481,12 +488,15 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
             if (!b.active) continue;
             const double *d = red[k].data();
             if (d[2] == 0.0 || !is_fin(d[2])) {
+                if ((st = settle_y(k)) != DD_OK) return lat_fail(m, k, st);
                 stop(b, DD_BREAKDOWN, d[2] == 0.0 ? 2 : 4);
                 continue;
             }
             omega[k] = cplx(d[0], d[1]) / d[2];
-            if ((st = reduce_to(m->L[k], mkb(dd::BLAS_UPDATE2, {F(k, 1), F(k, 8), F(k, 2), F(k, 6), F(k, 3)}, {1, 2, 1},
-                                             {omega[k].real(), omega[k].imag()}),
+            if ((st = reduce_to(m->L[k],
+                                mkb(dd::BLAS_UPDATE2_MM, {F(k, 1), F(k, 7), F(k, 8), F(k, 2), F(k, 6), F(k, 3)},
+                                    {1, 2, 2, 1, 1, 1},
+                                    {alpha[k].real(), alpha[k].imag(), omega[k].real(), omega[k].imag()}),
                                 3, 0)) != DD_OK)
                 return lat_fail(m, k, st);
         }
@@ -512,7 +522,7 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
                 continue;
             }
             b.rho0 = rho;
-            if ((st = blas(m->L[k], mkb(dd::BLAS_PUPDATE, {F(k, 4), F(k, 2), F(k, 5)}, {1, 1, 1},
+            if ((st = blas(m->L[k], mkb(dd::BLAS_PUPDATE_H, {F(k, 4), F(k, 2), F(k, 5), F(k, 10)}, {1, 1, 1, 2},
                                         {beta.real(), beta.imag(), omega[k].real(), omega[k].imag()}))) != DD_OK)
                 return lat_fail(m, k, st);
         }
