@@ -389,12 +389,13 @@ DD_INL void inblock_hops(const float2 *xs, const SapLinks<P> &lk, const typename
 //   [!TAIL] s_c <- s_c + b_c - A_cc x_c      (A_cc x = x - K x)
 // FIRST takes s_c from b (s = b at the start of Alg. 1).  One workgroup per
 // block, one thread per site; blockDim.x == block volume.
-template <int P>
-__global__ void __launch_bounds__(256) k_sap_half(Geom g, int colour, int flags, SpinorField<P> bsrc,
+template <int P, int B>
+__global__ void __launch_bounds__(256) k_sap_half(Geom gin, int colour, int flags, SpinorField<P> bsrc,
                                                   SpinorField<P> sw, SpinorField<P> xw, SapLinks<P> lk,
                                                   LinkField<P> U, CloverField<P> Ci, Phase4 ph, float kappa,
                                                   int n_jac)
 {
+    const Geom g = fixed_shape<B>(gin);
     using LT = typename SapLinks<P>::T;
     extern __shared__ float4 smem_raw[];
     const int bvol = g.bvol;
@@ -985,13 +986,14 @@ hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int 
 {
     const int nwg = g.nblk / 2;
     const size_t lds = sap_lds_bytes(g, a.prec);
+    const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
     if (a.prec == 1) {
-        hipLaunchKernelGGL(k_sap_half<1>, dim3(nwg), dim3(g.bvol), lds, st, g, colour, flags, sf<1>((void *)a.b, g),
+        hipLaunchKernelGGL((cube4 ? k_sap_half<1, 4> : k_sap_half<1, 0>), dim3(nwg), dim3(g.bvol), lds, st, g, colour, flags, sf<1>((void *)a.b, g),
                            sf<1>(a.s, g), sf<1>(a.x, g), SapLinks<1>{LinkField<1>{(const float2 *)a.links}},
                            LinkField<1>{(const float2 *)a.links}, CloverField<1>{(const float2 *)a.cinv}, a.phase,
                            (float)a.kappa, a.n_jac);
     } else if (a.prec == 2) {
-        hipLaunchKernelGGL(k_sap_half<2>, dim3(nwg), dim3(g.bvol), lds, st, g, colour, flags, sf<2>((void *)a.b, g),
+        hipLaunchKernelGGL((cube4 ? k_sap_half<2, 4> : k_sap_half<2, 0>), dim3(nwg), dim3(g.bvol), lds, st, g, colour, flags, sf<2>((void *)a.b, g),
                            sf<2>(a.s, g), sf<2>(a.x, g), SapLinks<2>{(const __half2 *)a.links},
                            LinkField<2>{(const __half2 *)a.links}, CloverField<2>{(const __half2 *)a.cinv}, a.phase,
                            (float)a.kappa, a.n_jac);
