@@ -1,8 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
 Sizes: the 4^4 correctness lattice (2^4 blocks), an anisotropic lattice with
-mixed block extents, and 8^4 with the 32^4 / 64^3 x 128 operator parameters
-(kappa 0.1365, c_SW 1.7, links exp(0.3 i H), 4^4 blocks).  Every case spans
+mixed block extents, 8^4 with the 32^4 / 64^3 x 128 operator parameters
+(kappa 0.1365, c_SW 1.7, links exp(0.3 i H), 4^4 blocks), and 8^4 with 4^4
+blocks and a complex boundary phase in every direction.  Every case spans
 several Schwarz blocks and several workgroups.
 
 Bars: FP64 Dirac apply within 1e-13 (relative, max norm); FP32 Dirac apply
@@ -26,6 +27,9 @@ CASES = {
     "4^4": ((4, 4, 4, 4), (2, 2, 2, 2), 0.12, 1.0, 0.5, (1, 1, 1, -1)),
     "aniso": ((8, 4, 16, 8), (4, 2, 4, 2), 0.13, 1.3, 0.4, (1, np.exp(0.3j), 1, -1)),
     "8^4": ((8, 8, 8, 8), (4, 4, 4, 4), 0.1365, 1.7, 0.3, (1, 1, 1, -1)),
+    # 4^4 blocks (the kernels specialised for that shape) with a complex phase in every direction
+    "8^4-twist": ((8, 8, 8, 8), (4, 4, 4, 4), 0.125, 1.5, 0.3,
+                  (np.exp(0.3j), np.exp(-0.5j), np.exp(1.1j), -np.exp(0.2j))),
 }
 
 
@@ -116,7 +120,7 @@ def test_sap_fp32(name, n_sap):
 
 
 @pytest.mark.parametrize("fp16_arith", [0, 1])
-@pytest.mark.parametrize("name", ["4^4", "aniso", "8^4"])
+@pytest.mark.parametrize("name", ["4^4", "aniso", "8^4", "8^4-twist"])
 def test_sap_fp16_storage(name, fp16_arith):
     """FP16 storage with FP32 arithmetic, or with packed FP16 block-local
     arithmetic (one rounding of ~5e-4 per operation on a block-normalised source)."""
@@ -146,7 +150,7 @@ def test_solve_plain_fp64(name):
     assert rel_l2(xn, ref.x) < 1e-7
 
 
-@pytest.mark.parametrize("name", ["4^4", "8^4"])
+@pytest.mark.parametrize("name", ["4^4", "8^4", "8^4-twist"])
 def test_solve_fp32_sap(name):
     c = case(name)
     b = c.spinor(8)
@@ -160,7 +164,7 @@ def test_solve_fp32_sap(name):
 
 @pytest.mark.parametrize("fp16_arith", [0, 1])
 @pytest.mark.parametrize("mode", [dd.DD_SOLVE_MIXED, dd.DD_SOLVE_MIXED_GCR])
-@pytest.mark.parametrize("name", ["4^4", "aniso", "8^4"])
+@pytest.mark.parametrize("name", ["4^4", "aniso", "8^4", "8^4-twist"])
 def test_solve_mixed(name, mode, fp16_arith):
     c = case(name, fp16_arith=fp16_arith)
     b = c.spinor(9)
