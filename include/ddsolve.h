@@ -233,23 +233,30 @@ typedef enum { DD_BATCH_INNER_SAP = 0, DD_BATCH_INNER_PLAIN = 1 } dd_batch_inner
  * out must not overlap).  DD_F32 / DD_OP_A runs the batched kernel: tiles of
  * up to 12 right-hand sides share every link and C_inv load, and each hop's
  * 3x3 link times 3x(2 x 12) half-spinor product runs on the matrix cores
- * (sixteen sites per wavefront, one 4x4x1 block per site).  The kernel
- * variant (right-hand sides per pass, workgroup size) is picked by timing
- * every variant on the first call for each tile size, unless
- * dd_batch_set_variant forced one.  DD_F64 / DD_OP_D and DD_OP_DDAG apply the
+ * (sixteen sites per wavefront, one 4x4x1 block per site), or, in the
+ * vector variants, each thread takes one site and 1-4 right-hand sides and
+ * loads the links and C_inv once for them.  The kernel variant (matrix-core:
+ * right-hand sides per pass and workgroup size; vector: right-hand sides per
+ * thread) is picked by timing every variant on the first call for each tile
+ * size, unless dd_batch_set_variant forced one.  The SAP-preconditioned
+ * batched solve reads FP16-storage fields and tunes the vector variants for
+ * them separately (a forced matrix-core variant leaves that choice to its
+ * own timing).  DD_F64 / DD_OP_D and DD_OP_DDAG apply the
  * single-field kernel to each right-hand side.  The first call allocates the
  * batch work fields (kept until dd_destroy; DD_ERR_NOMEM if that fails).
  * Asynchronous, except for the first call of a tile size, which synchronises
  * while it times the variants. */
 dd_status dirac_apply_batch(dd_ctx *ctx, void *out_dev, const void *in_dev, int nrhs, dd_prec prec, dd_op op);
 
-/* Force the batched kernel variant (0 .. variants-1), or -1 to let the
- * autotuner choose (the default). */
+/* Force the batched kernel variant (0 .. 11: 0-7 matrix-core, 8-11 vector
+ * with 1-4 right-hand sides per thread), or -1 to let the autotuner choose
+ * (the default). */
 dd_status dd_batch_set_variant(dd_ctx *ctx, int variant);
 
-/* The variant in use for tiles of nrhs (1..12) right-hand sides (-1 before the
- * first batched call of that size) and the autotuner's times in ms per launch
- * for the first n_ms variants (0 where not timed); ms may be NULL. */
+/* The variant in use for tiles of nrhs (1..12) right-hand sides of FP32
+ * inputs (dirac_apply_batch; -1 before its first call of that size) and the
+ * autotuner's times in ms per launch for the first n_ms variants (0 where not
+ * timed); ms may be NULL. */
 dd_status dd_batch_tuning(dd_ctx *ctx, int nrhs, int *variant, double *ms, int n_ms);
 
 /* Name of a batched kernel variant ("?" if out of range). */

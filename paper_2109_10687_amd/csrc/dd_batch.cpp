@@ -74,58 +74,58 @@ dd_status mrhs_launch(dd_ctx *c, int v, void *out, const void *in, int n, int pi
     return DD_OK;
 }
 
-// time every variant on this tile (two warm-up launches, three timed) and keep the fastest
-dd_status mrhs_tune(dd_ctx *c, int n, void *out, const void *in)
+// time every variant that takes inputs of precision pin on this tile (two warm-up
+// launches, three timed) and keep the fastest
+dd_status mrhs_tune(dd_ctx *c, int n, void *out, const void *in, int pin)
 {
     const int nv = dd::mrhs_variant_count();
+    const int v0 = pin == DD_F16 ? dd::MRHS_FIRST_VECTOR : 0;  // FP16 inputs: the vector variants
+    double *ms_tab = pin == DD_F16 ? c->mrhs_ms16[n] : c->mrhs_ms[n];
     hipEvent_t e0, e1;
     HIPCK(c, hipEventCreate(&e0));
     HIPCK(c, hipEventCreate(&e1));
     const bool timing = c->timing;
     c->timing = false;
-    int best = 0;
-    for (int v = 0; v < nv; ++v) {
+    int best = v0;
+    for (int v = v0; v < nv; ++v) {
         dd_status st;
         for (int k = 0; k < 2; ++k)
-            if ((st = mrhs_launch(c, v, out, in, n)) != DD_OK) return st;
+            if ((st = mrhs_launch(c, v, out, in, n, pin)) != DD_OK) return st;
         HIPCK(c, hipEventRecord(e0, c->stream));
         for (int k = 0; k < 3; ++k)
-            if ((st = mrhs_launch(c, v, out, in, n)) != DD_OK) return st;
+            if ((st = mrhs_launch(c, v, out, in, n, pin)) != DD_OK) return st;
         HIPCK(c, hipEventRecord(e1, c->stream));
         HIPCK(c, hipEventSynchronize(e1));
         float ms = 0;
         HIPCK(c, hipEventElapsedTime(&ms, e0, e1));
-        c->mrhs_ms[n][v] = ms / 3.0;
-        if (c->mrhs_ms[n][v] < c->mrhs_ms[n][best]) best = v;
+        ms_tab[v] = ms / 3.0;
+        if (ms_tab[v] < ms_tab[best]) best = v;
     }
     c->timing = timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c->mrhs_tuned[n] = best;
+    (pin == DD_F16 ? c->mrhs_tuned16 : c->mrhs_tuned)[n] = best;
     return DD_OK;
 }
 
 dd_status k_dirac_mrhs(dd_ctx *c, void *out, const void *in, int n, int pin)
 {
     const size_t fb = spinor_bytes(c->g, DD_F32), fi = spinor_bytes(c->g, pin);
+    int *tuned = pin == DD_F16 ? c->mrhs_tuned16 : c->mrhs_tuned;
     for (int r0 = 0; r0 < n; r0 += 12) {
         const int m = n - r0 < 12 ? n - r0 : 12;
         void *o = (char *)out + r0 * fb;
         const void *i = (const char *)in + r0 * fi;
-        if (pin == DD_F16) {  // FP16 inputs: the vector kernel, no autotuning
-            dd_status st = mrhs_launch(c, 8, o, i, m, DD_F16);
-            if (st != DD_OK) return st;
-            continue;
-        }
         int v = c->mrhs_force;
+        if (v >= 0 && pin == DD_F16 && v < dd::MRHS_FIRST_VECTOR) v = -1;  // a forced matrix-core variant: FP32 only
         if (v < 0) {
-            if (c->mrhs_tuned[m] < 0) {
-                dd_status st = mrhs_tune(c, m, o, i);
+            if (tuned[m] < 0) {
+                dd_status st = mrhs_tune(c, m, o, i, pin);
                 if (st != DD_OK) return st;
             }
-            v = c->mrhs_tuned[m];
+            v = tuned[m];
         }
-        dd_status st = mrhs_launch(c, v, o, i, m);
+        dd_status st = mrhs_launch(c, v, o, i, m, pin);
         if (st != DD_OK) return st;
     }
     return DD_OK;

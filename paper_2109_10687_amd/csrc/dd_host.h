@@ -51,6 +51,10 @@ struct dd_ctx {
     int mrhs_force = -1;                // multi-RHS kernel variant forced by the caller (-1: autotune)
     int mrhs_tuned[13] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // per right-hand sides in a tile
     double mrhs_ms[13][16] = {};         // autotuner timings (ms per launch) per variant
+    // the same for FP16-storage inputs (the SAP-preconditioned batched solve), where only the
+    // vector variants apply
+    int mrhs_tuned16[13] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+    double mrhs_ms16[13][16] = {};
     // work vectors
     void *f64[ddh::N64] = {}, *f32[ddh::N32] = {}, *f16[ddh::N16] = {};
     void *gz[dd::GCR_MAX_NKV] = {}, *gp[dd::GCR_MAX_NKV] = {};  // GCR images (FP32), directions (FP16)

@@ -78,6 +78,8 @@ struct BlasArgs {
     double *partials;
 };
 
+constexpr int MRHS_FIRST_VECTOR = 8;  // batched-A variants from here on are vector kernels (FP16 inputs too)
+
 // A = I - kappa C_inv H on a batch of FP32 internal-layout spinors (nrhs fields,
 // one after another, 12 V complex apart), FP32 links and C_inv
 struct MrhsArgs {

@@ -250,33 +250,37 @@ __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom gin, MrhsArgs a)
     }
 }
 
-// The vector alternative for the autotuner: one thread per (site, right-hand side),
-// the twelve workgroups of a block's right-hand sides launched back to back on the
-// same XCD, so the block's links and C_inv come from HBM once and from L2 for the
-// other right-hand sides (loaded with ordinary, cached loads for that reason).
-// PIN: input storage precision (1 FP32, 2 FP16 with per-site scales).
-template <int B, int PIN>
+// The vector alternative for the autotuner: one thread per site and group of NR
+// right-hand sides (each link and the C_inv block are loaded once per group), the
+// groups' workgroups of a block launched back to back on the same XCD, so the block's
+// links and C_inv come from HBM once and from L2 for the other groups (loaded with
+// ordinary, cached loads for that reason).  PIN: input storage precision (1 FP32,
+// 2 FP16 with per-site scales).
+template <int B, int PIN, int NR>
 __global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom gin, MrhsArgs a)
 {
     const Geom g = fixed_shape<B>(gin);
+    const int ngrp = (a.nrhs + NR - 1) / NR;
     const int w = xcd_remap(blockIdx.x, gridDim.x);
-    const int blk = w / a.nrhs, r = w - blk * a.nrhs;
+    const int blk = w / ngrp, grp = w - blk * ngrp;
+    const int r0 = grp * NR, cnt = a.nrhs - r0 < NR ? a.nrhs - r0 : NR;
     const long long i = (long long)blk * 256 + threadIdx.x;
     if (i >= g.V) return;
     Site st;
     decode(g, i, st);
     const long long RS = 12 * g.V;
-    SpinorField<1> out{a.out + r * RS};
-    SpinorField<PIN> in;
-    if constexpr (PIN == 1) {
-        in = SpinorField<1>{(float2 *)(a.in + r * RS)};
-    } else {
-        __half2 *h = (__half2 *)((char *)a.in16 + r * g.V * (12 * sizeof(__half2) + sizeof(float)));
-        in = SpinorField<2>{h, (float *)(h + RS)};
-    }
+    auto in_of = [&](int r) {
+        if constexpr (PIN == 1) {
+            return SpinorField<1>{(float2 *)(a.in + r * RS)};
+        } else {
+            __half2 *h = (__half2 *)((char *)a.in16 + r * g.V * (12 * sizeof(__half2) + sizeof(float)));
+            return SpinorField<2>{h, (float *)(h + RS)};
+        }
+    };
     LinkField<1> U{a.u};
-    Spinor<float> acc;
-    zero(acc);
+    Spinor<float> acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) zero(acc[q]);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
 #pragma unroll
@@ -284,15 +288,19 @@ __global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom gin, MrhsArgs a)
             bool wrap, inblk;
             const long long j = neighbour(g, st, mu, dir, wrap, inblk);
             const int lj = (int)(j >> g.lbvol), sj = (int)(j & (g.bvol - 1));
-            Spinor<float> psi;
-            in.load(g, lj, sj, psi);
             Mat3<float> W;
             if (dir > 0)
                 U.load(g, st.l, st.s, mu, W);
             else
                 U.load(g, lj, sj, mu, W);
-            cx<float> phase = {(float)a.phase.re[mu], (float)(dir > 0 ? a.phase.im[mu] : -a.phase.im[mu])};
-            hop(mu, dir, W, psi, wrap, phase, acc);
+            const cx<float> phase = {(float)a.phase.re[mu], (float)(dir > 0 ? a.phase.im[mu] : -a.phase.im[mu])};
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                if (q >= cnt) break;
+                Spinor<float> psi;
+                in_of(r0 + q).load(g, lj, sj, psi);
+                hop(mu, dir, W, psi, wrap, phase, acc[q]);
+            }
         }
     }
     Clov<float> cl;
@@ -310,21 +318,26 @@ __global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom gin, MrhsArgs a)
             cl.h[b][jj] = {t.x, t.y};
         }
     }
-    Spinor<float> x, t, o;
-    in.load(g, st.l, st.s, x);
-    clover_mul(cl, acc, t);
 #pragma unroll
-    for (int aa = 0; aa < 4; ++aa)
+    for (int q = 0; q < NR; ++q) {
+        if (q >= cnt) break;
+        Spinor<float> x, t, o;
+        in_of(r0 + q).load(g, st.l, st.s, x);
+        clover_mul(cl, acc[q], t);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) o.v[aa][c] = x.v[aa][c] - (float)a.kappa * t.v[aa][c];
-    out.store(g, st.l, st.s, o, true);
+        for (int aa = 0; aa < 4; ++aa)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.v[aa][c] = x.v[aa][c] - (float)a.kappa * t.v[aa][c];
+        SpinorField<1>{a.out + (r0 + q) * RS}.store(g, st.l, st.s, o, true);
+    }
 }
 
 // variants 0-7: column tiles per pass (1, 2, 3 or 6: 2, 4, 6 or 12 right-hand sides per
-// pass) x workgroup size (64 or 256 threads); variant 8: the vector kernel above.  Fewer right-hand sides per pass
+// pass) x workgroup size (64 or 256 threads); variants 8-11: the vector kernel above with
+// 1, 2, 3 or 4 right-hand sides per thread.  Fewer right-hand sides per pass or thread
 // need fewer registers, so more wavefronts hide the load latency, at the price of
-// reading the links and C_inv once per pass.
-int mrhs_variant_count() { return 9; }
+// reading the links and C_inv more often.
+int mrhs_variant_count() { return 12; }
 
 const char *mrhs_variant_name(int v)
 {
@@ -332,22 +345,34 @@ const char *mrhs_variant_name(int v)
                                   "mfma4x4x1 4 rhs/pass, 64-thread wg",  "mfma4x4x1 4 rhs/pass, 256-thread wg",
                                   "mfma4x4x1 6 rhs/pass, 64-thread wg",  "mfma4x4x1 6 rhs/pass, 256-thread wg",
                                   "mfma4x4x1 12 rhs/pass, 64-thread wg", "mfma4x4x1 12 rhs/pass, 256-thread wg",
-                                  "vector, one thread per site and rhs, rhs-interleaved workgroups"};
-    return (v >= 0 && v < 9) ? names[v] : "?";
+                                  "vector, 1 rhs per thread",            "vector, 2 rhs per thread",
+                                  "vector, 3 rhs per thread",            "vector, 4 rhs per thread"};
+    return (v >= 0 && v < 12) ? names[v] : "?";
+}
+
+// the vector kernel with NR right-hand sides per thread, FP32 or FP16 inputs
+template <int PIN, int NR> static void launch_vec(const Geom &g, hipStream_t st, const MrhsArgs &a, bool cube4)
+{
+    const dim3 G((unsigned)((g.V + 255) / 256 * ((a.nrhs + NR - 1) / NR))), T(256);
+    if (cube4)
+        hipLaunchKernelGGL((k_dirac_rhs_vec<4, PIN, NR>), G, T, 0, st, g, a);
+    else
+        hipLaunchKernelGGL((k_dirac_rhs_vec<0, PIN, NR>), G, T, 0, st, g, a);
 }
 
 hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, int variant)
 {
     auto grid = [&](int wgs) { return dim3((unsigned)((g.V * 4 + wgs - 1) / wgs)); };
-    // the vector kernel runs with the block shape fixed at compile time for 4^4 blocks (fewer
+    // the vector kernels run with the block shape fixed at compile time for 4^4 blocks (fewer
     // registers); the matrix-core kernels' registers are their accumulators, they stay generic
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
-    if (a.pin == 2) {  // FP16-storage inputs: the vector kernel
-        const dim3 G((unsigned)((g.V + 255) / 256 * a.nrhs)), T(256);
-        if (cube4)
-            hipLaunchKernelGGL((k_dirac_rhs_vec<4, 2>), G, T, 0, st, g, a);
-        else
-            hipLaunchKernelGGL((k_dirac_rhs_vec<0, 2>), G, T, 0, st, g, a);
+    if (a.pin == 2) {  // FP16-storage inputs: the vector kernels only
+        switch (variant) {
+        case 9: launch_vec<2, 2>(g, st, a, cube4); break;
+        case 10: launch_vec<2, 3>(g, st, a, cube4); break;
+        case 11: launch_vec<2, 4>(g, st, a, cube4); break;
+        default: launch_vec<2, 1>(g, st, a, cube4); break;
+        }
         return hipGetLastError();
     }
     if (a.pin != 1) return hipErrorInvalidValue;
@@ -360,14 +385,10 @@ hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, i
     case 5: hipLaunchKernelGGL((k_dirac_mrhs<3, 256, 0>), grid(256), dim3(256), 0, st, g, a); break;
     case 6: hipLaunchKernelGGL((k_dirac_mrhs<6, 64, 0>), grid(64), dim3(64), 0, st, g, a); break;
     case 7: hipLaunchKernelGGL((k_dirac_mrhs<6, 256, 0>), grid(256), dim3(256), 0, st, g, a); break;
-    default: {
-        const dim3 G((unsigned)((g.V + 255) / 256 * a.nrhs)), T(256);
-        if (cube4)
-            hipLaunchKernelGGL((k_dirac_rhs_vec<4, 1>), G, T, 0, st, g, a);
-        else
-            hipLaunchKernelGGL((k_dirac_rhs_vec<0, 1>), G, T, 0, st, g, a);
-        break;
-    }
+    case 9: launch_vec<1, 2>(g, st, a, cube4); break;
+    case 10: launch_vec<1, 3>(g, st, a, cube4); break;
+    case 11: launch_vec<1, 4>(g, st, a, cube4); break;
+    default: launch_vec<1, 1>(g, st, a, cube4); break;
     }
     return hipGetLastError();
 }

@@ -89,10 +89,10 @@ def test_new_entry_points_reject_null_handles_without_gpu():
 
 
 def test_batch_variant_names():
-    names = [dd.dd_batch_variant_name(v) for v in range(9)]
-    assert all(n and n != "?" for n in names) and len(set(names)) == 9
+    names = [dd.dd_batch_variant_name(v) for v in range(12)]
+    assert all(n and n != "?" for n in names) and len(set(names)) == 12
     assert any("mfma" in n for n in names) and any("vector" in n for n in names)
-    assert dd.dd_batch_variant_name(-1) == "?" and dd.dd_batch_variant_name(9) == "?"
+    assert dd.dd_batch_variant_name(-1) == "?" and dd.dd_batch_variant_name(12) == "?"
 
 
 def test_multi_create_checks_every_lattice_without_gpu():
