@@ -38,12 +38,16 @@ FP64_VEC_TFLOPS = 78.6
 
 def class_kernels(block):
     """Kernel class of the library's timers -> the kernel instantiation rocprofv3 reports.
-    The FP32 / FP16 Dirac kernels and the packed-FP16 SAP half-sweep are specialised for
-    4^4 blocks (last template argument 4); other block shapes run the generic ones (0)."""
-    b = 4 if tuple(block) == (4, 4, 4, 4) else 0
-    return {"dirac_f64": "k_dirac<0, 0, 0, 0, 0>", "dirac_f32": f"k_dirac<1, 1, 1, 1, {b}>",
-            "dirac_f16in": f"k_dirac<2, 1, 1, 1, {b}>", "dirac_f16": f"k_dirac<2, 2, 2, 1, {b}>",
-            "sap": "k_sap_half<2>", "sap_pk": f"k_sap_half_pk<{b}>", "blas": "vector kernels"}
+    With 4^4 blocks the FP64, FP32 and FP16-input Dirac applies run the t-streamed kernel
+    (k_dirac_ts), the all-FP16 apply and the packed-FP16 SAP half-sweep their 4^4
+    specialisations (last template argument 4); other block shapes run the generic kernels (0)."""
+    if tuple(block) == (4, 4, 4, 4):
+        return {"dirac_f64": "k_dirac_ts<0, 0, 0, 0>", "dirac_f32": "k_dirac_ts<1, 1, 1, 1>",
+                "dirac_f16in": "k_dirac_ts<2, 1, 1, 1>", "dirac_f16": "k_dirac<2, 2, 2, 1, 4>",
+                "sap": "k_sap_half<2>", "sap_pk": "k_sap_half_pk<4>", "blas": "vector kernels"}
+    return {"dirac_f64": "k_dirac<0, 0, 0, 0, 0>", "dirac_f32": "k_dirac<1, 1, 1, 1, 0>",
+            "dirac_f16in": "k_dirac<2, 1, 1, 1, 0>", "dirac_f16": "k_dirac<2, 2, 2, 1, 0>",
+            "sap": "k_sap_half<2>", "sap_pk": "k_sap_half_pk<0>", "blas": "vector kernels"}
 
 
 def log(*a):
@@ -133,21 +137,27 @@ def measured_hbm(reps=10, nbytes=2 << 30):
 
 
 def dirac_microbench(dd, solver, b, reps):
-    """Standalone applies on internal-layout fields: FP64 D, FP32 A, FP16 A."""
+    """Standalone applies on internal-layout fields: FP64 D, FP32 A, FP16 A, and the inner
+    solver's A (FP16 input, FP32 links / C_inv / output)."""
     import torch
     out = {}
     for name, prec, op in (("f64_D", dd.DD_F64, dd.DD_OP_D), ("f32_A", dd.DD_F32, dd.DD_OP_A),
-                           ("f16_A", dd.DD_F16, dd.DD_OP_A)):
+                           ("f16_A", dd.DD_F16, dd.DD_OP_A), ("f16in_A", dd.DD_F16, dd.DD_OP_A)):
         fin = solver.pack(b, prec)
-        fout = solver.field(prec)
+        if name == "f16in_A":
+            fout = solver.field(dd.DD_F32)
+            run = lambda: solver.apply_packed_f16in(fout, fin)  # noqa: E731
+        else:
+            fout = solver.field(prec)
+            run = lambda: solver.apply_packed(fout, fin, op=op, prec=prec)  # noqa: E731
         for _ in range(3):
-            solver.apply_packed(fout, fin, op=op, prec=prec)
+            run()
         solver.timing(True)
         for _ in range(reps):
-            solver.apply_packed(fout, fin, op=op, prec=prec)
+            run()
         rep = solver.timing_report()
         solver.timing(False)
-        cls = {"f64_D": "dirac_f64", "f32_A": "dirac_f32", "f16_A": "dirac_f16"}[name]
+        cls = {"f64_D": "dirac_f64", "f32_A": "dirac_f32", "f16_A": "dirac_f16", "f16in_A": "dirac_f16in"}[name]
         r = rep[cls]
         ms = r["ms"] / max(r["launches"], 1)
         out[name] = {"ms": ms, "GBps": r["bytes"] / r["ms"] / 1e6, "GFLOPs": r["flops"] / r["ms"] / 1e6,

@@ -327,6 +327,13 @@ dd_status dd_unpack_spinor(dd_ctx *ctx, void *dst_canonical, const void *src_int
 /* dirac_apply on internal-layout fields (same operator set as dirac_apply). */
 dd_status dirac_apply_packed(dd_ctx *ctx, void *out_internal, const void *in_internal, dd_prec prec, dd_op op);
 
+/* out = A in for an FP16-storage internal field in and an FP32 internal field
+ * out, with FP32 links and C_inv: the operator application of the mixed
+ * solver's inner BiCGStab on A M_SAP (Alg. 5), whose SAP output is stored in
+ * FP16 (Alg. 1).  in and out must not overlap; DD_ERR_STATE without a gauge
+ * field.  Asynchronous on the context's stream. */
+dd_status dirac_apply_packed_f16in(dd_ctx *ctx, void *out_f32_internal, const void *in_f16_internal);
+
 /* ---- kernel timing for roofline reporting -------------------------------- */
 
 typedef enum {

@@ -10,4 +10,5 @@ from .binding import (DD_BATCH_INNER_PLAIN, DD_BATCH_INNER_SAP, DD_F16, DD_F32, 
                       bicgstab_solve_batch, bicgstab_solve_dagger, dd_batch_set_variant, dd_batch_tuning,
                       dd_batch_variant_name, dd_create, dd_destroy, dd_field_bytes, dd_force, dd_load_gauge,
                       dd_pack_spinor, dd_set_csw, dd_spinor_norm2, dd_timing_enable, dd_timing_query,
-                      dd_unpack_spinor, dirac_apply, dirac_apply_batch, dirac_apply_packed, lib, sap_precondition)
+                      dd_unpack_spinor, dirac_apply, dirac_apply_batch, dirac_apply_packed, dirac_apply_packed_f16in, lib,
+                      sap_precondition)

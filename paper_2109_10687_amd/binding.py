@@ -35,7 +35,7 @@ STATUS = {0: "DD_OK", 1: "DD_NOT_CONVERGED", 2: "DD_BREAKDOWN", -1: "DD_ERR_ARG"
 
 EXPORTS = ["dd_create", "dd_destroy", "dd_load_gauge", "dirac_apply", "sap_precondition", "bicgstab_solve",
            "dd_last_error", "dd_field_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dirac_apply_packed",
-           "dd_timing_enable", "dd_timing_query", "bicgstab_solve_dagger", "dd_spinor_norm2", "dd_set_csw",
+           "dirac_apply_packed_f16in", "dd_timing_enable", "dd_timing_query", "bicgstab_solve_dagger", "dd_spinor_norm2", "dd_set_csw",
            "dd_force", "dirac_apply_batch", "dd_batch_set_variant", "dd_batch_tuning", "dd_batch_variant_name",
            "bicgstab_solve_batch", "dd_multi_create", "dd_multi_destroy", "dd_multi_last_error", "dd_multi_context",
            "dd_multi_load_gauge", "dirac_apply_multi", "bicgstab_solve_multi"]
@@ -84,6 +84,7 @@ def lib():
             "dd_pack_spinor": (i, [vp, vp, vp, i]),
             "dd_unpack_spinor": (i, [vp, vp, vp, i]),
             "dirac_apply_packed": (i, [vp, vp, vp, i, i]),
+            "dirac_apply_packed_f16in": (i, [vp, vp, vp]),
             "dd_timing_enable": (i, [vp, i]),
             "dd_timing_query": (i, [vp, i, ctypes.POINTER(ll), ctypes.POINTER(d), ctypes.POINTER(d),
                                     ctypes.POINTER(d)]),
@@ -291,6 +292,10 @@ def dirac_apply_packed(ctx, out, inp, prec, op):
     return _check(ctx, lib().dirac_apply_packed(ctx, _dev(out, what="out"), _dev(inp, what="in"), prec, op))
 
 
+def dirac_apply_packed_f16in(ctx, out, inp):
+    return _check(ctx, lib().dirac_apply_packed_f16in(ctx, _dev(out, what="out"), _dev(inp, what="in")))
+
+
 def dd_timing_enable(ctx, on):
     return _check(ctx, lib().dd_timing_enable(ctx, int(on)))
 
@@ -414,6 +419,11 @@ class Solver:
 
     def apply_packed(self, out, inp, op=DD_OP_A, prec=DD_F32):
         dirac_apply_packed(self.ctx, out, inp, prec, op)
+        return out
+
+    def apply_packed_f16in(self, out, inp):
+        """out (FP32 field) = A inp (FP16 field): the inner solver's operator application."""
+        dirac_apply_packed_f16in(self.ctx, out, inp)
         return out
 
     def timing(self, on=True):

@@ -166,6 +166,13 @@ dd_status dirac_apply_packed(dd_ctx *c, void *out, const void *in, dd_prec prec,
     return k_dirac(c, out, in, prec, prec, prec, op);
 }
 
+dd_status dirac_apply_packed_f16in(dd_ctx *c, void *out, const void *in)
+{
+    if (!c || !out || !in) return fail(c, DD_ERR_ARG, "null argument");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    return k_dirac(c, out, in, DD_F16, DD_F32, DD_F32, DD_OP_A);
+}
+
 dd_status dirac_apply(dd_ctx *c, void *out, const void *in, dd_prec prec, dd_op op)
 {
     if (!c || !out || !in) return fail(c, DD_ERR_ARG, "null argument");

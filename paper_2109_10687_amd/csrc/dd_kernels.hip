@@ -273,6 +273,172 @@ __global__ void __launch_bounds__(256) k_dirac(Geom gin, SpinorField<POUT> out, 
     dirac_site<PIN, POUT, PG, OP>(g, out, in, U, C, ph, kappa, i);
 }
 
+// ---- the same operator streamed along t (4^4 blocks)
+// A workgroup walks `ns` consecutive blocks of one column (fixed block x, y, z) in t.
+// Neighbouring blocks' data that a block-per-workgroup launch reads twice from HBM (once
+// as a face, once as the block itself, too far apart in time for the L2 to keep it) is
+// read once here:
+//  * the block's input spinor is staged in LDS, and in-block neighbours come from there;
+//  * the t' = 0 slice of the next block, which the top slice reads for its forward t hop,
+//    is kept in LDS and becomes the next step's t' = 0 slice;
+//  * the top slice computes the next block's backward t hop term, U_t^dagger times the
+//    projected spinor (the same arithmetic the hop does), so the next block reads neither
+//    that face's spinor nor its links.
+// The hop order and arithmetic are those of dirac_site; results agree to FP32 (FP64) rounding,
+// not bit for bit, since the compiler fuses multiply-adds differently in the two kernels.
+template <int P> struct StoreT;
+template <> struct StoreT<0> { using T = double2; };
+template <> struct StoreT<1> { using T = float2; };
+template <> struct StoreT<2> { using T = __half2; };
+
+// one site's spinor as stored: 12 elements (256 apart in a 4^4 block) and the FP16 scale
+template <int P> struct RawSp {
+    typename StoreT<P>::T e[12];
+    float sc;
+};
+
+template <int P> DD_INL void raw_load(const typename StoreT<P>::T *p, const float *sp, RawSp<P> &r)
+{
+#pragma unroll
+    for (int e = 0; e < 12; ++e) r.e[e] = p[e * 256];
+    r.sc = P == 2 ? *sp : 1.f;
+}
+
+// the conversion SpinorField<P>::load applies
+template <int P, typename R> DD_INL void raw_to(const RawSp<P> &r, Spinor<R> &x)
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if constexpr (P == 2) {
+                float2 t = __half22float2(r.e[a * 3 + c]);
+                x.v[a][c] = {R(t.x * r.sc), R(t.y * r.sc)};
+            } else {
+                x.v[a][c] = {R(r.e[a * 3 + c].x), R(r.e[a * 3 + c].y)};
+            }
+        }
+}
+
+template <int PIN, int POUT, int PG, int OP>
+__global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> out, SpinorField<PIN> in, LinkField<PG> U,
+                                                  CloverField<PG> C, Phase4 ph, double kappa, int ns)
+{
+    using R = typename Acc<PIN, PG>::T;
+    using T = typename StoreT<PIN>::T;
+    const Geom g = fixed_shape<4>(gin);
+    __shared__ T tile[12][256];                     // this block's input
+    __shared__ T nxt[12][64];                       // the next block's t' = 0 slice
+    __shared__ float tsc[PIN == 2 ? 256 : 1], nsc[PIN == 2 ? 64 : 1];
+    __shared__ cx<R> carry[2][6][64];               // backward t hop terms, by step parity
+    const int ncol = g.bstride[3];
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int seg = w / ncol, col = w - seg * ncol;  // consecutive items: neighbouring columns
+    const int s = threadIdx.x, tw = __builtin_amdgcn_readfirstlane(s >> 6);  // t' of the site: one per wavefront
+    const float *scale = nullptr;
+    if constexpr (PIN == 2) scale = in.scale;
+    const int bt0 = seg * ns;
+    for (int k = 0; k < ns; ++k) {
+        // the site is decoded afresh in every step, from a thread index the compiler cannot
+        // follow across steps: otherwise it keeps every hop's addresses from one step to the
+        // next in registers (some 40 VGPRs, one wavefront per SIMD less)
+        int sl = s;
+        asm volatile("" : "+v"(sl));
+        Site st;
+        decode(g, ((long long)(col + (bt0 + k) * ncol) << 8) + sl, st);
+        // stage the block (its t' = 0 slice is already here after the first step)
+        if (tw != 0 || k == 0) {
+            RawSp<PIN> own;
+            raw_load<PIN>(&in.p[elem(g, st.l, sl, 12, 0)], scale + ((long long)st.l << 8) + sl, own);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) tile[e][sl] = own.e[e];
+            if constexpr (PIN == 2) tsc[sl] = own.sc;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 12; ++e) tile[e][sl] = nxt[e][sl];
+            if constexpr (PIN == 2) tsc[sl] = nsc[sl];
+        }
+        __syncthreads();
+        Spinor<R> acc;
+        zero(acc);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+            for (int dir = 1; dir >= -1; dir -= 2) {
+                if (mu == 3 && dir < 0 && tw == 0 && k > 0) {  // computed by the previous block's top slice
+                    Half<R> kk;
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) kk.v[a][c] = carry[k & 1][a * 3 + c][sl];
+                    reconstruct(3, -1, kk, acc);
+                    continue;
+                }
+                bool wrap, inblk;
+                const long long j = neighbour(g, st, mu, dir, wrap, inblk);
+                const int lj = (int)(j >> 8), sj = (int)(j & 255);
+                // one load path for both sources: LDS and HBM hold the elements 256 apart
+                RawSp<PIN> r;
+                raw_load<PIN>(inblk ? &tile[0][sj] : &in.p[elem(g, lj, sj, 12, 0)],
+                              inblk ? &tsc[PIN == 2 ? sj : 0] : scale + j, r);
+                if (mu == 3 && dir > 0 && tw == 3 && k + 1 < ns) {  // the next block's t' = 0 slice
+#pragma unroll
+                    for (int e = 0; e < 12; ++e) nxt[e][sj] = r.e[e];
+                    if constexpr (PIN == 2) nsc[sj] = r.sc;
+                }
+                Spinor<R> psi;
+                raw_to<PIN>(r, psi);
+                if (OP == 2) gamma5(psi);
+                Mat3<R> W;
+                if (dir > 0)
+                    U.load(g, st.l, sl, mu, W);
+                else
+                    U.load(g, lj, sj, mu, W);
+                cx<R> phase = {R(ph.re[mu]), R(dir > 0 ? ph.im[mu] : -ph.im[mu])};
+                hop(mu, dir, W, psi, wrap, phase, acc);
+            }
+        }
+        Spinor<R> x, t, o;
+        {
+            RawSp<PIN> r;
+            raw_load<PIN>(&tile[0][sl], &tsc[PIN == 2 ? sl : 0], r);
+            raw_to<PIN>(r, x);
+        }
+        if (OP == 2) gamma5(x);
+        Clov<R> cl;
+        C.load(g, st.l, sl, cl);
+        const R kr = R(kappa);
+        if (OP == 1) {
+            clover_mul(cl, acc, t);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o.v[a][c] = x.v[a][c] - kr * t.v[a][c];
+        } else {
+            clover_mul(cl, x, t);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o.v[a][c] = t.v[a][c] - kr * acc.v[a][c];
+            if (OP == 2) gamma5(o);
+        }
+        out.store(g, st.l, sl, o, true);
+        // the next block's backward t hop term from this block's top slice
+        if (tw == 3 && k + 1 < ns) {
+            Mat3<R> W;
+            U.load(g, st.l, sl, 3, W);
+            Half<R> h, kk;
+            project(3, -1, x, h);
+            mat_half(W, true, h, kk);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) carry[(k + 1) & 1][a * 3 + c][sl - 192] = kk.v[a][c];
+        }
+        __syncthreads();
+    }
+}
+
 // A = I - kappa C_inv H (FP32 links and C_inv, FP32 output, input at precision PIN) on
 // several lattices in one persistent launch: the work items are (lattice, 256-site
 // chunk) pairs numbered lattice by lattice; each workgroup takes the next item from
@@ -933,18 +1099,38 @@ hipError_t launch_clover(const Geom &g, hipStream_t st, const void *u64, const S
     return hipGetLastError();
 }
 
+// blocks per workgroup of the t-streamed apply (0: block per workgroup): 4, else 2 (the blocks in
+// t are even).  Measured on 64^3x128: 4 beats 2, 8 and 32 by 2-4 %; longer walks let the
+// workgroups of neighbouring columns drift apart, so their shared faces leave the L2 in between.
+static int dirac_stream_len(const Geom &g)
+{
+    for (int ns = 4; ns > 1; ns >>= 1)
+        if (g.NB[3] % ns == 0) return ns;
+    return 0;
+}
+
 hipError_t launch_dirac(const Geom &g, hipStream_t st, const DiracArgs &a)
 {
     const int nwg = grid_sites(g.V, 256);
     const Phase4 ph = a.phase;
-    // 4^4 blocks: the FP32 / FP16 kernels are specialised for that shape (fewer registers, one more
-    // wavefront per SIMD); the FP64 kernel gains nothing from it and stays generic
+    // 4^4 blocks: the t-streamed kernel (FP64, FP32 and FP16-input operators); the all-FP16
+    // operator, whose faces are small, runs one block per workgroup specialised for the shape (it
+    // holds more wavefronts per SIMD that way).  Other block shapes: the generic kernel.
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
-#define DIRAC_LAUNCH(PIN, POUT, PG, OP, CLOV)                                                                   \
-    hipLaunchKernelGGL((cube4 ? k_dirac<PIN, POUT, PG, OP, (PG != 0 ? 4 : 0)> : k_dirac<PIN, POUT, PG, OP, 0>),  \
-                       dim3(nwg), dim3(256), 0, st, g, sf<POUT>(a.out, g),                                      \
-                       sf<PIN>((void *)a.in, g), LinkField<PG>{(decltype(LinkField<PG>::p))a.links},            \
-                       CloverField<PG>{(decltype(CloverField<PG>::p))CLOV}, ph, a.kappa)
+    const int ns = cube4 ? dirac_stream_len(g) : 0;
+#define DIRAC_LAUNCH(PIN, POUT, PG, OP, CLOV)                                                                    \
+    do {                                                                                                          \
+    if (ns > 1 && PG != 2)                                                                                        \
+        hipLaunchKernelGGL((k_dirac_ts<PIN, POUT, PG, OP>), dim3(g.nblk / ns), dim3(256), 0, st, g,               \
+                           sf<POUT>(a.out, g), sf<PIN>((void *)a.in, g),                                          \
+                           LinkField<PG>{(decltype(LinkField<PG>::p))a.links},                                    \
+                           CloverField<PG>{(decltype(CloverField<PG>::p))CLOV}, ph, a.kappa, ns);                 \
+    else                                                                                                          \
+        hipLaunchKernelGGL((cube4 ? k_dirac<PIN, POUT, PG, OP, (PG == 2 ? 4 : 0)> : k_dirac<PIN, POUT, PG, OP, 0>), \
+                           dim3(nwg), dim3(256), 0, st, g, sf<POUT>(a.out, g),                                     \
+                           sf<PIN>((void *)a.in, g), LinkField<PG>{(decltype(LinkField<PG>::p))a.links},           \
+                           CloverField<PG>{(decltype(CloverField<PG>::p))CLOV}, ph, a.kappa);             \
+    } while (0)
     if (a.pin == 0 && a.pout == 0 && a.pg == 0) {
         if (a.op == 0) DIRAC_LAUNCH(0, 0, 0, 0, a.clover);
         else if (a.op == 2) DIRAC_LAUNCH(0, 0, 0, 2, a.clover);

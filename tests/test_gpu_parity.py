@@ -100,6 +100,22 @@ def test_dirac_A_fp32(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_dirac_A_fp16_input(name):
+    """The inner solver's apply: FP16-storage input, FP32 links, C_inv and output.  The oracle
+    applies A to the values the FP16 field holds, so the FP32 bar applies."""
+    c = case(name)
+    x = c.spinor(5).cuda()
+    f16 = c.solver.pack(x, dd.DD_F16)
+    held = c.solver.unpack(f16, dd.DD_F16).cpu().numpy()
+    f32 = c.solver.field(dd.DD_F32)
+    c.solver.apply_packed_f16in(f32, f16)
+    got = c.solver.unpack(f32, dd.DD_F32).cpu().numpy()
+    want = c.orc.A(held)
+    assert rel_l2(got, want) < 1e-6
+    assert rel_max(got, want) < 1e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
 def test_dirac_A_fp16_storage(name):
     c = case(name)
     x = c.spinor(4)
