@@ -274,16 +274,17 @@ __global__ void __launch_bounds__(256) k_dirac(Geom gin, SpinorField<POUT> out, 
 }
 
 // ---- the same operator streamed along t (4^4 blocks)
-// A workgroup walks `ns` consecutive blocks of one column (fixed block x, y, z) in t.
-// Neighbouring blocks' data that a block-per-workgroup launch reads twice from HBM (once
-// as a face, once as the block itself, too far apart in time for the L2 to keep it) is
-// read once here:
-//  * the block's input spinor is staged in LDS, and in-block neighbours come from there;
-//  * the t' = 0 slice of the next block, which the top slice reads for its forward t hop,
-//    is kept in LDS and becomes the next step's t' = 0 slice;
+// A workgroup walks `ns` consecutive blocks of one column (fixed block x, y, z) in t:
+//  * the block's input spinor is staged in LDS, and in-block neighbours come from there
+//    (one HBM/L2 read per site instead of one per hop);
 //  * the top slice computes the next block's backward t hop term, U_t^dagger times the
 //    projected spinor (the same arithmetic the hop does), so the next block reads neither
-//    that face's spinor nor its links.
+//    that face's spinor nor its links: a block-per-workgroup launch reads them a second
+//    time, too long after the block itself for the L2 to still hold them.
+// The next block's t' = 0 slice, which the top slice reads for its forward hop, is read again
+// by the next step rather than kept in LDS: the neighbouring columns read it at that time too
+// (their x, y and z faces), and those reads then share the L2 lines (measured: keeping it was
+// no faster).
 // The hop order and arithmetic are those of dirac_site; results agree to FP32 (FP64) rounding,
 // not bit for bit, since the compiler fuses multiply-adds differently in the two kernels.
 template <int P> struct StoreT;
@@ -328,8 +329,7 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
     using T = typename StoreT<PIN>::T;
     const Geom g = fixed_shape<4>(gin);
     __shared__ T tile[12][256];                     // this block's input
-    __shared__ T nxt[12][64];                       // the next block's t' = 0 slice
-    __shared__ float tsc[PIN == 2 ? 256 : 1], nsc[PIN == 2 ? 64 : 1];
+    __shared__ float tsc[PIN == 2 ? 256 : 1];
     __shared__ cx<R> carry[2][6][64];               // backward t hop terms, by step parity
     const int ncol = g.bstride[3];
     const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -346,17 +346,13 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
         asm volatile("" : "+v"(sl));
         Site st;
         decode(g, ((long long)(col + (bt0 + k) * ncol) << 8) + sl, st);
-        // stage the block (its t' = 0 slice is already here after the first step)
-        if (tw != 0 || k == 0) {
+        // stage the block
+        {
             RawSp<PIN> own;
             raw_load<PIN>(&in.p[elem(g, st.l, sl, 12, 0)], scale + ((long long)st.l << 8) + sl, own);
 #pragma unroll
             for (int e = 0; e < 12; ++e) tile[e][sl] = own.e[e];
             if constexpr (PIN == 2) tsc[sl] = own.sc;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 12; ++e) tile[e][sl] = nxt[e][sl];
-            if constexpr (PIN == 2) tsc[sl] = nsc[sl];
         }
         __syncthreads();
         Spinor<R> acc;
@@ -381,11 +377,6 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
                 RawSp<PIN> r;
                 raw_load<PIN>(inblk ? &tile[0][sj] : &in.p[elem(g, lj, sj, 12, 0)],
                               inblk ? &tsc[PIN == 2 ? sj : 0] : scale + j, r);
-                if (mu == 3 && dir > 0 && tw == 3 && k + 1 < ns) {  // the next block's t' = 0 slice
-#pragma unroll
-                    for (int e = 0; e < 12; ++e) nxt[e][sj] = r.e[e];
-                    if constexpr (PIN == 2) nsc[sj] = r.sc;
-                }
                 Spinor<R> psi;
                 raw_to<PIN>(r, psi);
                 if (OP == 2) gamma5(psi);
@@ -1099,13 +1090,14 @@ hipError_t launch_clover(const Geom &g, hipStream_t st, const void *u64, const S
     return hipGetLastError();
 }
 
-// blocks per workgroup of the t-streamed apply (0: block per workgroup): 4, else 2 (the blocks in
-// t are even).  Measured on 64^3x128: 4 beats 2, 8 and 32 by 2-4 %; longer walks let the
-// workgroups of neighbouring columns drift apart, so their shared faces leave the L2 in between.
+// blocks per workgroup of the t-streamed apply, 0 for a block per workgroup: 4, else 2 (the
+// blocks in t are even), as long as that leaves 1024 workgroups (four per CU) to fill the chip;
+// smaller lattices keep a block per workgroup.  Measured on 64^3x128: walks of 4 beat 2, 8 and 32
+// by 2-4 %; longer walks let the workgroups of neighbouring columns drift apart.
 static int dirac_stream_len(const Geom &g)
 {
     for (int ns = 4; ns > 1; ns >>= 1)
-        if (g.NB[3] % ns == 0) return ns;
+        if (g.NB[3] % ns == 0 && g.nblk / ns >= 1024) return ns;
     return 0;
 }
 
@@ -1113,9 +1105,10 @@ hipError_t launch_dirac(const Geom &g, hipStream_t st, const DiracArgs &a)
 {
     const int nwg = grid_sites(g.V, 256);
     const Phase4 ph = a.phase;
-    // 4^4 blocks: the t-streamed kernel (FP64, FP32 and FP16-input operators); the all-FP16
-    // operator, whose faces are small, runs one block per workgroup specialised for the shape (it
-    // holds more wavefronts per SIMD that way).  Other block shapes: the generic kernel.
+    // 4^4 blocks on a lattice large enough: the t-streamed kernel (FP64, FP32 and FP16-input
+    // operators); the all-FP16 operator, whose faces are small, and smaller lattices run one block
+    // per workgroup, the FP32 / FP16 kernels specialised for the shape (fewer registers, one more
+    // wavefront per SIMD).  Other block shapes: the generic kernel.
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
     const int ns = cube4 ? dirac_stream_len(g) : 0;
 #define DIRAC_LAUNCH(PIN, POUT, PG, OP, CLOV)                                                                    \
@@ -1126,7 +1119,7 @@ hipError_t launch_dirac(const Geom &g, hipStream_t st, const DiracArgs &a)
                            LinkField<PG>{(decltype(LinkField<PG>::p))a.links},                                    \
                            CloverField<PG>{(decltype(CloverField<PG>::p))CLOV}, ph, a.kappa, ns);                 \
     else                                                                                                          \
-        hipLaunchKernelGGL((cube4 ? k_dirac<PIN, POUT, PG, OP, (PG == 2 ? 4 : 0)> : k_dirac<PIN, POUT, PG, OP, 0>), \
+        hipLaunchKernelGGL((cube4 ? k_dirac<PIN, POUT, PG, OP, (PG != 0 ? 4 : 0)> : k_dirac<PIN, POUT, PG, OP, 0>), \
                            dim3(nwg), dim3(256), 0, st, g, sf<POUT>(a.out, g),                                     \
                            sf<PIN>((void *)a.in, g), LinkField<PG>{(decltype(LinkField<PG>::p))a.links},           \
                            CloverField<PG>{(decltype(CloverField<PG>::p))CLOV}, ph, a.kappa);             \

@@ -82,9 +82,21 @@ class TestBenchmarkLattice:
         a16 = s.apply(x, op=dd.DD_OP_A, prec=dd.DD_F16).reshape(-1, 3, 4)[idx].cpu().numpy()
         e32 = np.linalg.norm(a32 - wantA) / np.linalg.norm(wantA)
         e16 = np.linalg.norm(a16 - wantA) / np.linalg.norm(wantA)
-        print(f"64^3x128, {len(sites)} sampled sites: FP32 A rel. error {e32:.2e}, FP16-storage A {e16:.2e}")
+        # the inner solver's apply: FP16-storage input, FP32 output, against the oracle's A of the
+        # values the FP16 field holds
+        f16 = s.pack(x, dd.DD_F16)
+        held = s.unpack(f16, dd.DD_F16)
+        f32 = s.field(dd.DD_F32)
+        s.apply_packed_f16in(f32, f16)
+        a16in = s.unpack(f32, dd.DD_F32).reshape(-1, 3, 4)[idx].cpu().numpy()
+        want16in = O.dirac_A_sites(op, Uh, held.cpu().numpy(), sites)
+        e16in = np.linalg.norm(a16in - want16in) / np.linalg.norm(want16in)
+        del f16, held, f32
+        print(f"64^3x128, {len(sites)} sampled sites: FP32 A rel. error {e32:.2e}, FP16-storage A {e16:.2e}, "
+              f"FP16-input A {e16in:.2e}")
         assert e32 < 1e-6
         assert e16 < 3e-3
+        assert e16in < 1e-6
 
     def test_full_size_mixed_solve(self, full):
         op, s, Uh, b, sites = full
@@ -106,6 +118,37 @@ def lattice_samples(dims, n_random=40, seed=11):
     for _ in range(n_random):
         pts.add(tuple(int(rng.integers(L)) for L in dims))
     return np.array(sorted(x + Lx * (y + Ly * (z + Lz * t)) for x, y, z, t in pts), dtype=np.int64)
+
+
+def test_32x32x32x32_streamed_dirac_applies_match_oracle():
+    """On 32^4 with 4^4 blocks the FP64 D, FP32 A and FP16-input A applies run the kernel that
+    walks four blocks along t per workgroup (two walks per column): every site against the oracle,
+    to the FP64 and FP32 bars of a single apply."""
+    dims = (32, 32, 32, 32)
+    U = synth.su3_links(dims, 0.3, 35, device="cuda")
+    xd = synth.gaussian_spinor(dims, 36, device="cuda")
+    xh = xd.cpu().numpy()
+    op = O.Params(dims=dims, kappa=0.1365, csw=1.7, block=(4, 4, 4, 4), phases=(1, np.exp(0.4j), 1, -1))
+    gp = dd.Params(dims=dims, kappa=0.1365, csw=1.7, block=(4, 4, 4, 4), phases=(1, np.exp(0.4j), 1, -1))
+    orc = O.Oracle(op, U.cpu().numpy())
+    s = dd.Solver(gp, U)
+    del U
+    d64 = s.apply(xd, op=dd.DD_OP_D, prec=dd.DD_F64).cpu().numpy()
+    want = orc.D(xh)
+    assert np.abs(d64 - want).max() < 1e-13 * np.abs(want).max()
+    a32 = s.apply(xd, op=dd.DD_OP_A, prec=dd.DD_F32).cpu().numpy()
+    wantA = orc.A(xh)
+    assert np.linalg.norm(a32 - wantA) / np.linalg.norm(wantA) < 1e-6
+    assert np.abs(a32 - wantA).max() < 1e-5 * np.abs(wantA).max()
+    f16 = s.pack(xd, dd.DD_F16)
+    held = s.unpack(f16, dd.DD_F16).cpu().numpy()
+    f32 = s.field(dd.DD_F32)
+    s.apply_packed_f16in(f32, f16)
+    a16in = s.unpack(f32, dd.DD_F32).cpu().numpy()
+    want16 = orc.A(held)
+    assert np.linalg.norm(a16in - want16) / np.linalg.norm(want16) < 1e-6
+    assert np.abs(a16in - want16).max() < 1e-5 * np.abs(want16).max()
+    s.close()
 
 
 def test_32x32x32x32_fp32_sap_solve_at_kappa_0_1365():
