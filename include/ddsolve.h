@@ -330,8 +330,10 @@ dd_status dirac_apply_packed(dd_ctx *ctx, void *out_internal, const void *in_int
 /* out = A in for an FP16-storage internal field in and an FP32 internal field
  * out, with FP32 links and C_inv: the operator application of the mixed
  * solver's inner BiCGStab on A M_SAP (Alg. 5), whose SAP output is stored in
- * FP16 (Alg. 1).  in and out must not overlap; DD_ERR_STATE without a gauge
- * field.  Asynchronous on the context's stream. */
+ * FP16 (Alg. 1).  Buffers as from dd_field_bytes (DD_F16 for in, DD_F32 for
+ * out), device, caller-owned, not overlapping.  DD_ERR_ARG for a null
+ * pointer, DD_ERR_STATE without a gauge field.  Asynchronous on the context's
+ * stream. */
 dd_status dirac_apply_packed_f16in(dd_ctx *ctx, void *out_f32_internal, const void *in_f16_internal);
 
 /* ---- kernel timing for roofline reporting -------------------------------- */

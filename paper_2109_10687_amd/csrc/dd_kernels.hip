@@ -335,8 +335,13 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     const int seg = w / ncol, col = w - seg * ncol;  // consecutive items: neighbouring columns
     const int s = threadIdx.x, tw = __builtin_amdgcn_readfirstlane(s >> 6);  // t' of the site: one per wavefront
-    const float *scale = nullptr;
-    if constexpr (PIN == 2) scale = in.scale;
+    // the FP16 scale of internal site i (FP32 / FP64 inputs have none)
+    auto scale_at = [&](long long i) -> const float * {
+        if constexpr (PIN == 2)
+            return in.scale + i;
+        else
+            return nullptr;
+    };
     const int bt0 = seg * ns;
     for (int k = 0; k < ns; ++k) {
         // the site is decoded afresh in every step, from a thread index the compiler cannot
@@ -349,7 +354,7 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
         // stage the block
         {
             RawSp<PIN> own;
-            raw_load<PIN>(&in.p[elem(g, st.l, sl, 12, 0)], scale + ((long long)st.l << 8) + sl, own);
+            raw_load<PIN>(&in.p[elem(g, st.l, sl, 12, 0)], scale_at(((long long)st.l << 8) + sl), own);
 #pragma unroll
             for (int e = 0; e < 12; ++e) tile[e][sl] = own.e[e];
             if constexpr (PIN == 2) tsc[sl] = own.sc;
@@ -376,7 +381,7 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
                 // one load path for both sources: LDS and HBM hold the elements 256 apart
                 RawSp<PIN> r;
                 raw_load<PIN>(inblk ? &tile[0][sj] : &in.p[elem(g, lj, sj, 12, 0)],
-                              inblk ? &tsc[PIN == 2 ? sj : 0] : scale + j, r);
+                              inblk ? &tsc[PIN == 2 ? sj : 0] : scale_at(j), r);
                 Spinor<R> psi;
                 raw_to<PIN>(r, psi);
                 if (OP == 2) gamma5(psi);
@@ -1101,45 +1106,54 @@ static int dirac_stream_len(const Geom &g)
     return 0;
 }
 
+// one operator / precision combination: the t-streamed kernel where dirac_stream_len allows it
+// (not for the all-FP16 operator, whose faces are small: there the block-per-workgroup kernel
+// holds more wavefronts per SIMD), else one block per workgroup, specialised for 4^4 blocks
+// except in FP64 (which gains nothing from it)
+template <int PIN, int POUT, int PG, int OP>
+static void dirac_launch(const Geom &g, hipStream_t st, const DiracArgs &a, bool cube4, int ns)
+{
+    const SpinorField<POUT> out = sf<POUT>(a.out, g);
+    const SpinorField<PIN> in = sf<PIN>((void *)a.in, g);
+    const LinkField<PG> U{(decltype(LinkField<PG>::p))a.links};
+    const CloverField<PG> C{(decltype(CloverField<PG>::p))a.clover};
+    if constexpr (PG != 2) {
+        if (ns > 1) {
+            hipLaunchKernelGGL((k_dirac_ts<PIN, POUT, PG, OP>), dim3(g.nblk / ns), dim3(256), 0, st, g, out, in, U, C,
+                               a.phase, a.kappa, ns);
+            return;
+        }
+    }
+    const dim3 grid(grid_sites(g.V, 256));
+    if (cube4)
+        hipLaunchKernelGGL((k_dirac<PIN, POUT, PG, OP, (PG != 0 ? 4 : 0)>), grid, dim3(256), 0, st, g, out, in, U, C,
+                           a.phase, a.kappa);
+    else
+        hipLaunchKernelGGL((k_dirac<PIN, POUT, PG, OP, 0>), grid, dim3(256), 0, st, g, out, in, U, C, a.phase, a.kappa);
+}
+
 hipError_t launch_dirac(const Geom &g, hipStream_t st, const DiracArgs &a)
 {
-    const int nwg = grid_sites(g.V, 256);
-    const Phase4 ph = a.phase;
-    // 4^4 blocks on a lattice large enough: the t-streamed kernel (FP64, FP32 and FP16-input
-    // operators); the all-FP16 operator, whose faces are small, and smaller lattices run one block
-    // per workgroup, the FP32 / FP16 kernels specialised for the shape (fewer registers, one more
-    // wavefront per SIMD).  Other block shapes: the generic kernel.
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
     const int ns = cube4 ? dirac_stream_len(g) : 0;
-#define DIRAC_LAUNCH(PIN, POUT, PG, OP, CLOV)                                                                    \
-    do {                                                                                                          \
-    if (ns > 1 && PG != 2)                                                                                        \
-        hipLaunchKernelGGL((k_dirac_ts<PIN, POUT, PG, OP>), dim3(g.nblk / ns), dim3(256), 0, st, g,               \
-                           sf<POUT>(a.out, g), sf<PIN>((void *)a.in, g),                                          \
-                           LinkField<PG>{(decltype(LinkField<PG>::p))a.links},                                    \
-                           CloverField<PG>{(decltype(CloverField<PG>::p))CLOV}, ph, a.kappa, ns);                 \
-    else                                                                                                          \
-        hipLaunchKernelGGL((cube4 ? k_dirac<PIN, POUT, PG, OP, (PG != 0 ? 4 : 0)> : k_dirac<PIN, POUT, PG, OP, 0>), \
-                           dim3(nwg), dim3(256), 0, st, g, sf<POUT>(a.out, g),                                     \
-                           sf<PIN>((void *)a.in, g), LinkField<PG>{(decltype(LinkField<PG>::p))a.links},           \
-                           CloverField<PG>{(decltype(CloverField<PG>::p))CLOV}, ph, a.kappa);             \
-    } while (0)
     if (a.pin == 0 && a.pout == 0 && a.pg == 0) {
-        if (a.op == 0) DIRAC_LAUNCH(0, 0, 0, 0, a.clover);
-        else if (a.op == 2) DIRAC_LAUNCH(0, 0, 0, 2, a.clover);
-        else return hipErrorInvalidValue;
+        if (a.op == 0)
+            dirac_launch<0, 0, 0, 0>(g, st, a, cube4, ns);
+        else if (a.op == 2)
+            dirac_launch<0, 0, 0, 2>(g, st, a, cube4, ns);
+        else
+            return hipErrorInvalidValue;
     } else if (a.op != 1) {
         return hipErrorInvalidValue;
     } else if (a.pin == 1 && a.pout == 1 && a.pg == 1) {
-        DIRAC_LAUNCH(1, 1, 1, 1, a.clover);
+        dirac_launch<1, 1, 1, 1>(g, st, a, cube4, ns);
     } else if (a.pin == 2 && a.pout == 1 && a.pg == 1) {
-        DIRAC_LAUNCH(2, 1, 1, 1, a.clover);
+        dirac_launch<2, 1, 1, 1>(g, st, a, cube4, ns);
     } else if (a.pin == 2 && a.pout == 2 && a.pg == 2) {
-        DIRAC_LAUNCH(2, 2, 2, 1, a.clover);
+        dirac_launch<2, 2, 2, 1>(g, st, a, cube4, ns);
     } else {
         return hipErrorInvalidValue;
     }
-#undef DIRAC_LAUNCH
     return hipGetLastError();
 }
 

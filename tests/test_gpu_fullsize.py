@@ -120,11 +120,12 @@ def lattice_samples(dims, n_random=40, seed=11):
     return np.array(sorted(x + Lx * (y + Ly * (z + Lz * t)) for x, y, z, t in pts), dtype=np.int64)
 
 
-def test_32x32x32x32_streamed_dirac_applies_match_oracle():
-    """On 32^4 with 4^4 blocks the FP64 D, FP32 A and FP16-input A applies run the kernel that
-    walks four blocks along t per workgroup (two walks per column): every site against the oracle,
-    to the FP64 and FP32 bars of a single apply."""
-    dims = (32, 32, 32, 32)
+@pytest.mark.parametrize("dims", [(32, 32, 32, 32), (32, 32, 32, 24)])
+def test_streamed_dirac_applies_match_oracle(dims):
+    """With 4^4 blocks on these lattices the FP64 D, FP32 A and FP16-input A applies run the kernel
+    that walks blocks along t per workgroup: four blocks (two walks per column) on 32^4, two
+    (three walks per column, six blocks in t) on 32^3 x 24.  Every site against the oracle, to the
+    FP64 and FP32 bars of a single apply."""
     U = synth.su3_links(dims, 0.3, 35, device="cuda")
     xd = synth.gaussian_spinor(dims, 36, device="cuda")
     xh = xd.cpu().numpy()
