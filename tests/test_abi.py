@@ -73,6 +73,7 @@ def test_new_entry_points_reject_null_handles_without_gpu():
     d = ctypes.c_double(0)
     info = dd.binding._Info()
     assert L.dirac_apply_batch(null, null, null, 12, dd.DD_F32, dd.DD_OP_A) == -1
+    assert L.dirac_apply_packed_f16in(null, null, null) == -1
     assert L.bicgstab_solve_batch(null, null, null, 12, 1e-10, 10, 0, ctypes.byref(info)) == -1
     assert L.bicgstab_solve_dagger(null, null, null, 1e-10, 10, dd.DD_SOLVE_MIXED, ctypes.byref(info)) == -1
     assert L.dd_force(null, null, ctypes.byref(d), null, null, 0) == -1
