@@ -122,8 +122,8 @@ def lattice_samples(dims, n_random=40, seed=11):
 
 @pytest.mark.parametrize("dims", [(32, 32, 32, 32), (32, 32, 32, 24)])
 def test_streamed_dirac_applies_match_oracle(dims):
-    """With 4^4 blocks on these lattices the FP64 D, FP32 A and FP16-input A applies run the kernel
-    that walks blocks along t per workgroup: four blocks (two walks per column) on 32^4, two
+    """With 4^4 blocks on these lattices the FP64 D and D^dagger, FP32 A and FP16-input A applies run
+    the kernel that walks blocks along t per workgroup: four blocks (two walks per column) on 32^4, two
     (three walks per column, six blocks in t) on 32^3 x 24.  Every site against the oracle, to the
     FP64 and FP32 bars of a single apply."""
     U = synth.su3_links(dims, 0.3, 35, device="cuda")
@@ -137,6 +137,12 @@ def test_streamed_dirac_applies_match_oracle(dims):
     d64 = s.apply(xd, op=dd.DD_OP_D, prec=dd.DD_F64).cpu().numpy()
     want = orc.D(xh)
     assert np.abs(d64 - want).max() < 1e-13 * np.abs(want).max()
+    # D^dagger = gamma_5 D gamma_5 (the adjoint solve's operator)
+    G = O.gamma(4)
+    g5 = lambda v: np.einsum("ij,...aj->...ai", G, v)  # noqa: E731
+    ddag = s.apply(xd, op=dd.DD_OP_DDAG, prec=dd.DD_F64).cpu().numpy()
+    wantdag = g5(orc.D(g5(xh)))
+    assert np.abs(ddag - wantdag).max() < 1e-13 * np.abs(wantdag).max()
     a32 = s.apply(xd, op=dd.DD_OP_A, prec=dd.DD_F32).cpu().numpy()
     wantA = orc.A(xh)
     assert np.linalg.norm(a32 - wantA) / np.linalg.norm(wantA) < 1e-6
