@@ -117,7 +117,11 @@ typedef struct {
     int sap_fp16_arith; /* 1: the FP16-storage SAP (sap_precondition at DD_F16 and the
                            mixed modes) also does its block-local Jacobi sweeps in
                            packed FP16 arithmetic, on a source scaled per block to unit
-                           maximum; 0: FP32 arithmetic on FP16 storage              */
+                           maximum; 0: FP32 arithmetic on FP16 storage.  A zeroed
+                           dd_params gives 0; the Python binding's default is 1      */
+    int stall_window;   /* an inner FP32 solve stops (status detail 6) when its recursive
+                           residual has not fallen 10x below the last such point within
+                           this many iterations (0 = 200; negative = never)          */
 } dd_params;
 
 typedef struct {
@@ -127,7 +131,14 @@ typedef struct {
     double relres_inner_last; /* last recursive residual of the last inner solve  */
     double seconds;           /* wall time of the call                            */
     int status_detail;        /* which breakdown: 1 <r~|q> = 0, 2 |t|^2 = 0, 3 omega = 0,
-                                 4 non-finite scalar, 5 outer stagnation          */
+                                 4 non-finite scalar, 5 outer stagnation (a defect-
+                                 correction pass did not lower the true residual, or
+                                 lowered it by less than 10% twice in a row), 6 inner
+                                 stagnation (an inner solve hit the stall window of
+                                 dd_params and its pass gained less than 10x)      */
+    int status;               /* the dd_status of this solve: the return value of a
+                                 single solve, this right-hand side's (lattice's) own
+                                 outcome in the batched and multi-lattice solves  */
 } dd_solve_info;
 
 typedef struct dd_ctx dd_ctx;
@@ -163,8 +174,10 @@ dd_status dirac_apply(dd_ctx *ctx, void *out_dev, const void *in_dev, dd_prec pr
 /* x = M_SAP b (Alg. 1 with loop count n_sap, Jacobi count n_jac from the
  * params) for canonical fields (device, caller-owned, must not overlap),
  * computed with internal storage at precision prec: DD_F32 (FP32 spinors,
- * links and C_inv) or DD_F16 (per-site-scaled FP16 spinors, 12-real FP16
- * links, FP16 C_inv); arithmetic is FP32 in both.  Asynchronous. */
+ * links and C_inv, FP32 arithmetic) or DD_F16 (per-site-scaled FP16 spinors,
+ * 12-real FP16 links, FP16 C_inv), whose block-local Jacobi sweeps run in
+ * packed FP16 arithmetic when dd_params.sap_fp16_arith is 1 and in FP32
+ * otherwise.  Asynchronous. */
 dd_status sap_precondition(dd_ctx *ctx, void *x_dev, const void *b_dev, dd_prec prec);
 
 /* Solve D x = b (canonical fields on the device).  On entry x holds the
@@ -181,6 +194,16 @@ dd_status bicgstab_solve(dd_ctx *ctx, void *x_dev, const void *b_dev, double tol
 
 /* Text of the last error on this context (never NULL). */
 const char *dd_last_error(const dd_ctx *ctx);
+
+/* Residual history of the last bicgstab_solve / bicgstab_solve_dagger on this
+ * context (host values, kept until the next solve):
+ *   which = 0: the true FP64 relative residual |b - D x| / |b| at the start and
+ *              after every defect-correction pass (Alg. 4);
+ *   which = 1: the recursive relative residual of the inner solver after every
+ *              iteration, all passes in order (Alg. 5's r, or GCR's).
+ * Copies at most cap values into out (host, may be NULL when cap is 0) and sets
+ * *n to the length of the whole history.  DD_ERR_ARG for a bad argument. */
+dd_status dd_solve_history(dd_ctx *ctx, int which, double *out, int cap, int *n);
 
 /* ---- differentiation: L = |D^{-1} phi|^2 --------------------------------- */
 

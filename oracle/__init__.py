@@ -312,8 +312,16 @@ def dcsw(p, U, psi, chi):
 
 
 def grad_from_force(W):
-    """The gradient dL/dRe U + i dL/dIm U of each link entry, from W: the conjugate transpose."""
+    """The gradient dL/dRe U + i dL/dIm U of each link entry, from W: the conjugate transpose.
+    With dL = Re sum tr(dU W) = Re sum_ab dU_ab W_ba and, for a real function of complex entries,
+    dL = Re sum_ab conj(G_ab) dU_ab, G_ab = conj(W_ba)."""
     return np.ascontiguousarray(np.conj(np.swapaxes(W, -1, -2)))
+
+
+def source_grad(chi):
+    """The gradient dL/dRe phi + i dL/dIm phi of L = |D^{-1} phi|^2 from chi = D^{-dagger} psi:
+    dL = 2 Re <psi| D^{-1} dphi> = 2 Re <chi| dphi>, so the gradient is 2 chi."""
+    return 2.0 * np.ascontiguousarray(chi)
 
 
 def su3_force(U, W):

@@ -38,7 +38,7 @@ EXPORTS = ["dd_create", "dd_destroy", "dd_load_gauge", "dirac_apply", "sap_preco
            "dirac_apply_packed_f16in", "dd_timing_enable", "dd_timing_query", "bicgstab_solve_dagger", "dd_spinor_norm2", "dd_set_csw",
            "dd_force", "dirac_apply_batch", "dd_batch_set_variant", "dd_batch_tuning", "dd_batch_variant_name",
            "bicgstab_solve_batch", "dd_multi_create", "dd_multi_destroy", "dd_multi_last_error", "dd_multi_context",
-           "dd_multi_load_gauge", "dirac_apply_multi", "bicgstab_solve_multi"]
+           "dd_multi_load_gauge", "dirac_apply_multi", "bicgstab_solve_multi", "dd_solve_history"]
 
 
 class DDError(RuntimeError):
@@ -51,13 +51,14 @@ class _Params(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("block", ctypes.c_int * 4), ("kappa", ctypes.c_double),
                 ("csw", ctypes.c_double), ("phase_re", ctypes.c_double * 4), ("phase_im", ctypes.c_double * 4),
                 ("n_sap", ctypes.c_int), ("n_jac", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("inner_maxiter", ctypes.c_int), ("gcr_nkv", ctypes.c_int), ("sap_fp16_arith", ctypes.c_int)]
+                ("inner_maxiter", ctypes.c_int), ("gcr_nkv", ctypes.c_int), ("sap_fp16_arith", ctypes.c_int),
+                ("stall_window", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("iters_outer", ctypes.c_int), ("iters_inner_total", ctypes.c_int),
                 ("relres_true", ctypes.c_double), ("relres_inner_last", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("status_detail", ctypes.c_int)]
+                ("seconds", ctypes.c_double), ("status_detail", ctypes.c_int), ("status", ctypes.c_int)]
 
 
 _LIB = None
@@ -80,6 +81,7 @@ def lib():
             "sap_precondition": (i, [vp, vp, vp, i]),
             "bicgstab_solve": (i, [vp, vp, vp, d, i, i, ctypes.POINTER(_Info)]),
             "dd_last_error": (ctypes.c_char_p, [vp]),
+            "dd_solve_history": (i, [vp, i, ctypes.POINTER(d), i, ctypes.POINTER(i)]),
             "dd_field_bytes": (ll, [vp, i]),
             "dd_pack_spinor": (i, [vp, vp, vp, i]),
             "dd_unpack_spinor": (i, [vp, vp, vp, i]),
@@ -127,6 +129,7 @@ class Params:
     inner_maxiter: int = 2000
     gcr_nkv: int = 16
     sap_fp16_arith: int = 1
+    stall_window: int = 200
 
     def c(self):
         p = _Params()
@@ -144,6 +147,7 @@ class Params:
         p.inner_maxiter = int(self.inner_maxiter)
         p.gcr_nkv = int(self.gcr_nkv)
         p.sap_fp16_arith = int(self.sap_fp16_arith)
+        p.stall_window = int(self.stall_window)
         return p
 
     @property
@@ -211,12 +215,29 @@ def sap_precondition(ctx, x, b, prec, shape):
     return _check(ctx, lib().sap_precondition(ctx, _c128(x, sp, "x"), _c128(b, sp, "b"), prec))
 
 
+def _info_dict(info):
+    """dd_solve_info as a dict; "status" is the C side's status of that solve, by name."""
+    d = {k: getattr(info, k) for k, _ in _Info._fields_}
+    d["status"] = STATUS[d["status"]]
+    return d
+
+
 def bicgstab_solve(ctx, x, b, tol, maxiter, mode, shape):
     sp = shape + (3, 4)
     info = _Info()
     st = _check(ctx, lib().bicgstab_solve(ctx, _c128(x, sp, "x"), _c128(b, sp, "b"), float(tol), int(maxiter),
                                           int(mode), ctypes.byref(info)))
-    return st, {k: getattr(info, k) for k, _ in _Info._fields_}
+    return st, _info_dict(info)
+
+
+def dd_solve_history(ctx, which):
+    """Residual history of the last single-field solve: which = 0 the true FP64 residual per outer
+    pass (and at the start), 1 the recursive inner residual per inner iteration."""
+    n = ctypes.c_int(0)
+    _check(ctx, lib().dd_solve_history(ctx, int(which), None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_double * max(n.value, 1))()
+    _check(ctx, lib().dd_solve_history(ctx, int(which), buf, n.value, ctypes.byref(n)))
+    return [buf[k] for k in range(n.value)]
 
 
 def bicgstab_solve_dagger(ctx, x, b, tol, maxiter, mode, shape):
@@ -224,7 +245,7 @@ def bicgstab_solve_dagger(ctx, x, b, tol, maxiter, mode, shape):
     info = _Info()
     st = _check(ctx, lib().bicgstab_solve_dagger(ctx, _c128(x, sp, "x"), _c128(b, sp, "b"), float(tol),
                                                  int(maxiter), int(mode), ctypes.byref(info)))
-    return st, {k: getattr(info, k) for k, _ in _Info._fields_}
+    return st, _info_dict(info)
 
 
 def dd_spinor_norm2(ctx, x, shape):
@@ -273,7 +294,7 @@ def bicgstab_solve_batch(ctx, x, b, nrhs, tol, maxiter, inner, shape):
     infos = (_Info * nrhs)()
     st = _check(ctx, lib().bicgstab_solve_batch(ctx, _c128(x, sp, "x"), _c128(b, sp, "b"), int(nrhs), float(tol),
                                                 int(maxiter), int(inner), infos))
-    return st, [{k: getattr(inf, k) for k, _ in _Info._fields_} for inf in infos]
+    return st, [_info_dict(inf) for inf in infos]
 
 
 def dd_field_bytes(ctx, prec):
@@ -353,14 +374,17 @@ class Solver:
     def solve(self, b, tol=1e-10, maxiter=10000, mode=DD_SOLVE_MIXED, x0=None):
         x = self.new_spinor() if x0 is None else x0.clone()
         st, info = bicgstab_solve(self.ctx, x, b, tol, maxiter, mode, self.shape)
-        info["status"] = STATUS[st]
         return x, info
+
+    def history(self):
+        """{"outer": true FP64 residual per defect-correction pass, "inner": recursive residual per
+        inner iteration} of the last solve on this context."""
+        return {"outer": dd_solve_history(self.ctx, 0), "inner": dd_solve_history(self.ctx, 1)}
 
     def solve_dagger(self, b, tol=1e-10, maxiter=10000, mode=DD_SOLVE_MIXED, x0=None):
         """x with D^dagger x = b (through D^dagger = gamma_5 D gamma_5)."""
         x = self.new_spinor() if x0 is None else x0.clone()
         st, info = bicgstab_solve_dagger(self.ctx, x, b, tol, maxiter, mode, self.shape)
-        info["status"] = STATUS[st]
         return x, info
 
     def norm2(self, x):
@@ -398,8 +422,6 @@ class Solver:
         """x_r with D x_r = b_r for every r (bs: (nrhs,) + lattice + (3, 4)); returns (x, infos)."""
         x = torch.zeros_like(bs) if x0 is None else x0.clone()
         st, infos = bicgstab_solve_batch(self.ctx, x, bs, bs.shape[0], tol, maxiter, inner, self.shape)
-        for inf in infos:
-            inf["status"] = STATUS[0] if inf["relres_true"] < tol else STATUS[st]
         return x, infos
 
     def field(self, prec):
@@ -491,10 +513,7 @@ class Multi:
         infos = (_Info * len(bs))()
         st = self._check(lib().bicgstab_solve_multi(self.m, self._ptrs(xs, "x"), self._ptrs(bs, "b"), float(tol),
                                                     int(maxiter), infos))
-        out = [{k: getattr(inf, k) for k, _ in _Info._fields_} for inf in infos]
-        for o in out:
-            o["status"] = STATUS[0] if o["relres_true"] < tol else STATUS[st]
-        return xs, out
+        return xs, [_info_dict(inf) for inf in infos]
 
     def timing(self, on=True):
         dd_timing_enable(self.context(0), on)

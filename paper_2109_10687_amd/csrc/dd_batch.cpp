@@ -153,6 +153,7 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
         b.bn2 = b.rn2 = red[r];
         b.rho0 = red[r];
         b.st = DD_OK;
+        b.stall = Stall{c->prm.stall_window};
         if (!is_fin(red[r])) return fail(c, DD_ERR_NONFINITE, "inner source holds NaN or Inf");
         b.active = red[r] > 0.0;
         nact += b.active;
@@ -270,6 +271,10 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
             b.o.relres = std::sqrt(b.rn2 / b.bn2);
             if (b.o.relres < b.tol) {
                 stop(b, DD_OK, 0);
+                continue;
+            }
+            if (b.stall.hit(it + 1, b.o.relres)) {
+                stop(b, DD_BREAKDOWN, DETAIL_INNER_STALL);
                 continue;
             }
             if (omega[r] == 0.0) {
@@ -414,6 +419,7 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
         b.bn2 = b.rn2 = red[k][0];
         b.rho0 = red[k][0];
         b.st = DD_OK;
+        b.stall = Stall{m->L[k]->prm.stall_window};
         if (!is_fin(red[k][0])) return mfail(m, DD_ERR_NONFINITE, "inner source holds NaN or Inf");
         b.active = red[k][0] > 0.0;
         nact += b.active;
@@ -510,6 +516,10 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
             b.o.relres = std::sqrt(b.rn2 / b.bn2);
             if (b.o.relres < b.tol) {
                 stop(b, DD_OK, 0);
+                continue;
+            }
+            if (b.stall.hit(it + 1, b.o.relres)) {
+                stop(b, DD_BREAKDOWN, DETAIL_INNER_STALL);
                 continue;
             }
             if (omega[k] == 0.0) {
@@ -667,7 +677,13 @@ dd_status bicgstab_solve_batch(dd_ctx *c, void *x_dev, const void *b_dev, int nr
                     return st;
                 state[r] = 2;
                 res[r] = DD_BREAKDOWN;
-                inf[r].status_detail = is_fin(rn2[r]) ? 5 : 4;
+                inf[r].status_detail = is_fin(rn2[r]) ? DETAIL_OUTER_STALL : 4;
+                continue;
+            }
+            if (R[r].o.detail == DETAIL_INNER_STALL && rn2[r] > 1e-2 * prev[r]) {
+                state[r] = 2;
+                res[r] = DD_BREAKDOWN;
+                inf[r].status_detail = DETAIL_INNER_STALL;
                 continue;
             }
             stall[r] = rn2[r] > 0.81 * prev[r] ? stall[r] + 1 : 0;
@@ -675,7 +691,7 @@ dd_status bicgstab_solve_batch(dd_ctx *c, void *x_dev, const void *b_dev, int nr
             if (stall[r] >= 2) {
                 state[r] = 2;
                 res[r] = DD_BREAKDOWN;
-                inf[r].status_detail = 5;
+                inf[r].status_detail = DETAIL_OUTER_STALL;
             }
         }
         if (c->verbose) {
@@ -700,6 +716,7 @@ dd_status bicgstab_solve_batch(dd_ctx *c, void *x_dev, const void *b_dev, int nr
     for (int r = 0; r < n; ++r) {
         inf[r].seconds = secs;
         if (res[r] == DD_BREAKDOWN && inf[r].status_detail == 0) inf[r].status_detail = 4;
+        inf[r].status = res[r];
         if (info) info[r] = inf[r];
     }
     return worst;
@@ -876,7 +893,13 @@ dd_status bicgstab_solve_multi(dd_multi *m, void *const *x_dev, const void *cons
                     return lat_fail(m, k, st);
                 state[k] = 2;
                 res[k] = DD_BREAKDOWN;
-                inf[k].status_detail = is_fin(rn2[k]) ? 5 : 4;
+                inf[k].status_detail = is_fin(rn2[k]) ? DETAIL_OUTER_STALL : 4;
+                continue;
+            }
+            if (R[k].o.detail == DETAIL_INNER_STALL && rn2[k] > 1e-2 * prev[k]) {
+                state[k] = 2;
+                res[k] = DD_BREAKDOWN;
+                inf[k].status_detail = DETAIL_INNER_STALL;
                 continue;
             }
             stall[k] = rn2[k] > 0.81 * prev[k] ? stall[k] + 1 : 0;
@@ -884,7 +907,7 @@ dd_status bicgstab_solve_multi(dd_multi *m, void *const *x_dev, const void *cons
             if (stall[k] >= 2) {
                 state[k] = 2;
                 res[k] = DD_BREAKDOWN;
-                inf[k].status_detail = 5;
+                inf[k].status_detail = DETAIL_OUTER_STALL;
             }
         }
     }
@@ -902,6 +925,7 @@ dd_status bicgstab_solve_multi(dd_multi *m, void *const *x_dev, const void *cons
     for (int k = 0; k < n; ++k) {
         inf[k].seconds = secs;
         if (res[k] == DD_BREAKDOWN && inf[k].status_detail == 0) inf[k].status_detail = 4;
+        inf[k].status = res[k];
         if (info) info[k] = inf[k];
     }
     return worst;

@@ -32,6 +32,7 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
     if (c->prm.inner_tol <= 0) c->prm.inner_tol = 1e-6;
     if (c->prm.inner_maxiter <= 0) c->prm.inner_maxiter = 2000;
     if (c->prm.gcr_nkv <= 0) c->prm.gcr_nkv = dd::GCR_MAX_NKV;
+    if (c->prm.stall_window == 0) c->prm.stall_window = 200;
     if (c->prm.gcr_nkv > dd::GCR_MAX_NKV) {
         delete c;
         return DD_ERR_ARG;
@@ -118,6 +119,16 @@ dd_status dd_destroy(dd_ctx *c)
 }
 
 const char *dd_last_error(const dd_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+dd_status dd_solve_history(dd_ctx *c, int which, double *out, int cap, int *n)
+{
+    if (!c || !n || (which != 0 && which != 1) || cap < 0 || (cap > 0 && !out))
+        return fail(c, DD_ERR_ARG, "bad argument");
+    const std::vector<double> &h = which == 0 ? c->hist_outer : c->hist_inner;
+    *n = (int)h.size();
+    for (int k = 0; k < cap && k < (int)h.size(); ++k) out[k] = h[k];
+    return DD_OK;
+}
 
 dd_status dd_load_gauge(dd_ctx *c, const void *U)
 {
@@ -210,6 +221,8 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
     if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
     auto t0 = std::chrono::steady_clock::now();
     dd_solve_info inf{};
+    c->hist_outer.clear();
+    c->hist_inner.clear();
     void *b = c->f64[0], *x = c->f64[1];
     HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, b, b_dev, dagger));
     double bn2;
@@ -244,6 +257,7 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
         void *src = c->f32[0], *y = c->f32[1];
         double rn2;
         if ((st = residual64(c, r, b, x, tmp, &rn2)) != DD_OK) return st;
+        if (bn2 > 0) c->hist_outer.push_back(std::sqrt(rn2 / bn2));
         double prev = rn2;
         int stall = 0, outer = 0;
         res = DD_NOT_CONVERGED;
@@ -274,19 +288,27 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
                 // take it back, so x stays the best iterate, and stop
                 if ((st = blas(c, mkb(dd::BLAS_AXPBY, {y, x}, {1, 0}, {-err, 1.0}))) != DD_OK) return st;
                 if ((st = residual64(c, r, b, x, tmp, &rn2)) != DD_OK) return st;
-                inf.status_detail = is_fin(rn2) ? 5 : 4;
+                inf.status_detail = is_fin(rn2) ? DETAIL_OUTER_STALL : 4;
                 res = DD_BREAKDOWN;
                 break;
             }
+            c->hist_outer.push_back(std::sqrt(rn2 / bn2));
             if (c->verbose) {
                 std::fprintf(stderr, "[ddsolve] outer pass %d: %d inner iterations (inner tol %.1e, reached %.2e), "
                              "true residual %.3e\n", outer, o.iters, itol, o.relres, std::sqrt(rn2 / bn2));
                 std::fflush(stderr);
             }
+            if (o.detail == DETAIL_INNER_STALL && rn2 > 1e-2 * prev) {
+                // the inner solve stagnated and its pass gained less than 10x: further
+                // passes would crawl at that rate
+                inf.status_detail = DETAIL_INNER_STALL;
+                res = DD_BREAKDOWN;
+                break;
+            }
             stall = rn2 > 0.81 * prev ? stall + 1 : 0;  // |r| fell by less than 10%
             prev = rn2;
             if (stall >= 2) {
-                inf.status_detail = 5;
+                inf.status_detail = DETAIL_OUTER_STALL;
                 res = DD_BREAKDOWN;
                 break;
             }
@@ -302,6 +324,7 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
     HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F64, x_dev, x, dagger));
     HIPCK(c, hipStreamSynchronize(c->stream));
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    inf.status = res;
     if (info) *info = inf;
     return res;
 }

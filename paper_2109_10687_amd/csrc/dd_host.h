@@ -67,6 +67,9 @@ struct dd_ctx {
     size_t pool_used = 0;
     long long launches[DD_KT_COUNT] = {};
     double ms[DD_KT_COUNT] = {}, bytes[DD_KT_COUNT] = {}, flops[DD_KT_COUNT] = {};
+    // residual history of the last single-field solve: true FP64 residual per outer pass,
+    // recursive inner residual per inner iteration
+    std::vector<double> hist_outer, hist_inner;
 };
 
 struct dd_multi {
@@ -190,6 +193,27 @@ struct SolveOut {
     int detail = 0;
 };
 
+constexpr int DETAIL_OUTER_STALL = 5;  // a defect-correction pass gained nothing (or twice < 10%)
+constexpr int DETAIL_INNER_STALL = 6;  // an inner solve hit its stall window and its pass gained < 10x
+
+// Stall window of an inner solve: hit() is true once the relative residual has not
+// fallen 10x below the last point where it did so within `window` iterations.
+struct Stall {
+    int window = 0;  // <= 0: never
+    int ref_it = 0;
+    double ref = 1.0;
+    bool hit(int it, double relres)
+    {
+        if (window <= 0) return false;
+        if (relres < 0.1 * ref) {
+            ref = relres;
+            ref_it = it;
+            return false;
+        }
+        return it - ref_it >= window;
+    }
+};
+
 // plain FP64 BiCGStab on D (x: initial guess and result)
 dd_status solve_plain64(dd_ctx *c, void *x, void *b, double tol, int maxiter, SolveOut &o);
 // FP32 BiCGStab on A M_SAP (SAP storage precision prec) for the source src, y = the solution
@@ -220,6 +244,7 @@ struct BRhs {
     cplx rho0 = 0.0;
     double bn2 = 0, rn2 = 0, tol = 0;
     SolveOut o;
+    Stall stall;
     dd_status st = DD_OK;
 };
 

@@ -130,6 +130,7 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
     if (fused && (st = copy(c, p16, 2, src, 1)) != DD_OK) return st;
     cplx rho0 = bn2;
     double rn2 = bn2;
+    Stall stall{c->prm.stall_window};
     auto precond = [&](void *in, void *in16, void *Mout, void *Aout) -> dd_status {
         dd_status s2;
         const void *bsrc = in;
@@ -148,6 +149,7 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
     };
     for (int it = 0; it < maxiter; ++it) {
         o.iters = it + 1;
+        c->hist_inner.push_back(std::sqrt(rn2 / bn2));  // one entry per iteration: its last residual
         if ((st = precond(p, p16, Mp, q)) != DD_OK) return st;
         double d[3];
         if ((st = reduce(c, mkb(dd::BLAS_DOT, {rt, q}, {1, 1}), 2, d)) != DD_OK) return st;
@@ -164,6 +166,7 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
             st = reduce(c, mkb(dd::BLAS_UPDATE1, {y, Mp, r, q}, {1, prec, 1}, {alpha.real(), alpha.imag()}), 1, &rn2);
         if (st != DD_OK) return st;
         o.relres = std::sqrt(rn2 / bn2);
+        c->hist_inner.back() = o.relres;
         if (o.relres < tol) return settle_y();
         if (c->verbose && (it + 1) % 100 == 0) {
             std::fprintf(stderr, "[ddsolve] inner iteration %d: relative residual %.3e\n", it + 1, o.relres);
@@ -187,7 +190,12 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
         rn2 = d[0];
         cplx rho(d[1], d[2]);
         o.relres = std::sqrt(rn2 / bn2);
+        c->hist_inner.back() = o.relres;
         if (o.relres < tol) return DD_OK;
+        if (stall.hit(it + 1, o.relres)) {  // y is complete here: both half steps are in
+            o.detail = DETAIL_INNER_STALL;
+            return DD_BREAKDOWN;
+        }
         if (omega == 0.0) {
             o.detail = 3;
             return DD_BREAKDOWN;
@@ -231,6 +239,8 @@ dd_status solve_gcr32(dd_ctx *c, void *src, void *y, double tol, int maxiter, So
     if (bn2 == 0.0) return DD_OK;
     if ((st = copy(c, r, 1, src, 1)) != DD_OK) return st;
     double rn2 = bn2;
+    Stall stall{c->prm.stall_window};
+    bool stalled = false;
     std::vector<cplx> a((size_t)nkv * nkv), cc(nkv), alpha(nkv);
     std::vector<double> bk(nkv);
     bool done = false;
@@ -277,11 +287,13 @@ dd_status solve_gcr32(dd_ctx *c, void *src, void *y, double tol, int maxiter, So
             n = k + 1;
             ++o.iters;
             o.relres = std::sqrt(rn2 / bn2);
+            c->hist_inner.push_back(o.relres);
             if (c->verbose && o.iters % 100 == 0) {
                 std::fprintf(stderr, "[ddsolve] GCR iteration %d: relative residual %.3e\n", o.iters, o.relres);
                 std::fflush(stderr);
             }
-            if (o.relres < tol || o.iters >= maxiter) {
+            stalled = o.relres >= tol && stall.hit(o.iters, o.relres);
+            if (o.relres < tol || o.iters >= maxiter || stalled) {
                 done = true;
                 break;
             }
@@ -303,6 +315,7 @@ dd_status solve_gcr32(dd_ctx *c, void *src, void *y, double tol, int maxiter, So
                              [&] { return dd::launch_multi_axpy(g, c->stream, ps, n, 2, y); });
         if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("gcr solution update: ") + hipGetErrorString(e));
     }
+    if (stalled) o.detail = DETAIL_INNER_STALL;
     return o.relres < tol ? DD_OK : (o.detail ? DD_BREAKDOWN : DD_NOT_CONVERGED);
 }
 

@@ -87,6 +87,27 @@ def test_new_entry_points_reject_null_handles_without_gpu():
     assert L.dd_multi_context(null, 0) is None
     assert L.dd_multi_last_error(null) == b"null handle"
     assert L.dd_destroy(null) == 0 and L.dd_multi_destroy(null) == 0
+    n = ctypes.c_int(-1)
+    assert L.dd_solve_history(null, 0, None, 0, ctypes.byref(n)) == -1
+
+
+def struct_fields(name):
+    """Field names of `typedef struct { ... } name;` in the header, in order."""
+    src = open(os.path.join(ROOT, "include", "ddsolve.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", src).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            fields += [re.sub(r"\[.*?\]", "", v).strip().lstrip("*") for v in decl.split(None, 1)[1].split(",")]
+    return fields
+
+
+def test_binding_structs_follow_the_header():
+    """The ctypes mirrors of dd_params and dd_solve_info list the header's fields in its order."""
+    assert [f for f, _ in dd.binding._Params._fields_] == struct_fields("dd_params")
+    assert [f for f, _ in dd.binding._Info._fields_] == struct_fields("dd_solve_info")
 
 
 def test_batch_variant_names():

@@ -92,7 +92,7 @@ def test_autograd_gradient_matches_oracle():
     ref = O.loss_and_force(op, U.numpy(), phi.numpy())
     assert abs(L.item() - ref.loss) < 1e-10 * ref.loss
     assert rel_max(Ud.grad.cpu().numpy(), O.grad_from_force(ref.W)) < 1e-8
-    assert rel_max(phid.grad.cpu().numpy(), 2 * ref.chi) < 1e-8
+    assert rel_max(phid.grad.cpu().numpy(), O.source_grad(ref.chi)) < 1e-8
     assert abs(csw.grad.item() - ref.dcsw) < 1e-8 * abs(ref.dcsw)
     print(f"8^4: L = {L.item():.10e}, dL/dc_SW = {csw.grad.item():.10e} (oracle {ref.dcsw:.10e})")
 

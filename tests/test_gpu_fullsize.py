@@ -9,10 +9,11 @@ on the fly): lattice corners, sites on every lattice face (where the boundary
 phase acts) and on Schwarz block faces, and random sites.
   * FP64 D: within 1e-13 of the oracle (max norm over the samples);
   * FP32 A: within 1e-6 (relative L2 over the samples), the FP32 bar;
-  * FP16-storage A: within 3e-3;
-  * the mixed-precision solve reaches the true FP64 residual 1e-10 (the library's
-    own measure), and the oracle's residual b - D x on the samples is below 1e-8
-    relative to b there.
+  * FP16-storage A: within 1e-3 (2.9e-4 measured);
+  * the mixed-precision solve reaches the true FP64 residual 1e-10: the library's
+    own measure, and the oracle's |b - D x| / |b| over the whole lattice, D applied
+    site by site in chunks with each site's clover built on the fly from the links
+    (the oracle never holds the clover field of this lattice).
 """
 import numpy as np
 import pytest
@@ -95,20 +96,32 @@ class TestBenchmarkLattice:
         print(f"64^3x128, {len(sites)} sampled sites: FP32 A rel. error {e32:.2e}, FP16-storage A {e16:.2e}, "
               f"FP16-input A {e16in:.2e}")
         assert e32 < 1e-6
-        assert e16 < 3e-3
+        assert e16 < 1e-3
         assert e16in < 1e-6
 
+    @pytest.mark.timeout(900)
     def test_full_size_mixed_solve(self, full):
+        """The benchmark solve to 1e-10, then the oracle's true residual of its solution over every
+        site of the lattice (about a minute on 16 host cores)."""
         op, s, Uh, b, sites = full
         x, info = s.solve(b, tol=1e-10, maxiter=50, mode=dd.DD_SOLVE_MIXED)
-        print(f"64^3x128 mixed solve: {info}")
+        print(f"64^3x128 mixed solve: {info}", flush=True)
         assert info["status"] == "DD_OK" and info["relres_true"] < 1e-10
-        idx = torch.from_numpy(sites).cuda()
-        bs = b.reshape(-1, 3, 4)[idx].cpu().numpy()
-        r = bs - O.dirac_D_sites(op, Uh, x.cpu().numpy(), sites)
-        rel = np.linalg.norm(r) / np.linalg.norm(bs)
-        print(f"oracle residual on {len(sites)} sampled sites: {rel:.2e}")
-        assert rel < 1e-8
+        xh = x.cpu().numpy()
+        del x
+        bh = b.cpu().numpy().reshape(-1, 3, 4)
+        V = bh.shape[0]
+        rr = bb = 0.0
+        chunk = 1 << 21
+        for n0 in range(0, V, chunk):
+            n1 = min(V, n0 + chunk)
+            r = bh[n0:n1] - O.dirac_D_sites(op, Uh, xh, np.arange(n0, n1, dtype=np.int64))
+            rr += float(np.vdot(r, r).real)
+            bb += float(np.vdot(bh[n0:n1], bh[n0:n1]).real)
+        rel = (rr / bb) ** 0.5
+        print(f"oracle true residual over all {V} sites: {rel:.3e} (library: {info['relres_true']:.3e})")
+        assert rel < 1e-10
+        assert abs(rel - info["relres_true"]) < 1e-3 * rel
 
 
 def lattice_samples(dims, n_random=40, seed=11):
@@ -176,7 +189,40 @@ def test_32x32x32x32_fp32_sap_solve_at_kappa_0_1365():
     r = bs - O.dirac_D_sites(op, U.cpu().numpy(), x.cpu().numpy(), sites)
     rel = np.linalg.norm(r) / np.linalg.norm(bs)
     print(f"true residual {info['relres_true']:.2e}; oracle residual on {len(sites)} sampled sites {rel:.2e}")
-    assert info["relres_true"] < 1e-5 and rel < 1e-5
+    # Alg. 5's test is on the recursive FP32 residual of the A system; the true FP64 residual of
+    # D x = b sits within a few times of it (1.2e-6 measured)
+    assert info["relres_true"] < 5e-6 and rel < 5e-6
+    s.close()
+
+
+def test_32x32x32x32_mixed_fp16_sap_stagnation_exits_early():
+    """At kappa 0.1365 on 32^4 the FP16-SAP BiCGStab stagnates (the operator is near critical for
+    this ensemble): the inner stall window (200 iterations without a 10x drop of the recursive
+    residual) ends each inner solve, and the defect correction stops with a status once a pass
+    gains less than 10x.  The call returns in seconds with x the best iterate, and the residual
+    history is monotone in the outer passes."""
+    import time
+    dims = (32, 32, 32, 32)
+    U = synth.su3_links(dims, 0.3, 33, device="cuda")
+    b = synth.gaussian_spinor(dims, 34, device="cuda")
+    gp = dd.Params(dims=dims, kappa=0.1365, csw=1.7, block=(4, 4, 4, 4), n_sap=4, n_jac=4, stall_window=200,
+                   inner_maxiter=6000)
+    s = dd.Solver(gp, U)
+    t0 = time.time()
+    x, info = s.solve(b, tol=1e-10, maxiter=20, mode=dd.DD_SOLVE_MIXED)
+    wall = time.time() - t0
+    h = s.history()
+    print(f"32^4 mixed FP16-SAP at kappa 0.1365: {info}, {wall:.1f} s; outer residuals {h['outer']}")
+    assert wall < 60
+    assert info["status"] in ("DD_OK", "DD_BREAKDOWN", "DD_NOT_CONVERGED")
+    if info["status"] == "DD_BREAKDOWN":
+        assert info["status_detail"] in (5, 6)
+    assert len(h["inner"]) == info["iters_inner_total"]
+    assert h["outer"][0] == pytest.approx(1.0) and len(h["outer"]) >= 1
+    assert all(b2 < a2 for a2, b2 in zip(h["outer"], h["outer"][1:]))
+    assert info["relres_true"] == pytest.approx(h["outer"][-1], rel=1e-6)
+    # an inner solve that stalled ran at most its window past its last 10x drop
+    assert info["iters_inner_total"] < 20 * 6000
     s.close()
 
 

@@ -8,9 +8,10 @@ several Schwarz blocks and several workgroups.
 
 Bars: FP64 Dirac apply within 1e-13 (relative, max norm); FP32 Dirac apply
 within 1e-6 relative (L2), the bound the FP32 operator must meet; FP32 SAP
-within 1e-5; FP16-storage results are reported with a loose bound; solves must
-reach the requested true FP64 residual, recomputed by the oracle on the GPU's
-solution.
+within 1e-5; FP16-storage results within about three times the largest error
+measured over these cases (A 1e-3; SAP 3e-3 with packed FP16 arithmetic,
+1.5e-3 with FP32 arithmetic); solves must reach the requested true FP64
+residual, recomputed by the oracle on the GPU's solution.
 """
 import numpy as np
 import pytest
@@ -123,7 +124,7 @@ def test_dirac_A_fp16_storage(name):
     want = c.orc.A(x.numpy())
     err = rel_l2(got, want)
     print(f"FP16-storage A apply relative L2 error {err:.3e}")
-    assert err < 3e-3
+    assert err < 1e-3
 
 
 @pytest.mark.parametrize("name,n_sap", [("4^4", 0), ("4^4", 2), ("aniso", 1), ("8^4", 0), ("8^4", 1), ("8^4", 2)])
@@ -146,7 +147,8 @@ def test_sap_fp16_storage(name, fp16_arith):
     want = c.orc.sap(b.numpy())
     err = rel_l2(got, want)
     print(f"FP16-storage SAP (fp16 arithmetic {fp16_arith}) relative L2 error {err:.3e}")
-    assert err < (2e-2 if fp16_arith else 1e-2)
+    # about three times the largest error measured over these cases (1.2e-3 packed FP16, 4e-4 FP32)
+    assert err < (3e-3 if fp16_arith else 1.5e-3)
 
 
 def true_relres(c, x, b):
@@ -175,7 +177,7 @@ def test_solve_fp32_sap(name):
     assert info["relres_inner_last"] < 1e-6
     res = true_relres(c, x.cpu().numpy(), b.numpy())
     print(f"FP32 SAP-BiCGStab: {info['iters_inner_total']} iterations, true residual {res:.2e}")
-    assert res < 1e-4
+    assert res < 1e-5
 
 
 @pytest.mark.parametrize("fp16_arith", [0, 1])
@@ -190,5 +192,8 @@ def test_solve_mixed(name, mode, fp16_arith):
     res = true_relres(c, xn, b.numpy())
     print(f"mixed: {info['iters_outer']} outer, {info['iters_inner_total']} inner, true residual {res:.2e}")
     assert res < 1e-10
+    h = c.solver.history()
+    assert len(h["outer"]) == info["iters_outer"] + 1 and len(h["inner"]) == info["iters_inner_total"]
+    assert h["outer"][-1] == pytest.approx(info["relres_true"], rel=1e-6)
     ref = c.orc.solve(b.numpy(), op=O.OP_D, tol=1e-12, maxiter=20000)
     assert rel_l2(xn, ref.x) < 1e-7

@@ -9,7 +9,9 @@ already fix (the operator D of the appendix and the plain BiCGStab):
     solve  psi+ - psi- = -D+^{-1} (D+ - D-) psi-,  whose source is O(h), so the
     difference is free of solve noise;
   * dL/dc_SW the same way;
-  * gauge covariance of the bilinear.
+  * gauge covariance of the bilinear;
+  * the link gradient in PyTorch's convention (grad_from_force) and the source
+    gradient 2 chi (source_grad), against central differences of L.
 """
 import numpy as np
 import pytest
@@ -170,3 +172,45 @@ def test_loss_and_adjoint_solution(setup):
     Ddag_chi = O.gamma5_apply(O.dirac_D(p, U, C, O.gamma5_apply(g.chi)))
     assert np.linalg.norm(Ddag_chi - g.psi) < 1e-12 * np.linalg.norm(g.psi)
     assert abs(g.loss - np.vdot(g.psi, g.psi).real) < 1e-12 * g.loss
+
+
+def test_link_gradient_in_torch_convention(setup):
+    """grad_from_force gives PyTorch's gradient of a real function of complex entries,
+    G = dL/dRe U + i dL/dIm U, for which dL = Re sum conj(G) dU: pinned by central differences of L
+    along a random complex direction on every link, and along a purely real and a purely imaginary
+    one (a transpose without the conjugate, or a conjugate without the transpose, fails them)."""
+    p, U, phi, g = setup
+    G = O.grad_from_force(g.W)
+    rng = np.random.default_rng(71)
+    h = 1e-6
+    slips = {"transpose only": np.swapaxes(g.W, -1, -2), "conjugate only": np.conj(g.W), "W itself": g.W}
+    missed = {k: False for k in slips}
+    for kind in ("complex", "real", "imag"):
+        E = rng.normal(size=U.shape) + (1j * rng.normal(size=U.shape) if kind == "complex" else 0)
+        if kind == "imag":
+            E = 1j * E
+        want = float(np.sum(np.conj(G) * E).real)
+        got = delta_loss(p, U + h * E, U - h * E, phi) / (2 * h)
+        assert abs(got - want) <= 1e-7 * abs(want), (kind, got, want)
+        for k, wrong in slips.items():
+            missed[k] |= abs(got - float(np.sum(np.conj(wrong) * E).real)) > 1e-3 * abs(want)
+    # each plausible slip in the convention fails along at least one of the directions
+    assert all(missed.values()), missed
+
+
+def test_source_gradient_finite_difference(setup):
+    """source_grad(chi) = 2 chi is the gradient of L in phi in PyTorch's convention: the central
+    difference of L along a random complex direction E (L is quadratic in phi, so the difference is
+    exact up to the solves' rounding) equals Re sum conj(2 chi) E."""
+    p, U, phi, g = setup
+    C = O.clover_field(p, U)
+    E = rand_direction(phi.shape, 72)
+    h = 1e-3
+    L = []
+    for sgn in (+1, -1):
+        r = O.bicgstab(p, U, C, None, phi + sgn * h * E, op=O.OP_D, tol=1e-14, maxiter=20000)
+        assert r.status == 0
+        L.append(float(np.vdot(r.x, r.x).real))
+    got = (L[0] - L[1]) / (2 * h)
+    want = float(np.sum(np.conj(O.source_grad(g.chi)) * E).real)
+    assert abs(got - want) <= 1e-8 * abs(want), (got, want)
