@@ -244,6 +244,20 @@ dd_status dd_set_csw(dd_ctx *ctx, double csw);
  * vectors.  Synchronises the stream. */
 dd_status dd_force(dd_ctx *ctx, void *out_dev, double *dcsw, const void *psi_dev, const void *chi_dev, int su3);
 
+/* dd_force for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results as dd_force, but the work field (54 complex doubles = 864
+ * bytes per site) lives in a fixed 64 MiB device array that the library holds on
+ * every GPU it runs on until the process ends, instead of a field the first call
+ * allocates; the call makes no hipMalloc, hipFree or other allocating call.
+ * Lattices of at most 77672 sites (64 MiB / 864 B; 16^4 fits) -- a larger one
+ * returns DD_ERR_ARG, naming the limit, before any device work.  Every call on one
+ * GPU shares that array (each call rewrites all of it that it reads): calls that
+ * overlap on one GPU, from two streams or two host threads, race -- serialise them.
+ * Its launches are not recorded by dd_timing_*.  Synchronises the stream. */
+dd_status dd_force_noalloc(dd_ctx *ctx, void *out_dev, double *dcsw, const void *psi_dev, const void *chi_dev,
+                           int su3);
+
 /* ---- batched right-hand sides ------------------------------------------- */
 
 /* Inner solver of bicgstab_solve_batch: BiCGStab on A M_SAP with the SAP of

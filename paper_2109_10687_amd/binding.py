@@ -38,7 +38,8 @@ EXPORTS = ["dd_create", "dd_destroy", "dd_load_gauge", "dirac_apply", "sap_preco
            "dirac_apply_packed_f16in", "dd_timing_enable", "dd_timing_query", "bicgstab_solve_dagger", "dd_spinor_norm2", "dd_set_csw",
            "dd_force", "dirac_apply_batch", "dd_batch_set_variant", "dd_batch_tuning", "dd_batch_variant_name",
            "bicgstab_solve_batch", "dd_multi_create", "dd_multi_destroy", "dd_multi_last_error", "dd_multi_context",
-           "dd_multi_load_gauge", "dirac_apply_multi", "bicgstab_solve_multi", "dd_solve_history"]
+           "dd_multi_load_gauge", "dirac_apply_multi", "bicgstab_solve_multi", "dd_solve_history",
+           "dd_force_noalloc"]
 
 
 class DDError(RuntimeError):
@@ -94,6 +95,7 @@ def lib():
             "dd_spinor_norm2": (i, [vp, vp, ctypes.POINTER(d)]),
             "dd_set_csw": (i, [vp, d]),
             "dd_force": (i, [vp, vp, ctypes.POINTER(d), vp, vp, i]),
+            "dd_force_noalloc": (i, [vp, vp, ctypes.POINTER(d), vp, vp, i]),
             "dirac_apply_batch": (i, [vp, vp, vp, i, i, i]),
             "dd_batch_set_variant": (i, [vp, i]),
             "dd_batch_tuning": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(d), i]),
@@ -264,6 +266,16 @@ def dd_force(ctx, out, psi, chi, su3, shape, want_dcsw=True):
     d = ctypes.c_double(0)
     _check(ctx, lib().dd_force(ctx, _c128(out, (4,) + shape + (3, 3), "out"), ctypes.byref(d) if want_dcsw else None,
                                _c128(psi, sp, "psi"), _c128(chi, sp, "chi"), int(su3)))
+    return d.value if want_dcsw else None
+
+
+def dd_force_noalloc(ctx, out, psi, chi, su3, shape, want_dcsw=True):
+    """dd_force with the work field in the library's fixed device array (no allocation)."""
+    sp = shape + (3, 4)
+    d = ctypes.c_double(0)
+    _check(ctx, lib().dd_force_noalloc(ctx, _c128(out, (4,) + shape + (3, 3), "out"),
+                                       ctypes.byref(d) if want_dcsw else None, _c128(psi, sp, "psi"),
+                                       _c128(chi, sp, "chi"), int(su3)))
     return d.value if want_dcsw else None
 
 

@@ -89,6 +89,10 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
         dd_destroy(c);
         return DD_ERR_NOMEM;
     }
+    // the device address of dd_force_noalloc's work array on this (the current) device;
+    // a failed lookup is reported by that entry point, not here
+    c->yscratch_err = dd::force_scratch_address(&c->yscratch);
+    if (c->yscratch_err != hipSuccess) c->yscratch = nullptr;
     *out = c;
     return DD_OK;
 }
@@ -358,24 +362,19 @@ dd_status dd_set_csw(dd_ctx *c, double csw)
     return DD_OK;
 }
 
-dd_status dd_force(dd_ctx *c, void *out_dev, double *dcsw, const void *psi_dev, const void *chi_dev, int su3)
+// the force of dd_force and dd_force_noalloc with the work field y (54 complex doubles
+// per site); timed = false launches without the kernel timers (whose event pool may grow)
+static dd_status force_entry(dd_ctx *c, void *out_dev, double *dcsw, const void *psi_dev, const void *chi_dev,
+                             int su3, void *y, bool timed_launch)
 {
-    if (!c || !out_dev || !psi_dev || !chi_dev) return fail(c, DD_ERR_ARG, "null argument");
-    if (su3 != 0 && su3 != 1) return fail(c, DD_ERR_ARG, "su3 must be 0 or 1");
-    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
     const Geom &g = c->g;
-    if (!c->yforce && hipMalloc(&c->yforce, (size_t)g.V * 54 * 16) != hipSuccess) {
-        (void)hipGetLastError();
-        c->yforce = nullptr;
-        return fail(c, DD_ERR_NOMEM, "force work field");
-    }
     dd::ForceArgs a{};
     a.psi = c->f64[0];
     a.chi = c->f64[1];
     HIPCK(c, dd::launch_pack_spinor(g, c->stream, DD_F64, c->f64[0], psi_dev));
     HIPCK(c, dd::launch_pack_spinor(g, c->stream, DD_F64, c->f64[1], chi_dev));
     a.u64 = c->U64;
-    a.y = c->yforce;
+    a.y = y;
     a.out = out_dev;
     a.partials = dcsw ? c->partials : nullptr;
     a.dcsw = c->red;
@@ -390,7 +389,8 @@ dd_status dd_force(dd_ctx *c, void *out_dev, double *dcsw, const void *psi_dev, 
     const double V = (double)g.V;
     const double bytes = V * (2 * 192.0 + 4 * 144.0 + 2 * 864.0 + 4 * 144.0 + (dcsw ? 4 * 144.0 : 0.0));
     const double flops = V * (4 * FORCE_LINK_FLOPS + FORCE_Y_FLOPS + (dcsw ? FORCE_DCSW_FLOPS : 0.0));
-    hipError_t e = timed(c, DD_KT_FORCE, bytes, flops, [&] { return dd::launch_force(g, c->stream, a); });
+    hipError_t e = timed_launch ? timed(c, DD_KT_FORCE, bytes, flops, [&] { return dd::launch_force(g, c->stream, a); })
+                                : dd::launch_force(g, c->stream, a);
     if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("force launch: ") + hipGetErrorString(e));
     if (dcsw) {
         HIPCK(c, hipMemcpyAsync(c->red_host, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -400,6 +400,35 @@ dd_status dd_force(dd_ctx *c, void *out_dev, double *dcsw, const void *psi_dev, 
         HIPCK(c, hipStreamSynchronize(c->stream));
     }
     return DD_OK;
+}
+
+dd_status dd_force(dd_ctx *c, void *out_dev, double *dcsw, const void *psi_dev, const void *chi_dev, int su3)
+{
+    if (!c || !out_dev || !psi_dev || !chi_dev) return fail(c, DD_ERR_ARG, "null argument");
+    if (su3 != 0 && su3 != 1) return fail(c, DD_ERR_ARG, "su3 must be 0 or 1");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    if (!c->yforce && hipMalloc(&c->yforce, (size_t)c->g.V * 54 * 16) != hipSuccess) {
+        (void)hipGetLastError();
+        c->yforce = nullptr;
+        return fail(c, DD_ERR_NOMEM, "force work field");
+    }
+    return force_entry(c, out_dev, dcsw, psi_dev, chi_dev, su3, c->yforce, true);
+}
+
+dd_status dd_force_noalloc(dd_ctx *c, void *out_dev, double *dcsw, const void *psi_dev, const void *chi_dev, int su3)
+{
+    if (!c || !out_dev || !psi_dev || !chi_dev) return fail(c, DD_ERR_ARG, "null argument");
+    if (su3 != 0 && su3 != 1) return fail(c, DD_ERR_ARG, "su3 must be 0 or 1");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    const size_t need = (size_t)c->g.V * 54 * 16;
+    if (need > dd::FORCE_SCRATCH_BYTES)
+        return fail(c, DD_ERR_ARG, "lattice too large for dd_force_noalloc: " + std::to_string(c->g.V) +
+                                       " sites need " + std::to_string(need) + " bytes of work space, the fixed "
+                                       "array holds " + std::to_string(dd::FORCE_SCRATCH_BYTES) + " (at most " +
+                                       std::to_string(dd::FORCE_SCRATCH_BYTES / (54 * 16)) + " sites)");
+    if (!c->yscratch)
+        return fail(c, DD_ERR_HIP, std::string("work array address: ") + hipGetErrorString(c->yscratch_err));
+    return force_entry(c, out_dev, dcsw, psi_dev, chi_dev, su3, c->yscratch, false);
 }
 
 dd_status dd_timing_enable(dd_ctx *c, int on)

@@ -30,11 +30,39 @@
 // Two kernels: k_force_y computes Y for the six planes of every site (FP64,
 // 54 complex per site, block-major like every other field) and the c_SW sum;
 // k_force_w gathers per link.  Both in FP64: the force is taken once per solve.
+#include <mutex>
+
 #include "dd_device.h"
 #include "dd_gauge.h"
 #include "dd_launch.h"
 
 namespace dd {
+
+// Work field of the force for the entry point that allocates nothing: a fixed
+// file-scope device array (each GPU holds its own copy, at its own address, until
+// the process ends).  Host code never passes `scratch` itself to a kernel -- on the
+// host that name is only a stand-in -- but the device address looked up below.
+static __device__ __align__(256) unsigned char scratch[FORCE_SCRATCH_BYTES];
+
+hipError_t force_scratch_address(void **ptr)
+{
+    // once per device, with that device current
+    static std::mutex mu;
+    static void *addr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 // chiral components of a spinor: u[blk][s][c] = psi_s + (-1)^blk psi_{s+2}
 // (the rotation P = [[1, 1], [1, -1]] / sqrt 2 without the 1/sqrt 2)

@@ -44,6 +44,8 @@ struct dd_ctx {
     void *U64 = nullptr, *U32 = nullptr, *U16 = nullptr;
     void *clov64 = nullptr, *cinv32 = nullptr, *cinv16 = nullptr;
     void *yforce = nullptr;  // force work field (54 complex per site), allocated by the first dd_force
+    void *yscratch = nullptr;       // the fixed device array that dd_force_noalloc uses instead
+    hipError_t yscratch_err = hipSuccess;  // the result of looking its address up in dd_create
     // batched right-hand sides: contiguous arrays of per-RHS internal fields, allocated by the
     // first batched call and grown on demand (kinds: see BK_* below)
     int bcap = 0;

@@ -190,4 +190,11 @@ hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, i
 // fermion force of L = |D^{-1} phi|^2 from psi = D^{-1} phi and chi = D^{-dagger} psi
 hipError_t launch_force(const Geom &g, hipStream_t st, const ForceArgs &a);
 
+// the force's work field (54 complex doubles per site) in a fixed device array, for
+// the entry point that allocates nothing: its size, and its address on the current
+// device (looked up once per device)
+constexpr size_t FORCE_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int MAX_DEVICES = 64;
+hipError_t force_scratch_address(void **ptr);
+
 }  // namespace dd
