@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--only-batch", action="store_true", help="run the batched leg only (profiling runs)")
     ap.add_argument("--multi", choices=["on", "off"], default="on",
                     help="the multi-lattice leg: 8^4, 12^4, 16^4, 16^3x32, two each, in one launch")
+    ap.add_argument("--single-prec", choices=["on", "off"], default="on",
+                    help="the 32^4 leg: FP32 SAP-BiCGStab at kappa 0.1365 to 1e-6 against plain FP64")
+    ap.add_argument("--single-prec-fp64-maxiter", type=int, default=6000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of 4 GiB five times (scale for HBM byte counters) and exit")
     return ap.parse_args()
@@ -290,6 +293,69 @@ def batch_bench(dd, args, reps=10):
     return out
 
 
+def single_prec_bench(dd, args, reps=3, apply_reps=20):
+    """The 32^4 leg at the operator parameters the paper's single-precision runs stand for:
+    kappa 0.1365, c_SW 1.7, links exp(0.3 i H), 4^4 blocks, N_SAP = N_JAC = 4; FP32 SAP-BiCGStab
+    (Alg. 5 on A M_SAP, FP32 SAP) to Alg. 5's single-precision tolerance 1e-6 on its recursive
+    residual, against plain FP64 BiCGStab on D to a true residual of 1e-6 on the same GPU.  At this
+    kappa plain BiCGStab breaks down before reaching 1e-6 on this ensemble: its time is then a lower
+    bound.  The FP32 apply of this lattice (0.8 GB per apply) partly stays in the 256 MB Infinity
+    Cache, so its GB/s are reported as such, not as HBM bandwidth."""
+    import torch
+    import synth
+    dims = (32, 32, 32, 32)
+    params = dd.Params(dims=dims, kappa=0.1365, csw=1.7, block=(4, 4, 4, 4), n_sap=4, n_jac=4)
+    U = synth.su3_links(dims, 0.3, args.seed + 60, device="cuda")
+    b = synth.gaussian_spinor(dims, args.seed + 61, device="cuda")
+    s = dd.Solver(params, U)
+    del U
+    x, info = s.solve(b, tol=1e-6, maxiter=2000, mode=dd.DD_SOLVE_F32_SAP)  # warm-up
+    secs = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = s.solve(b, tol=1e-6, maxiter=2000, mode=dd.DD_SOLVE_F32_SAP)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+    t32 = sorted(secs)[len(secs) // 2]
+    out = {"workload": "32x32x32x32 FP32 SAP-BiCGStab, kappa 0.1365, c_SW 1.7, tol 1e-6",
+           "fp32_sap": {"seconds": round(t32, 4), "iters": info["iters_inner_total"], "status": info["status"],
+                        "relres_recursive": info["relres_inner_last"], "relres_true": info["relres_true"]}}
+    # the two mixed-precision outer loops to 1e-10 at this kappa: defect correction (Alg. 4) and
+    # flexible GMRES, both around the FP32 BiCGStab with the FP16 SAP
+    out["mixed_to_1e-10"] = {}
+    for name, mode in (("defect_correction", dd.DD_SOLVE_MIXED), ("fgmres", dd.DD_SOLVE_FGMRES)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, im = s.solve(b, tol=1e-10, maxiter=12, mode=mode)
+        torch.cuda.synchronize()
+        out["mixed_to_1e-10"][name] = {"seconds": round(time.perf_counter() - t0, 3), "status": im["status"],
+                                       "status_detail": im["status_detail"], "outer": im["iters_outer"],
+                                       "inner": im["iters_inner_total"], "relres_true": im["relres_true"]}
+    x64, i64 = s.solve(b, tol=1e-6, maxiter=args.single_prec_fp64_maxiter, mode=dd.DD_SOLVE_F64_PLAIN)
+    conv = i64["status"] == "DD_OK"
+    out["fp64_plain"] = {"seconds": round(i64["seconds"], 3), "iters": i64["iters_inner_total"],
+                         "status": i64["status"], "status_detail": i64["status_detail"],
+                         "relres_true": i64["relres_true"], "converged": conv}
+    out["speedup_fp32_sap_vs_fp64" if conv else "speedup_fp32_sap_vs_fp64_lower_bound"] = round(i64["seconds"] / t32, 2)
+    fin = s.pack(b, dd.DD_F32)
+    fout = s.field(dd.DD_F32)
+    for _ in range(3):
+        s.apply_packed(fout, fin, op=dd.DD_OP_A, prec=dd.DD_F32)
+    s.timing(True)
+    for _ in range(apply_reps):
+        s.apply_packed(fout, fin, op=dd.DD_OP_A, prec=dd.DD_F32)
+    r = s.timing_report()["dirac_f32"]
+    s.timing(False)
+    out["apply_f32_A"] = {"ms": round(r["ms"] / r["launches"], 4), "GBps": round(r["bytes"] / r["ms"] / 1e6, 1),
+                          "note": "partly Infinity-Cache resident (0.8 GB per apply against 256 MB): not an HBM figure"}
+    s.close()
+    del b, x, x64, fin, fout
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 MULTI_SET = [((8, 8, 8, 8), (4, 4, 4, 4)), ((12, 12, 12, 12), (2, 2, 2, 2)), ((16, 16, 16, 16), (4, 4, 4, 4)),
              ((16, 16, 16, 32), (4, 4, 4, 4))]
 
@@ -360,15 +426,20 @@ def multi_bench(dd, args, reps=20):
     return out
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The FP64 oracle's D apply on a 32^4 sample of the workload (same kappa,
-    c_SW and link recipe), on the host cores; reported in the metric's unit
-    (algorithmic GB/s at 1536 B/site)."""
+def cpu_baseline(gpu_fp64_iters=None, seconds_target=8.0, iter_sample=20):
+    """The FP64 oracle on the host cores, on bounded samples of the workload (same c_SW and link
+    recipe): its D apply on 32^4 in the metric's unit (algorithmic GB/s at 1536 B/site), and its
+    plain FP64 BiCGStab (Alg. 5, M = I): to 1e-10 on the 4^4 correctness lattice and on 16^4 at
+    kappa 0.133 (measured), and on 32^4 at kappa 0.133 as `iter_sample` timed iterations.  kappa
+    0.133 because at 0.1365 plain BiCGStab does not reach 1e-10 on this ensemble at 32^4 and
+    above.  The 32^4 and 64^3 x 128 solve times are estimates, labelled so: the oracle's time per
+    iteration (at 64^3 x 128 the 32^4 figure times the volume ratio) times the iteration count
+    of the GPU's plain FP64 solve."""
     import numpy as np
     import oracle as O
     import synth
     dims = (32, 32, 32, 32)
-    p = O.Params(dims=dims, kappa=0.1365, csw=1.7, block=(4, 4, 4, 4))
+    p = O.Params(dims=dims, kappa=0.133, csw=1.7, block=(4, 4, 4, 4))
     U = synth.su3_links(dims, 0.3, 5).numpy()
     C = O.clover_field(p, U)
     x = synth.gaussian_spinor(dims, 6).numpy()
@@ -383,9 +454,61 @@ def cpu_baseline(seconds_target=15.0):
     V = math.prod(dims)
     cores = os.environ.get("OMP_NUM_THREADS")
     cores = int(cores) if cores else (len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count())
+    solves = {}
+    for name, d, kappa, csw, eps in (("4x4x4x4", (4, 4, 4, 4), 0.12, 1.0, 0.5), ("16x16x16x16", (16, 16, 16, 16), 0.133, 1.7, 0.3)):
+        q = O.Params(dims=d, kappa=kappa, csw=csw, block=(2, 2, 2, 2))
+        Uq = synth.su3_links(d, eps, 7).numpy()
+        bq = synth.gaussian_spinor(d, 8).numpy()
+        Cq = O.clover_field(q, Uq)
+        t1 = time.perf_counter()
+        r = O.bicgstab(q, Uq, Cq, None, bq, op=O.OP_D, tol=1e-10, maxiter=20000)
+        solves[name] = {"kappa": kappa, "csw": csw, "seconds": round(time.perf_counter() - t1, 3), "iters": r.iters,
+                        "relres": r.relres, "kind": "measured"}
+    b = synth.gaussian_spinor(dims, 9).numpy()
+    t1 = time.perf_counter()
+    r = O.bicgstab(p, U, C, None, b, op=O.OP_D, tol=1e-10, maxiter=iter_sample)
+    per_iter = (time.perf_counter() - t1) / max(r.iters, 1)
+    est = {"kappa": 0.133, "csw": 1.7, "seconds_per_iter": round(per_iter, 4), "sampled_iters": r.iters,
+           "kind": "estimate: oracle time per iteration x the GPU plain FP64 iteration count"}
+    if gpu_fp64_iters and gpu_fp64_iters.get("32x32x32x32"):
+        est["gpu_fp64_iters"] = gpu_fp64_iters["32x32x32x32"]
+        est["seconds"] = round(per_iter * est["gpu_fp64_iters"], 1)
+    solves["32x32x32x32"] = est
+    if gpu_fp64_iters and gpu_fp64_iters.get("64x64x64x128"):
+        it = gpu_fp64_iters["64x64x64x128"]
+        solves["64x64x64x128"] = {"kappa": 0.133, "csw": 1.7, "gpu_fp64_iters": it,
+                                  "seconds": round(per_iter * 32 * it, 1),
+                                  "kind": "estimate: 32^4 oracle time per iteration x 32 (volume ratio) x the GPU "
+                                          "plain FP64 iteration count; the oracle cannot hold this lattice's clover"}
     return {"value": round(1536.0 * V * n / el / 1e9, 4), "unit": "GB/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle D apply on a 32^4 lattice (kappa 0.1365, c_SW 1.7, eps 0.3), {n} applies in "
-                      f"{el:.1f} s; {el / n * 1e3:.0f} ms per apply; clover precomputed"}
+            "sample": f"FP64 oracle D apply on a 32^4 lattice (kappa 0.133, c_SW 1.7, eps 0.3), {n} applies in "
+                      f"{el:.1f} s; {el / n * 1e3:.0f} ms per apply; clover precomputed",
+            "cpu_model": cpu_model(), "solves": solves}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def gpu_plain_iters_32(dd, args):
+    """Iterations of the GPU's plain FP64 BiCGStab to 1e-10 on the oracle's 32^4 baseline system
+    (kappa 0.133; the same links and source as cpu_baseline), for its labelled estimate."""
+    import synth
+    dims = (32, 32, 32, 32)
+    # drawn by the CPU generator, as the oracle's inputs are
+    s = dd.Solver(dd.Params(dims=dims, kappa=0.133, csw=1.7, block=(4, 4, 4, 4)),
+                  synth.su3_links(dims, 0.3, 5).cuda())
+    _, info = s.solve(synth.gaussian_spinor(dims, 9).cuda(), tol=1e-10, maxiter=4000,
+                      mode=dd.DD_SOLVE_F64_PLAIN)
+    s.close()
+    return info["iters_inner_total"] if info["status"] == "DD_OK" else None
 
 
 def main():
@@ -429,6 +552,14 @@ def main():
         if args.only_batch:
             print(json.dumps({"batch": batch}))
             return
+
+    single = None
+    if args.single_prec == "on" and not args.only_apply:
+        log("32^4 single-precision leg (kappa 0.1365)")
+        single = single_prec_bench(dd, args)
+        log(f"32^4: FP32 SAP {single['fp32_sap']['seconds']:.3f} s ({single['fp32_sap']['iters']} it., "
+            f"{single['fp32_sap']['status']}); plain FP64 {single['fp64_plain']['seconds']:.2f} s "
+            f"({single['fp64_plain']['iters']} it., {single['fp64_plain']['status']})")
 
     multi = None
     if args.multi == "on" and not args.only_apply:
@@ -482,6 +613,7 @@ def main():
             f"inner {info['iters_inner_total']}, true residual {info['relres_true']:.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    hist = solver.history()  # of the last timed solve
     rep = solver.timing_report()
     solver.timing(False)
     ms_step = wall / args.steps * 1e3
@@ -544,13 +676,28 @@ def main():
                    "sap_fp16_arith": args.sap_fp16_arith, "parallelism": "single GPU"},
         "solve_mixed": {"seconds": round(ms_step / 1e3, 3), "iters_outer": infos[-1]["iters_outer"],
                         "iters_inner": infos[-1]["iters_inner_total"],
-                        "relres_true": infos[-1]["relres_true"], "status": infos[-1]["status"]},
+                        "relres_true": infos[-1]["relres_true"], "status": infos[-1]["status"],
+                        "history": {k: [float(f"{v:.3e}") for v in h] for k, h in hist.items()}},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "dirac_apply": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in micro.items()},
         "roofline": roof,
         "roofline_dirac": roof_dirac,
     }
+    # the flexible outer loop (flexible GMRES around the same inner solver) on the same system,
+    # after the timed steps: a first solve allocates its extra fields, the second is reported
+    for rep in range(2):
+        xf, inf_f = solver.solve(b, tol=args.tol, maxiter=50, mode=dd.DD_SOLVE_FGMRES)
+    log(f"flexible GMRES: {inf_f['status']} {inf_f['seconds']:.2f} s, outer {inf_f['iters_outer']}, "
+        f"inner {inf_f['iters_inner_total']}, true residual {inf_f['relres_true']:.2e}")
+    result["solve_fgmres"] = {"seconds": round(inf_f["seconds"], 3), "iters_outer": inf_f["iters_outer"],
+                              "iters_inner": inf_f["iters_inner_total"], "relres_true": inf_f["relres_true"],
+                              "status": inf_f["status"],
+                              "vs_defect_correction": round(inf_f["seconds"] / (ms_step / 1e3), 3),
+                              "solution_relerr_vs_defect_correction":
+                                  (torch.linalg.vector_norm(xf - x) / torch.linalg.vector_norm(x)).item()}
+    del xf
+
     # the practical streaming ceiling of this GPU, measured beside the 8 TB/s peak
     hbm = measured_hbm()
     best = max(hbm.values())
@@ -565,6 +712,8 @@ def main():
         result["batch"] = batch
     if multi is not None:
         result["multi"] = multi
+    if single is not None:
+        result["single_prec_32x32x32x32"] = single
 
     # ---- plain FP64 BiCGStab on the same system (speedup denominator), once
     if args.fp64 == "on":
@@ -586,8 +735,13 @@ def main():
         del x64
 
     if args.cpu_baseline == "on":
-        log("timing the FP64 CPU oracle on a 32^4 sample")
-        result["cpu_baseline"] = cpu_baseline()
+        log("timing the FP64 CPU oracle on bounded samples (D apply on 32^4, solves on 4^4 and 16^4, "
+            "iterations on 32^4)")
+        gpu_iters = {}
+        if "solve_fp64_plain" in result and result["solve_fp64_plain"]["converged"] and args.kappa == 0.133:
+            gpu_iters["64x64x64x128"] = result["solve_fp64_plain"]["iters"]
+        gpu_iters["32x32x32x32"] = gpu_plain_iters_32(dd, args)
+        result["cpu_baseline"] = cpu_baseline(gpu_iters)
     print(json.dumps(result))
 
 

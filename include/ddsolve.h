@@ -34,8 +34,12 @@
  *    antiperiodic in time.  The clover term is built from the links alone.
  *  - All *_dev pointers are device (HBM) addresses owned by the caller;
  *    the library never frees them.  The library owns its packed fields and
- *    work vectors: they are allocated in dd_create / dd_load_gauge and freed
- *    in dd_destroy.  No entry point allocates device memory during a solve.
+ *    work vectors, freed in dd_destroy: dd_create allocates those of the
+ *    Dirac apply, the SAP and the solve modes DD_SOLVE_F64_PLAIN,
+ *    DD_SOLVE_F32_SAP and DD_SOLVE_MIXED; the GCR and flexible GMRES modes,
+ *    the batched solves and dd_force allocate their extra fields on first use
+ *    (DD_ERR_NOMEM if that fails) and keep them.  dd_force_noalloc never
+ *    allocates.
  *  - Work runs on the HIP stream given to dd_create (NULL = default stream).
  *    dirac_apply and sap_precondition are asynchronous on that stream;
  *    bicgstab_solve synchronises it.
@@ -94,7 +98,15 @@ typedef enum {
      * alternative to BiCGStab that Sec. 3 names for a preconditioner that varies
      * between applications, as a rounded FP16 SAP does.  Each inner iteration
      * applies M_SAP and A once; the residual never grows. */
-    DD_SOLVE_MIXED_GCR = 3
+    DD_SOLVE_MIXED_GCR = 3,
+    /* restarted flexible GMRES on D in FP64 (cycle length fgmres_nkv) in place of
+     * the defect correction: the outer loop Sec. 3 proposes, with the FP32
+     * SAP-BiCGStab of DD_SOLVE_MIXED (FP16 SAP) as a flexible preconditioner
+     * that may differ from one application to the next.  Each outer iteration
+     * runs one inner solve of A z = C_inv v for the current Arnoldi vector v and
+     * keeps z; the solution minimises the FP64 residual over the kept z.  tol
+     * is the true FP64 relative residual; maxiter bounds the outer iterations. */
+    DD_SOLVE_FGMRES = 4
 } dd_solve_mode;
 
 typedef struct {
@@ -112,8 +124,8 @@ typedef struct {
                            (0 = 1e-6, the per-pass reduction Sec. 3 expects); a pass
                            whose start is already close to tol stops earlier       */
     int inner_maxiter;  /* iteration cap of each inner solve (0 = 2000)            */
-    int gcr_nkv;        /* GCR cycle length for DD_SOLVE_MIXED_GCR, 1..16 (0 = 16);
-                           dd_create allocates gcr_nkv FP32 and gcr_nkv FP16 fields */
+    int gcr_nkv;        /* GCR cycle length for DD_SOLVE_MIXED_GCR, 1..16 (0 = 16); the
+                           first such solve allocates gcr_nkv FP32 and FP16 fields   */
     int sap_fp16_arith; /* 1: the FP16-storage SAP (sap_precondition at DD_F16 and the
                            mixed modes) also does its block-local Jacobi sweeps in
                            packed FP16 arithmetic, on a source scaled per block to unit
@@ -122,10 +134,15 @@ typedef struct {
     int stall_window;   /* an inner FP32 solve stops (status detail 6) when its recursive
                            residual has not fallen 10x below the last such point within
                            this many iterations (0 = 200; negative = never)          */
+    int fgmres_nkv;     /* flexible GMRES cycle length for DD_SOLVE_FGMRES, 1..16 (0 = 4);
+                           the basis takes four FP64 and the directions three FP32 work
+                           vectors of the context, the first such solve allocates the
+                           rest (fgmres_nkv - 3 FP64, fgmres_nkv - 3 FP32 fields)    */
 } dd_params;
 
 typedef struct {
-    int iters_outer;          /* defect-correction passes (1 for the single-level modes) */
+    int iters_outer;          /* defect-correction passes or flexible GMRES iterations
+                                 (1 for the single-level modes)                   */
     int iters_inner_total;    /* BiCGStab loop passes summed over all solves      */
     double relres_true;       /* |b - D x| / |b| in FP64 at exit                  */
     double relres_inner_last; /* last recursive residual of the last inner solve  */
@@ -181,11 +198,12 @@ dd_status dirac_apply(dd_ctx *ctx, void *out_dev, const void *in_dev, dd_prec pr
 dd_status sap_precondition(dd_ctx *ctx, void *x_dev, const void *b_dev, dd_prec prec);
 
 /* Solve D x = b (canonical fields on the device).  On entry x holds the
- * initial guess for DD_SOLVE_F64_PLAIN and DD_SOLVE_MIXED (pass zeros for a
- * cold start; a previous solution resumes the solve) and is ignored for
+ * initial guess for every mode but DD_SOLVE_F32_SAP (pass zeros for a cold
+ * start; a previous solution resumes the solve) and is ignored for
  * DD_SOLVE_F32_SAP; on exit it holds the solution.  maxiter bounds the
- * BiCGStab loop passes of a single-level solve, or the defect-correction
- * passes of DD_SOLVE_MIXED and DD_SOLVE_MIXED_GCR.  Returns DD_OK, DD_NOT_CONVERGED or DD_BREAKDOWN
+ * BiCGStab loop passes of a single-level solve, the defect-correction
+ * passes of DD_SOLVE_MIXED and DD_SOLVE_MIXED_GCR, or the outer iterations of
+ * DD_SOLVE_FGMRES.  Returns DD_OK, DD_NOT_CONVERGED or DD_BREAKDOWN
  * (x then holds the best iterate) and fills info (may be NULL).  A source
  * with NaN or Inf returns DD_ERR_NONFINITE without touching x.
  * Synchronises the stream. */

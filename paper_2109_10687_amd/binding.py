@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libddsolve.so")
 
 DD_F64, DD_F32, DD_F16 = 0, 1, 2
 DD_OP_D, DD_OP_A, DD_OP_DDAG = 0, 1, 2
-DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED, DD_SOLVE_MIXED_GCR = 0, 1, 2, 3
+DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED, DD_SOLVE_MIXED_GCR, DD_SOLVE_FGMRES = 0, 1, 2, 3, 4
 (DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16IN, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS, DD_KT_FORCE,
  DD_KT_DIRAC_MRHS, DD_KT_DIRAC_MULTI) = range(9)
 KERNEL_CLASSES = {"dirac_f64": DD_KT_DIRAC_F64, "dirac_f32": DD_KT_DIRAC_F32, "dirac_f16in": DD_KT_DIRAC_F16IN,
@@ -53,7 +53,7 @@ class _Params(ctypes.Structure):
                 ("csw", ctypes.c_double), ("phase_re", ctypes.c_double * 4), ("phase_im", ctypes.c_double * 4),
                 ("n_sap", ctypes.c_int), ("n_jac", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("inner_maxiter", ctypes.c_int), ("gcr_nkv", ctypes.c_int), ("sap_fp16_arith", ctypes.c_int),
-                ("stall_window", ctypes.c_int)]
+                ("stall_window", ctypes.c_int), ("fgmres_nkv", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -132,6 +132,7 @@ class Params:
     gcr_nkv: int = 16
     sap_fp16_arith: int = 1
     stall_window: int = 200
+    fgmres_nkv: int = 4
 
     def c(self):
         p = _Params()
@@ -150,6 +151,7 @@ class Params:
         p.gcr_nkv = int(self.gcr_nkv)
         p.sap_fp16_arith = int(self.sap_fp16_arith)
         p.stall_window = int(self.stall_window)
+        p.fgmres_nkv = int(self.fgmres_nkv)
         return p
 
     @property

@@ -33,7 +33,8 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
     if (c->prm.inner_maxiter <= 0) c->prm.inner_maxiter = 2000;
     if (c->prm.gcr_nkv <= 0) c->prm.gcr_nkv = dd::GCR_MAX_NKV;
     if (c->prm.stall_window == 0) c->prm.stall_window = 200;
-    if (c->prm.gcr_nkv > dd::GCR_MAX_NKV) {
+    if (c->prm.fgmres_nkv <= 0) c->prm.fgmres_nkv = 4;
+    if (c->prm.gcr_nkv > dd::GCR_MAX_NKV || c->prm.fgmres_nkv > dd::GCR_MAX_NKV) {
         delete c;
         return DD_ERR_ARG;
     }
@@ -79,8 +80,6 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
     for (int i = 0; ok && i < N64; ++i) ok = alloc(&c->f64[i], spinor_bytes(g, DD_F64));
     for (int i = 0; ok && i < N32; ++i) ok = alloc(&c->f32[i], spinor_bytes(g, DD_F32));
     for (int i = 0; ok && i < N16; ++i) ok = alloc(&c->f16[i], spinor_bytes(g, DD_F16));
-    for (int i = 0; ok && i < c->prm.gcr_nkv; ++i)
-        ok = alloc(&c->gz[i], spinor_bytes(g, DD_F32)) && alloc(&c->gp[i], spinor_bytes(g, DD_F16));
     ok = ok && alloc((void **)&c->partials, dd::MAX_PARTIALS * sizeof(double)) &&
          alloc((void **)&c->red, RED_MAX * sizeof(double)) && alloc((void **)&c->flag, 4 * sizeof(int)) &&
          hipHostMalloc((void **)&c->red_host, RED_MAX * sizeof(double), hipHostMallocDefault) == hipSuccess;
@@ -113,6 +112,10 @@ dd_status dd_destroy(dd_ctx *c)
     for (void *p : c->gz)
         if (p) (void)hipFree(p);
     for (void *p : c->gp)
+        if (p) (void)hipFree(p);
+    for (void *p : c->fv_own)
+        if (p) (void)hipFree(p);
+    for (void *p : c->fz_own)
         if (p) (void)hipFree(p);
     for (void *p : c->bk)
         if (p) (void)hipFree(p);
@@ -220,7 +223,7 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
                              dd_solve_info *info, bool dagger)
 {
     if (!c || !x_dev || !b_dev) return fail(c, DD_ERR_ARG, "null argument");
-    if (!(tol > 0) || maxiter < 0 || mode < DD_SOLVE_F64_PLAIN || mode > DD_SOLVE_MIXED_GCR)
+    if (!(tol > 0) || maxiter < 0 || mode < DD_SOLVE_F64_PLAIN || mode > DD_SOLVE_FGMRES)
         return fail(c, DD_ERR_ARG, "bad tolerance, maxiter or mode");
     if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
     auto t0 = std::chrono::steady_clock::now();
@@ -243,6 +246,17 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
         inf.iters_inner_total = o.iters;
         inf.relres_inner_last = o.relres;
         inf.status_detail = o.detail;
+    } else if (mode == DD_SOLVE_FGMRES) {
+        if ((st = ensure_fgmres(c)) != DD_OK) return st;
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, x, x_dev, dagger));
+        if (bn2 == 0.0) HIPCK(c, hipMemsetAsync(x, 0, spinor_bytes(c->g, DD_F64), c->stream));
+        OuterOut o;
+        res = bn2 == 0.0 ? DD_OK : solve_fgmres64(c, x, b, bn2, tol, maxiter, o);
+        if (res < 0) return res;
+        inf.iters_outer = o.outer;
+        inf.iters_inner_total = o.inner;
+        inf.relres_inner_last = o.inner_last;
+        inf.status_detail = o.detail;
     } else if (mode == DD_SOLVE_F32_SAP) {
         void *src = c->f32[0], *y = c->f32[1];
         if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {src, b, c->cinv32}, {1, 0}, {1.0}))) != DD_OK) return st;
@@ -256,6 +270,7 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
         inf.status_detail = o.detail;
     } else {
         // Alg. 4: x += err * P_DP(A_SP^{-1} R_SP(C_inv r / err)), r = b - D x in FP64
+        if (mode == DD_SOLVE_MIXED_GCR && (st = ensure_gcr(c)) != DD_OK) return st;
         HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F64, x, x_dev, dagger));
         void *r = c->f64[2], *tmp = c->f64[3];
         void *src = c->f32[0], *y = c->f32[1];

@@ -60,6 +60,10 @@ struct dd_ctx {
     // work vectors
     void *f64[ddh::N64] = {}, *f32[ddh::N32] = {}, *f16[ddh::N16] = {};
     void *gz[dd::GCR_MAX_NKV] = {}, *gp[dd::GCR_MAX_NKV] = {};  // GCR images (FP32), directions (FP16)
+    // flexible GMRES basis (FP64) and directions (FP32): the first ones alias work vectors the
+    // inner solve never touches, the rest are allocated by the first such solve (fv_own, fz_own)
+    void *fv[dd::GCR_MAX_NKV + 1] = {}, *fz[dd::GCR_MAX_NKV] = {};
+    void *fv_own[dd::GCR_MAX_NKV + 1] = {}, *fz_own[dd::GCR_MAX_NKV] = {};
     double *partials = nullptr, *red = nullptr, *red_host = nullptr;
     int *flag = nullptr;
     // kernel timing
@@ -222,6 +226,18 @@ dd_status solve_plain64(dd_ctx *c, void *x, void *b, double tol, int maxiter, So
 dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int maxiter, SolveOut &o);
 // flexible GCR on A M_SAP with the FP16 SAP
 dd_status solve_gcr32(dd_ctx *c, void *src, void *y, double tol, int maxiter, SolveOut &o);
+// the GCR and flexible GMRES fields, allocated on the first solve of that mode
+dd_status ensure_gcr(dd_ctx *c);
+dd_status ensure_fgmres(dd_ctx *c);
+
+struct OuterOut {
+    int outer = 0, inner = 0;
+    double inner_last = 0;
+    int detail = 0;
+};
+// restarted flexible GMRES on D x = b in FP64 (x: initial guess and result), preconditioned by
+// the FP32 SAP-BiCGStab with the FP16 SAP; |b|^2 = bn2 > 0
+dd_status solve_fgmres64(dd_ctx *c, void *x, void *b, double bn2, double tol, int maxiter, OuterOut &o);
 
 // ---- dd_batch.cpp: batched right-hand sides and several lattices
 

@@ -962,23 +962,60 @@ template <int NV> DD_INL void wg_reduce_store_dyn(double (&v)[NV], int nv, doubl
         }
 }
 
-__global__ void __launch_bounds__(BLAS_WG) k_multidot(Geom g, VecSet zs, int k, const float2 *z, double *partials)
+// <z_j | z> for j < k; T2 = float2 (GCR images) or double2 (the FP64 basis of flexible GMRES)
+template <typename T2>
+__global__ void __launch_bounds__(BLAS_WG) k_multidot(Geom g, VecSet zs, int k, const T2 *z, double *partials)
 {
     double v[2 * GCR_MAX_NKV];
 #pragma unroll
     for (int q = 0; q < 2 * GCR_MAX_NKV; ++q) v[q] = 0;
     GRID_STRIDE(o, 12 * g.V)
     {
-        const float2 zo = z[o];
+        const T2 zo = z[o];
 #pragma unroll
         for (int j = 0; j < GCR_MAX_NKV; ++j) {
             if (j >= k) break;
-            const float2 a = ((const float2 *)zs.v[j])[o];
+            const T2 a = ((const T2 *)zs.v[j])[o];
             v[2 * j] += (double)a.x * zo.x + (double)a.y * zo.y;
             v[2 * j + 1] += (double)a.x * zo.y - (double)a.y * zo.x;
         }
     }
     wg_reduce_store_dyn<2 * GCR_MAX_NKV>(v, 2 * k, partials);
+}
+
+// ------------------------------------------------------------ flexible GMRES (FP64 basis)
+
+// w -= sum_j coef_j v_j (j < k, FP64); partial |w|^2
+__global__ void __launch_bounds__(BLAS_WG) k_orth64(Geom g, VecSet vs, int k, double2 *w, double *partials)
+{
+    double v[1] = {0};
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        double2 wo = w[o];
+        for (int j = 0; j < k; ++j) {
+            const double2 a = ((const double2 *)vs.v[j])[o];
+            wo.x -= vs.re[j] * a.x - vs.im[j] * a.y;
+            wo.y -= vs.re[j] * a.y + vs.im[j] * a.x;
+        }
+        w[o] = wo;
+        v[0] += wo.x * wo.x + wo.y * wo.y;
+    }
+    wg_reduce_store<1>(v, partials);
+}
+
+// x (FP64) += sum_j coef_j z_j (j < k, FP32)
+__global__ void __launch_bounds__(BLAS_WG) k_multi_axpy64(Geom g, VecSet zs, int k, double2 *x)
+{
+    GRID_STRIDE(o, 12 * g.V)
+    {
+        double2 xo = x[o];
+        for (int j = 0; j < k; ++j) {
+            const float2 a = ((const float2 *)zs.v[j])[o];
+            xo.x += zs.re[j] * a.x - zs.im[j] * a.y;
+            xo.y += zs.re[j] * a.y + zs.im[j] * a.x;
+        }
+        x[o] = xo;
+    }
 }
 
 __global__ void __launch_bounds__(BLAS_WG)
@@ -1335,10 +1372,31 @@ hipError_t launch_blas(const Geom &g, hipStream_t st, const BlasArgs &a)
     return hipGetLastError();
 }
 
-hipError_t launch_multidot(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *z, double *partials)
+hipError_t launch_multidot(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *z, double *partials, int prec)
 {
     if (k < 1 || k > GCR_MAX_NKV) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_multidot, dim3(blas_grid(g)), dim3(BLAS_WG), 0, st, g, zs, k, (const float2 *)z, partials);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_multidot<double2>, dim3(blas_grid(g)), dim3(BLAS_WG), 0, st, g, zs, k, (const double2 *)z,
+                           partials);
+    else if (prec == 1)
+        hipLaunchKernelGGL(k_multidot<float2>, dim3(blas_grid(g)), dim3(BLAS_WG), 0, st, g, zs, k, (const float2 *)z,
+                           partials);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_orth64(const Geom &g, hipStream_t st, const VecSet &vs, int k, void *w, double *partials)
+{
+    if (k < 0 || k > GCR_MAX_NKV) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_orth64, dim3(blas_grid(g)), dim3(BLAS_WG), 0, st, g, vs, k, (double2 *)w, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy64(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *x)
+{
+    if (k < 1 || k > GCR_MAX_NKV) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_multi_axpy64, dim3(blas_grid(g)), dim3(BLAS_WG), 0, st, g, zs, k, (double2 *)x);
     return hipGetLastError();
 }
 

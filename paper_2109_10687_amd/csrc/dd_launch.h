@@ -166,8 +166,12 @@ struct VecSet {
     void *v[GCR_MAX_NKV];
     double re[GCR_MAX_NKV], im[GCR_MAX_NKV];
 };
-// <z_j | z> for j < k: 2k partial sums per workgroup
-hipError_t launch_multidot(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *z, double *partials);
+// <z_j | z> for j < k: 2k partial sums per workgroup; z_j and z FP32 (prec 1) or FP64 (prec 0)
+hipError_t launch_multidot(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *z, double *partials,
+                           int prec = 1);
+// flexible GMRES: w -= sum_j coef_j v_j (FP64, j < k), partial |w|^2; x (FP64) += sum_j coef_j z_j (FP32)
+hipError_t launch_orth64(const Geom &g, hipStream_t st, const VecSet &vs, int k, void *w, double *partials);
+hipError_t launch_multi_axpy64(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *x);
 // z -= sum_j coef_j z_j (j < k); partials: |z|^2, <z|r>
 hipError_t launch_gcr_orth(const Geom &g, hipStream_t st, const VecSet &zs, int k, void *z, void *r,
                            double *partials);

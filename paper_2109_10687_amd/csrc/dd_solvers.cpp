@@ -3,6 +3,8 @@
 //   FP32 BiCGStab on A M_SAP (Alg. 5 with Alg. 1 as right preconditioner),
 //   restarted flexible GCR on A M_SAP (FP16 SAP).
 // The kernels do every step; these loops sequence launches and evaluate the scalars.
+#include <algorithm>
+
 #include "dd_host.h"
 
 namespace ddh {
@@ -317,6 +319,194 @@ dd_status solve_gcr32(dd_ctx *c, void *src, void *y, double tol, int maxiter, So
     }
     if (stalled) o.detail = DETAIL_INNER_STALL;
     return o.relres < tol ? DD_OK : (o.detail ? DD_BREAKDOWN : DD_NOT_CONVERGED);
+}
+
+dd_status ensure_gcr(dd_ctx *c)
+{
+    for (int i = 0; i < c->prm.gcr_nkv; ++i) {
+        if (!c->gz[i] && hipMalloc(&c->gz[i], spinor_bytes(c->g, DD_F32)) != hipSuccess) c->gz[i] = nullptr;
+        if (!c->gp[i] && hipMalloc(&c->gp[i], spinor_bytes(c->g, DD_F16)) != hipSuccess) c->gp[i] = nullptr;
+        if (!c->gz[i] || !c->gp[i]) {
+            (void)hipGetLastError();
+            return fail(c, DD_ERR_NOMEM, "GCR fields");
+        }
+    }
+    return DD_OK;
+}
+
+// The flexible GMRES basis takes the FP64 work vectors that neither the outer loop (b, x, the
+// product D z) nor the inner FP32 solve touch, and the directions the FP32 vectors of the
+// FP32-storage SAP (the inner solve runs the FP16 SAP); only the rest is allocated.
+dd_status ensure_fgmres(dd_ctx *c)
+{
+    const int m = c->prm.fgmres_nkv;
+    void *v_alias[] = {c->f64[2], c->f64[4], c->f64[5], c->f64[6]};
+    void *z_alias[] = {c->f32[7], c->f32[8], c->f32[9]};
+    constexpr int NVA = sizeof(v_alias) / sizeof(v_alias[0]), NZA = sizeof(z_alias) / sizeof(z_alias[0]);
+    for (int i = 0; i <= m; ++i) {
+        if (i < NVA) {
+            c->fv[i] = v_alias[i];
+        } else {
+            if (!c->fv_own[i] && hipMalloc(&c->fv_own[i], spinor_bytes(c->g, DD_F64)) != hipSuccess)
+                c->fv_own[i] = nullptr;
+            c->fv[i] = c->fv_own[i];
+        }
+        if (i == m) break;
+        if (i < NZA) {
+            c->fz[i] = z_alias[i];
+        } else {
+            if (!c->fz_own[i] && hipMalloc(&c->fz_own[i], spinor_bytes(c->g, DD_F32)) != hipSuccess)
+                c->fz_own[i] = nullptr;
+            c->fz[i] = c->fz_own[i];
+        }
+        if (!c->fv[i] || !c->fz[i]) {
+            (void)hipGetLastError();
+            return fail(c, DD_ERR_NOMEM, "flexible GMRES fields");
+        }
+    }
+    if (!c->fv[m]) {
+        (void)hipGetLastError();
+        return fail(c, DD_ERR_NOMEM, "flexible GMRES fields");
+    }
+    return DD_OK;
+}
+
+// Restarted flexible GMRES (Saad's FGMRES, the flexible outer loop Sec. 3 names) on D x = b
+// in FP64.  A cycle starts from r = b - D x, v_0 = r / |r|; iteration j preconditions the
+// Arnoldi vector by an inner FP32 solve, z_j ~ D^{-1} v_j (BiCGStab on A M_SAP with the FP16
+// SAP for A z = C_inv v_j, A = C_inv D), keeps z_j, and orthogonalises w = D z_j against
+// v_0 .. v_j (classical Gram-Schmidt applied twice, FP64 sums) into H and v_{j+1}; Givens
+// rotations keep the least-squares residual |beta e_0 - H y| at hand.  At the cycle's end
+// x += sum_j y_j z_j.  The kept z_j make the varying preconditioner harmless: x minimises
+// the FP64 residual over x_0 + span{z_j} whatever the inner solves returned.
+dd_status solve_fgmres64(dd_ctx *c, void *x, void *b, double bn2, double tol, int maxiter, OuterOut &o)
+{
+    const Geom &g = c->g;
+    const int m = c->prm.fgmres_nkv;
+    const double V = (double)g.V, bnorm = std::sqrt(bn2);
+    void *tmp = c->f64[3], *src = c->f32[0];
+    dd_status st;
+    std::vector<cplx> H((size_t)(m + 1) * m), gv(m + 1), cs(m), sn(m), yv(m);
+    auto h_at = [&](int i, int j) -> cplx & { return H[(size_t)i * m + j]; };
+    double rn2 = 0, prev = 0;
+    int stall = 0;
+    for (int cycle = 0;; ++cycle) {
+        if ((st = residual64(c, c->fv[0], b, x, tmp, &rn2)) != DD_OK) return st;
+        const double beta = std::sqrt(rn2);
+        if (!is_fin(rn2)) {
+            o.detail = 4;
+            return DD_BREAKDOWN;
+        }
+        if (cycle == 0)
+            c->hist_outer.push_back(beta / bnorm);
+        else
+            c->hist_outer.back() = beta / bnorm;  // the true residual in place of the estimate
+        if (beta / bnorm < tol) return DD_OK;
+        if (cycle > 0) {
+            stall = rn2 > 0.81 * prev ? stall + 1 : 0;  // a cycle lowered |r| by less than 10%
+            if (stall >= 2) {
+                o.detail = DETAIL_OUTER_STALL;
+                return DD_BREAKDOWN;
+            }
+        }
+        prev = rn2;
+        if (o.outer >= maxiter) return DD_NOT_CONVERGED;
+        if ((st = blas(c, mkb(dd::BLAS_AXPBY, {c->fv[0], c->fv[0]}, {0, 0}, {1.0 / beta, 0.0}))) != DD_OK) return st;
+        std::fill(gv.begin(), gv.end(), cplx(0.0));
+        gv[0] = beta;
+        double resid = beta;
+        int n = 0;
+        for (int j = 0; j < m && o.outer < maxiter; ++j) {
+            // z_j = M v_j: the inner solve of A z = C_inv v_j to the reduction still needed
+            const double need = 0.5 * tol * bnorm / resid;
+            const double itol = need > c->prm.inner_tol ? (need < 0.1 ? need : 0.1) : c->prm.inner_tol;
+            if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {src, c->fv[j], c->cinv32}, {1, 0}, {1.0}))) != DD_OK) return st;
+            SolveOut io;
+            dd_status si = solve_sap32(c, 2, src, c->fz[j], itol, c->prm.inner_maxiter, io);
+            if (si < 0) return si;
+            ++o.outer;
+            o.inner += io.iters;
+            o.inner_last = io.relres;
+            // w = D z_j, orthogonalised against v_0 .. v_j
+            if ((st = copy(c, tmp, 0, c->fz[j], 1)) != DD_OK) return st;
+            if ((st = k_dirac(c, c->fv[j + 1], tmp, 0, 0, 0, 0)) != DD_OK) return st;
+            dd::VecSet vs{};
+            for (int i = 0; i <= j; ++i) vs.v[i] = c->fv[i];
+            double wn2 = 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                double d[2 * dd::GCR_MAX_NKV];
+                hipError_t e = timed(c, DD_KT_BLAS, V * 192.0 * (j + 2), V * 96.0 * (j + 1), [&] {
+                    return dd::launch_multidot(g, c->stream, vs, j + 1, c->fv[j + 1], c->partials, 0);
+                });
+                if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("multidot: ") + hipGetErrorString(e));
+                if ((st = fetch(c, 2 * (j + 1), d)) != DD_OK) return st;
+                for (int i = 0; i <= j; ++i) {
+                    const cplx hij(d[2 * i], d[2 * i + 1]);
+                    h_at(i, j) = pass == 0 ? hij : h_at(i, j) + hij;
+                    vs.re[i] = hij.real();
+                    vs.im[i] = hij.imag();
+                }
+                e = timed(c, DD_KT_BLAS, V * 192.0 * (j + 3), V * 96.0 * (j + 2), [&] {
+                    return dd::launch_orth64(g, c->stream, vs, j + 1, c->fv[j + 1], c->partials);
+                });
+                if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("orthogonalise: ") + hipGetErrorString(e));
+                if ((st = fetch(c, 1, &wn2)) != DD_OK) return st;
+            }
+            if (!is_fin(wn2)) {
+                o.detail = 4;
+                return DD_BREAKDOWN;
+            }
+            const double hn = std::sqrt(wn2);
+            // earlier rotations on column j, then the one that removes h_{j+1,j}
+            for (int i = 0; i < j; ++i) {
+                const cplx a = h_at(i, j), bb = h_at(i + 1, j);
+                h_at(i, j) = cs[i] * a + sn[i] * bb;
+                h_at(i + 1, j) = -std::conj(sn[i]) * a + cs[i] * bb;
+            }
+            const cplx a = h_at(j, j);
+            const double rho = std::sqrt(std::norm(a) + hn * hn);
+            if (std::abs(a) == 0.0) {
+                cs[j] = 0.0;
+                sn[j] = 1.0;
+            } else {
+                cs[j] = std::abs(a) / rho;
+                sn[j] = (a / std::abs(a)) * hn / rho;
+            }
+            h_at(j, j) = cs[j] * a + sn[j] * hn;
+            gv[j + 1] = -std::conj(sn[j]) * gv[j];
+            gv[j] = cs[j] * gv[j];
+            n = j + 1;
+            resid = std::abs(gv[j + 1]);
+            c->hist_outer.push_back(resid / bnorm);
+            if (c->verbose) {
+                std::fprintf(stderr, "[ddsolve] FGMRES iteration %d: %d inner iterations (inner tol %.1e), "
+                             "residual estimate %.3e\n", o.outer, io.iters, itol, resid / bnorm);
+                std::fflush(stderr);
+            }
+            if (hn == 0.0 || resid / bnorm < tol) break;  // exact in the subspace, or converged
+            if ((st = blas(c, mkb(dd::BLAS_AXPBY, {c->fv[j + 1], c->fv[j + 1]}, {0, 0}, {1.0 / hn, 0.0}))) != DD_OK)
+                return st;
+        }
+        // y = R^{-1} g (R: the rotated, upper-triangular H), x += sum_j y_j z_j
+        for (int i = n - 1; i >= 0; --i) {
+            cplx t = gv[i];
+            for (int k = i + 1; k < n; ++k) t -= h_at(i, k) * yv[k];
+            if (h_at(i, i) == 0.0 || !is_fin(t)) {
+                o.detail = 4;
+                return DD_BREAKDOWN;
+            }
+            yv[i] = t / h_at(i, i);
+        }
+        dd::VecSet zs{};
+        for (int i = 0; i < n; ++i) {
+            zs.v[i] = c->fz[i];
+            zs.re[i] = yv[i].real();
+            zs.im[i] = yv[i].imag();
+        }
+        hipError_t e = timed(c, DD_KT_BLAS, V * (2 * 192.0 + 96.0 * n), V * 96.0 * n,
+                             [&] { return dd::launch_multi_axpy64(g, c->stream, zs, n, x); });
+        if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("solution update: ") + hipGetErrorString(e));
+    }
 }
 
 }  // namespace ddh

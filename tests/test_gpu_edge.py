@@ -82,7 +82,8 @@ def test_gauge_covariance_16x8x8x16():
 def test_zero_source_gives_zero_solution():
     s, _ = make((8, 8, 8, 8))
     b = s.new_spinor()
-    for mode in (dd.DD_SOLVE_F64_PLAIN, dd.DD_SOLVE_F32_SAP, dd.DD_SOLVE_MIXED):
+    for mode in (dd.DD_SOLVE_F64_PLAIN, dd.DD_SOLVE_F32_SAP, dd.DD_SOLVE_MIXED, dd.DD_SOLVE_MIXED_GCR,
+                 dd.DD_SOLVE_FGMRES):
         x0 = synth.gaussian_spinor(s.params.dims, 5, device="cuda")
         x, info = s.solve(b, tol=1e-10, maxiter=10, mode=mode, x0=x0)
         assert info["status"] == "DD_OK"
@@ -108,13 +109,27 @@ def test_maxiter_reached_returns_not_converged():
     assert 1e-10 < info["relres_true"] < 1.0
 
 
-def test_resume_from_previous_solution():
+@pytest.mark.parametrize("mode", [dd.DD_SOLVE_MIXED, dd.DD_SOLVE_FGMRES])
+def test_resume_from_previous_solution(mode):
     s, _ = make((8, 8, 8, 8))
     b = synth.gaussian_spinor(s.params.dims, 8, device="cuda")
-    x1, i1 = s.solve(b, tol=1e-6, mode=dd.DD_SOLVE_MIXED)
-    x2, i2 = s.solve(b, tol=1e-10, mode=dd.DD_SOLVE_MIXED, x0=x1)
+    x1, i1 = s.solve(b, tol=1e-6, mode=mode)
+    x2, i2 = s.solve(b, tol=1e-10, mode=mode, x0=x1)
     assert i2["status"] == "DD_OK" and i2["relres_true"] < 1e-10
     assert i2["iters_outer"] < 3
+
+
+def test_fgmres_cycle_of_one_restarts_and_maxiter_caps():
+    """fgmres_nkv = 1 restarts after every outer iteration (each cycle then is one defect-correction
+    pass with a least-squares step length); maxiter caps the outer iterations."""
+    dims = (8, 8, 8, 8)
+    p = dd.Params(dims=dims, kappa=0.13, csw=1.5, fgmres_nkv=1)
+    s = dd.Solver(p, synth.su3_links(dims, 0.3, 91, device="cuda"))
+    b = synth.gaussian_spinor(dims, 92, device="cuda")
+    x, info = s.solve(b, tol=1e-10, maxiter=20, mode=dd.DD_SOLVE_FGMRES)
+    assert info["status"] == "DD_OK" and info["relres_true"] < 1e-10 and info["iters_outer"] >= 2
+    x, info = s.solve(b, tol=1e-10, maxiter=1, mode=dd.DD_SOLVE_FGMRES)
+    assert info["status"] == "DD_NOT_CONVERGED" and info["iters_outer"] == 1 and info["relres_true"] < 1e-3
 
 
 def test_operator_precision_combinations_and_state():

@@ -10,7 +10,7 @@ Bars: FP64 Dirac apply within 1e-13 (relative, max norm); FP32 Dirac apply
 within 1e-6 relative (L2), the bound the FP32 operator must meet; FP32 SAP
 within 1e-5; FP16-storage results within about three times the largest error
 measured over these cases (A 1e-3; SAP 3e-3 with packed FP16 arithmetic,
-1.5e-3 with FP32 arithmetic); solves must reach the requested true FP64
+1.2e-3 with FP32 arithmetic); solves must reach the requested true FP64
 residual, recomputed by the oracle on the GPU's solution.
 """
 import numpy as np
@@ -147,8 +147,8 @@ def test_sap_fp16_storage(name, fp16_arith):
     want = c.orc.sap(b.numpy())
     err = rel_l2(got, want)
     print(f"FP16-storage SAP (fp16 arithmetic {fp16_arith}) relative L2 error {err:.3e}")
-    # about three times the largest error measured over these cases (1.2e-3 packed FP16, 4e-4 FP32)
-    assert err < (3e-3 if fp16_arith else 1.5e-3)
+    # about three times the largest error measured over these cases (1.26e-3 packed FP16, 4.0e-4 FP32)
+    assert err < (3e-3 if fp16_arith else 1.2e-3)
 
 
 def true_relres(c, x, b):
@@ -181,7 +181,7 @@ def test_solve_fp32_sap(name):
 
 
 @pytest.mark.parametrize("fp16_arith", [0, 1])
-@pytest.mark.parametrize("mode", [dd.DD_SOLVE_MIXED, dd.DD_SOLVE_MIXED_GCR])
+@pytest.mark.parametrize("mode", [dd.DD_SOLVE_MIXED, dd.DD_SOLVE_MIXED_GCR, dd.DD_SOLVE_FGMRES])
 @pytest.mark.parametrize("name", ["4^4", "aniso", "8^4", "8^4-twist"])
 def test_solve_mixed(name, mode, fp16_arith):
     c = case(name, fp16_arith=fp16_arith)
