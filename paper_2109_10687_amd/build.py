@@ -42,7 +42,8 @@ def build(verbose=False, jobs=None):
         cmds.append([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
     with ThreadPoolExecutor(max_workers=jobs or len(cmds)) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs, verbose)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs +
+         ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"], verbose)
     os.replace(LIB + ".tmp", LIB)
     for o in objs:
         os.remove(o)

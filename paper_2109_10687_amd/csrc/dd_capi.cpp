@@ -226,6 +226,7 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
     if (!(tol > 0) || maxiter < 0 || mode < DD_SOLVE_F64_PLAIN || mode > DD_SOLVE_FGMRES)
         return fail(c, DD_ERR_ARG, "bad tolerance, maxiter or mode");
     if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    Range range(dagger ? "ddsolve: adjoint solve" : "ddsolve: solve");
     auto t0 = std::chrono::steady_clock::now();
     dd_solve_info inf{};
     c->hist_outer.clear();
@@ -294,6 +295,7 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
             const double need = 0.5 * tol * std::sqrt(bn2) / err;
             const double itol = need > c->prm.inner_tol ? (need < 0.1 ? need : 0.1) : c->prm.inner_tol;
             SolveOut o;
+            Range pass("ddsolve: defect-correction pass");
             dd_status si = mode == DD_SOLVE_MIXED_GCR ? solve_gcr32(c, src, y, itol, c->prm.inner_maxiter, o)
                                                       : solve_sap32(c, 2, src, y, itol, c->prm.inner_maxiter, o);
             if (si < 0) return si;

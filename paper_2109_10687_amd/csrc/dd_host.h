@@ -12,10 +12,20 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/ddsolve.h"
 #include "dd_launch.h"
 
 namespace ddh {
+
+// a roctx range around a solver phase (seen by rocprofv3 --marker-trace; free otherwise)
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 using dd::Geom;
 using cplx = std::complex<double>;

@@ -149,6 +149,7 @@ dd_status k_dirac(dd_ctx *c, void *out, const void *in, int pin, int pout, int p
 // x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s
 dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
 {
+    Range range("ddsolve: SAP preconditioner");
     dd::SapArgs a{};
     a.b = b;
     a.s = s;
@@ -266,6 +267,7 @@ dd_status copy(dd_ctx *c, void *dst, int pd, void *src, int ps)
 // r = b - D x (FP64) ; returns |r|^2
 dd_status residual64(dd_ctx *c, void *r, void *b, void *x, void *tmp, double *rn2)
 {
+    Range range("ddsolve: FP64 residual");
     dd_status st = k_dirac(c, tmp, x, 0, 0, 0, 0);
     if (st != DD_OK) return st;
     return reduce(c, mkb(dd::BLAS_SUB_NORM, {r, b, tmp}, {0, 0, 0}), 1, rn2);

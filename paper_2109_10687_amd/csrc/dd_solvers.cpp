@@ -39,6 +39,7 @@ dd_status solve_plain64(dd_ctx *c, void *x, void *b, double tol, int maxiter, So
         cplx rho0 = rn2;
         bool conv = false;
         while (it < maxiter) {
+            Range range("ddsolve: FP64 BiCGStab iteration");
             ++it;
             if ((st = k_dirac(c, q, p, 0, 0, 0, 0)) != DD_OK) return st;
             double d[3];
@@ -150,6 +151,7 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
         return blas(c, mkb(dd::BLAS_CAXPY, {y, Mp}, {1, prec}, {alpha.real(), alpha.imag()}));
     };
     for (int it = 0; it < maxiter; ++it) {
+        Range range("ddsolve: inner BiCGStab iteration");
         o.iters = it + 1;
         c->hist_inner.push_back(std::sqrt(rn2 / bn2));  // one entry per iteration: its last residual
         if ((st = precond(p, p16, Mp, q)) != DD_OK) return st;
@@ -420,6 +422,7 @@ dd_status solve_fgmres64(dd_ctx *c, void *x, void *b, double bn2, double tol, in
             // z_j = M v_j: the inner solve of A z = C_inv v_j to the reduction still needed
             const double need = 0.5 * tol * bnorm / resid;
             const double itol = need > c->prm.inner_tol ? (need < 0.1 ? need : 0.1) : c->prm.inner_tol;
+            Range range("ddsolve: flexible GMRES iteration");
             if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {src, c->fv[j], c->cinv32}, {1, 0}, {1.0}))) != DD_OK) return st;
             SolveOut io;
             dd_status si = solve_sap32(c, 2, src, c->fz[j], itol, c->prm.inner_maxiter, io);
