@@ -76,7 +76,8 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
     auto alloc = [&](void **p, size_t bytes) -> bool { return hipMalloc(p, bytes) == hipSuccess; };
     bool ok = alloc(&c->U64, (size_t)V * 36 * 16) && alloc(&c->U32, (size_t)V * 36 * 8) &&
               alloc(&c->U16, (size_t)V * 24 * 4) && alloc(&c->clov64, (size_t)V * 36 * 16) &&
-              alloc(&c->cinv32, (size_t)V * 36 * 8) && alloc(&c->cinv16, (size_t)V * 36 * 4);
+              alloc(&c->cinv32, (size_t)V * 36 * 8) && alloc(&c->cinv16, (size_t)V * 36 * 4) &&
+              alloc(&c->faces, dd::sap_face_bytes(g));
     for (int i = 0; ok && i < N64; ++i) ok = alloc(&c->f64[i], spinor_bytes(g, DD_F64));
     for (int i = 0; ok && i < N32; ++i) ok = alloc(&c->f32[i], spinor_bytes(g, DD_F32));
     for (int i = 0; ok && i < N16; ++i) ok = alloc(&c->f16[i], spinor_bytes(g, DD_F16));
@@ -100,7 +101,8 @@ dd_status dd_destroy(dd_ctx *c)
 {
     if (!c) return DD_OK;
     (void)hipStreamSynchronize(c->stream);
-    void *bufs[] = {c->U64, c->U32, c->U16, c->clov64, c->cinv32, c->cinv16, c->yforce, c->partials, c->red, c->flag};
+    void *bufs[] = {c->U64,   c->U32,     c->U16,     c->clov64, c->cinv32, c->cinv16,
+                    c->faces, c->yforce, c->partials, c->red,    c->flag};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     for (void *p : c->f64)

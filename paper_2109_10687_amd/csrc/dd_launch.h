@@ -18,6 +18,7 @@ constexpr int MAX_BLOCK_VOLUME = 256;  // one SAP block per workgroup, one threa
 constexpr int SAP_FIRST = 1;  // read s from the source b (s = b at the start of Alg. 1)
 constexpr int SAP_PRE = 2;    // subtract the cross-block term A_{c c'} x_{c'} first
 constexpr int SAP_TAIL = 4;   // tail of Alg. 1: produce x only, leave s alone
+constexpr int SAP_FACES_OUT = 8;  // packed-FP16 half-sweep: leave face hop terms for the next half-sweep
 
 struct Phase4 {
     double re[4], im[4];
@@ -51,6 +52,7 @@ struct SapArgs {
     int n_jac;
     double kappa;
     Phase4 phase;
+    void *faces;  // packed-FP16 half-sweep: face hop terms (sap_face_bytes), written and read in turn
 };
 
 enum BlasKind {
@@ -153,8 +155,10 @@ hipError_t launch_clover(const Geom &g, hipStream_t st, const void *u64, const S
 hipError_t launch_dirac(const Geom &g, hipStream_t st, const DiracArgs &a);
 size_t sap_lds_bytes(const Geom &g, int prec);
 hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
-// the same half-sweep with FP16 storage and packed FP16 block-local arithmetic
+// the same half-sweep with FP16 storage and packed FP16 block-local arithmetic; the cross-block
+// term travels between half-sweeps as face hop terms (sap_face_bytes per lattice)
 size_t sap_pk_lds_bytes(const Geom &g);
+size_t sap_face_bytes(const Geom &g);
 hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
 int blas_grid(const Geom &g);
 // grid of a grid-stride loop over the sites (one thread per site, at most BLAS_MAX_WG workgroups)

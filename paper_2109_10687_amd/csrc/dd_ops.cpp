@@ -160,27 +160,37 @@ dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
     a.n_jac = c->prm.n_jac;
     a.kappa = c->prm.kappa;
     a.phase = c->phase;
+    a.faces = c->faces;
     const int E = 0, O = 1;
     const int n = c->prm.n_sap;
     const Geom &g = c->g;
+    const bool pk = prec == 2 && c->prm.sap_fp16_arith;
     auto half = [&](int colour, int flags) -> dd_status {
-        // per site of the swept colour: source, links, C_inv, x written; without
-        // TAIL also b read and s written; with PRE the neighbour-block face
-        // spinors and the links that point into the block from outside
+        // per site of the swept colour: source (s, or b in the first), links, C_inv; without
+        // TAIL also b read and s written.  FP32 arithmetic: x written, and with PRE the
+        // neighbour-block face spinors and the links that point into the block from outside.
+        // Packed FP16: x written by the tails only; with PRE the face hop terms read (6 half2
+        // per face site, the neighbour block's scale), with FACES_OUT this block's written
         const bool tail = flags & dd::SAP_TAIL, pre = flags & dd::SAP_PRE, first = flags & dd::SAP_FIRST;
         double face_sp = 0, face_lk = 0;
         for (int mu = 0; mu < 4; ++mu) {
             face_sp += 2.0 / g.b[mu];
             face_lk += 1.0 / g.b[mu];
         }
-        double per = sp_b(prec) + 4 * lk_b(prec) + cl_b(prec) + sp_b(prec);
+        double per = sp_b(prec) + 4 * lk_b(prec) + cl_b(prec);
         if (!tail) per += (first ? 0.0 : sp_b(prec)) + sp_b(prec);
-        if (pre) per += face_sp * sp_b(prec) + face_lk * lk_b(prec);
+        if (!pk || tail) per += sp_b(prec);
+        if (pk) {
+            const double term = 6 * 4.0 + 4.0 / g.bvol;
+            if (pre) per += face_sp * term;
+            if (flags & dd::SAP_FACES_OUT) per += face_sp * term;
+        } else if (pre) {
+            per += face_sp * sp_b(prec) + face_lk * lk_b(prec);
+        }
         double fl = c->prm.n_jac * (hops_in(g) + CLOVF);
         if (!tail) fl += hops_in(g) + CLOVF + 48;
         if (pre) fl += hops_out(g) + CLOVF;
         const double sites = 0.5 * (double)g.V;
-        const bool pk = prec == 2 && c->prm.sap_fp16_arith;
         hipError_t e = timed(c, DD_KT_SAP, sites * per, sites * fl, [&] {
             return pk ? dd::launch_sap_half_pk(c->g, c->stream, a, colour, flags)
                       : dd::launch_sap_half(c->g, c->stream, a, colour, flags);
@@ -188,12 +198,15 @@ dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
         if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("sap launch: ") + hipGetErrorString(e));
         return DD_OK;
     };
+    // the packed-FP16 half-sweeps hand the cross-block term on as face hop terms: every
+    // half-sweep but the last leaves them
+    const int out = pk ? dd::SAP_FACES_OUT : 0;
     dd_status st;
     for (int i = 0; i < n; ++i) {
-        if ((st = half(E, i == 0 ? dd::SAP_FIRST : dd::SAP_PRE)) != DD_OK) return st;
-        if ((st = half(O, i == 0 ? (dd::SAP_FIRST | dd::SAP_PRE) : dd::SAP_PRE)) != DD_OK) return st;
+        if ((st = half(E, (i == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out)) != DD_OK) return st;
+        if ((st = half(O, (i == 0 ? (dd::SAP_FIRST | dd::SAP_PRE) : dd::SAP_PRE) | out)) != DD_OK) return st;
     }
-    if ((st = half(E, dd::SAP_TAIL | (n == 0 ? dd::SAP_FIRST : dd::SAP_PRE))) != DD_OK) return st;
+    if ((st = half(E, dd::SAP_TAIL | (n == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out)) != DD_OK) return st;
     if ((st = half(O, dd::SAP_TAIL | dd::SAP_PRE | (n == 0 ? dd::SAP_FIRST : 0))) != DD_OK) return st;
     return DD_OK;
 }

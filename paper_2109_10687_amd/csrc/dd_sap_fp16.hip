@@ -13,12 +13,17 @@
 // pair coefficients,
 //   w_pair[c] = sum_c' A[c][c'] (.) z_pair[c'] + B[c][c'] (.) swap(z_pair[c']).
 // The cross-block term of Alg. 1 (the neighbouring blocks' x_{c'} hopping into
-// the block) is computed in packed FP16 too, one face hop per thread, and is not
+// the block) travels between half-sweeps as face hop terms: each half-sweep leaves,
+// at the faces of its blocks, the projected half spinors of its result (multiplied
+// by its own link for the hops that run backwards into the neighbour), straight
+// from LDS in packed FP16, and the next half-sweep of the other colour reads them
+// instead of its neighbours' whole spinors and links.  x itself is written only by
+// the last two half-sweeps (the preconditioner's output).  The term is not
 // multiplied by C_inv on its own: with h = H_{c c'} x_{c'} the updated source is
 // s_c + kappa C_inv h, and every Jacobi step x <- s_c + kappa C_inv (H_in x + h)
 // carries h inside the clover product it already does; the first step, from
-// x = 0, yields the updated source itself.  The face hops are summed per site in
-// FP32 (each neighbour has its own storage scale).  FP16 range: the block's
+// x = 0, yields the updated source itself.  The face terms are summed per site in
+// FP32 (each neighbouring block has its own scale).  FP16 range: the block's
 // source and h are scaled by 1 / max|component| before the sweeps (the sweeps
 // are linear) and the result is scaled back in FP32; the final s update of
 // Alg. 1 is evaluated in FP32.
@@ -72,7 +77,9 @@ DD_INL void mat_pair(const h2 (&U)[3][3], bool dag, const PC (&h)[3], PC (&k)[3]
     }
 }
 
-// half spinor (h0, h1) of (1 - s gamma_mu) p, pair form, for the gamma matrices of the appendix
+// half spinor (h0, h1) of (1 - s gamma_mu) p, pair form, for the gamma matrices of the appendix;
+// for mu = 3 (gamma_4 diagonal) the surviving spin pair itself: the factor 2 of (1 - s gamma_4)
+// is applied when the hop is rebuilt (recon_pair, recon_mix)
 DD_INL void proj_pair(int mu, int s, const SpH &p, PC (&h)[3])
 {
     const h2 S = __float2half2_rn((float)s);                      // (s, s)
@@ -88,10 +95,8 @@ DD_INL void proj_pair(int mu, int s, const SpH &p, PC (&h)[3])
         } else if (mu == 2) {  // (h0, h1) = (psi0, psi1) + i (-s, s) (psi2, psi3)
             h[c].re = fma2(neg2(Cm), p.l[c].im, p.u[c].re);
             h[c].im = fma2(Cm, p.l[c].re, p.u[c].im);
-        } else {  // gamma_4 diagonal: twice the surviving spin pair
-            const PC &q = s > 0 ? p.l[c] : p.u[c];
-            h[c].re = add2(q.re, q.re);
-            h[c].im = add2(q.im, q.im);
+        } else {  // gamma_4 diagonal: the surviving spin pair (the factor 2 comes later)
+            h[c] = s > 0 ? p.l[c] : p.u[c];
         }
     }
 }
@@ -101,12 +106,13 @@ DD_INL void recon_pair(int mu, int s, const PC (&k)[3], SpH &acc)
 {
     const h2 S = __float2half2_rn((float)s);                      // (s, s)
     const h2 Cp = __floats2half2_rn((float)s, -(float)s);         // (s, -s)
+    const h2 TWO = __float2half2_rn(2.f);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        if (mu == 3) {
+        if (mu == 3) {  // twice the rebuilt pair (the factor 2 of 1 - s gamma_4, see proj_pair)
             PC &t = s > 0 ? acc.l[c] : acc.u[c];
-            t.re = add2(t.re, k[c].re);
-            t.im = add2(t.im, k[c].im);
+            t.re = fma2(TWO, k[c].re, t.re);
+            t.im = fma2(TWO, k[c].im, t.im);
             continue;
         }
         acc.u[c].re = add2(acc.u[c].re, k[c].re);
@@ -341,10 +347,10 @@ DD_INL void recon_mix(int mu, int s, const PC (&k)[3], float f, Spinor<float> &a
     for (int c = 0; c < 3; ++c) {
         const float r0 = __low2float(k[c].re), r1 = __high2float(k[c].re);
         const float i0 = __low2float(k[c].im), i1 = __high2float(k[c].im);
-        if (mu == 3) {
+        if (mu == 3) {  // twice the pair (the factor 2 of 1 - s gamma_4, see proj_pair)
             const int o = s > 0 ? 2 : 0;
-            add(acc.v[o][c], f * r0, f * i0);
-            add(acc.v[o + 1][c], f * r1, f * i1);
+            add(acc.v[o][c], 2.f * f * r0, 2.f * f * i0);
+            add(acc.v[o + 1][c], 2.f * f * r1, 2.f * f * i1);
             continue;
         }
         add(acc.v[0][c], f * r0, f * i0);
@@ -433,53 +439,76 @@ DD_INL int face_offset(const Geom &g, int mu, int side)
     return o + side * (g.bvol >> log2b(g, mu));
 }
 
-// One face hop of the block st.l in direction MU, side DIR (kk: the hop's index on the
-// face, the other three in-block coordinates in order): the neighbouring block's
-// spinor at the opposite face, spin-projected and multiplied by U (forward) or
-// U^dagger (backward), parked in LDS (pair form, relative to the neighbour's storage
-// scale) with that scale
-template <int MU, int DIR>
-DD_INL void face_hop(const Geom &g, const Site &st, int kk, int p, int P, const SpinorField<2> &xw, const __half2 *u16,
-                     h2 *fk, float *fsc)
+// Face hop terms.  A half-sweep that is followed by one of the other colour leaves, for
+// every site m of each of its block's faces, the part of that site's hop into the
+// neighbouring block that it can form from its own data (pair form, relative to the
+// block normalisation of its x, which is stored once per block):
+//   +mu face (slot face_offset(mu, 0) + kk): the neighbour block l + mu takes x(m) by a
+//     backward hop, U_mu(m)^dagger (1 + gamma_mu) x(m) -- the link is this block's own;
+//   -mu face (slot face_offset(mu, 1) + kk): the neighbour block l - mu takes x(m) by a
+//     forward hop, U_mu(m - mu) (1 - gamma_mu) x(m) -- the link belongs to the receiver,
+//     which multiplies it in; the term is the projection alone.
+// kk numbers the face's sites by their other three in-block coordinates in order, so a
+// face site and the site across the face share it.
+template <int MU, int SIDE>
+DD_INL void face_out(const Geom &g, int l, int kk, int p, int P, const uint4 *xs, const h2 *ul, int bvol, h2 *ft)
 {
-    const int bm = g.b[MU], shm = g.sh[MU];
-    int fsite = (DIR > 0 ? bm - 1 : 0) << shm;
+    int m = (SIDE == 0 ? g.b[MU] - 1 : 0) << g.sh[MU];
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == MU) continue;
-        fsite += (kk & (g.b[nu] - 1)) << g.sh[nu];
+        m += (kk & (g.b[nu] - 1)) << g.sh[nu];
         kk >>= log2b(g, nu);
     }
-    int lj = st.l + DIR * g.bstride[MU];
-    if (st.B[MU] + DIR < 0)
-        lj += g.NB[MU] * g.bstride[MU];
-    else if (st.B[MU] + DIR >= g.NB[MU])
-        lj -= g.NB[MU] * g.bstride[MU];
-    const int sj = fsite - DIR * ((bm - 1) << shm);
-    SpH ps;
-    const float scj = load_pair(xw, g, lj, sj, ps);
-    h2 U[3][3];  // U_mu at the face site (forward) or at its neighbour (backward)
-    load_link_pair(u16, g, DIR > 0 ? st.l : lj, DIR > 0 ? fsite : sj, MU, U);
-    PC h[3], k[3];
-    proj_pair(MU, DIR, ps, h);
-    mat_pair(U, DIR < 0, h, k);
+    SpH xp;
+    lds_get(xs, bvol, m, xp);
+    PC k[3];
+    if (SIDE == 0) {
+        PC h[3];
+        h2 U[3][3];
+        proj_pair(MU, -1, xp, h);
+        lds_link(ul, bvol, m, MU, U);
+        mat_pair(U, true, h, k);
+    } else {
+        proj_pair(MU, +1, xp, k);
+    }
+    h2 *dst = ft + (long long)l * 6 * P + p;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        fk[(2 * c) * P + p] = k[c].re;
-        fk[(2 * c + 1) * P + p] = k[c].im;
+        dst[(2 * c) * P] = k[c].re;
+        dst[(2 * c + 1) * P] = k[c].im;
     }
-    fsc[p] = scj;
 }
 
-// One half-sweep with FP16 arithmetic; same flags and result (up to FP16
-// rounding) as k_sap_half<2>.  B > 0 fixes the block shape to B^4 at compile time:
-// the block extents, in-block strides and the block volume become constants, so
-// every LDS offset of the sweeps is an immediate instead of a register and the
-// face-hop index arithmetic folds; B = 0 takes the shape from the geometry.
+// the face term at slot `slot` of block l and the scale of that block
+DD_INL float face_in(const h2 *ft, const float *fs, int l, int slot, int P, PC (&k)[3])
+{
+    const h2 *src = ft + (long long)l * 6 * P + slot;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) k[c] = PC{src[(2 * c) * P], src[(2 * c + 1) * P]};
+    return fs[l];
+}
+
+// k times the boundary phase (re, im) of a hop that crosses the lattice edge
+DD_INL void phase_pair(PC (&k)[3], float re, float im)
+{
+    const h2 pr = __float2half2_rn(re), pi = __float2half2_rn(im);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) k[c] = PC{fma2(pr, k[c].re, mul2(neg2(pi), k[c].im)), fma2(pr, k[c].im, mul2(pi, k[c].re))};
+}
+
+// One half-sweep with FP16 arithmetic; same flags and result (up to FP16 rounding) as
+// k_sap_half<2>, except that the cross-block term comes from the face hop terms of the
+// previous half-sweep (faces: the terms, then one scale per block) and that x is written
+// only by the tails of Alg. 1 (a middle half-sweep's x is only ever read through those
+// terms).  FACES_OUT leaves this half-sweep's terms for the next one.  B > 0 fixes the
+// block shape to B^4 at compile time: the block extents, in-block strides and the block
+// volume become constants, so every LDS offset of the sweeps is an immediate instead of a
+// register and the face index arithmetic folds; B = 0 takes the shape from the geometry.
 template <int B>
 __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int flags, SpinorField<2> bsrc,
                                                      SpinorField<2> sw, SpinorField<2> xw, const __half2 *u16,
-                                                     CloverField<2> Ci, Phase4 ph, float kappa, int n_jac)
+                                                     CloverField<2> Ci, Phase4 ph, float kappa, int n_jac, h2 *ft)
 {
     extern __shared__ uint4 smem_pk[];
     const Geom g = fixed_shape<B>(gin);
@@ -487,6 +516,8 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
     uint4 *xs = smem_pk;                                    // 3 x bvol uint4
     h2 *ul = reinterpret_cast<h2 *>(xs + 3 * bvol);         // 36 x bvol half2
     __shared__ float wmax[4];
+    const int P = face_offset(g, 3, 1) + (bvol >> log2b(g, 3));  // face sites of a block
+    float *fs = reinterpret_cast<float *>(ft + (long long)g.nblk * 6 * P);  // one scale per block
 
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     Site st;
@@ -500,85 +531,15 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
     SpH sraw;
     const float ssc = load_pair((flags & SAP_FIRST) ? bsrc : sw, g, st.l, st.s, sraw);
 
-    // h = H_{c c'} x_{c'} at this site: the hops from the neighbouring blocks
+    // Stage the block's links as full 3x3 FP16 matrices.  With PRE, h = H_{c c'} x_{c'} at this
+    // site: the hops from the neighbouring blocks, taken from the terms they left at the shared
+    // faces -- on the +mu face the projection of the neighbour's x, multiplied here by this
+    // site's U_mu; on the -mu face the finished backward term -- summed in FP32 with each
+    // neighbour block's scale.
     const bool pre = (flags & SAP_PRE) != 0;
     Spinor<float> hc;
     zero(hc);
-    if (pre) {
-        // Each (direction, side, face site) hop once, spread evenly over the workgroup (a
-        // per-site loop would run all eight hop bodies in every wavefront with most lanes
-        // idle).  The hop results, relative to the neighbour's storage scale, and the
-        // scales are parked in LDS (the link staging area, not in use yet) and summed per
-        // site afterwards.
-        const int P = face_offset(g, 3, 1) + (bvol >> log2b(g, 3));  // all face hops
-        const bool equal_faces = g.b[0] == g.b[1] && g.b[1] == g.b[2] && g.b[2] == g.b[3];
-        const int lnf = g.lbvol - log2b(g, 0);                       // log2 of hops per face
-        h2 *fk = ul;                                           // [6][P] half2
-        float *fsc = reinterpret_cast<float *>(fk + 6 * P);    // [P]
-        for (int p = threadIdx.x; p < P; p += bvol) {
-            int q = 0, base = 0;
-            if (equal_faces) {  // hypercubic block: face q holds hops q * nf ... q * nf + nf - 1
-                q = p >> lnf;
-                base = q << lnf;
-            } else {
 #pragma unroll
-                for (int qq = 0; qq < 7; ++qq) {
-                    const int n = bvol >> log2b(g, qq >> 1);
-                    if (q == qq && p >= base + n) {
-                        base += n;
-                        q = qq + 1;
-                    }
-                }
-            }
-            const int kk = p - base;
-            switch (q) {  // faces in order +x, -x, +y, -y, +z, -z, +t, -t
-            case 0: face_hop<0, 1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
-            case 1: face_hop<0, -1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
-            case 2: face_hop<1, 1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
-            case 3: face_hop<1, -1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
-            case 4: face_hop<2, 1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
-            case 5: face_hop<2, -1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
-            case 6: face_hop<3, 1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
-            default: face_hop<3, -1>(g, st, kk, p, P, xw, u16, fk, fsc); break;
-            }
-        }
-        __syncthreads();
-        // per site: at most one face per direction (blocks are at least 2 wide)
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            const int c = st.c[mu];
-            const bool hi = c == g.b[mu] - 1;
-            if (c != 0 && !hi) continue;
-            const int dir = hi ? 1 : -1;
-            int kk = 0, w8 = 0;
-#pragma unroll
-            for (int nu = 0; nu < 4; ++nu) {
-                if (nu == mu) continue;
-                kk += st.c[nu] << w8;
-                w8 += log2b(g, nu);
-            }
-            const int p = face_offset(g, mu, hi ? 0 : 1) + kk;
-            PC k[3];
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) k[cc] = PC{fk[(2 * cc) * P + p], fk[(2 * cc + 1) * P + p]};
-            if (hi ? st.B[mu] == g.NB[mu] - 1 : st.B[mu] == 0) {  // the hop crosses the lattice edge
-                const h2 pr = __float2half2_rn((float)ph.re[mu]);
-                const h2 pi = __float2half2_rn((float)(hi ? ph.im[mu] : -ph.im[mu]));
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    k[cc] = PC{fma2(pr, k[cc].re, mul2(neg2(pi), k[cc].im)), fma2(pr, k[cc].im, mul2(pi, k[cc].re))};
-            }
-            if (mu < 3)
-                recon_mix(mu, dir, k, fsc[p], hc);
-            else if (hi)  // the spin pair that gamma_4 keeps depends on the side
-                recon_mix(3, 1, k, fsc[p], hc);
-            else
-                recon_mix(3, -1, k, fsc[p], hc);
-        }
-        __syncthreads();  // the face buffer is about to become the link staging area
-    }
-
-    // stage the block's links as full 3x3 FP16 matrices
     for (int mu = 0; mu < 4; ++mu) {
         h2 U[3][3];
         load_link_pair(u16, g, st.l, st.s, mu, U);
@@ -586,8 +547,35 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) ul[(mu * 9 + a * 3 + b) * bvol + st.s] = U[a][b];
+        if (!pre) continue;
+        const int c = st.c[mu];
+        int kk = 0, w8 = 0;
+#pragma unroll
+        for (int nu = 0; nu < 4; ++nu) {
+            if (nu == mu) continue;
+            kk += st.c[nu] << w8;
+            w8 += log2b(g, nu);
+        }
+        if (c == g.b[mu] - 1) {  // forward hop from block l + mu, whose -mu face holds the projection
+            const bool edge = st.B[mu] == g.NB[mu] - 1;
+            const int lj = st.l + (edge ? (1 - g.NB[mu]) : 1) * g.bstride[mu];
+            PC t[3], k[3];
+            const float sc = face_in(ft, fs, lj, face_offset(g, mu, 1) + kk, P, t);
+            mat_pair(U, false, t, k);
+            if (edge) phase_pair(k, (float)ph.re[mu], (float)ph.im[mu]);
+            recon_mix(mu, 1, k, sc, hc);
+        }
+        if (c == 0) {  // backward hop from block l - mu, whose +mu face holds U^dagger times the projection
+            const bool edge = st.B[mu] == 0;
+            const int lj = st.l - (edge ? (1 - g.NB[mu]) : 1) * g.bstride[mu];
+            PC k[3];
+            const float sc = face_in(ft, fs, lj, face_offset(g, mu, 0) + kk, P, k);
+            if (edge) phase_pair(k, (float)ph.re[mu], (float)-ph.im[mu]);
+            recon_mix(mu, -1, k, sc, hc);
+        }
     }
 
+    // kappa C_inv as pair coefficients (kappa folded in once: x <- x0 + (kappa C_inv) H x)
     ClovPair CP;
     clov_pairs_ld(Ci, g, st.l, st.s, CP);
 
@@ -601,7 +589,7 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
     const int wv = bvol < 64 ? bvol : 64;  // lanes of this workgroup in one wavefront
     for (int off = wv / 2; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, wv));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-    __syncthreads();
+    __syncthreads();  // also: every link is staged
     m = 0.f;
     for (int q = 0; q < (bvol + 63) / 64; ++q) m = fmaxf(m, wmax[q]);
     const float sc = m > 0.f ? 1.f / m : 0.f;
@@ -617,10 +605,8 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
         clover_pair(CP, hp, t);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            x0.u[c].re = fma2(K, t.u[c].re, x0.u[c].re);
-            x0.u[c].im = fma2(K, t.u[c].im, x0.u[c].im);
-            x0.l[c].re = fma2(K, t.l[c].re, x0.l[c].re);
-            x0.l[c].im = fma2(K, t.l[c].im, x0.l[c].im);
+            x0.u[c] = PC{fma2(K, t.u[c].re, x0.u[c].re), fma2(K, t.u[c].im, x0.u[c].im)};
+            x0.l[c] = PC{fma2(K, t.l[c].re, x0.l[c].re), fma2(K, t.l[c].im, x0.l[c].im)};
         }
     }
     x = x0;
@@ -632,15 +618,11 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
         clover_pair(CP, acc, t);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            x.u[c].re = fma2(K, t.u[c].re, x0.u[c].re);
-            x.u[c].im = fma2(K, t.u[c].im, x0.u[c].im);
-            x.l[c].re = fma2(K, t.l[c].re, x0.l[c].re);
-            x.l[c].im = fma2(K, t.l[c].im, x0.l[c].im);
+            x.u[c] = PC{fma2(K, t.u[c].re, x0.u[c].re), fma2(K, t.u[c].im, x0.u[c].im)};
+            x.l[c] = PC{fma2(K, t.l[c].re, x0.l[c].re), fma2(K, t.l[c].im, x0.l[c].im)};
         }
     }
     const float inv = m;  // undo the normalisation
-    Spinor<float> xf;
-    from_pair(x, inv, xf);
     if (!(flags & SAP_TAIL)) {
         // s_c <- (s_c + kappa C_inv h) + b_c - x_c + kappa C_inv H_in x_c, in FP32
         __syncthreads();
@@ -653,23 +635,75 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
         Spinor<float> snew;
         combine_pair(x0, inv, braw, sb, x, -inv, t, kappa * inv, snew);
         sw.store(g, st.l, st.s, snew);
+    } else {
+        Spinor<float> xf;
+        from_pair(x, inv, xf);
+        xw.store(g, st.l, st.s, xf);
+        if (flags & SAP_FACES_OUT) {
+            __syncthreads();
+            lds_put(xs, bvol, st.s, x);
+        }
     }
-    xw.store(g, st.l, st.s, xf);
+    if (flags & SAP_FACES_OUT) {
+        // this block's face terms from x in LDS (put there by the s update, or just above),
+        // spread evenly over the workgroup
+        __syncthreads();
+        const bool equal_faces = g.b[0] == g.b[1] && g.b[1] == g.b[2] && g.b[2] == g.b[3];
+        const int lnf = g.lbvol - log2b(g, 0);  // log2 of the sites per face
+        for (int p = threadIdx.x; p < P; p += bvol) {
+            int q = 0, base = 0;
+            if (equal_faces) {  // hypercubic block: face q holds sites q * nf ... q * nf + nf - 1
+                q = p >> lnf;
+                base = q << lnf;
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < 7; ++qq) {
+                    const int n = bvol >> log2b(g, qq >> 1);
+                    if (q == qq && p >= base + n) {
+                        base += n;
+                        q = qq + 1;
+                    }
+                }
+            }
+            const int kk = p - base;
+            switch (q) {  // faces in order +x, -x, +y, -y, +z, -z, +t, -t
+            case 0: face_out<0, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
+            case 1: face_out<0, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
+            case 2: face_out<1, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
+            case 3: face_out<1, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
+            case 4: face_out<2, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
+            case 5: face_out<2, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
+            case 6: face_out<3, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
+            default: face_out<3, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
+            }
+        }
+        if (threadIdx.x == 0) fs[st.l] = inv;
+    }
+}
+
+// face sites of one block, and the bytes of the face terms of a lattice (6 half2 per face
+// site, one FP32 scale per block)
+static size_t face_sites(const Geom &g)
+{
+    size_t faces = 0;
+    for (int mu = 0; mu < 4; ++mu) faces += 2 * (size_t)(g.bvol / g.b[mu]);
+    return faces;
+}
+
+size_t sap_face_bytes(const Geom &g)
+{
+    return (size_t)g.nblk * (face_sites(g) * 6 * sizeof(__half2) + sizeof(float));
 }
 
 size_t sap_pk_lds_bytes(const Geom &g)
 {
-    // the Jacobi iterate, then the larger of the link staging area and the face buffer of
-    // the cross-block hops (6 half2 and one FP32 scale per face hop)
-    size_t faces = 0;
-    for (int mu = 0; mu < 4; ++mu) faces += 2 * (size_t)(g.bvol / g.b[mu]);
-    const size_t links = (size_t)g.bvol * 36 * sizeof(__half2), fbuf = faces * (6 * sizeof(__half2) + sizeof(float));
-    return (size_t)g.bvol * 3 * sizeof(uint4) + (links > fbuf ? links : fbuf);
+    // the Jacobi iterate and the staged links
+    return (size_t)g.bvol * (3 * sizeof(uint4) + 36 * sizeof(__half2));
 }
 
 hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags)
 {
-    if (a.prec != 2) return hipErrorInvalidValue;
+    if (a.prec != 2 || !a.faces) return hipErrorInvalidValue;
     auto sfh = [&](void *p) {
         return SpinorField<2>{(__half2 *)p, (float *)((char *)p + 12 * g.V * sizeof(__half2))};
     };
@@ -677,7 +711,7 @@ hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, i
     auto kern = cube4 ? k_sap_half_pk<4> : k_sap_half_pk<0>;
     hipLaunchKernelGGL(kern, dim3(g.nblk / 2), dim3(g.bvol), sap_pk_lds_bytes(g), st, g, colour, flags,
                        sfh((void *)a.b), sfh(a.s), sfh(a.x), (const __half2 *)a.links,
-                       CloverField<2>{(const __half2 *)a.cinv}, a.phase, (float)a.kappa, a.n_jac);
+                       CloverField<2>{(const __half2 *)a.cinv}, a.phase, (float)a.kappa, a.n_jac, (h2 *)a.faces);
     return hipGetLastError();
 }
 
