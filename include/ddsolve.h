@@ -303,6 +303,17 @@ typedef enum { DD_BATCH_INNER_SAP = 0, DD_BATCH_INNER_PLAIN = 1 } dd_batch_inner
  * while it times the variants. */
 dd_status dirac_apply_batch(dd_ctx *ctx, void *out_dev, const void *in_dev, int nrhs, dd_prec prec, dd_op op);
 
+/* x_r = M_SAP b_r (Alg. 1, loop count n_sap, Jacobi count n_jac) for nrhs (1..16) canonical
+ * spinor fields stored one after another ([nrhs][Lt][Lz][Ly][Lx][3][4] complex double, device,
+ * caller-owned, x and b must not overlap), with the FP16 storage of sap_precondition at DD_F16.
+ * With packed FP16 arithmetic (dd_params.sap_fp16_arith = 1) each half-sweep is one launch for
+ * all right-hand sides, every workgroup staging its block's links and C_inv once and sweeping
+ * the block for each right-hand side in turn; the result of each equals that of
+ * sap_precondition on it alone.  With FP32 arithmetic it runs one SAP per right-hand side.
+ * The first call allocates the batch work fields (kept until dd_destroy; DD_ERR_NOMEM if that
+ * fails).  Asynchronous. */
+dd_status sap_precondition_batch(dd_ctx *ctx, void *x_dev, const void *b_dev, int nrhs);
+
 /* Force the batched kernel variant (0 .. 11: 0-7 matrix-core, 8-11 vector
  * with 1-4 right-hand sides per thread), or -1 to let the autotuner choose
  * (the default). */

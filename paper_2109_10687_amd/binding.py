@@ -39,7 +39,7 @@ EXPORTS = ["dd_create", "dd_destroy", "dd_load_gauge", "dirac_apply", "sap_preco
            "dd_force", "dirac_apply_batch", "dd_batch_set_variant", "dd_batch_tuning", "dd_batch_variant_name",
            "bicgstab_solve_batch", "dd_multi_create", "dd_multi_destroy", "dd_multi_last_error", "dd_multi_context",
            "dd_multi_load_gauge", "dirac_apply_multi", "bicgstab_solve_multi", "dd_solve_history",
-           "dd_force_noalloc"]
+           "dd_force_noalloc", "sap_precondition_batch"]
 
 
 class DDError(RuntimeError):
@@ -98,6 +98,7 @@ def lib():
             "dd_force_noalloc": (i, [vp, vp, ctypes.POINTER(d), vp, vp, i]),
             "dirac_apply_batch": (i, [vp, vp, vp, i, i, i]),
             "dd_batch_set_variant": (i, [vp, i]),
+            "sap_precondition_batch": (i, [vp, vp, vp, i]),
             "dd_batch_tuning": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(d), i]),
             "dd_batch_variant_name": (ctypes.c_char_p, [i]),
             "bicgstab_solve_batch": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(_Info)]),
@@ -286,6 +287,11 @@ def dirac_apply_batch(ctx, out, inp, nrhs, prec, op, shape):
     return _check(ctx, lib().dirac_apply_batch(ctx, _c128(out, sp, "out"), _c128(inp, sp, "in"), int(nrhs), prec, op))
 
 
+def sap_precondition_batch(ctx, x, b, nrhs, shape):
+    sp = (nrhs,) + shape + (3, 4)
+    return _check(ctx, lib().sap_precondition_batch(ctx, _c128(x, sp, "x"), _c128(b, sp, "b"), int(nrhs)))
+
+
 def dd_batch_set_variant(ctx, variant):
     return _check(ctx, lib().dd_batch_set_variant(ctx, int(variant)))
 
@@ -420,6 +426,12 @@ class Solver:
         """op applied to each of xs[r] (shape (nrhs,) + lattice + (3, 4)), one batched launch per 12."""
         out = torch.empty_like(xs) if out is None else out
         dirac_apply_batch(self.ctx, out, xs, xs.shape[0], prec, op, self.shape)
+        return out
+
+    def precondition_batch(self, bs, out=None):
+        """M_SAP b_r for each of bs[r] (FP16 storage; one launch per half-sweep for all of them)."""
+        out = torch.empty_like(bs) if out is None else out
+        sap_precondition_batch(self.ctx, out, bs, bs.shape[0], self.shape)
         return out
 
     def batch_variant(self, variant=-1):

@@ -16,8 +16,15 @@ dd_status batch_alloc(dd_ctx *c, int n)
     if (n <= c->bcap) return DD_OK;
     for (void *p : c->bk)
         if (p) (void)hipFree(p);
+    if (c->bfaces) (void)hipFree(c->bfaces);
+    c->bfaces = nullptr;
     c->bk.assign(BK_COUNT, nullptr);
     c->bcap = 0;
+    if (hipMalloc(&c->bfaces, (size_t)n * dd::sap_face_bytes(c->g)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->bfaces = nullptr;
+        return fail(c, DD_ERR_NOMEM, "batch face terms");
+    }
     for (int k = 0; k < BK_COUNT; ++k)
         if (hipMalloc(&c->bk[k], (size_t)n * spinor_bytes(c->g, bk_prec(k))) != hipSuccess) {
             (void)hipGetLastError();
@@ -166,15 +173,16 @@ dd_status solve_batch32(dd_ctx *c, int n, bool sap, std::vector<BRhs> &R, int ma
     // M = the FP16-storage SAP of each right-hand side (as in the single right-hand-side
     // mixed solver), reading the FP16 copies of r and p that the updates write and writing
     // FP16 fields that the batched A reads as they are
+    // all active right-hand sides in one launch per half-sweep: a block's links and C_inv are
+    // staged once for all of them
     auto precond = [&](int from16, int to16) -> dd_status {
         if (!sap) return DD_OK;
-        void *s16 = c->f16[4];
-        for (int r = 0; r < n; ++r) {
-            if (!R[r].active) continue;
-            dd_status s2;
-            if ((s2 = k_sap(c, 2, bf(c, from16, r), bf(c, to16, r), s16)) != DD_OK) return s2;
-        }
-        return DD_OK;
+        dd::SapRhs rhs{};
+        for (int r = 0; r < n; ++r)
+            if (R[r].active) rhs.idx[rhs.n++] = r;
+        rhs.sp_stride = (long long)spinor_bytes(c->g, DD_F16);
+        rhs.face_stride = (long long)dd::sap_face_bytes(c->g);
+        return k_sap_batch(c, rhs, bf(c, from16, 0), bf(c, to16, 0), bf(c, BK_S16, 0), c->bfaces);
     };
     // with the SAP, y takes alpha Mp + omega Mr in one pass; a right-hand side that stops
     // between the two half steps gets its alpha Mp here
@@ -594,6 +602,28 @@ dd_status dd_batch_tuning(dd_ctx *c, int nrhs, int *variant, double *ms, int n_m
     if (variant) *variant = c->mrhs_force >= 0 ? c->mrhs_force : c->mrhs_tuned[nrhs];
     const int nv = dd::mrhs_variant_count();
     for (int v = 0; ms && v < n_ms; ++v) ms[v] = v < nv ? c->mrhs_ms[nrhs][v] : 0.0;
+    return DD_OK;
+}
+
+dd_status sap_precondition_batch(dd_ctx *c, void *x_dev, const void *b_dev, int nrhs)
+{
+    if (!c || !x_dev || !b_dev) return fail(c, DD_ERR_ARG, "null argument");
+    if (nrhs < 1 || nrhs > BATCH_MAX) return fail(c, DD_ERR_ARG, "nrhs must be 1..16");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    dd_status st = batch_alloc(c, nrhs);
+    if (st != DD_OK) return st;
+    const size_t cb = (size_t)c->g.V * 12 * 16;
+    dd::SapRhs rhs{};
+    for (int r = 0; r < nrhs; ++r) {
+        HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, DD_F16, bf(c, BK_P16, r), (const char *)b_dev + r * cb));
+        rhs.idx[rhs.n++] = r;
+    }
+    rhs.sp_stride = (long long)spinor_bytes(c->g, DD_F16);
+    rhs.face_stride = (long long)dd::sap_face_bytes(c->g);
+    if ((st = k_sap_batch(c, rhs, bf(c, BK_P16, 0), bf(c, BK_MP16, 0), bf(c, BK_S16, 0), c->bfaces)) != DD_OK)
+        return st;
+    for (int r = 0; r < nrhs; ++r)
+        HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F16, (char *)x_dev + r * cb, bf(c, BK_MP16, r)));
     return DD_OK;
 }
 

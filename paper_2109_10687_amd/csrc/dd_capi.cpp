@@ -121,6 +121,7 @@ dd_status dd_destroy(dd_ctx *c)
         if (p) (void)hipFree(p);
     for (void *p : c->bk)
         if (p) (void)hipFree(p);
+    if (c->bfaces) (void)hipFree(c->bfaces);
     if (c->red_host) (void)hipHostFree(c->red_host);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     delete c;

@@ -61,6 +61,7 @@ struct dd_ctx {
     // first batched call and grown on demand (kinds: see BK_* below)
     int bcap = 0;
     std::vector<void *> bk;
+    void *bfaces = nullptr;  // the packed-FP16 SAP's face terms, one set per right-hand side
     int mrhs_force = -1;                // multi-RHS kernel variant forced by the caller (-1: autotune)
     int mrhs_tuned[13] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // per right-hand sides in a tile
     double mrhs_ms[13][16] = {};         // autotuner timings (ms per launch) per variant
@@ -188,6 +189,10 @@ bool sigma_blocks(dd::SigmaBlocks &sb);
 dd_status k_dirac(dd_ctx *c, void *out, const void *in, int pin, int pout, int pg, int op);
 // x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s
 dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s);
+// the same for the right-hand sides rhs.idx[0 .. n) of a batch of FP16 fields (the packed-FP16
+// SAP: one launch per half-sweep for all of them; otherwise one SAP per right-hand side):
+// field r of b, x and s at byte offset r * spinor_bytes(FP16), face terms per right-hand side
+dd_status k_sap_batch(dd_ctx *c, const dd::SapRhs &rhs, const void *b, void *x, void *s, void *faces);
 dd_status blas(dd_ctx *c, dd::BlasArgs a);
 // run a reducing vector kernel and bring its nv sums to the host
 dd_status reduce(dd_ctx *c, dd::BlasArgs a, int nv, double *out);
@@ -254,7 +259,7 @@ dd_status solve_fgmres64(dd_ctx *c, void *x, void *b, double bn2, double tol, in
 
 // kinds of per-RHS fields in the batch buffers (each kind: nrhs fields one after another)
 enum { BK_B64, BK_X64, BK_R64, BK_T64, BK_SRC, BK_Y, BK_R, BK_RT, BK_P, BK_Q, BK_T, BK_IN, BK_OUT,
-       BK_R16, BK_P16, BK_MP16, BK_MR16, BK_COUNT };
+       BK_R16, BK_P16, BK_MP16, BK_MR16, BK_S16, BK_COUNT };
 
 inline int bk_prec(int k) { return k <= BK_T64 ? DD_F64 : k >= BK_R16 ? DD_F16 : DD_F32; }
 

@@ -42,6 +42,16 @@ struct DiracArgs {
     Phase4 phase;
 };
 
+// the right-hand sides one packed-FP16 SAP launch sweeps, one after another in each workgroup:
+// right-hand side idx[k] has its spinor fields sp_stride bytes and its face terms face_stride
+// bytes after those of right-hand side 0 (n = 0: the single fields of the arguments)
+constexpr int SAP_RHS_MAX = 16;
+struct SapRhs {
+    int n;
+    int idx[SAP_RHS_MAX];
+    long long sp_stride, face_stride;
+};
+
 struct SapArgs {
     const void *b;  // source (storage precision)
     void *s;        // work vector
@@ -53,6 +63,7 @@ struct SapArgs {
     double kappa;
     Phase4 phase;
     void *faces;  // packed-FP16 half-sweep: face hop terms (sap_face_bytes), written and read in turn
+    SapRhs rhs;   // packed-FP16 half-sweep: the right-hand sides of a batch (n = 0: one)
 };
 
 enum BlasKind {

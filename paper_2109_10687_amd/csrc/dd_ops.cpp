@@ -146,11 +146,14 @@ dd_status k_dirac(dd_ctx *c, void *out, const void *in, int pin, int pout, int p
     return DD_OK;
 }
 
-// x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s
-dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
+// x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s; rhs.n > 0 sweeps the
+// listed right-hand sides of a batch in each launch (packed FP16 only), faces: their face terms
+static dd_status sap_sweeps(dd_ctx *c, int prec, const void *b, void *x, void *s, void *faces,
+                            const dd::SapRhs &rhs)
 {
     Range range("ddsolve: SAP preconditioner");
     dd::SapArgs a{};
+    a.rhs = rhs;
     a.b = b;
     a.s = s;
     a.x = x;
@@ -160,7 +163,8 @@ dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
     a.n_jac = c->prm.n_jac;
     a.kappa = c->prm.kappa;
     a.phase = c->phase;
-    a.faces = c->faces;
+    a.faces = faces;
+    const double nr = rhs.n > 0 ? rhs.n : 1;  // right-hand sides per launch
     const int E = 0, O = 1;
     const int n = c->prm.n_sap;
     const Geom &g = c->g;
@@ -177,7 +181,8 @@ dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
             face_sp += 2.0 / g.b[mu];
             face_lk += 1.0 / g.b[mu];
         }
-        double per = sp_b(prec) + 4 * lk_b(prec) + cl_b(prec);
+        const double stat = 4 * lk_b(prec) + cl_b(prec);  // links and C_inv, once for all right-hand sides
+        double per = sp_b(prec);
         if (!tail) per += (first ? 0.0 : sp_b(prec)) + sp_b(prec);
         if (!pk || tail) per += sp_b(prec);
         if (pk) {
@@ -191,7 +196,7 @@ dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
         if (!tail) fl += hops_in(g) + CLOVF + 48;
         if (pre) fl += hops_out(g) + CLOVF;
         const double sites = 0.5 * (double)g.V;
-        hipError_t e = timed(c, DD_KT_SAP, sites * per, sites * fl, [&] {
+        hipError_t e = timed(c, DD_KT_SAP, sites * (nr * per + stat), sites * nr * fl, [&] {
             return pk ? dd::launch_sap_half_pk(c->g, c->stream, a, colour, flags)
                       : dd::launch_sap_half(c->g, c->stream, a, colour, flags);
         });
@@ -208,6 +213,24 @@ dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
     }
     if ((st = half(E, dd::SAP_TAIL | (n == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out)) != DD_OK) return st;
     if ((st = half(O, dd::SAP_TAIL | dd::SAP_PRE | (n == 0 ? dd::SAP_FIRST : 0))) != DD_OK) return st;
+    return DD_OK;
+}
+
+dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
+{
+    return sap_sweeps(c, prec, b, x, s, c->faces, dd::SapRhs{});
+}
+
+dd_status k_sap_batch(dd_ctx *c, const dd::SapRhs &rhs, const void *b, void *x, void *s, void *faces)
+{
+    if (rhs.n <= 0) return DD_OK;
+    if (c->prm.sap_fp16_arith) return sap_sweeps(c, 2, b, x, s, faces, rhs);
+    // FP32 arithmetic on FP16 storage: one SAP per right-hand side
+    for (int k = 0; k < rhs.n; ++k) {
+        const long long o = rhs.idx[k] * rhs.sp_stride;
+        dd_status st = sap_sweeps(c, 2, (const char *)b + o, (char *)x + o, (char *)s + o, c->faces, dd::SapRhs{});
+        if (st != DD_OK) return st;
+    }
     return DD_OK;
 }
 

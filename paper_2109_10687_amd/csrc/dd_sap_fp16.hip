@@ -497,18 +497,27 @@ DD_INL void phase_pair(PC (&k)[3], float re, float im)
     for (int c = 0; c < 3; ++c) k[c] = PC{fma2(pr, k[c].re, mul2(neg2(pi), k[c].im)), fma2(pr, k[c].im, mul2(pi, k[c].re))};
 }
 
+// the field of right-hand side r of a batch whose fields lie `off` bytes apart
+DD_INL SpinorField<2> rhs_field(const SpinorField<2> &f, long long off)
+{
+    return SpinorField<2>{(__half2 *)((char *)f.p + off), (float *)((char *)f.scale + off)};
+}
+
 // One half-sweep with FP16 arithmetic; same flags and result (up to FP16 rounding) as
 // k_sap_half<2>, except that the cross-block term comes from the face hop terms of the
 // previous half-sweep (faces: the terms, then one scale per block) and that x is written
 // only by the tails of Alg. 1 (a middle half-sweep's x is only ever read through those
-// terms).  FACES_OUT leaves this half-sweep's terms for the next one.  B > 0 fixes the
-// block shape to B^4 at compile time: the block extents, in-block strides and the block
-// volume become constants, so every LDS offset of the sweeps is an immediate instead of a
-// register and the face index arithmetic folds; B = 0 takes the shape from the geometry.
+// terms).  FACES_OUT leaves this half-sweep's terms for the next one.  The workgroup sweeps
+// its block for every right-hand side of `rhs` in turn (b, s, x and the face terms of each
+// at their own offsets) with the block's links staged and its C_inv loaded once.  B > 0
+// fixes the block shape to B^4 at compile time: the block extents, in-block strides and the
+// block volume become constants, so every LDS offset of the sweeps is an immediate instead
+// of a register and the face index arithmetic folds; B = 0 takes the shape from the geometry.
 template <int B>
 __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int flags, SpinorField<2> bsrc,
                                                      SpinorField<2> sw, SpinorField<2> xw, const __half2 *u16,
-                                                     CloverField<2> Ci, Phase4 ph, float kappa, int n_jac, h2 *ft)
+                                                     CloverField<2> Ci, Phase4 ph, float kappa, int n_jac, h2 *ft,
+                                                     SapRhs rhs)
 {
     extern __shared__ uint4 smem_pk[];
     const Geom g = fixed_shape<B>(gin);
@@ -517,7 +526,6 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
     h2 *ul = reinterpret_cast<h2 *>(xs + 3 * bvol);         // 36 x bvol half2
     __shared__ float wmax[4];
     const int P = face_offset(g, 3, 1) + (bvol >> log2b(g, 3));  // face sites of a block
-    float *fs = reinterpret_cast<float *>(ft + (long long)g.nblk * 6 * P);  // one scale per block
 
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     Site st;
@@ -527,18 +535,8 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
     for (int mu = 0; mu < 4; ++mu) st.c[mu] = (st.s >> g.sh[mu]) & (g.b[mu] - 1);
     block_coords(g, st.l, st.B);
 
-    // s_c as stored: pair form relative to the site scale ssc
-    SpH sraw;
-    const float ssc = load_pair((flags & SAP_FIRST) ? bsrc : sw, g, st.l, st.s, sraw);
-
-    // Stage the block's links as full 3x3 FP16 matrices.  With PRE, h = H_{c c'} x_{c'} at this
-    // site: the hops from the neighbouring blocks, taken from the terms they left at the shared
-    // faces -- on the +mu face the projection of the neighbour's x, multiplied here by this
-    // site's U_mu; on the -mu face the finished backward term -- summed in FP32 with each
-    // neighbour block's scale.
-    const bool pre = (flags & SAP_PRE) != 0;
-    Spinor<float> hc;
-    zero(hc);
+    // stage the block's links as full 3x3 FP16 matrices, and its C_inv as pair coefficients,
+    // once for all right-hand sides
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         h2 U[3][3];
@@ -547,137 +545,161 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) ul[(mu * 9 + a * 3 + b) * bvol + st.s] = U[a][b];
-        if (!pre) continue;
-        const int c = st.c[mu];
-        int kk = 0, w8 = 0;
-#pragma unroll
-        for (int nu = 0; nu < 4; ++nu) {
-            if (nu == mu) continue;
-            kk += st.c[nu] << w8;
-            w8 += log2b(g, nu);
-        }
-        if (c == g.b[mu] - 1) {  // forward hop from block l + mu, whose -mu face holds the projection
-            const bool edge = st.B[mu] == g.NB[mu] - 1;
-            const int lj = st.l + (edge ? (1 - g.NB[mu]) : 1) * g.bstride[mu];
-            PC t[3], k[3];
-            const float sc = face_in(ft, fs, lj, face_offset(g, mu, 1) + kk, P, t);
-            mat_pair(U, false, t, k);
-            if (edge) phase_pair(k, (float)ph.re[mu], (float)ph.im[mu]);
-            recon_mix(mu, 1, k, sc, hc);
-        }
-        if (c == 0) {  // backward hop from block l - mu, whose +mu face holds U^dagger times the projection
-            const bool edge = st.B[mu] == 0;
-            const int lj = st.l - (edge ? (1 - g.NB[mu]) : 1) * g.bstride[mu];
-            PC k[3];
-            const float sc = face_in(ft, fs, lj, face_offset(g, mu, 0) + kk, P, k);
-            if (edge) phase_pair(k, (float)ph.re[mu], (float)-ph.im[mu]);
-            recon_mix(mu, -1, k, sc, hc);
-        }
     }
-
-    // kappa C_inv as pair coefficients (kappa folded in once: x <- x0 + (kappa C_inv) H x)
     ClovPair CP;
     clov_pairs_ld(Ci, g, st.l, st.s, CP);
+    const bool pre = (flags & SAP_PRE) != 0;
 
-    // block normalisation: scale s_c and h to max |component| <= 1 (a stored FP16
-    // spinor has max |component| = 1 relative to its scale)
-    float m = ssc;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(hc.v[a][c].re), fabsf(hc.v[a][c].im)));
-    const int wv = bvol < 64 ? bvol : 64;  // lanes of this workgroup in one wavefront
-    for (int off = wv / 2; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, wv));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-    __syncthreads();  // also: every link is staged
-    m = 0.f;
-    for (int q = 0; q < (bvol + 63) / 64; ++q) m = fmaxf(m, wmax[q]);
-    const float sc = m > 0.f ? 1.f / m : 0.f;
+    for (int ri = 0; ri < rhs.n; ++ri) {
+        if (ri > 0) __syncthreads();  // the previous right-hand side is done with LDS
+        const long long off = (long long)rhs.idx[ri] * rhs.sp_stride;
+        const SpinorField<2> b_r = rhs_field(bsrc, off), s_r = rhs_field(sw, off), x_r = rhs_field(xw, off);
+        h2 *ft_r = (h2 *)((char *)ft + (long long)rhs.idx[ri] * rhs.face_stride);
+        float *fs_r = reinterpret_cast<float *>(ft_r + (long long)g.nblk * 6 * P);  // one scale per block
 
-    // x0 = s_c + kappa C_inv h (normalised): the first Jacobi step from x = 0; every later
-    // step is x <- x0 + kappa C_inv H_in x
-    SpH x0, x, acc, t;
-    scale_pair(sraw, ssc * sc, x0);
-    const h2 K = __float2half2_rn(kappa);
-    if (pre) {
-        SpH hp;
-        to_pair(hc, sc, hp);
-        clover_pair(CP, hp, t);
+        // s_c as stored: pair form relative to the site scale ssc
+        SpH sraw;
+        const float ssc = load_pair((flags & SAP_FIRST) ? b_r : s_r, g, st.l, st.s, sraw);
+
+        // With PRE, h = H_{c c'} x_{c'} at this site: the hops from the neighbouring blocks, taken
+        // from the terms they left at the shared faces -- on the +mu face the projection of the
+        // neighbour's x, multiplied here by this site's U_mu; on the -mu face the finished
+        // backward term -- summed in FP32 with each neighbour block's scale.
+        Spinor<float> hc;
+        zero(hc);
+        if (pre) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            x0.u[c] = PC{fma2(K, t.u[c].re, x0.u[c].re), fma2(K, t.u[c].im, x0.u[c].im)};
-            x0.l[c] = PC{fma2(K, t.l[c].re, x0.l[c].re), fma2(K, t.l[c].im, x0.l[c].im)};
-        }
-    }
-    x = x0;
-    for (int j = 0; j < n_jac; ++j) {
-        __syncthreads();
-        lds_put(xs, bvol, st.s, x);
-        __syncthreads();
-        inblock_pair(xs, ul, g, bvol, st, acc);
-        clover_pair(CP, acc, t);
+            for (int mu = 0; mu < 4; ++mu) {
+                const int c = st.c[mu];
+                int kk = 0, w8 = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            x.u[c] = PC{fma2(K, t.u[c].re, x0.u[c].re), fma2(K, t.u[c].im, x0.u[c].im)};
-            x.l[c] = PC{fma2(K, t.l[c].re, x0.l[c].re), fma2(K, t.l[c].im, x0.l[c].im)};
-        }
-    }
-    const float inv = m;  // undo the normalisation
-    if (!(flags & SAP_TAIL)) {
-        // s_c <- (s_c + kappa C_inv h) + b_c - x_c + kappa C_inv H_in x_c, in FP32
-        __syncthreads();
-        lds_put(xs, bvol, st.s, x);
-        __syncthreads();
-        inblock_pair(xs, ul, g, bvol, st, acc);
-        clover_pair(CP, acc, t);
-        SpH braw;
-        const float sb = load_pair(bsrc, g, st.l, st.s, braw);
-        Spinor<float> snew;
-        combine_pair(x0, inv, braw, sb, x, -inv, t, kappa * inv, snew);
-        sw.store(g, st.l, st.s, snew);
-    } else {
-        Spinor<float> xf;
-        from_pair(x, inv, xf);
-        xw.store(g, st.l, st.s, xf);
-        if (flags & SAP_FACES_OUT) {
-            __syncthreads();
-            lds_put(xs, bvol, st.s, x);
-        }
-    }
-    if (flags & SAP_FACES_OUT) {
-        // this block's face terms from x in LDS (put there by the s update, or just above),
-        // spread evenly over the workgroup
-        __syncthreads();
-        const bool equal_faces = g.b[0] == g.b[1] && g.b[1] == g.b[2] && g.b[2] == g.b[3];
-        const int lnf = g.lbvol - log2b(g, 0);  // log2 of the sites per face
-        for (int p = threadIdx.x; p < P; p += bvol) {
-            int q = 0, base = 0;
-            if (equal_faces) {  // hypercubic block: face q holds sites q * nf ... q * nf + nf - 1
-                q = p >> lnf;
-                base = q << lnf;
-            } else {
-#pragma unroll
-                for (int qq = 0; qq < 7; ++qq) {
-                    const int n = bvol >> log2b(g, qq >> 1);
-                    if (q == qq && p >= base + n) {
-                        base += n;
-                        q = qq + 1;
-                    }
+                for (int nu = 0; nu < 4; ++nu) {
+                    if (nu == mu) continue;
+                    kk += st.c[nu] << w8;
+                    w8 += log2b(g, nu);
+                }
+                if (c == g.b[mu] - 1) {  // forward hop from block l + mu, whose -mu face holds the projection
+                    const bool edge = st.B[mu] == g.NB[mu] - 1;
+                    const int lj = st.l + (edge ? (1 - g.NB[mu]) : 1) * g.bstride[mu];
+                    PC t[3], k[3];
+                    const float sc = face_in(ft_r, fs_r, lj, face_offset(g, mu, 1) + kk, P, t);
+                    h2 U[3][3];
+                    lds_link(ul, bvol, st.s, mu, U);  // this site's own link, staged by this thread
+                    mat_pair(U, false, t, k);
+                    if (edge) phase_pair(k, (float)ph.re[mu], (float)ph.im[mu]);
+                    recon_mix(mu, 1, k, sc, hc);
+                }
+                if (c == 0) {  // backward hop from block l - mu, whose +mu face holds U^dagger times the projection
+                    const bool edge = st.B[mu] == 0;
+                    const int lj = st.l - (edge ? (1 - g.NB[mu]) : 1) * g.bstride[mu];
+                    PC k[3];
+                    const float sc = face_in(ft_r, fs_r, lj, face_offset(g, mu, 0) + kk, P, k);
+                    if (edge) phase_pair(k, (float)ph.re[mu], (float)-ph.im[mu]);
+                    recon_mix(mu, -1, k, sc, hc);
                 }
             }
-            const int kk = p - base;
-            switch (q) {  // faces in order +x, -x, +y, -y, +z, -z, +t, -t
-            case 0: face_out<0, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
-            case 1: face_out<0, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
-            case 2: face_out<1, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
-            case 3: face_out<1, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
-            case 4: face_out<2, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
-            case 5: face_out<2, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
-            case 6: face_out<3, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
-            default: face_out<3, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft); break;
+        }
+
+        // block normalisation: scale s_c and h to max |component| <= 1 (a stored FP16
+        // spinor has max |component| = 1 relative to its scale)
+        float m = ssc;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(hc.v[a][c].re), fabsf(hc.v[a][c].im)));
+        const int wv = bvol < 64 ? bvol : 64;  // lanes of this workgroup in one wavefront
+        for (int o2 = wv / 2; o2 >= 1; o2 >>= 1) m = fmaxf(m, __shfl_xor(m, o2, wv));
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+        __syncthreads();  // also: every link is staged
+        m = 0.f;
+        for (int q = 0; q < (bvol + 63) / 64; ++q) m = fmaxf(m, wmax[q]);
+        const float sc = m > 0.f ? 1.f / m : 0.f;
+
+        // x0 = s_c + kappa C_inv h (normalised): the first Jacobi step from x = 0; every later
+        // step is x <- x0 + kappa C_inv H_in x
+        SpH x0, x, acc, t;
+        scale_pair(sraw, ssc * sc, x0);
+        const h2 K = __float2half2_rn(kappa);
+        if (pre) {
+            SpH hp;
+            to_pair(hc, sc, hp);
+            clover_pair(CP, hp, t);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                x0.u[c] = PC{fma2(K, t.u[c].re, x0.u[c].re), fma2(K, t.u[c].im, x0.u[c].im)};
+                x0.l[c] = PC{fma2(K, t.l[c].re, x0.l[c].re), fma2(K, t.l[c].im, x0.l[c].im)};
             }
         }
-        if (threadIdx.x == 0) fs[st.l] = inv;
+        x = x0;
+        for (int j = 0; j < n_jac; ++j) {
+            __syncthreads();
+            lds_put(xs, bvol, st.s, x);
+            __syncthreads();
+            inblock_pair(xs, ul, g, bvol, st, acc);
+            clover_pair(CP, acc, t);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                x.u[c] = PC{fma2(K, t.u[c].re, x0.u[c].re), fma2(K, t.u[c].im, x0.u[c].im)};
+                x.l[c] = PC{fma2(K, t.l[c].re, x0.l[c].re), fma2(K, t.l[c].im, x0.l[c].im)};
+            }
+        }
+        const float inv = m;  // undo the normalisation
+        if (!(flags & SAP_TAIL)) {
+            // s_c <- (s_c + kappa C_inv h) + b_c - x_c + kappa C_inv H_in x_c, in FP32
+            __syncthreads();
+            lds_put(xs, bvol, st.s, x);
+            __syncthreads();
+            inblock_pair(xs, ul, g, bvol, st, acc);
+            clover_pair(CP, acc, t);
+            SpH braw;
+            const float sb = load_pair(b_r, g, st.l, st.s, braw);
+            Spinor<float> snew;
+            combine_pair(x0, inv, braw, sb, x, -inv, t, kappa * inv, snew);
+            s_r.store(g, st.l, st.s, snew);
+        } else {
+            Spinor<float> xf;
+            from_pair(x, inv, xf);
+            x_r.store(g, st.l, st.s, xf);
+            if (flags & SAP_FACES_OUT) {
+                __syncthreads();
+                lds_put(xs, bvol, st.s, x);
+            }
+        }
+        if (flags & SAP_FACES_OUT) {
+            // this block's face terms from x in LDS (put there by the s update, or just above),
+            // spread evenly over the workgroup
+            __syncthreads();
+            const bool equal_faces = g.b[0] == g.b[1] && g.b[1] == g.b[2] && g.b[2] == g.b[3];
+            const int lnf = g.lbvol - log2b(g, 0);  // log2 of the sites per face
+            for (int p = threadIdx.x; p < P; p += bvol) {
+                int q = 0, base = 0;
+                if (equal_faces) {  // hypercubic block: face q holds sites q * nf ... q * nf + nf - 1
+                    q = p >> lnf;
+                    base = q << lnf;
+                } else {
+#pragma unroll
+                    for (int qq = 0; qq < 7; ++qq) {
+                        const int n = bvol >> log2b(g, qq >> 1);
+                        if (q == qq && p >= base + n) {
+                            base += n;
+                            q = qq + 1;
+                        }
+                    }
+                }
+                const int kk = p - base;
+                switch (q) {  // faces in order +x, -x, +y, -y, +z, -z, +t, -t
+                case 0: face_out<0, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft_r); break;
+                case 1: face_out<0, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft_r); break;
+                case 2: face_out<1, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft_r); break;
+                case 3: face_out<1, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft_r); break;
+                case 4: face_out<2, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft_r); break;
+                case 5: face_out<2, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft_r); break;
+                case 6: face_out<3, 0>(g, st.l, kk, p, P, xs, ul, bvol, ft_r); break;
+                default: face_out<3, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft_r); break;
+                }
+            }
+            if (threadIdx.x == 0) fs_r[st.l] = inv;
+        }
     }
 }
 
@@ -709,9 +731,15 @@ hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, i
     };
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
     auto kern = cube4 ? k_sap_half_pk<4> : k_sap_half_pk<0>;
+    SapRhs rhs = a.rhs;
+    if (rhs.n <= 0) {  // one right-hand side (the fields as given)
+        rhs = SapRhs{};
+        rhs.n = 1;
+    }
+    if (rhs.n > SAP_RHS_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kern, dim3(g.nblk / 2), dim3(g.bvol), sap_pk_lds_bytes(g), st, g, colour, flags,
                        sfh((void *)a.b), sfh(a.s), sfh(a.x), (const __half2 *)a.links,
-                       CloverField<2>{(const __half2 *)a.cinv}, a.phase, (float)a.kappa, a.n_jac, (h2 *)a.faces);
+                       CloverField<2>{(const __half2 *)a.cinv}, a.phase, (float)a.kappa, a.n_jac, (h2 *)a.faces, rhs);
     return hipGetLastError();
 }
 
