@@ -87,6 +87,7 @@ def parse():
     ap.add_argument("--single-prec", choices=["on", "off"], default="on",
                     help="the 32^4 leg: FP32 SAP-BiCGStab at kappa 0.1365 to 1e-6 against plain FP64")
     ap.add_argument("--single-prec-fp64-maxiter", type=int, default=6000)
+    ap.add_argument("--only-single", action="store_true", help="run the 32^4 single-precision leg only (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of 4 GiB five times (scale for HBM byte counters) and exit")
     return ap.parse_args()
@@ -320,7 +321,22 @@ def single_prec_bench(dd, args, reps=3, apply_reps=20):
     t32 = sorted(secs)[len(secs) // 2]
     out = {"workload": "32x32x32x32 FP32 SAP-BiCGStab, kappa 0.1365, c_SW 1.7, tol 1e-6",
            "fp32_sap": {"seconds": round(t32, 4), "iters": info["iters_inner_total"], "status": info["status"],
-                        "relres_recursive": info["relres_inner_last"], "relres_true": info["relres_true"]}}
+                        "relres_recursive": info["relres_inner_last"], "relres_true": info["relres_true"],
+                        "ms_per_iter": round(t32 / max(info["iters_inner_total"], 1) * 1e3, 3),
+                        "a_msap": "fused tail of Alg. 3"}}
+    # the same solve with A applied separately to the SAP's output: same operator, other rounding
+    sep = dd.Solver(dd.Params(dims=dims, kappa=0.1365, csw=1.7, block=(4, 4, 4, 4), n_sap=4, n_jac=4,
+                              sap_separate_tail=1), synth.su3_links(dims, 0.3, args.seed + 60, device="cuda"))
+    sep.solve(b, tol=1e-6, maxiter=2000, mode=dd.DD_SOLVE_F32_SAP)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, isep = sep.solve(b, tol=1e-6, maxiter=2000, mode=dd.DD_SOLVE_F32_SAP)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out["fp32_sap_separate_product"] = {"seconds": round(ts, 4), "iters": isep["iters_inner_total"],
+                                        "status": isep["status"], "relres_true": isep["relres_true"],
+                                        "ms_per_iter": round(ts / max(isep["iters_inner_total"], 1) * 1e3, 3)}
+    sep.close()
     # the two mixed-precision outer loops to 1e-10 at this kappa: defect correction (Alg. 4) and
     # flexible GMRES, both around the FP32 BiCGStab with the FP16 SAP
     out["mixed_to_1e-10"] = {}
@@ -560,6 +576,9 @@ def main():
         log(f"32^4: FP32 SAP {single['fp32_sap']['seconds']:.3f} s ({single['fp32_sap']['iters']} it., "
             f"{single['fp32_sap']['status']}); plain FP64 {single['fp64_plain']['seconds']:.2f} s "
             f"({single['fp64_plain']['iters']} it., {single['fp64_plain']['status']})")
+        if args.only_single:
+            print(json.dumps({"single_prec_32x32x32x32": single}))
+            return
 
     multi = None
     if args.multi == "on" and not args.only_apply:

@@ -134,6 +134,9 @@ typedef struct {
     int stall_window;   /* an inner FP32 solve stops (status detail 6) when its recursive
                            residual has not fallen 10x below the last such point within
                            this many iterations (0 = 200; negative = never)          */
+    int sap_separate_tail; /* FP32 SAP (DD_SOLVE_F32_SAP): 0 forms A M_SAP by the fused tail of
+                           Alg. 3; 1 applies A separately to the SAP's output (the same
+                           product, other rounding order)                            */
     int fgmres_nkv;     /* flexible GMRES cycle length for DD_SOLVE_FGMRES, 1..16 (0 = 4);
                            the basis takes four FP64 and the directions three FP32 work
                            vectors of the context, the first such solve allocates the
@@ -196,6 +199,16 @@ dd_status dirac_apply(dd_ctx *ctx, void *out_dev, const void *in_dev, dd_prec pr
  * packed FP16 arithmetic when dd_params.sap_fp16_arith is 1 and in FP32
  * otherwise.  Asynchronous. */
 dd_status sap_precondition(dd_ctx *ctx, void *x_dev, const void *b_dev, dd_prec prec);
+
+/* ax = A M_SAP b (Alg. 3: the preconditioned operator of the BiCGStab of Alg. 5) for canonical
+ * fields (device, caller-owned, must not overlap).  DD_F32: FP32 storage and arithmetic, the
+ * product formed by the fused tail of Alg. 3 -- the last two half-sweeps of Alg. 1 also apply
+ * A to the blocks they have just solved, and one more pass over the even blocks adds the
+ * cross-block hops of the final odd result.  DD_F16: the FP16-storage SAP (as
+ * sap_precondition), then the FP32 operator applied to its FP16-stored output (the inner
+ * solver's operator must stay accurate to FP32, which an FP16 product would not be).
+ * Asynchronous. */
+dd_status sap_precondition_amsap(dd_ctx *ctx, void *ax_dev, const void *b_dev, dd_prec prec);
 
 /* Solve D x = b (canonical fields on the device).  On entry x holds the
  * initial guess for every mode but DD_SOLVE_F32_SAP (pass zeros for a cold

@@ -39,7 +39,8 @@ EXPORTS = ["dd_create", "dd_destroy", "dd_load_gauge", "dirac_apply", "sap_preco
            "dd_force", "dirac_apply_batch", "dd_batch_set_variant", "dd_batch_tuning", "dd_batch_variant_name",
            "bicgstab_solve_batch", "dd_multi_create", "dd_multi_destroy", "dd_multi_last_error", "dd_multi_context",
            "dd_multi_load_gauge", "dirac_apply_multi", "bicgstab_solve_multi", "dd_solve_history",
-           "dd_force_noalloc", "sap_precondition_batch"]
+           "dd_force_noalloc", "sap_precondition_batch",
+           "sap_precondition_amsap"]
 
 
 class DDError(RuntimeError):
@@ -53,7 +54,7 @@ class _Params(ctypes.Structure):
                 ("csw", ctypes.c_double), ("phase_re", ctypes.c_double * 4), ("phase_im", ctypes.c_double * 4),
                 ("n_sap", ctypes.c_int), ("n_jac", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("inner_maxiter", ctypes.c_int), ("gcr_nkv", ctypes.c_int), ("sap_fp16_arith", ctypes.c_int),
-                ("stall_window", ctypes.c_int), ("fgmres_nkv", ctypes.c_int)]
+                ("stall_window", ctypes.c_int), ("sap_separate_tail", ctypes.c_int), ("fgmres_nkv", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -80,6 +81,7 @@ def lib():
             "dd_load_gauge": (i, [vp, vp]),
             "dirac_apply": (i, [vp, vp, vp, i, i]),
             "sap_precondition": (i, [vp, vp, vp, i]),
+            "sap_precondition_amsap": (i, [vp, vp, vp, i]),
             "bicgstab_solve": (i, [vp, vp, vp, d, i, i, ctypes.POINTER(_Info)]),
             "dd_last_error": (ctypes.c_char_p, [vp]),
             "dd_solve_history": (i, [vp, i, ctypes.POINTER(d), i, ctypes.POINTER(i)]),
@@ -133,6 +135,7 @@ class Params:
     gcr_nkv: int = 16
     sap_fp16_arith: int = 1
     stall_window: int = 200
+    sap_separate_tail: int = 0
     fgmres_nkv: int = 4
 
     def c(self):
@@ -152,6 +155,7 @@ class Params:
         p.gcr_nkv = int(self.gcr_nkv)
         p.sap_fp16_arith = int(self.sap_fp16_arith)
         p.stall_window = int(self.stall_window)
+        p.sap_separate_tail = int(self.sap_separate_tail)
         p.fgmres_nkv = int(self.fgmres_nkv)
         return p
 
@@ -225,6 +229,11 @@ def _info_dict(info):
     d = {k: getattr(info, k) for k, _ in _Info._fields_}
     d["status"] = STATUS[d["status"]]
     return d
+
+
+def sap_precondition_amsap(ctx, ax, b, prec, shape):
+    sp = shape + (3, 4)
+    return _check(ctx, lib().sap_precondition_amsap(ctx, _c128(ax, sp, "ax"), _c128(b, sp, "b"), prec))
 
 
 def bicgstab_solve(ctx, x, b, tol, maxiter, mode, shape):
@@ -426,6 +435,12 @@ class Solver:
         """op applied to each of xs[r] (shape (nrhs,) + lattice + (3, 4)), one batched launch per 12."""
         out = torch.empty_like(xs) if out is None else out
         dirac_apply_batch(self.ctx, out, xs, xs.shape[0], prec, op, self.shape)
+        return out
+
+    def amsap(self, b, prec=DD_F32, out=None):
+        """A M_SAP b (Alg. 3; fused into the SAP's last half-sweeps at FP32)."""
+        out = self.new_spinor() if out is None else out
+        sap_precondition_amsap(self.ctx, out, b, prec, self.shape)
         return out
 
     def precondition_batch(self, bs, out=None):

@@ -219,6 +219,24 @@ dd_status sap_precondition(dd_ctx *c, void *x, const void *b, dd_prec prec)
     return DD_OK;
 }
 
+dd_status sap_precondition_amsap(dd_ctx *c, void *ax, const void *b, dd_prec prec)
+{
+    if (!c || !ax || !b) return fail(c, DD_ERR_ARG, "null argument");
+    if (!c->gauge) return fail(c, DD_ERR_STATE, "no gauge field loaded");
+    if (prec != DD_F32 && prec != DD_F16) return fail(c, DD_ERR_ARG, "A M_SAP is available at FP32 and FP16");
+    void *tb = c->f64[5], *tx = c->f64[6], *ts = c->f64[4], *tax = c->f64[3];
+    HIPCK(c, dd::launch_pack_spinor(c->g, c->stream, prec, tb, b));
+    dd_status st;
+    if (prec == DD_F32) {
+        if ((st = k_sap(c, 1, tb, tx, ts, tax)) != DD_OK) return st;
+    } else {
+        if ((st = k_sap(c, 2, tb, tx, ts)) != DD_OK) return st;
+        if ((st = k_dirac(c, tax, tx, DD_F16, DD_F32, DD_F32, DD_OP_A)) != DD_OK) return st;
+    }
+    HIPCK(c, dd::launch_unpack_spinor(c->g, c->stream, DD_F32, ax, tax));
+    return DD_OK;
+}
+
 // D x = b, or D^dagger x = b when dagger is set: D^dagger = gamma_5 D gamma_5, so
 // y = gamma_5 x solves D y = gamma_5 b; the gamma_5 is applied while packing b
 // and x and while unpacking the result

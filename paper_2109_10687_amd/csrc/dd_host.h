@@ -187,8 +187,9 @@ inline bool is_fin(cplx v) { return std::isfinite(v.real()) && std::isfinite(v.i
 bool sigma_blocks(dd::SigmaBlocks &sb);
 // operator op at input / output / gauge precisions pin, pout, pg (0 FP64, 1 FP32, 2 FP16)
 dd_status k_dirac(dd_ctx *c, void *out, const void *in, int pin, int pout, int pg, int op);
-// x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s
-dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s);
+// x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s; with ax (FP32 only)
+// also ax = A M_SAP b by the fused tail of Alg. 3
+dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s, void *ax = nullptr);
 // the same for the right-hand sides rhs.idx[0 .. n) of a batch of FP16 fields (the packed-FP16
 // SAP: one launch per half-sweep for all of them; otherwise one SAP per right-hand side):
 // field r of b, x and s at byte offset r * spinor_bytes(FP16), face terms per right-hand side

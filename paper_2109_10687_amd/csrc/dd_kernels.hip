@@ -549,13 +549,16 @@ DD_INL void inblock_hops(const float2 *xs, const SapLinks<P> &lk, const typename
 //   [PRE]   s_c <- s_c - A_{c c'} x_{c'}     (cross-block hops from the other colour)
 //           x_c  = B_cc s_c                   (Alg. 2: x = s + K x, n_jac times, K = kappa C_inv H_in)
 //   [!TAIL] s_c <- s_c + b_c - A_cc x_c      (A_cc x = x - K x)
-// FIRST takes s_c from b (s = b at the start of Alg. 1).  One workgroup per
-// block, one thread per site; blockDim.x == block volume.
+// FIRST takes s_c from b (s = b at the start of Alg. 1).  The fused tail of Alg. 3 (A M_SAP b,
+// written to ax): with TAIL, AMSAP also writes ax_c = A_cc x_c, AMSAP_PRE includes the
+// cross-block term A_{c c'} x_{c'} (the odd tail, whose neighbours already hold the final even
+// x), and a CROSS_ONLY launch on the even blocks then adds A_{c c'} x_{c'} of the final odd x.  One
+// workgroup per block, one thread per site; blockDim.x == block volume.
 template <int P, int B>
 __global__ void __launch_bounds__(256) k_sap_half(Geom gin, int colour, int flags, SpinorField<P> bsrc,
                                                   SpinorField<P> sw, SpinorField<P> xw, SapLinks<P> lk,
                                                   LinkField<P> U, CloverField<P> Ci, Phase4 ph, float kappa,
-                                                  int n_jac)
+                                                  int n_jac, SpinorField<P> axw)
 {
     const Geom g = fixed_shape<B>(gin);
     using LT = typename SapLinks<P>::T;
@@ -572,19 +575,21 @@ __global__ void __launch_bounds__(256) k_sap_half(Geom gin, int colour, int flag
     for (int mu = 0; mu < 4; ++mu) st.c[mu] = (st.s >> g.sh[mu]) & (g.b[mu] - 1);
     block_coords(g, st.l, st.B);
 
-    lk.stage(ul, g, st.l, st.s);
+    const bool cross_only = (flags & SAP_CROSS_ONLY) != 0;
+    if (!cross_only) lk.stage(ul, g, st.l, st.s);
 
     Clov<float> cl;
     Ci.load(g, st.l, st.s, cl);
     Spinor<float> src;
-    if (flags & SAP_FIRST)
-        bsrc.load(g, st.l, st.s, src);
-    else
-        sw.load(g, st.l, st.s, src);
+    if (!cross_only) {
+        if (flags & SAP_FIRST)
+            bsrc.load(g, st.l, st.s, src);
+        else
+            sw.load(g, st.l, st.s, src);
+    }
 
-    Spinor<float> acc, t;
-    if (flags & SAP_PRE) {
-        zero(acc);
+    // acc += H_{c c'} x_{c'} at this site: the hops that come from the neighbouring blocks
+    auto cross_hops = [&](Spinor<float> &acc) {
         for (int mu = 0; mu < 4; ++mu) {
             for (int dir = 1; dir >= -1; dir -= 2) {
                 int c = st.c[mu] + dir;
@@ -603,7 +608,22 @@ __global__ void __launch_bounds__(256) k_sap_half(Geom gin, int colour, int flag
                 hop(mu, dir, W, psi, wrap, phase, acc);
             }
         }
+    };
+    Spinor<float> acc, t;
+    if ((flags & SAP_PRE) || cross_only) {
+        zero(acc);
+        cross_hops(acc);
         clover_mul(cl, acc, t);
+        if (cross_only) {  // ax_c += A_{c c'} x_{c'} = -kappa C_inv H_{c c'} x_{c'}
+            Spinor<float> q;
+            axw.load(g, st.l, st.s, q);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) q.v[a][c] = q.v[a][c] - kappa * t.v[a][c];
+            axw.store(g, st.l, st.s, q);
+            return;
+        }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -636,6 +656,23 @@ __global__ void __launch_bounds__(256) k_sap_half(Geom gin, int colour, int flag
             for (int c = 0; c < 3; ++c)
                 src.v[a][c] = src.v[a][c] + b.v[a][c] - x.v[a][c] + kappa * t.v[a][c];
         sw.store(g, st.l, st.s, src);
+    } else if (flags & SAP_AMSAP) {
+        // Alg. 3: this colour's rows of A x, x - kappa C_inv (H_in x + H_{c c'} x_{c'}): the
+        // in-block hops of the final x, and with AMSAP_PRE the hops from the other colour's final
+        // x, the same ones this launch's prologue read (formed again here rather than kept
+        // through the sweeps), all under one C_inv product as in the Dirac apply
+        __syncthreads();
+        lds_store_spinor(xs, bvol, st.s, x);
+        __syncthreads();
+        inblock_hops<P>(xs, lk, ul, g, st, acc);
+        if (flags & SAP_AMSAP_PRE) cross_hops(acc);
+        clover_mul(cl, acc, t);
+        Spinor<float> q;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) q.v[a][c] = x.v[a][c] - kappa * t.v[a][c];
+        axw.store(g, st.l, st.s, q);
     }
     xw.store(g, st.l, st.s, x);
 }
@@ -1214,6 +1251,7 @@ size_t sap_lds_bytes(const Geom &g, int prec)
 
 hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags)
 {
+    if ((flags & (SAP_AMSAP | SAP_CROSS_ONLY)) && !a.ax) return hipErrorInvalidValue;
     const int nwg = g.nblk / 2;
     const size_t lds = sap_lds_bytes(g, a.prec);
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
@@ -1221,12 +1259,12 @@ hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int 
         hipLaunchKernelGGL((cube4 ? k_sap_half<1, 4> : k_sap_half<1, 0>), dim3(nwg), dim3(g.bvol), lds, st, g, colour, flags, sf<1>((void *)a.b, g),
                            sf<1>(a.s, g), sf<1>(a.x, g), SapLinks<1>{LinkField<1>{(const float2 *)a.links}},
                            LinkField<1>{(const float2 *)a.links}, CloverField<1>{(const float2 *)a.cinv}, a.phase,
-                           (float)a.kappa, a.n_jac);
+                           (float)a.kappa, a.n_jac, sf<1>(a.ax, g));
     } else if (a.prec == 2) {
         hipLaunchKernelGGL((cube4 ? k_sap_half<2, 4> : k_sap_half<2, 0>), dim3(nwg), dim3(g.bvol), lds, st, g, colour, flags, sf<2>((void *)a.b, g),
                            sf<2>(a.s, g), sf<2>(a.x, g), SapLinks<2>{(const __half2 *)a.links},
                            LinkField<2>{(const __half2 *)a.links}, CloverField<2>{(const __half2 *)a.cinv}, a.phase,
-                           (float)a.kappa, a.n_jac);
+                           (float)a.kappa, a.n_jac, sf<2>(a.ax, g));
     } else {
         return hipErrorInvalidValue;
     }

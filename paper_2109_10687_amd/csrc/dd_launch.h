@@ -19,6 +19,10 @@ constexpr int SAP_FIRST = 1;  // read s from the source b (s = b at the start of
 constexpr int SAP_PRE = 2;    // subtract the cross-block term A_{c c'} x_{c'} first
 constexpr int SAP_TAIL = 4;   // tail of Alg. 1: produce x only, leave s alone
 constexpr int SAP_FACES_OUT = 8;  // packed-FP16 half-sweep: leave face hop terms for the next half-sweep
+// the fused tail of Alg. 3 (FP32 arithmetic): with TAIL also write this colour's rows of A x
+constexpr int SAP_AMSAP = 16;      //   the in-block part A_cc x_c
+constexpr int SAP_AMSAP_PRE = 32;  //   and the cross-block term of this launch, A_{c c'} x_{c'}
+constexpr int SAP_CROSS_ONLY = 64; // only add A_{c c'} x_{c'} of the final x to those rows (Alg. 3, last step)
 
 struct Phase4 {
     double re[4], im[4];
@@ -62,6 +66,7 @@ struct SapArgs {
     int n_jac;
     double kappa;
     Phase4 phase;
+    void *ax;     // FP32 arithmetic with SAP_AMSAP / SAP_CROSS_ONLY: A M_SAP b (storage precision)
     void *faces;  // packed-FP16 half-sweep: face hop terms (sap_face_bytes), written and read in turn
     SapRhs rhs;   // packed-FP16 half-sweep: the right-hand sides of a batch (n = 0: one)
 };

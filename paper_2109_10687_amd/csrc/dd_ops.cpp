@@ -149,11 +149,12 @@ dd_status k_dirac(dd_ctx *c, void *out, const void *in, int pin, int pout, int p
 // x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s; rhs.n > 0 sweeps the
 // listed right-hand sides of a batch in each launch (packed FP16 only), faces: their face terms
 static dd_status sap_sweeps(dd_ctx *c, int prec, const void *b, void *x, void *s, void *faces,
-                            const dd::SapRhs &rhs)
+                            const dd::SapRhs &rhs, void *ax = nullptr)
 {
     Range range("ddsolve: SAP preconditioner");
     dd::SapArgs a{};
     a.rhs = rhs;
+    a.ax = ax;
     a.b = b;
     a.s = s;
     a.x = x;
@@ -195,6 +196,18 @@ static dd_status sap_sweeps(dd_ctx *c, int prec, const void *b, void *x, void *s
         double fl = c->prm.n_jac * (hops_in(g) + CLOVF);
         if (!tail) fl += hops_in(g) + CLOVF + 48;
         if (pre) fl += hops_out(g) + CLOVF;
+        if (flags & dd::SAP_AMSAP) {  // Alg. 3: one more in-block sweep, ax written
+            per += sp_b(prec);
+            fl += hops_in(g) + CLOVF + 48;
+            if (flags & dd::SAP_AMSAP_PRE) {  // and the cross-block hops formed again
+                per += face_sp * sp_b(prec) + face_lk * lk_b(prec);
+                fl += hops_out(g);
+            }
+        }
+        if (flags & dd::SAP_CROSS_ONLY) {  // the cross-block hops of the final x into ax (read, written)
+            per = face_sp * sp_b(prec) + face_lk * lk_b(prec) + 2 * sp_b(prec);
+            fl = hops_out(g) + CLOVF + 24;
+        }
         const double sites = 0.5 * (double)g.V;
         hipError_t e = timed(c, DD_KT_SAP, sites * (nr * per + stat), sites * nr * fl, [&] {
             return pk ? dd::launch_sap_half_pk(c->g, c->stream, a, colour, flags)
@@ -211,14 +224,22 @@ static dd_status sap_sweeps(dd_ctx *c, int prec, const void *b, void *x, void *s
         if ((st = half(E, (i == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out)) != DD_OK) return st;
         if ((st = half(O, (i == 0 ? (dd::SAP_FIRST | dd::SAP_PRE) : dd::SAP_PRE) | out)) != DD_OK) return st;
     }
-    if ((st = half(E, dd::SAP_TAIL | (n == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out)) != DD_OK) return st;
-    if ((st = half(O, dd::SAP_TAIL | dd::SAP_PRE | (n == 0 ? dd::SAP_FIRST : 0))) != DD_OK) return st;
+    // with ax, the fused tail of Alg. 3: the tails also write their rows of A x, and one more
+    // launch adds the even rows' cross-block term of the final odd x
+    const int am = ax ? dd::SAP_AMSAP : 0;
+    if ((st = half(E, dd::SAP_TAIL | (n == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out | am)) != DD_OK) return st;
+    if ((st = half(O, dd::SAP_TAIL | dd::SAP_PRE | (n == 0 ? dd::SAP_FIRST : 0) | am | (ax ? dd::SAP_AMSAP_PRE : 0))) !=
+        DD_OK)
+        return st;
+    if (ax && (st = half(E, dd::SAP_CROSS_ONLY)) != DD_OK) return st;
     return DD_OK;
 }
 
-dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s)
+dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s, void *ax)
 {
-    return sap_sweeps(c, prec, b, x, s, c->faces, dd::SapRhs{});
+    if (ax && prec != 1)
+        return fail(c, DD_ERR_ARG, "the fused A M_SAP is available with FP32 storage");
+    return sap_sweeps(c, prec, b, x, s, c->faces, dd::SapRhs{}, ax);
 }
 
 dd_status k_sap_batch(dd_ctx *c, const dd::SapRhs &rhs, const void *b, void *x, void *s, void *faces)

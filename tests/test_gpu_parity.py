@@ -136,6 +136,30 @@ def test_sap_fp32(name, n_sap):
     assert rel_l2(got, want) < 1e-5
 
 
+@pytest.mark.parametrize("name,n_sap", [("4^4", 0), ("4^4", 2), ("aniso", 1), ("8^4", 2), ("8^4-twist", 4)])
+def test_amsap_fp32_fused_tail(name, n_sap):
+    """Alg. 3 at FP32: A M_SAP b from the fused tail against the oracle's A(M_SAP b), within the FP32
+    SAP bar, and against the GPU's own FP32 A applied to its M_SAP b (the separate product the
+    fused tail replaces) within FP32 rounding."""
+    c = case(name, n_sap=n_sap)
+    b = c.spinor(11)
+    got = c.solver.amsap(b.cuda(), prec=dd.DD_F32).cpu().numpy()
+    want = c.orc.amsap(b.numpy())
+    assert rel_l2(got, want) < 1e-5
+    mb = c.solver.precondition(b.cuda(), prec=dd.DD_F32)
+    sep = c.solver.apply(mb, op=dd.DD_OP_A, prec=dd.DD_F32).cpu().numpy()
+    assert rel_l2(got, sep) < 2e-6
+
+
+@pytest.mark.parametrize("name", ["4^4", "8^4"])
+def test_amsap_fp16(name):
+    """A M_SAP b with the FP16-storage SAP: the FP32 operator on its FP16-stored output."""
+    c = case(name, fp16_arith=1)
+    b = c.spinor(12)
+    got = c.solver.amsap(b.cuda(), prec=dd.DD_F16).cpu().numpy()
+    assert rel_l2(got, c.orc.amsap(b.numpy())) < 3e-3
+
+
 @pytest.mark.parametrize("fp16_arith", [0, 1])
 @pytest.mark.parametrize("name", ["4^4", "aniso", "8^4", "8^4-twist"])
 def test_sap_fp16_storage(name, fp16_arith):
