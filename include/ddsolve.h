@@ -141,7 +141,18 @@ typedef struct {
                            the basis takes four FP64 and the directions three FP32 work
                            vectors of the context, the first such solve allocates the
                            rest (fgmres_nkv - 3 FP64, fgmres_nkv - 3 FP32 fields)    */
+    int no_fallback;    /* DD_SOLVE_MIXED / DD_SOLVE_MIXED_GCR: 0 (default) falls back in
+                           precision when a defect-correction pass stagnates or its inner
+                           solve breaks down (the mode's FP16-SAP inner solve, then FP32
+                           SAP-BiCGStab, then plain FP64 BiCGStab from the current x);
+                           1 returns DD_BREAKDOWN there instead                       */
+    int debug_flags;    /* forces failures from the host, for tests: DD_DEBUG_ZERO_OMEGA_F16
+                           sets omega = 0 in every FP16-SAP BiCGStab iteration,
+                           DD_DEBUG_ZERO_OMEGA_F32 in every FP32-SAP one (0 = none)   */
 } dd_params;
+
+#define DD_DEBUG_ZERO_OMEGA_F16 1
+#define DD_DEBUG_ZERO_OMEGA_F32 2
 
 typedef struct {
     int iters_outer;          /* defect-correction passes or flexible GMRES iterations
@@ -159,6 +170,9 @@ typedef struct {
     int status;               /* the dd_status of this solve: the return value of a
                                  single solve, this right-hand side's (lattice's) own
                                  outcome in the batched and multi-lattice solves  */
+    int precision_level;      /* inner solver the solve ended with: 0 the mode's own,
+                                 1 FP32 SAP-BiCGStab, 2 plain FP64 BiCGStab (levels
+                                 1 and 2 only after a fallback, see no_fallback)  */
 } dd_solve_info;
 
 typedef struct dd_ctx dd_ctx;
@@ -216,7 +230,12 @@ dd_status sap_precondition_amsap(dd_ctx *ctx, void *ax_dev, const void *b_dev, d
  * DD_SOLVE_F32_SAP; on exit it holds the solution.  maxiter bounds the
  * BiCGStab loop passes of a single-level solve, the defect-correction
  * passes of DD_SOLVE_MIXED and DD_SOLVE_MIXED_GCR, or the outer iterations of
- * DD_SOLVE_FGMRES.  Returns DD_OK, DD_NOT_CONVERGED or DD_BREAKDOWN
+ * DD_SOLVE_FGMRES.  In the two defect-correction modes a pass that
+ * stagnates or whose inner solve breaks down switches the remaining passes to
+ * the FP32 SAP-BiCGStab, and a second such pass to plain FP64 BiCGStab from
+ * the current x, capped at inner_maxiter iterations (unless
+ * dd_params.no_fallback; info->precision_level tells which level ended the
+ * solve).  Returns DD_OK, DD_NOT_CONVERGED or DD_BREAKDOWN
  * (x then holds the best iterate) and fills info (may be NULL).  A source
  * with NaN or Inf returns DD_ERR_NONFINITE without touching x.
  * Synchronises the stream. */

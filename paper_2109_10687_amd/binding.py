@@ -9,6 +9,7 @@ canonical layout (complex128):
 Every step of the solver runs in the HIP library.  There is no fallback: if
 libddsolve.so is missing or fails to load, every call raises.
 """
+import contextlib
 import ctypes
 import math
 import os
@@ -18,10 +19,12 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libddsolve.so")
+LIB_RACE_PATH = os.path.join(HERE, "libddsolve_racecheck.so")
 
 DD_F64, DD_F32, DD_F16 = 0, 1, 2
 DD_OP_D, DD_OP_A, DD_OP_DDAG = 0, 1, 2
 DD_SOLVE_F64_PLAIN, DD_SOLVE_F32_SAP, DD_SOLVE_MIXED, DD_SOLVE_MIXED_GCR, DD_SOLVE_FGMRES = 0, 1, 2, 3, 4
+DD_DEBUG_ZERO_OMEGA_F16, DD_DEBUG_ZERO_OMEGA_F32 = 1, 2
 (DD_KT_DIRAC_F64, DD_KT_DIRAC_F32, DD_KT_DIRAC_F16IN, DD_KT_DIRAC_F16, DD_KT_SAP, DD_KT_BLAS, DD_KT_FORCE,
  DD_KT_DIRAC_MRHS, DD_KT_DIRAC_MULTI) = range(9)
 KERNEL_CLASSES = {"dirac_f64": DD_KT_DIRAC_F64, "dirac_f32": DD_KT_DIRAC_F32, "dirac_f16in": DD_KT_DIRAC_F16IN,
@@ -54,13 +57,15 @@ class _Params(ctypes.Structure):
                 ("csw", ctypes.c_double), ("phase_re", ctypes.c_double * 4), ("phase_im", ctypes.c_double * 4),
                 ("n_sap", ctypes.c_int), ("n_jac", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("inner_maxiter", ctypes.c_int), ("gcr_nkv", ctypes.c_int), ("sap_fp16_arith", ctypes.c_int),
-                ("stall_window", ctypes.c_int), ("sap_separate_tail", ctypes.c_int), ("fgmres_nkv", ctypes.c_int)]
+                ("stall_window", ctypes.c_int), ("sap_separate_tail", ctypes.c_int), ("fgmres_nkv", ctypes.c_int),
+                ("no_fallback", ctypes.c_int), ("debug_flags", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("iters_outer", ctypes.c_int), ("iters_inner_total", ctypes.c_int),
                 ("relres_true", ctypes.c_double), ("relres_inner_last", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("status_detail", ctypes.c_int), ("status", ctypes.c_int)]
+                ("seconds", ctypes.c_double), ("status_detail", ctypes.c_int), ("status", ctypes.c_int),
+                ("precision_level", ctypes.c_int)]
 
 
 _LIB = None
@@ -70,54 +75,71 @@ def lib():
     """Load libddsolve.so; raises when it has not been built."""
     global _LIB
     if _LIB is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
-                               "or python paper_2109_10687_amd/build.py")
-        L = ctypes.CDLL(LIB_PATH)
-        vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
-        sig = {
-            "dd_create": (i, [ctypes.POINTER(_Params), vp, ctypes.POINTER(vp)]),
-            "dd_destroy": (i, [vp]),
-            "dd_load_gauge": (i, [vp, vp]),
-            "dirac_apply": (i, [vp, vp, vp, i, i]),
-            "sap_precondition": (i, [vp, vp, vp, i]),
-            "sap_precondition_amsap": (i, [vp, vp, vp, i]),
-            "bicgstab_solve": (i, [vp, vp, vp, d, i, i, ctypes.POINTER(_Info)]),
-            "dd_last_error": (ctypes.c_char_p, [vp]),
-            "dd_solve_history": (i, [vp, i, ctypes.POINTER(d), i, ctypes.POINTER(i)]),
-            "dd_field_bytes": (ll, [vp, i]),
-            "dd_pack_spinor": (i, [vp, vp, vp, i]),
-            "dd_unpack_spinor": (i, [vp, vp, vp, i]),
-            "dirac_apply_packed": (i, [vp, vp, vp, i, i]),
-            "dirac_apply_packed_f16in": (i, [vp, vp, vp]),
-            "dd_timing_enable": (i, [vp, i]),
-            "dd_timing_query": (i, [vp, i, ctypes.POINTER(ll), ctypes.POINTER(d), ctypes.POINTER(d),
-                                    ctypes.POINTER(d)]),
-            "bicgstab_solve_dagger": (i, [vp, vp, vp, d, i, i, ctypes.POINTER(_Info)]),
-            "dd_spinor_norm2": (i, [vp, vp, ctypes.POINTER(d)]),
-            "dd_set_csw": (i, [vp, d]),
-            "dd_force": (i, [vp, vp, ctypes.POINTER(d), vp, vp, i]),
-            "dd_force_noalloc": (i, [vp, vp, ctypes.POINTER(d), vp, vp, i]),
-            "dirac_apply_batch": (i, [vp, vp, vp, i, i, i]),
-            "dd_batch_set_variant": (i, [vp, i]),
-            "sap_precondition_batch": (i, [vp, vp, vp, i]),
-            "dd_batch_tuning": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(d), i]),
-            "dd_batch_variant_name": (ctypes.c_char_p, [i]),
-            "bicgstab_solve_batch": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(_Info)]),
-            "dd_multi_create": (i, [ctypes.POINTER(_Params), i, vp, ctypes.POINTER(vp)]),
-            "dd_multi_destroy": (i, [vp]),
-            "dd_multi_last_error": (ctypes.c_char_p, [vp]),
-            "dd_multi_context": (vp, [vp, i]),
-            "dd_multi_load_gauge": (i, [vp, i, vp]),
-            "dirac_apply_multi": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
-            "bicgstab_solve_multi": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), d, i, ctypes.POINTER(_Info)]),
-        }
-        for name, (res, args) in sig.items():
-            f = getattr(L, name)
-            f.restype = res
-            f.argtypes = args
-        _LIB = L
+        _LIB = _load(LIB_PATH)
     return _LIB
+
+
+@contextlib.contextmanager
+def use_library(path):
+    """Route every call of this module to another build of the library (the LDS race-check
+    build, LIB_RACE_PATH) inside the with block; contexts made there belong to that build."""
+    global _LIB
+    saved = lib()
+    _LIB = _load(path)
+    try:
+        yield _LIB
+    finally:
+        _LIB = saved
+
+
+def _load(path):
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is not built; run __graft_entry__.build() "
+                           "or python paper_2109_10687_amd/build.py")
+    L = ctypes.CDLL(path)
+    vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    sig = {
+        "dd_create": (i, [ctypes.POINTER(_Params), vp, ctypes.POINTER(vp)]),
+        "dd_destroy": (i, [vp]),
+        "dd_load_gauge": (i, [vp, vp]),
+        "dirac_apply": (i, [vp, vp, vp, i, i]),
+        "sap_precondition": (i, [vp, vp, vp, i]),
+        "sap_precondition_amsap": (i, [vp, vp, vp, i]),
+        "bicgstab_solve": (i, [vp, vp, vp, d, i, i, ctypes.POINTER(_Info)]),
+        "dd_last_error": (ctypes.c_char_p, [vp]),
+        "dd_solve_history": (i, [vp, i, ctypes.POINTER(d), i, ctypes.POINTER(i)]),
+        "dd_field_bytes": (ll, [vp, i]),
+        "dd_pack_spinor": (i, [vp, vp, vp, i]),
+        "dd_unpack_spinor": (i, [vp, vp, vp, i]),
+        "dirac_apply_packed": (i, [vp, vp, vp, i, i]),
+        "dirac_apply_packed_f16in": (i, [vp, vp, vp]),
+        "dd_timing_enable": (i, [vp, i]),
+        "dd_timing_query": (i, [vp, i, ctypes.POINTER(ll), ctypes.POINTER(d), ctypes.POINTER(d),
+                                ctypes.POINTER(d)]),
+        "bicgstab_solve_dagger": (i, [vp, vp, vp, d, i, i, ctypes.POINTER(_Info)]),
+        "dd_spinor_norm2": (i, [vp, vp, ctypes.POINTER(d)]),
+        "dd_set_csw": (i, [vp, d]),
+        "dd_force": (i, [vp, vp, ctypes.POINTER(d), vp, vp, i]),
+        "dd_force_noalloc": (i, [vp, vp, ctypes.POINTER(d), vp, vp, i]),
+        "dirac_apply_batch": (i, [vp, vp, vp, i, i, i]),
+        "dd_batch_set_variant": (i, [vp, i]),
+        "sap_precondition_batch": (i, [vp, vp, vp, i]),
+        "dd_batch_tuning": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(d), i]),
+        "dd_batch_variant_name": (ctypes.c_char_p, [i]),
+        "bicgstab_solve_batch": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(_Info)]),
+        "dd_multi_create": (i, [ctypes.POINTER(_Params), i, vp, ctypes.POINTER(vp)]),
+        "dd_multi_destroy": (i, [vp]),
+        "dd_multi_last_error": (ctypes.c_char_p, [vp]),
+        "dd_multi_context": (vp, [vp, i]),
+        "dd_multi_load_gauge": (i, [vp, i, vp]),
+        "dirac_apply_multi": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "bicgstab_solve_multi": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), d, i, ctypes.POINTER(_Info)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
 
 
 @dataclass
@@ -137,6 +159,8 @@ class Params:
     stall_window: int = 200
     sap_separate_tail: int = 0
     fgmres_nkv: int = 4
+    no_fallback: int = 0
+    debug_flags: int = 0
 
     def c(self):
         p = _Params()
@@ -157,6 +181,8 @@ class Params:
         p.stall_window = int(self.stall_window)
         p.sap_separate_tail = int(self.sap_separate_tail)
         p.fgmres_nkv = int(self.fgmres_nkv)
+        p.no_fallback = int(self.no_fallback)
+        p.debug_flags = int(self.debug_flags)
         return p
 
     @property

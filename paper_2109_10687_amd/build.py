@@ -3,6 +3,11 @@
 All device code is compiled for gfx950 only.  Packed FP32 instructions are
 switched off (-packed-fp32-ops) for the device pass; hipcc's host pass prints a
 harmless warning that it does not know that feature.
+
+A second library, libddsolve_racecheck.so, links the same host objects with the
+kernels built under -DDD_RACE_CHECK=1 (the wavefronts of every LDS-sharing
+workgroup run each phase between barriers in reverse order); its results must
+equal the product library's bit for bit.
 """
 import os
 import subprocess
@@ -11,6 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddsolve.so")
+LIB_RACE = os.path.join(HERE, "libddsolve_racecheck.so")
 SOURCES = ["dd_kernels.hip", "dd_sap_fp16.hip", "dd_force.hip", "dd_mrhs.hip",
            "dd_ops.cpp", "dd_solvers.cpp", "dd_batch.cpp", "dd_capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -32,20 +38,25 @@ def _run(cmd, verbose):
 
 
 def build(verbose=False, jobs=None):
-    """Compile every source to an object, then link libddsolve.so."""
+    """Compile every source to an object, then link libddsolve.so and libddsolve_racecheck.so."""
     from concurrent.futures import ThreadPoolExecutor
-    objs = []
-    cmds = []
+    objs, race_objs, cmds = [], [], []
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        objs.append(obj)
-        cmds.append([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
-    with ThreadPoolExecutor(max_workers=jobs or len(cmds)) as ex:
+        stem = os.path.join(CSRC, os.path.splitext(src)[0])
+        objs.append(stem + ".o")
+        cmds.append([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", stem + ".o"])
+        if src.endswith(".hip"):  # the kernels; the .cpp files hold host code only
+            race_objs.append(stem + "_race.o")
+            cmds.append([HIPCC] + FLAGS + ["-DDD_RACE_CHECK=1", "-c", os.path.join(CSRC, src), "-o", stem + "_race.o"])
+        else:
+            race_objs.append(stem + ".o")
+    with ThreadPoolExecutor(max_workers=jobs or min(len(cmds), os.cpu_count() or 8)) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs +
-         ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"], verbose)
-    os.replace(LIB + ".tmp", LIB)
-    for o in objs:
+    for lib, ob in ((LIB, objs), (LIB_RACE, race_objs)):
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib + ".tmp"] + ob +
+             ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"], verbose)
+        os.replace(lib + ".tmp", lib)
+    for o in set(objs + race_objs):
         os.remove(o)
     return LIB
 

@@ -301,6 +301,24 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
         if (bn2 > 0) c->hist_outer.push_back(std::sqrt(rn2 / bn2));
         double prev = rn2;
         int stall = 0, outer = 0;
+        // 0: the mode's own inner solver (FP16 SAP), 1: FP32 SAP-BiCGStab, 2: plain FP64 BiCGStab
+        int level = 0;
+        // a stagnating pass or a broken-down inner solve: fall back one level, or stop
+        auto give_up = [&](int detail) -> bool {
+            if (c->prm.no_fallback || level == 2) {
+                inf.status_detail = detail;
+                res = DD_BREAKDOWN;
+                return true;
+            }
+            ++level;
+            stall = 0;
+            if (c->verbose) {
+                std::fprintf(stderr, "[ddsolve] falling back to %s after outer pass %d\n",
+                             level == 1 ? "FP32 SAP-BiCGStab" : "plain FP64 BiCGStab", outer);
+                std::fflush(stderr);
+            }
+            return false;
+        };
         res = DD_NOT_CONVERGED;
         if (bn2 == 0.0) HIPCK(c, hipMemsetAsync(x, 0, spinor_bytes(c->g, DD_F64), c->stream));
         while (true) {
@@ -309,6 +327,24 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
                 break;
             }
             if (outer >= maxiter) break;
+            if (level == 2) {
+                // the last level: plain FP64 BiCGStab on D x = b from the current x
+                SolveOut o;
+                Range pass("ddsolve: FP64 fallback solve");
+                dd_status sp = solve_plain64(c, x, b, tol, c->prm.inner_maxiter, o);
+                if (sp < 0) return sp;
+                ++outer;
+                inf.iters_inner_total += o.iters;
+                inf.relres_inner_last = o.relres;
+                if ((st = residual64(c, r, b, x, tmp, &rn2)) != DD_OK) return st;
+                c->hist_outer.push_back(std::sqrt(rn2 / bn2));
+                if (sp != DD_OK || std::sqrt(rn2 / bn2) >= tol) {
+                    res = sp == DD_OK ? DD_NOT_CONVERGED : sp;
+                    inf.status_detail = o.detail;
+                    break;
+                }
+                continue;
+            }
             double err = std::sqrt(rn2);
             if ((st = blas(c, mkb(dd::BLAS_CINV_SRC, {src, r, c->cinv32}, {1, 0}, {1.0 / err}))) != DD_OK) return st;
             // each pass reduces the residual by inner_tol, except that the last
@@ -317,8 +353,9 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
             const double itol = need > c->prm.inner_tol ? (need < 0.1 ? need : 0.1) : c->prm.inner_tol;
             SolveOut o;
             Range pass("ddsolve: defect-correction pass");
-            dd_status si = mode == DD_SOLVE_MIXED_GCR ? solve_gcr32(c, src, y, itol, c->prm.inner_maxiter, o)
-                                                      : solve_sap32(c, 2, src, y, itol, c->prm.inner_maxiter, o);
+            dd_status si = level == 1                    ? solve_sap32(c, 1, src, y, itol, c->prm.inner_maxiter, o)
+                           : mode == DD_SOLVE_MIXED_GCR ? solve_gcr32(c, src, y, itol, c->prm.inner_maxiter, o)
+                                                        : solve_sap32(c, 2, src, y, itol, c->prm.inner_maxiter, o);
             if (si < 0) return si;
             inf.iters_inner_total += o.iters;
             inf.relres_inner_last = o.relres;
@@ -327,12 +364,11 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
             ++outer;
             if (!is_fin(rn2) || rn2 >= prev) {
                 // the correction made the true residual worse (inner solve failed):
-                // take it back, so x stays the best iterate, and stop
+                // take it back, so x stays the best iterate
                 if ((st = blas(c, mkb(dd::BLAS_AXPBY, {y, x}, {1, 0}, {-err, 1.0}))) != DD_OK) return st;
                 if ((st = residual64(c, r, b, x, tmp, &rn2)) != DD_OK) return st;
-                inf.status_detail = is_fin(rn2) ? DETAIL_OUTER_STALL : 4;
-                res = DD_BREAKDOWN;
-                break;
+                if (give_up(is_fin(rn2) ? DETAIL_OUTER_STALL : 4)) break;
+                continue;
             }
             c->hist_outer.push_back(std::sqrt(rn2 / bn2));
             if (c->verbose) {
@@ -340,22 +376,27 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
                              "true residual %.3e\n", outer, o.iters, itol, o.relres, std::sqrt(rn2 / bn2));
                 std::fflush(stderr);
             }
-            if (o.detail == DETAIL_INNER_STALL && rn2 > 1e-2 * prev) {
-                // the inner solve stagnated and its pass gained less than 10x: further
-                // passes would crawl at that rate
-                inf.status_detail = DETAIL_INNER_STALL;
-                res = DD_BREAKDOWN;
-                break;
+            if (si == DD_BREAKDOWN && std::sqrt(rn2 / bn2) >= tol) {
+                // the inner solve broke down or stagnated (its stall window): the next passes
+                // run one level up; without the fallback, a stagnated pass that gained less
+                // than 10x ends the solve (further passes would crawl at that rate)
+                if (!c->prm.no_fallback && level < 2) {
+                    prev = rn2;
+                    give_up(o.detail);
+                    continue;
+                }
+                if (o.detail == DETAIL_INNER_STALL && rn2 > 1e-2 * prev) {
+                    inf.status_detail = DETAIL_INNER_STALL;
+                    res = DD_BREAKDOWN;
+                    break;
+                }
             }
             stall = rn2 > 0.81 * prev ? stall + 1 : 0;  // |r| fell by less than 10%
             prev = rn2;
-            if (stall >= 2) {
-                inf.status_detail = DETAIL_OUTER_STALL;
-                res = DD_BREAKDOWN;
-                break;
-            }
+            if (stall >= 2 && give_up(DETAIL_OUTER_STALL)) break;
         }
         inf.iters_outer = outer;
+        inf.precision_level = level;
     }
     // true FP64 residual of the returned x
     {

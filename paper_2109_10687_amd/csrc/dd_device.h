@@ -29,6 +29,34 @@ namespace dd {
 #define DD_INL __device__ __forceinline__
 #define DD_HDI __host__ __device__ __forceinline__
 
+// ------------------------------------------------------------------ LDS race check
+// Compiled with -DDD_RACE_CHECK=n (n > 0), the kernels that share LDS between the
+// wavefronts of a workgroup let wavefront w of W wait n*(W-1-w) sleep periods (about
+// 3.4 us each) at entry and after every workgroup barrier, so the wavefronts run each
+// phase between barriers in the reverse of their usual order.  A missing barrier then
+// changes what a wavefront reads; the results of such a build must equal the normal
+// build's bit for bit.  n = 0 (the product build) compiles the waits away.
+#ifndef DD_RACE_CHECK
+#define DD_RACE_CHECK 0
+#endif
+
+DD_INL void wg_skew()
+{
+    if constexpr (DD_RACE_CHECK > 0) {
+        const unsigned nthr = blockDim.x * blockDim.y * blockDim.z;
+        const unsigned tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+        const int nw = (int)((nthr + 63) >> 6), w = (int)(tid >> 6);
+        for (int i = 0; i < (nw - 1 - w) * DD_RACE_CHECK; ++i) __builtin_amdgcn_s_sleep(127);
+    }
+}
+
+// workgroup barrier (plus the race check's wait)
+DD_INL void wg_barrier()
+{
+    __syncthreads();
+    wg_skew();
+}
+
 // ------------------------------------------------------------------ complex
 template <typename R>
 struct cx {

@@ -331,6 +331,7 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
     __shared__ T tile[12][256];                     // this block's input
     __shared__ float tsc[PIN == 2 ? 256 : 1];
     __shared__ cx<R> carry[2][6][64];               // backward t hop terms, by step parity
+    wg_skew();
     const int ncol = g.bstride[3];
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     const int seg = w / ncol, col = w - seg * ncol;  // consecutive items: neighbouring columns
@@ -359,7 +360,7 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
             for (int e = 0; e < 12; ++e) tile[e][sl] = own.e[e];
             if constexpr (PIN == 2) tsc[sl] = own.sc;
         }
-        __syncthreads();
+        wg_barrier();
         Spinor<R> acc;
         zero(acc);
 #pragma unroll
@@ -431,7 +432,7 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
 #pragma unroll
                 for (int c = 0; c < 3; ++c) carry[(k + 1) & 1][a * 3 + c][sl - 192] = kk.v[a][c];
         }
-        __syncthreads();
+        wg_barrier();
     }
 }
 
@@ -447,9 +448,9 @@ __global__ void __launch_bounds__(256) k_dirac_multi(const LatDesc *desc, int nl
     __shared__ int item_s;
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
-        __syncthreads();
+        wg_barrier();
         const int item = item_s;
-        __syncthreads();
+        wg_barrier();
         if (item >= total) break;
         int lat = 0;
         while (lat + 1 < nlat && item >= desc[lat + 1].item0) ++lat;
@@ -566,6 +567,7 @@ __global__ void __launch_bounds__(256) k_sap_half(Geom gin, int colour, int flag
     const int bvol = g.bvol;
     float2 *xs = reinterpret_cast<float2 *>(smem_raw);
     LT *ul = reinterpret_cast<LT *>(xs + 12 * bvol);
+    wg_skew();
 
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     Site st;
@@ -632,9 +634,9 @@ __global__ void __launch_bounds__(256) k_sap_half(Geom gin, int colour, int flag
 
     Spinor<float> x = src;
     for (int j = 0; j < n_jac; ++j) {
-        __syncthreads();  // previous readers of xs are done (and links staged)
+        wg_barrier();  // previous readers of xs are done (and links staged)
         lds_store_spinor(xs, bvol, st.s, x);
-        __syncthreads();
+        wg_barrier();
         inblock_hops<P>(xs, lk, ul, g, st, acc);
         clover_mul(cl, acc, t);
 #pragma unroll
@@ -643,9 +645,9 @@ __global__ void __launch_bounds__(256) k_sap_half(Geom gin, int colour, int flag
             for (int c = 0; c < 3; ++c) x.v[a][c] = src.v[a][c] + kappa * t.v[a][c];
     }
     if (!(flags & SAP_TAIL)) {
-        __syncthreads();
+        wg_barrier();
         lds_store_spinor(xs, bvol, st.s, x);
-        __syncthreads();
+        wg_barrier();
         inblock_hops<P>(xs, lk, ul, g, st, acc);
         clover_mul(cl, acc, t);
         Spinor<float> b;
@@ -661,9 +663,9 @@ __global__ void __launch_bounds__(256) k_sap_half(Geom gin, int colour, int flag
         // in-block hops of the final x, and with AMSAP_PRE the hops from the other colour's final
         // x, the same ones this launch's prologue read (formed again here rather than kept
         // through the sweeps), all under one C_inv product as in the Dirac apply
-        __syncthreads();
+        wg_barrier();
         lds_store_spinor(xs, bvol, st.s, x);
-        __syncthreads();
+        wg_barrier();
         inblock_hops<P>(xs, lk, ul, g, st, acc);
         if (flags & SAP_AMSAP_PRE) cross_hops(acc);
         clover_mul(cl, acc, t);
@@ -721,13 +723,13 @@ __global__ void __launch_bounds__(256) k_finalize(const double *partials, int nw
         double t = 0;
         for (int w = threadIdx.x; w < nwg; w += 256) t += partials[(long long)w * nv + k];
         sh[threadIdx.x] = t;
-        __syncthreads();
+        wg_barrier();
         for (int h = 128; h >= 1; h >>= 1) {
             if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-            __syncthreads();
+            wg_barrier();
         }
         if (threadIdx.x == 0) out[k] = sh[0];
-        __syncthreads();
+        wg_barrier();
     }
 }
 
@@ -990,7 +992,7 @@ template <int NV> DD_INL void wg_reduce_store_dyn(double (&v)[NV], int nv, doubl
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0)
         for (int q = 0; q < nv; ++q) red[q][wave] = v[q];
-    __syncthreads();
+    wg_barrier();
     if (threadIdx.x == 0)
         for (int q = 0; q < nv; ++q) {
             double t = 0;

@@ -151,7 +151,7 @@ template <int NV> DD_INL void wg_reduce_store(double (&v)[NV], double *partials)
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
-    __syncthreads();
+    wg_barrier();
     if (threadIdx.x == 0)
 #pragma unroll
         for (int k = 0; k < NV; ++k) {

@@ -526,6 +526,7 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
     h2 *ul = reinterpret_cast<h2 *>(xs + 3 * bvol);         // 36 x bvol half2
     __shared__ float wmax[4];
     const int P = face_offset(g, 3, 1) + (bvol >> log2b(g, 3));  // face sites of a block
+    wg_skew();
 
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     Site st;
@@ -551,7 +552,7 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
     const bool pre = (flags & SAP_PRE) != 0;
 
     for (int ri = 0; ri < rhs.n; ++ri) {
-        if (ri > 0) __syncthreads();  // the previous right-hand side is done with LDS
+        if (ri > 0) wg_barrier();  // the previous right-hand side is done with LDS
         const long long off = (long long)rhs.idx[ri] * rhs.sp_stride;
         const SpinorField<2> b_r = rhs_field(bsrc, off), s_r = rhs_field(sw, off), x_r = rhs_field(xw, off);
         h2 *ft_r = (h2 *)((char *)ft + (long long)rhs.idx[ri] * rhs.face_stride);
@@ -610,7 +611,7 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
         const int wv = bvol < 64 ? bvol : 64;  // lanes of this workgroup in one wavefront
         for (int o2 = wv / 2; o2 >= 1; o2 >>= 1) m = fmaxf(m, __shfl_xor(m, o2, wv));
         if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-        __syncthreads();  // also: every link is staged
+        wg_barrier();  // also: every link is staged
         m = 0.f;
         for (int q = 0; q < (bvol + 63) / 64; ++q) m = fmaxf(m, wmax[q]);
         const float sc = m > 0.f ? 1.f / m : 0.f;
@@ -632,9 +633,9 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
         }
         x = x0;
         for (int j = 0; j < n_jac; ++j) {
-            __syncthreads();
+            wg_barrier();
             lds_put(xs, bvol, st.s, x);
-            __syncthreads();
+            wg_barrier();
             inblock_pair(xs, ul, g, bvol, st, acc);
             clover_pair(CP, acc, t);
 #pragma unroll
@@ -646,9 +647,9 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
         const float inv = m;  // undo the normalisation
         if (!(flags & SAP_TAIL)) {
             // s_c <- (s_c + kappa C_inv h) + b_c - x_c + kappa C_inv H_in x_c, in FP32
-            __syncthreads();
+            wg_barrier();
             lds_put(xs, bvol, st.s, x);
-            __syncthreads();
+            wg_barrier();
             inblock_pair(xs, ul, g, bvol, st, acc);
             clover_pair(CP, acc, t);
             SpH braw;
@@ -661,14 +662,14 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
             from_pair(x, inv, xf);
             x_r.store(g, st.l, st.s, xf);
             if (flags & SAP_FACES_OUT) {
-                __syncthreads();
+                wg_barrier();
                 lds_put(xs, bvol, st.s, x);
             }
         }
         if (flags & SAP_FACES_OUT) {
             // this block's face terms from x in LDS (put there by the s update, or just above),
             // spread evenly over the workgroup
-            __syncthreads();
+            wg_barrier();
             const bool equal_faces = g.b[0] == g.b[1] && g.b[1] == g.b[2] && g.b[2] == g.b[3];
             const int lnf = g.lbvol - log2b(g, 0);  // log2 of the sites per face
             for (int p = threadIdx.x; p < P; p += bvol) {

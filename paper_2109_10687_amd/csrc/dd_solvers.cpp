@@ -187,6 +187,7 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
             return DD_BREAKDOWN;
         }
         cplx omega = cplx(d[0], d[1]) / d[2];
+        if (c->prm.debug_flags & (prec == 2 ? DD_DEBUG_ZERO_OMEGA_F16 : DD_DEBUG_ZERO_OMEGA_F32)) omega = 0.0;
         if (fused)
             st = reduce(c, mkb(dd::BLAS_UPDATE2_MM, {y, Mp, Mr, r, t, rt}, {1, prec, 1, 1, 1, 1},
                                {alpha.real(), alpha.imag(), omega.real(), omega.imag()}),

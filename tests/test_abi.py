@@ -110,6 +110,13 @@ def test_binding_structs_follow_the_header():
     assert [f for f, _ in dd.binding._Info._fields_] == struct_fields("dd_solve_info")
 
 
+def test_debug_flags_follow_the_header():
+    src = open(os.path.join(ROOT, "include", "ddsolve.h")).read()
+    defs = dict(re.findall(r"#define (DD_DEBUG_\w+)\s+(\d+)", src))
+    assert defs == {"DD_DEBUG_ZERO_OMEGA_F16": str(dd.DD_DEBUG_ZERO_OMEGA_F16),
+                    "DD_DEBUG_ZERO_OMEGA_F32": str(dd.DD_DEBUG_ZERO_OMEGA_F32)}
+
+
 def test_batch_variant_names():
     names = [dd.dd_batch_variant_name(v) for v in range(12)]
     assert all(n and n != "?" for n in names) and len(set(names)) == 12

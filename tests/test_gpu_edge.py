@@ -132,6 +132,37 @@ def test_fgmres_cycle_of_one_restarts_and_maxiter_caps():
     assert info["status"] == "DD_NOT_CONVERGED" and info["iters_outer"] == 1 and info["relres_true"] < 1e-3
 
 
+@pytest.mark.parametrize("flags,level", [(0, 0), (dd.DD_DEBUG_ZERO_OMEGA_F16, 1),
+                                         (dd.DD_DEBUG_ZERO_OMEGA_F16 | dd.DD_DEBUG_ZERO_OMEGA_F32, 2)])
+def test_precision_fallback_after_forced_breakdown(flags, level):
+    """omega forced to zero from the host in every FP16-SAP inner iteration (and in every FP32-SAP
+    one): the first pass of each level breaks down, the solve falls back to FP32 SAP-BiCGStab (then
+    to plain FP64 BiCGStab) and still reaches 1e-10, checked by the oracle's residual."""
+    dims, kappa, csw = (8, 8, 8, 8), 0.13, 1.5
+    U = synth.su3_links(dims, 0.3, 41)
+    s = dd.Solver(dd.Params(dims=dims, kappa=kappa, csw=csw, debug_flags=flags), U.cuda())
+    b = synth.gaussian_spinor(dims, 42)
+    x, info = s.solve(b.cuda(), tol=1e-10, maxiter=20, mode=dd.DD_SOLVE_MIXED)
+    assert info["status"] == "DD_OK" and info["precision_level"] == level, info
+    orc = O.Oracle(O.Params(dims=dims, kappa=kappa, csw=csw, block=(4, 4, 4, 4)), U.numpy())
+    r = b.numpy() - orc.D(x.cpu().numpy())
+    assert np.linalg.norm(r.ravel()) / np.linalg.norm(b.numpy().ravel()) < 1e-10
+    h = s.history()["outer"]
+    assert all(h[i + 1] < h[i] for i in range(len(h) - 1))
+
+
+def test_forced_breakdown_without_fallback_is_reported():
+    """With no_fallback the forced inner breakdowns stay at the FP16 SAP: the solve keeps its best
+    iterate and reports DD_NOT_CONVERGED or DD_BREAKDOWN, never DD_OK, within maxiter passes."""
+    dims = (8, 8, 8, 8)
+    p = dd.Params(dims=dims, kappa=0.13, csw=1.5, no_fallback=1, debug_flags=dd.DD_DEBUG_ZERO_OMEGA_F16)
+    s = dd.Solver(p, synth.su3_links(dims, 0.3, 41, device="cuda"))
+    b = synth.gaussian_spinor(dims, 42, device="cuda")
+    x, info = s.solve(b, tol=1e-10, maxiter=4, mode=dd.DD_SOLVE_MIXED)
+    assert info["status"] in ("DD_NOT_CONVERGED", "DD_BREAKDOWN") and info["precision_level"] == 0, info
+    assert info["iters_outer"] <= 4 and info["relres_true"] <= 1.0
+
+
 def test_operator_precision_combinations_and_state():
     p = dd.Params(dims=(8, 8, 8, 8), kappa=0.13, csw=1.0)
     s = dd.Solver(p)
