@@ -134,9 +134,10 @@ typedef struct {
     int stall_window;   /* an inner FP32 solve stops (status detail 6) when its recursive
                            residual has not fallen 10x below the last such point within
                            this many iterations (0 = 200; negative = never)          */
-    int sap_separate_tail; /* FP32 SAP (DD_SOLVE_F32_SAP): 0 forms A M_SAP by the fused tail of
-                           Alg. 3; 1 applies A separately to the SAP's output (the same
-                           product, other rounding order)                            */
+    int sap_fused_tail; /* FP32 SAP-BiCGStab (DD_SOLVE_F32_SAP and the first fallback level):
+                           1 forms A M_SAP by the fused tail of Alg. 3; 0 (default, as fast or
+                           faster where measured) applies A separately to the SAP's output
+                           (the same product, other rounding order)                  */
     int fgmres_nkv;     /* flexible GMRES cycle length for DD_SOLVE_FGMRES, 1..16 (0 = 4);
                            the basis takes four FP64 and the directions three FP32 work
                            vectors of the context, the first such solve allocates the

@@ -57,7 +57,7 @@ class _Params(ctypes.Structure):
                 ("csw", ctypes.c_double), ("phase_re", ctypes.c_double * 4), ("phase_im", ctypes.c_double * 4),
                 ("n_sap", ctypes.c_int), ("n_jac", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("inner_maxiter", ctypes.c_int), ("gcr_nkv", ctypes.c_int), ("sap_fp16_arith", ctypes.c_int),
-                ("stall_window", ctypes.c_int), ("sap_separate_tail", ctypes.c_int), ("fgmres_nkv", ctypes.c_int),
+                ("stall_window", ctypes.c_int), ("sap_fused_tail", ctypes.c_int), ("fgmres_nkv", ctypes.c_int),
                 ("no_fallback", ctypes.c_int), ("debug_flags", ctypes.c_int)]
 
 
@@ -157,7 +157,7 @@ class Params:
     gcr_nkv: int = 16
     sap_fp16_arith: int = 1
     stall_window: int = 200
-    sap_separate_tail: int = 0
+    sap_fused_tail: int = 0
     fgmres_nkv: int = 4
     no_fallback: int = 0
     debug_flags: int = 0
@@ -179,7 +179,7 @@ class Params:
         p.gcr_nkv = int(self.gcr_nkv)
         p.sap_fp16_arith = int(self.sap_fp16_arith)
         p.stall_window = int(self.stall_window)
-        p.sap_separate_tail = int(self.sap_separate_tail)
+        p.sap_fused_tail = int(self.sap_fused_tail)
         p.fgmres_nkv = int(self.fgmres_nkv)
         p.no_fallback = int(self.no_fallback)
         p.debug_flags = int(self.debug_flags)

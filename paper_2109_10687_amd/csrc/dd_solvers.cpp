@@ -141,9 +141,9 @@ dd_status solve_sap32(dd_ctx *c, int prec, void *src, void *y, double tol, int m
             if (!fused && (s2 = copy(c, in16, 2, in, 1)) != DD_OK) return s2;
             bsrc = in16;
         }
-        // FP32 SAP: A M_SAP by the fused tail of Alg. 3; FP16 SAP: the FP32 operator applied to
-        // the FP16-stored M output (the inner recursion needs A to FP32 accuracy)
-        if (prec == 1 && !c->prm.sap_separate_tail) return k_sap(c, 1, bsrc, Mout, s, Aout);
+        // FP32 SAP: A M_SAP by the fused tail of Alg. 3 when asked for; FP16 SAP: the FP32 operator
+        // applied to the FP16-stored M output (the inner recursion needs A to FP32 accuracy)
+        if (prec == 1 && c->prm.sap_fused_tail) return k_sap(c, 1, bsrc, Mout, s, Aout);
         if ((s2 = k_sap(c, prec, bsrc, Mout, s)) != DD_OK) return s2;
         return k_dirac(c, Aout, Mout, prec, 1, 1, 1);
     };

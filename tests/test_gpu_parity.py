@@ -43,13 +43,13 @@ def rel_max(a, b):
 
 
 class Case:
-    def __init__(self, name, n_sap=2, n_jac=4, seed=101, fp16_arith=0):
+    def __init__(self, name, n_sap=2, n_jac=4, seed=101, fp16_arith=0, fused_tail=0):
         dims, block, kappa, csw, eps, phases = CASES[name]
         self.name = name
         self.U = synth.su3_links(dims, eps, seed)
         self.op = O.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases, n_sap=n_sap, n_jac=n_jac)
         self.gp = dd.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases, n_sap=n_sap, n_jac=n_jac,
-                            sap_fp16_arith=fp16_arith)
+                            sap_fp16_arith=fp16_arith, sap_fused_tail=fused_tail)
         self.orc = O.Oracle(self.op, self.U.numpy())
         self.solver = dd.Solver(self.gp, self.U.cuda())
 
@@ -192,9 +192,11 @@ def test_solve_plain_fp64(name):
     assert rel_l2(xn, ref.x) < 1e-7
 
 
+@pytest.mark.parametrize("fused_tail", [0, 1])
 @pytest.mark.parametrize("name", ["4^4", "8^4", "8^4-twist"])
-def test_solve_fp32_sap(name):
-    c = case(name)
+def test_solve_fp32_sap(name, fused_tail):
+    """FP32 SAP-BiCGStab, A M_SAP applied separately to the SAP output or by the fused tail of Alg. 3."""
+    c = case(name, fused_tail=fused_tail)
     b = c.spinor(8)
     x, info = c.solver.solve(b.cuda(), tol=1e-6, maxiter=500, mode=dd.DD_SOLVE_F32_SAP)
     assert info["status"] == "DD_OK", info
