@@ -197,6 +197,22 @@ def test_nonfinite_gauge_field_is_rejected():
     assert e.value.status == -5
 
 
+def test_lattice_beyond_device_memory_is_refused_and_released():
+    """96^3 x 128 needs about 530 GB of fields against the 288 GB of one MI355X: dd_create fails
+    part-way with DD_ERR_NOMEM, frees what it had allocated, and a context made afterwards works."""
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    with pytest.raises(dd.DDError) as e:
+        dd.dd_create(dd.Params(dims=(96, 96, 96, 128), kappa=0.13, csw=1.7))
+    assert e.value.status == -4
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 > free0 - (1 << 30)  # nothing of the failed context is left behind
+    s, U = make((8, 8, 8, 8))
+    x = synth.gaussian_spinor((8, 8, 8, 8), 9, device="cuda")
+    assert torch.isfinite(s.apply(x, op=dd.DD_OP_D, prec=dd.DD_F64)).all()
+
+
 def test_minimal_lattice_one_block_pair_per_direction():
     """The smallest legal geometry: two blocks per direction."""
     dims = (4, 4, 4, 4)
