@@ -287,7 +287,8 @@ dd_status dd_set_csw(dd_ctx *ctx, double csw);
  *     Hermitian F with dL = tr(omega F) for U -> exp(i omega) U, omega
  *     Hermitian (the force projected to su(3)).
  *   dcsw: host pointer receiving dL/dc_SW = -2 Re <chi| (C / c_SW) psi>, or
- *     NULL to skip it.
+ *     NULL to skip it (formed from the clover blocks already built when
+ *     c_SW != 0, from the four-leaf field strength when c_SW = 0).
  * The hop term carries the boundary phases; the clover term differentiates
  * every leaf through the link (24 per link).  FP64 throughout.  The first
  * call allocates a work field of 864 bytes per site, kept until dd_destroy

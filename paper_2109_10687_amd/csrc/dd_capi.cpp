@@ -460,14 +460,19 @@ static dd_status force_entry(dd_ctx *c, void *out_dev, double *dcsw, const void 
     if (!sigma_blocks(a.sig)) return fail(c, DD_ERR_ARG, "sigma blocks not block diagonal");
     a.kcsw = c->prm.kappa * c->prm.csw;
     a.kappa = c->prm.kappa;
+    a.csw = c->prm.csw;
+    a.clov64 = c->clov64;
     a.phase = c->phase;
     a.su3 = su3;
     // per site: psi, chi, four links and the six Y planes read twice over (once
     // written), the output links written; flops of the hop outer products, the
     // 24 leaves per link (nine 3x3 products per plaquette) and the dcsw traces
     const double V = (double)g.V;
-    const double bytes = V * (2 * 192.0 + 4 * 144.0 + 2 * 864.0 + 4 * 144.0 + (dcsw ? 4 * 144.0 : 0.0));
-    const double flops = V * (4 * FORCE_LINK_FLOPS + FORCE_Y_FLOPS + (dcsw ? FORCE_DCSW_FLOPS : 0.0));
+    const bool csw_from_clover = c->prm.csw != 0.0;
+    const double bytes = V * (2 * 192.0 + 4 * 144.0 + 2 * 864.0 + 4 * 144.0 +
+                              (dcsw ? (csw_from_clover ? 576.0 : 4 * 144.0) : 0.0));
+    const double flops = V * (4 * FORCE_LINK_FLOPS + FORCE_Y_FLOPS +
+                              (dcsw ? (csw_from_clover ? FORCE_DCSW_CLOVER_FLOPS : FORCE_DCSW_FLOPS) : 0.0));
     hipError_t e = timed_launch ? timed(c, DD_KT_FORCE, bytes, flops, [&] { return dd::launch_force(g, c->stream, a); })
                                 : dd::launch_force(g, c->stream, a);
     if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("force launch: ") + hipGetErrorString(e));

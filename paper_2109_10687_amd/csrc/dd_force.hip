@@ -77,10 +77,15 @@ DD_INL void chiral(const Spinor<double> &p, cx<double> (&u)[2][2][3])
         }
 }
 
+// dL/dc_SW: with c_SW != 0 from the clover blocks already built, -(2 / c_SW) Re <chi| C psi>
+// with C psi = (1 + C) psi - psi per site; at c_SW = 0 (no clover to read it from) from the
+// field strength, 2 kappa sum Im tr(F Lambda) over the planes
 __global__ void __launch_bounds__(BLAS_WG) k_force_y(Geom g, SpinorField<0> psi, SpinorField<0> chi,
-                                                     const double2 *u64, SigmaBlocks sig, double kcsw, double kappa,
-                                                     double2 *Y, double *partials)
+                                                     const double2 *u64, CloverField<0> clov, SigmaBlocks sig,
+                                                     double kcsw, double kappa, double csw, double2 *Y,
+                                                     double *partials)
 {
+    const bool from_clover = csw != 0.0;
     double v[1] = {0.0};
     for (long long i = (long long)blockIdx.x * BLAS_WG + threadIdx.x; i < g.V; i += (long long)gridDim.x * BLAS_WG) {
         const int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
@@ -115,7 +120,7 @@ __global__ void __launch_bounds__(BLAS_WG) k_force_y(Geom g, SpinorField<0> psi,
                         cx<double> h = lam[b][a] + conj(lam[a][b]);
                         Y[elem(g, l, s, 54, plane * 9 + b * 3 + a)] = make_double2(f * h.im, -f * h.re);
                     }
-                if (partials) {
+                if (partials && !from_clover) {
                     Mat3<double> F;
                     field_strength(g, u64, i, mu, nu, F);
                     cx<double> tr = {0.0, 0.0};
@@ -124,6 +129,18 @@ __global__ void __launch_bounds__(BLAS_WG) k_force_y(Geom g, SpinorField<0> psi,
                     v[0] += 2.0 * kappa * tr.im;
                 }
             }
+        if (partials && from_clover) {
+            Clov<double> cl;
+            clov.load(g, l, s, cl);
+            Spinor<double> t;
+            clover_mul(cl, p, t);
+            double re = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) re += cmulc(x.v[a][c], t.v[a][c] - p.v[a][c]).re;
+            v[0] -= (2.0 / csw) * re;
+        }
     }
     if (partials) wg_reduce_store<1>(v, partials);
 }
@@ -138,20 +155,91 @@ DD_INL void load_y(const Geom &g, const double2 *Y, long long i, int plane, doub
     }
 }
 
-// C += A B
-DD_INL void madd3(Mat3<double> &C, const Mat3<double> &A, const Mat3<double> &B)
+// element (i, k) of A or of A^dagger
+template <bool DAG> DD_INL cx<double> el(const Mat3<double> &A, int i, int k)
 {
+    return DAG ? conj(A.m[k][i]) : A.m[i][k];
+}
+
+// C = op(A) op(B), op the dagger where asked (no daggered copy is formed)
+template <bool DA, bool DB> DD_INL void mulx(const Mat3<double> &A, const Mat3<double> &B, Mat3<double> &C)
+{
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) {
-            cx<double> s = C.m[i][j];
-            for (int k = 0; k < 3; ++k) s = s + A.m[i][k] * B.m[k][j];
-            C.m[i][j] = s;
+            cx<double> s = el<DA>(A, i, 0) * el<DB>(B, 0, j);
+            s = s + el<DA>(A, i, 1) * el<DB>(B, 1, j);
+            C.m[i][j] = s + el<DA>(A, i, 2) * el<DB>(B, 2, j);
+        }
+}
+
+// C += op(A) op(B)
+template <bool DA, bool DB> DD_INL void maddx(const Mat3<double> &A, const Mat3<double> &B, Mat3<double> &C)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<double> s = C.m[i][j] + el<DA>(A, i, 0) * el<DB>(B, 0, j);
+            s = s + el<DA>(A, i, 1) * el<DB>(B, 1, j);
+            C.m[i][j] = s + el<DA>(A, i, 2) * el<DB>(B, 2, j);
+        }
+}
+
+// W += f sum_k conj(a[k][col]) b[k][row] over the two spins of two half spinors: the spin
+// trace of an outer product of two projected spinors
+DD_INL void half_outer(const Half<double> &a, const Half<double> &b, cx<double> f, Mat3<double> &W)
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<double> s = cmulc(a.v[0][c], b.v[0][r]);
+            s = s + cmulc(a.v[1][c], b.v[1][r]);
+            W.m[r][c] = W.m[r][c] + f * s;
         }
 }
 
 DD_INL int plane_index(int a, int b)  // a < b
 {
     return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+}
+
+// the derivative of the plaquettes through U_mu(n) in the (mu, nu) plane on the sd side,
+// with Y of that plane (sign sgn) at its corners: for the closed path U Z2 Z3 Z4,
+// W += Y(d2) S + S Y(d1) + Z2 (Z3 Y(d4) Z4 + Y(d3) Z3 Z4), S = Z2 Z3 Z4.  Z3 = U_mu(.)^dagger
+// always; Z2 is daggered on the -nu side and Z4 on the +nu side.  Eight 3x3 products per
+// plaquette, no daggered copies formed.
+template <int SD>
+DD_INL void staple_force(const Geom &g, const double2 *u64, const double2 *Y, long long i, long long j, int mu,
+                         int nu, int plane, double sgn, Mat3<double> &W)
+{
+    constexpr bool DZ2 = SD < 0, DZ4 = SD > 0;
+    const long long n_s = step(g, i, nu, SD);  // n + sd nu
+    const long long j_s = step(g, j, nu, SD);  // n + mu + sd nu
+    Mat3<double> L4, L3, T, A, B;
+    load_link64(g, u64, SD > 0 ? i : n_s, nu, L4);  // Z4 = U_nu(n)^dagger, or U_nu(n - nu)
+    load_y(g, Y, n_s, plane, sgn, T);               // Y(d4), d4 = n + sd nu
+    {
+        Mat3<double> t;
+        mulx<false, DZ4>(T, L4, t);                 // Y(d4) Z4
+        load_link64(g, u64, n_s, mu, L3);           // Z3 = U_mu(n + sd nu)^dagger
+        mulx<true, DZ4>(L3, L4, A);                 // A = Z3 Z4
+        mulx<true, false>(L3, t, B);                // B = Z3 Y(d4) Z4
+    }
+    Mat3<double> &L2 = L3;
+    load_y(g, Y, j_s, plane, sgn, T);               // Y(d3), d3 = n + mu + sd nu
+    load_link64(g, u64, SD > 0 ? j : j_s, nu, L2);  // Z2 = U_nu(n + mu), or U_nu(n + mu - nu)^dagger
+    maddx<false, false>(T, A, B);                   // B += Y(d3) Z3 Z4
+    maddx<DZ2, false>(L2, B, W);                    // W += Z2 B
+    Mat3<double> &S = B;
+    mulx<DZ2, false>(L2, A, S);                     // S = Z2 Z3 Z4
+    Mat3<double> &T1 = A;
+    load_y(g, Y, j, plane, sgn, T);                 // Y(d2), d2 = n + mu
+    load_y(g, Y, i, plane, sgn, T1);                // Y(d1), d1 = n
+    maddx<false, false>(T, S, W);
+    maddx<false, false>(S, T1, W);
 }
 
 // one thread per site, blockIdx.y = mu; writes the canonical [4][Lt][Lz][Ly][Lx][3][3]
@@ -167,79 +255,42 @@ __global__ void __launch_bounds__(256) k_force_w(Geom g, SpinorField<0> psi, Spi
     const long long j = neighbour(g, st, mu, +1, wrap, inblk);
     const int lj = (int)(j >> g.lbvol), sj = (int)(j & (g.bvol - 1));
 
-    // ---- hop term
+    // ---- hop term: 2 kappa phase times the spin traces of
+    //   [(1 - gamma_mu) psi(n+mu)] chi(n)^dagger  and  ([(1 + gamma_mu) psi(n)] chi(n+mu)^dagger)^dagger,
+    // each the trace over the two projected spins (1 -+ gamma_mu is twice a projector: the
+    // trace equals sum_k conj(P chi)_k (P psi)_k for mu < 3, half of it for mu = 3, where the
+    // projection carries the factor 2)
     Mat3<double> W;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) W.m[a][b] = {0.0, 0.0};
     {
-        Spinor<double> pn, pj, xn, xj, t1, t2;
-        psi.load(g, st.l, st.s, pn);
-        psi.load(g, lj, sj, pj);
-        chi.load(g, st.l, st.s, xn);
-        chi.load(g, lj, sj, xj);
-        Half<double> h;
-        zero(t1);
-        zero(t2);
-        project(mu, +1, pj, h);
-        reconstruct(mu, +1, h, t1);  // (1 - gamma_mu) psi(n+mu)
-        project(mu, -1, pn, h);
-        reconstruct(mu, -1, h, t2);  // (1 + gamma_mu) psi(n)
-        cx<double> phase = wrap ? cx<double>{ph.re[mu], ph.im[mu]} : cx<double>{1.0, 0.0};
-        const cx<double> k2 = (2.0 * kappa) * phase;
-        for (int b = 0; b < 3; ++b)
-            for (int a = 0; a < 3; ++a) {
-                cx<double> s = {0.0, 0.0};
-                for (int al = 0; al < 4; ++al) {
-                    s = s + cmulc(xn.v[al][a], t1.v[al][b]);  // t1_b conj(chi(n)_a)
-                    s = s + cmulc(t2.v[al][a], xj.v[al][b]);  // conj(t2_a) chi(n+mu)_b
-                }
-                W.m[b][a] = k2 * s;
-            }
+        const cx<double> phase = wrap ? cx<double>{ph.re[mu], ph.im[mu]} : cx<double>{1.0, 0.0};
+        const cx<double> k2 = ((mu == 3 ? 1.0 : 2.0) * kappa) * phase;
+        Spinor<double> p;
+        Half<double> hp, hx;
+        psi.load(g, lj, sj, p);
+        project(mu, +1, p, hp);        // P^- psi(n+mu)
+        chi.load(g, st.l, st.s, p);
+        project(mu, +1, p, hx);        // P^- chi(n)
+        half_outer(hx, hp, k2, W);     // W[b][a] += k2 sum conj(hx_a) hp_b
+        psi.load(g, st.l, st.s, p);
+        project(mu, -1, p, hp);        // P^+ psi(n)
+        chi.load(g, lj, sj, p);
+        project(mu, -1, p, hx);        // P^+ chi(n+mu)
+        half_outer(hp, hx, k2, W);     // W[b][a] += k2 sum conj(hp_a) hx_b
     }
 
-    // ---- clover term
+    // ---- clover term: the six plaquettes through the link, staple by staple
     if (Y) {
+#pragma unroll 1
         for (int nu = 0; nu < 4; ++nu) {
             if (nu == mu) continue;
             const int plane = mu < nu ? plane_index(mu, nu) : plane_index(nu, mu);
             const double orient = mu < nu ? 1.0 : -1.0;
-            for (int sd = 1; sd >= -1; sd -= 2) {
-                // the staple path n+mu -> n+mu+sd*nu -> n+sd*nu -> n
-                const long long n_s = step(g, i, nu, sd);    // n + sd nu
-                const long long j_s = step(g, j, nu, sd);    // n + mu + sd nu
-                Mat3<double> Z2, Z3, Z4, m;
-                if (sd > 0) {
-                    load_link64(g, u64, j, nu, m);
-                    Z2 = m;                                  // U_nu(n+mu)
-                    load_link64(g, u64, n_s, mu, m);
-                    dag3(m, Z3);                             // U_mu(n+nu)^dagger
-                    load_link64(g, u64, i, nu, m);
-                    dag3(m, Z4);                             // U_nu(n)^dagger
-                } else {
-                    load_link64(g, u64, j_s, nu, m);
-                    dag3(m, Z2);                             // U_nu(n+mu-nu)^dagger
-                    load_link64(g, u64, n_s, mu, m);
-                    dag3(m, Z3);                             // U_mu(n-nu)^dagger
-                    load_link64(g, u64, n_s, nu, Z4);        // U_nu(n-nu)
-                }
-                const double sgn = orient * (double)sd;
-                Mat3<double> T34, Z23, S, Yc, t;
-                mul3(Z3, Z4, T34);
-                mul3(Z2, Z3, Z23);
-                // Z2 Z3 Y(d4) Z4, d4 = n + sd nu
-                load_y(g, Y, n_s, plane, sgn, Yc);
-                mul3(Yc, Z4, t);
-                madd3(W, Z23, t);
-                // Z2 Y(d3) Z3 Z4, d3 = n + mu + sd nu
-                load_y(g, Y, j_s, plane, sgn, Yc);
-                mul3(Yc, T34, t);
-                madd3(W, Z2, t);
-                mul3(Z2, T34, S);
-                // Y(d2) S, d2 = n + mu
-                load_y(g, Y, j, plane, sgn, Yc);
-                madd3(W, Yc, S);
-                // S Y(d1), d1 = n
-                load_y(g, Y, i, plane, sgn, Yc);
-                madd3(W, S, Yc);
-            }
+            staple_force<+1>(g, u64, Y, i, j, mu, nu, plane, orient, W);
+            staple_force<-1>(g, u64, Y, i, j, mu, nu, plane, -orient, W);
         }
     }
 
@@ -269,8 +320,9 @@ hipError_t launch_force(const Geom &g, hipStream_t st, const ForceArgs &a)
 {
     const int nwg = blas_grid_sites(g);
     hipLaunchKernelGGL(k_force_y, dim3(nwg), dim3(BLAS_WG), 0, st, g, SpinorField<0>{(double2 *)a.psi},
-                       SpinorField<0>{(double2 *)a.chi}, (const double2 *)a.u64, a.sig, a.kcsw, a.kappa,
-                       (double2 *)a.y, a.partials);
+                       SpinorField<0>{(double2 *)a.chi}, (const double2 *)a.u64,
+                       CloverField<0>{(const double2 *)a.clov64}, a.sig, a.kcsw, a.kappa, a.csw, (double2 *)a.y,
+                       a.partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (a.partials) {

@@ -159,10 +159,14 @@ inline double cl_b(int prec) { return prec == 0 ? 576.0 : prec == 1 ? 288.0 : 14
 constexpr double HOPF[4] = {168, 168, 168, 156};                                            // flops of one hop per direction
 constexpr double CLOVF = 600;                                                      // clover multiply + combine
 // fermion force, counted flops (complex multiply 6, add 2; a 3x3 product 198, C += A B 216):
-// per link 6 plaquettes x 1854 + hop outer products 730; per site the Y planes 6 x 400
-// and, for dL/dc_SW, the six field strengths and traces 6 x 2500
-constexpr double FORCE_LINK_FLOPS = 6 * 1854.0 + 730.0;
+// per link 6 plaquettes x (4 products + 4 accumulated products) + the hop term (four spin
+// projections of 12 flops and two 9-entry traces over two spins, 22 flops an entry); per site
+// the Y planes 6 x 400 and, for dL/dc_SW, either the six field strengths and traces 6 x 2500
+// (c_SW = 0) or the clover product, 12 complex differences and 12 real parts of conjugate
+// products summed (600 + 24 + 48)
+constexpr double FORCE_LINK_FLOPS = 6 * (4 * 198.0 + 4 * 216.0) + (4 * 12.0 + 2 * 9 * 22.0);
 constexpr double FORCE_Y_FLOPS = 6 * 400.0, FORCE_DCSW_FLOPS = 6 * 2500.0;
+constexpr double FORCE_DCSW_CLOVER_FLOPS = 600.0 + 24.0 + 48.0;
 
 // hop flops per site that stay inside a block, and those that leave it
 inline double hops_in(const Geom &g)

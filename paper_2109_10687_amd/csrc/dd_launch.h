@@ -128,12 +128,13 @@ struct LatDesc {
 struct ForceArgs {
     const void *psi, *chi;  // FP64 internal-layout spinors
     const void *u64;        // FP64 links
+    const void *clov64;     // FP64 clover blocks 1 + C (dL/dc_SW when c_SW != 0)
     void *y;                // work: 54 complex per site (six planes of 3x3)
     void *out;              // canonical [4][Lt][Lz][Ly][Lx][3][3] complex double
     double *partials;       // per-workgroup partial sums of dL/dc_SW (nullptr: skip)
     double *dcsw;           // device scalar receiving dL/dc_SW
     SigmaBlocks sig;
-    double kcsw, kappa;
+    double kcsw, kappa, csw;
     Phase4 phase;
     int su3;  // 0: gradient W^dagger per link; 1: traceless Hermitian su(3) force
 };
