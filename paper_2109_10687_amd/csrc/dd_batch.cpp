@@ -387,6 +387,32 @@ dd_status multi_fetch(dd_multi *m, int nv, std::vector<std::array<double, 3>> &o
     return DD_OK;
 }
 
+// the packed-FP16 SAP of every lattice of the shared group, one launch per half-sweep
+// (table v: 0 the SAP of p16 into M p, 1 of r16 into M r)
+static dd_status sap_multi(dd_multi *m, int v)
+{
+    if (m->sap_group.empty()) return DD_OK;
+    dd_ctx *c0 = m->L[m->sap_group[0]];  // its timers hold the shared launches
+    const int ng = (int)m->sap_group.size();
+    const dd::SapLat *tab = m->sap_dev + (size_t)v * m->L.size();
+    const size_t lds = dd::sap_pk_lds_bytes(c0->g);
+    Range range("ddsolve: multi-lattice SAP preconditioner");
+    return sap_schedule(c0->prm.n_sap, true, false, [&](int colour, int flags) -> dd_status {
+        double bytes = 0, flops = 0;
+        for (int k : m->sap_group) {
+            double b, f;
+            sap_half_cost(m->L[k]->g, 2, true, flags, 1.0, m->L[k]->prm.n_jac, b, f);
+            bytes += b;
+            flops += f;
+        }
+        hipError_t e = timed(c0, DD_KT_SAP, bytes, flops, [&] {
+            return dd::launch_sap_half_pk_multi(m->stream, tab, ng, m->sap_items, lds, colour, flags);
+        });
+        if (e != hipSuccess) return mfail(m, DD_ERR_HIP, std::string("multi-lattice sap launch: ") + hipGetErrorString(e));
+        return DD_OK;
+    });
+}
+
 // the inner FP32 BiCGStab of every lattice in lockstep (Alg. 5 on A M_SAP with the FP16
 // SAP of each lattice, as in the single-lattice mixed solver, flexible accumulation):
 // per lattice its own fields and scalars, the A applications of a step as one launch
@@ -439,10 +465,14 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
     }
     // the FP16 SAP of each lattice reads the FP16 copies of p and r that the fused updates
     // write (as in solve_sap32); y takes alpha Mp + omega Mr in one pass
+    // (one launch per half-sweep for the lattices of the shared SAP, converged ones included)
+    std::vector<char> shared(n, 0);
+    for (int k : m->sap_group) shared[k] = 1;
     auto precond = [&](int from16, int to) -> dd_status {
+        dd_status s2;
+        if ((s2 = sap_multi(m, from16 == 10 ? 0 : 1)) != DD_OK) return s2;
         for (int k = 0; k < n; ++k) {
-            if (!R[k].active) continue;
-            dd_status s2;
+            if (!R[k].active || shared[k]) continue;
             if ((s2 = k_sap(m->L[k], 2, F(k, from16), F(k, to), F(k, 9))) != DD_OK) return lat_fail(m, k, s2);
         }
         return DD_OK;
@@ -771,7 +801,18 @@ dd_status dd_multi_create(const dd_params *params, int nlat, void *hip_stream, d
     }
     bool ok = hipMalloc((void **)&m->counter, sizeof(int)) == hipSuccess &&
               hipMalloc((void **)&m->desc_dev, 3 * nlat * sizeof(dd::LatDesc)) == hipSuccess &&
-              hipHostMalloc((void **)&m->desc_host, 3 * nlat * sizeof(dd::LatDesc), hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc((void **)&m->desc_host, 3 * nlat * sizeof(dd::LatDesc), hipHostMallocDefault) == hipSuccess &&
+              hipMalloc((void **)&m->sap_dev, 2 * nlat * sizeof(dd::SapLat)) == hipSuccess &&
+              hipHostMalloc((void **)&m->sap_host, 2 * nlat * sizeof(dd::SapLat), hipHostMallocDefault) == hipSuccess;
+    // the lattices whose SAP half-sweeps share one launch
+    for (int k = 0; k < nlat; ++k) {
+        const dd_ctx *c = m->L[k];
+        const bool cube4 = c->g.b[0] == 4 && c->g.b[1] == 4 && c->g.b[2] == 4 && c->g.b[3] == 4;
+        if (!cube4 || !c->prm.sap_fp16_arith) continue;
+        if (!m->sap_group.empty() && c->prm.n_sap != m->L[m->sap_group[0]]->prm.n_sap) continue;
+        m->sap_group.push_back(k);
+        m->sap_items += c->g.nblk / 2;
+    }
     if (!ok) {
         (void)hipGetLastError();
         dd_multi_destroy(m);
@@ -789,6 +830,8 @@ dd_status dd_multi_destroy(dd_multi *m)
     if (m->counter) (void)hipFree(m->counter);
     if (m->desc_dev) (void)hipFree(m->desc_dev);
     if (m->desc_host) (void)hipHostFree(m->desc_host);
+    if (m->sap_dev) (void)hipFree(m->sap_dev);
+    if (m->sap_host) (void)hipHostFree(m->sap_host);
     delete m;
     return DD_OK;
 }
@@ -865,6 +908,29 @@ dd_status bicgstab_solve_multi(dd_multi *m, void *const *x_dev, const void *cons
         fill_desc(m, m->desc_host + 2 * n, i2, o2);
         MHIPCK(m, hipMemcpyAsync(m->desc_dev + n, m->desc_host + n, 2 * n * sizeof(dd::LatDesc), hipMemcpyHostToDevice,
                                  m->stream));
+        // the shared SAP launches: p16 -> M p and r16 -> M r, the SAP work vector
+        for (int v = 0; v < 2; ++v) {
+            int item0 = 0;
+            for (size_t q = 0; q < m->sap_group.size(); ++q) {
+                dd_ctx *c = m->L[m->sap_group[q]];
+                dd::SapArgs a{};
+                a.b = c->f16[v];
+                a.x = c->f16[2 + v];
+                a.s = c->f16[4];
+                a.prec = 2;
+                a.links = c->U16;
+                a.cinv = c->cinv16;
+                a.n_jac = c->prm.n_jac;
+                a.kappa = c->prm.kappa;
+                a.phase = c->phase;
+                a.faces = c->faces;
+                m->sap_host[v * n + q] = dd::sap_lat(c->g, a, item0);
+                item0 += c->g.nblk / 2;
+            }
+        }
+        if (!m->sap_group.empty())
+            MHIPCK(m, hipMemcpyAsync(m->sap_dev, m->sap_host, 2 * n * sizeof(dd::SapLat), hipMemcpyHostToDevice,
+                                     m->stream));
         MHIPCK(m, hipStreamSynchronize(m->stream));
     }
     std::vector<dd_solve_info> inf(n);

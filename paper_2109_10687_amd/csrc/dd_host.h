@@ -8,6 +8,7 @@
 #include <array>
 #include <cmath>
 #include <complex>
+#include <functional>
 #include <initializer_list>
 #include <string>
 #include <vector>
@@ -98,6 +99,12 @@ struct dd_multi {
     dd::LatDesc *desc_dev = nullptr;             // three descriptor tables: the caller's apply, A Mp, A Mr
     dd::LatDesc *desc_host = nullptr;            // pinned staging for the caller's apply
     int total = 0;                               // work items (256-site chunks) over all lattices
+    // the multi-lattice packed-FP16 SAP: the lattices with 4^4 blocks, packed-FP16 arithmetic and
+    // the first such lattice's n_sap share one launch per half-sweep; two tables (the SAP of p
+    // and of r in the inner solve), the others run their own SAP
+    dd::SapLat *sap_dev = nullptr, *sap_host = nullptr;
+    std::vector<int> sap_group;  // lattice indices in the shared launches
+    int sap_items = 0;           // blocks of one colour over the group
 };
 
 namespace ddh {
@@ -194,6 +201,9 @@ dd_status k_dirac(dd_ctx *c, void *out, const void *in, int pin, int pout, int p
 // x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s; with ax (FP32 only)
 // also ax = A M_SAP b by the fused tail of Alg. 3
 dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s, void *ax = nullptr);
+// the half-sweeps of one SAP application in order, and the timer figures of one of them
+dd_status sap_schedule(int n_sap, bool pk, bool amsap, const std::function<dd_status(int, int)> &half);
+void sap_half_cost(const Geom &g, int prec, bool pk, int flags, double nr, int n_jac, double &bytes, double &flops);
 // the same for the right-hand sides rhs.idx[0 .. n) of a batch of FP16 fields (the packed-FP16
 // SAP: one launch per half-sweep for all of them; otherwise one SAP per right-hand side):
 // field r of b, x and s at byte offset r * spinor_bytes(FP16), face terms per right-hand side

@@ -125,6 +125,19 @@ struct LatDesc {
     int item0;  // first work item (256-site chunk) of this lattice
 };
 
+// one lattice of a multi-lattice packed-FP16 half-sweep (4^4 blocks, one right-hand side)
+struct SapLat {
+    Geom g;
+    SpinorField<2> b, s, x;  // source, work vector, output (FP16 storage)
+    const __half2 *u16;      // FP16 links
+    CloverField<2> Ci;       // FP16 C_inv
+    Phase4 ph;
+    float kappa;
+    int n_jac;
+    __half2 *ft;  // face hop terms (sap_face_bytes)
+    int item0;    // first work item (block of the swept colour) of this lattice
+};
+
 struct ForceArgs {
     const void *psi, *chi;  // FP64 internal-layout spinors
     const void *u64;        // FP64 links
@@ -177,6 +190,12 @@ hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int 
 size_t sap_pk_lds_bytes(const Geom &g);
 size_t sap_face_bytes(const Geom &g);
 hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
+// the table entry of one lattice for the multi-lattice half-sweep, and that launch: items =
+// the blocks of one colour summed over the nlat lattices of the table (device memory), all
+// with 4^4 blocks; lds = sap_pk_lds_bytes of such a block
+SapLat sap_lat(const Geom &g, const SapArgs &a, int item0);
+hipError_t launch_sap_half_pk_multi(hipStream_t st, const SapLat *lat, int nlat, int items, size_t lds, int colour,
+                                    int flags);
 int blas_grid(const Geom &g);
 // grid of a grid-stride loop over the sites (one thread per site, at most BLAS_MAX_WG workgroups)
 int blas_grid_sites(const Geom &g);

@@ -1,6 +1,8 @@
 // dd_ops.cpp -- launches of the single-field kernels with their algorithmic
 // byte and flop counts (kernel timing), the vector kernels and reductions, and
 // the sigma blocks of the clover setup.
+#include <functional>
+
 #include "dd_host.h"
 
 using namespace ddh;
@@ -148,6 +150,75 @@ dd_status k_dirac(dd_ctx *c, void *out, const void *in, int pin, int pout, int p
 
 // x = M_SAP b at storage precision prec (1 FP32, 2 FP16), work vector s; rhs.n > 0 sweeps the
 // listed right-hand sides of a batch in each launch (packed FP16 only), faces: their face terms
+// algorithmic bytes and counted flops per swept site of one half-sweep with these flags
+// (nr right-hand sides), for the kernel timers
+void sap_half_cost(const Geom &g, int prec, bool pk, int flags, double nr, int n_jac, double &bytes, double &flops)
+{
+    // per site of the swept colour: source (s, or b in the first), links, C_inv; without
+    // TAIL also b read and s written.  FP32 arithmetic: x written, and with PRE the
+    // neighbour-block face spinors and the links that point into the block from outside.
+    // Packed FP16: x written by the tails only; with PRE the face hop terms read (6 half2
+    // per face site, the neighbour block's scale), with FACES_OUT this block's written
+    const bool tail = flags & dd::SAP_TAIL, pre = flags & dd::SAP_PRE, first = flags & dd::SAP_FIRST;
+    double face_sp = 0, face_lk = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        face_sp += 2.0 / g.b[mu];
+        face_lk += 1.0 / g.b[mu];
+    }
+    const double stat = 4 * lk_b(prec) + cl_b(prec);  // links and C_inv, once for all right-hand sides
+    double per = sp_b(prec);
+    if (!tail) per += (first ? 0.0 : sp_b(prec)) + sp_b(prec);
+    if (!pk || tail) per += sp_b(prec);
+    if (pk) {
+        const double term = 6 * 4.0 + 4.0 / g.bvol;
+        if (pre) per += face_sp * term;
+        if (flags & dd::SAP_FACES_OUT) per += face_sp * term;
+    } else if (pre) {
+        per += face_sp * sp_b(prec) + face_lk * lk_b(prec);
+    }
+    double fl = n_jac * (hops_in(g) + CLOVF);
+    if (!tail) fl += hops_in(g) + CLOVF + 48;
+    if (pre) fl += hops_out(g) + CLOVF;
+    if (flags & dd::SAP_AMSAP) {  // Alg. 3: one more in-block sweep, ax written
+        per += sp_b(prec);
+        fl += hops_in(g) + CLOVF + 48;
+        if (flags & dd::SAP_AMSAP_PRE) {  // and the cross-block hops formed again
+            per += face_sp * sp_b(prec) + face_lk * lk_b(prec);
+            fl += hops_out(g);
+        }
+    }
+    if (flags & dd::SAP_CROSS_ONLY) {  // the cross-block hops of the final x into ax (read, written)
+        per = face_sp * sp_b(prec) + face_lk * lk_b(prec) + 2 * sp_b(prec);
+        fl = hops_out(g) + CLOVF + 24;
+    }
+    const double sites = 0.5 * (double)g.V;
+    bytes = sites * (nr * per + stat);
+    flops = sites * nr * fl;
+}
+
+// The half-sweeps of one application of Alg. 1 (loop count n_sap) in order: half(colour,
+// flags).  The packed-FP16 half-sweeps (pk) hand the cross-block term on as face hop terms:
+// every half-sweep but the last leaves them.  With amsap, the fused tail of Alg. 3: the
+// tails also write their rows of A x, and one more launch adds the even rows' cross-block
+// term of the final odd x.
+dd_status sap_schedule(int n_sap, bool pk, bool amsap, const std::function<dd_status(int, int)> &half)
+{
+    const int E = 0, O = 1;
+    const int out = pk ? dd::SAP_FACES_OUT : 0;
+    dd_status st;
+    for (int i = 0; i < n_sap; ++i) {
+        if ((st = half(E, (i == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out)) != DD_OK) return st;
+        if ((st = half(O, (i == 0 ? (dd::SAP_FIRST | dd::SAP_PRE) : dd::SAP_PRE) | out)) != DD_OK) return st;
+    }
+    const int am = amsap ? dd::SAP_AMSAP : 0;
+    if ((st = half(E, dd::SAP_TAIL | (n_sap == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out | am)) != DD_OK) return st;
+    if ((st = half(O, dd::SAP_TAIL | dd::SAP_PRE | (n_sap == 0 ? dd::SAP_FIRST : 0) | am |
+                          (amsap ? dd::SAP_AMSAP_PRE : 0))) != DD_OK)
+        return st;
+    if (amsap && (st = half(E, dd::SAP_CROSS_ONLY)) != DD_OK) return st;
+    return DD_OK;
+}
+
 static dd_status sap_sweeps(dd_ctx *c, int prec, const void *b, void *x, void *s, void *faces,
                             const dd::SapRhs &rhs, void *ax = nullptr)
 {
@@ -166,73 +237,17 @@ static dd_status sap_sweeps(dd_ctx *c, int prec, const void *b, void *x, void *s
     a.phase = c->phase;
     a.faces = faces;
     const double nr = rhs.n > 0 ? rhs.n : 1;  // right-hand sides per launch
-    const int E = 0, O = 1;
-    const int n = c->prm.n_sap;
-    const Geom &g = c->g;
     const bool pk = prec == 2 && c->prm.sap_fp16_arith;
-    auto half = [&](int colour, int flags) -> dd_status {
-        // per site of the swept colour: source (s, or b in the first), links, C_inv; without
-        // TAIL also b read and s written.  FP32 arithmetic: x written, and with PRE the
-        // neighbour-block face spinors and the links that point into the block from outside.
-        // Packed FP16: x written by the tails only; with PRE the face hop terms read (6 half2
-        // per face site, the neighbour block's scale), with FACES_OUT this block's written
-        const bool tail = flags & dd::SAP_TAIL, pre = flags & dd::SAP_PRE, first = flags & dd::SAP_FIRST;
-        double face_sp = 0, face_lk = 0;
-        for (int mu = 0; mu < 4; ++mu) {
-            face_sp += 2.0 / g.b[mu];
-            face_lk += 1.0 / g.b[mu];
-        }
-        const double stat = 4 * lk_b(prec) + cl_b(prec);  // links and C_inv, once for all right-hand sides
-        double per = sp_b(prec);
-        if (!tail) per += (first ? 0.0 : sp_b(prec)) + sp_b(prec);
-        if (!pk || tail) per += sp_b(prec);
-        if (pk) {
-            const double term = 6 * 4.0 + 4.0 / g.bvol;
-            if (pre) per += face_sp * term;
-            if (flags & dd::SAP_FACES_OUT) per += face_sp * term;
-        } else if (pre) {
-            per += face_sp * sp_b(prec) + face_lk * lk_b(prec);
-        }
-        double fl = c->prm.n_jac * (hops_in(g) + CLOVF);
-        if (!tail) fl += hops_in(g) + CLOVF + 48;
-        if (pre) fl += hops_out(g) + CLOVF;
-        if (flags & dd::SAP_AMSAP) {  // Alg. 3: one more in-block sweep, ax written
-            per += sp_b(prec);
-            fl += hops_in(g) + CLOVF + 48;
-            if (flags & dd::SAP_AMSAP_PRE) {  // and the cross-block hops formed again
-                per += face_sp * sp_b(prec) + face_lk * lk_b(prec);
-                fl += hops_out(g);
-            }
-        }
-        if (flags & dd::SAP_CROSS_ONLY) {  // the cross-block hops of the final x into ax (read, written)
-            per = face_sp * sp_b(prec) + face_lk * lk_b(prec) + 2 * sp_b(prec);
-            fl = hops_out(g) + CLOVF + 24;
-        }
-        const double sites = 0.5 * (double)g.V;
-        hipError_t e = timed(c, DD_KT_SAP, sites * (nr * per + stat), sites * nr * fl, [&] {
+    return sap_schedule(c->prm.n_sap, pk, ax != nullptr, [&](int colour, int flags) -> dd_status {
+        double bytes, flops;
+        sap_half_cost(c->g, prec, pk, flags, nr, c->prm.n_jac, bytes, flops);
+        hipError_t e = timed(c, DD_KT_SAP, bytes, flops, [&] {
             return pk ? dd::launch_sap_half_pk(c->g, c->stream, a, colour, flags)
                       : dd::launch_sap_half(c->g, c->stream, a, colour, flags);
         });
         if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("sap launch: ") + hipGetErrorString(e));
         return DD_OK;
-    };
-    // the packed-FP16 half-sweeps hand the cross-block term on as face hop terms: every
-    // half-sweep but the last leaves them
-    const int out = pk ? dd::SAP_FACES_OUT : 0;
-    dd_status st;
-    for (int i = 0; i < n; ++i) {
-        if ((st = half(E, (i == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out)) != DD_OK) return st;
-        if ((st = half(O, (i == 0 ? (dd::SAP_FIRST | dd::SAP_PRE) : dd::SAP_PRE) | out)) != DD_OK) return st;
-    }
-    // with ax, the fused tail of Alg. 3: the tails also write their rows of A x, and one more
-    // launch adds the even rows' cross-block term of the final odd x
-    const int am = ax ? dd::SAP_AMSAP : 0;
-    if ((st = half(E, dd::SAP_TAIL | (n == 0 ? dd::SAP_FIRST : dd::SAP_PRE) | out | am)) != DD_OK) return st;
-    if ((st = half(O, dd::SAP_TAIL | dd::SAP_PRE | (n == 0 ? dd::SAP_FIRST : 0) | am | (ax ? dd::SAP_AMSAP_PRE : 0))) !=
-        DD_OK)
-        return st;
-    if (ax && (st = half(E, dd::SAP_CROSS_ONLY)) != DD_OK) return st;
-    return DD_OK;
+    });
 }
 
 dd_status k_sap(dd_ctx *c, int prec, const void *b, void *x, void *s, void *ax)

@@ -513,11 +513,12 @@ DD_INL SpinorField<2> rhs_field(const SpinorField<2> &f, long long off)
 // fixes the block shape to B^4 at compile time: the block extents, in-block strides and the
 // block volume become constants, so every LDS offset of the sweeps is an immediate instead
 // of a register and the face index arithmetic folds; B = 0 takes the shape from the geometry.
+// The body of the half-sweep for the w-th block of the swept colour; the kernels below
+// take w from their launch (one lattice) or from a table of lattices.
 template <int B>
-__global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int flags, SpinorField<2> bsrc,
-                                                     SpinorField<2> sw, SpinorField<2> xw, const __half2 *u16,
-                                                     CloverField<2> Ci, Phase4 ph, float kappa, int n_jac, h2 *ft,
-                                                     SapRhs rhs)
+DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField<2> bsrc, SpinorField<2> sw,
+                             SpinorField<2> xw, const __half2 *u16, CloverField<2> Ci, Phase4 ph, float kappa,
+                             int n_jac, h2 *ft, SapRhs rhs)
 {
     extern __shared__ uint4 smem_pk[];
     const Geom g = fixed_shape<B>(gin);
@@ -528,7 +529,6 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
     const int P = face_offset(g, 3, 1) + (bvol >> log2b(g, 3));  // face sites of a block
     wg_skew();
 
-    const int w = xcd_remap(blockIdx.x, gridDim.x);
     Site st;
     st.l = colour_block(g, colour, w);
     st.s = threadIdx.x;
@@ -704,6 +704,32 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
     }
 }
 
+template <int B>
+__global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int flags, SpinorField<2> bsrc,
+                                                     SpinorField<2> sw, SpinorField<2> xw, const __half2 *u16,
+                                                     CloverField<2> Ci, Phase4 ph, float kappa, int n_jac, h2 *ft,
+                                                     SapRhs rhs)
+{
+    sap_half_pk_body<B>(gin, xcd_remap(blockIdx.x, gridDim.x), colour, flags, bsrc, sw, xw, u16, Ci, ph, kappa, n_jac,
+                        ft, rhs);
+}
+
+// The same half-sweep on several lattices in one launch: the work items are the blocks of
+// the swept colour, numbered lattice by lattice (item0 of each table entry); a workgroup
+// finds its lattice in the table and sweeps that block.  One right-hand side per lattice.
+template <int B>
+__global__ void __launch_bounds__(256) k_sap_half_pk_multi(const SapLat *lat, int nlat, int colour, int flags)
+{
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    int k = 0;
+    while (k + 1 < nlat && w >= lat[k + 1].item0) ++k;
+    const SapLat &L = lat[k];
+    SapRhs one{};
+    one.n = 1;
+    sap_half_pk_body<B>(L.g, w - L.item0, colour, flags, L.b, L.s, L.x, L.u16, L.Ci, L.ph, L.kappa, L.n_jac, L.ft,
+                        one);
+}
+
 // face sites of one block, and the bytes of the face terms of a lattice (6 half2 per face
 // site, one FP32 scale per block)
 static size_t face_sites(const Geom &g)
@@ -741,6 +767,34 @@ hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, i
     hipLaunchKernelGGL(kern, dim3(g.nblk / 2), dim3(g.bvol), sap_pk_lds_bytes(g), st, g, colour, flags,
                        sfh((void *)a.b), sfh(a.s), sfh(a.x), (const __half2 *)a.links,
                        CloverField<2>{(const __half2 *)a.cinv}, a.phase, (float)a.kappa, a.n_jac, (h2 *)a.faces, rhs);
+    return hipGetLastError();
+}
+
+SapLat sap_lat(const Geom &g, const SapArgs &a, int item0)
+{
+    auto sfh = [&](void *p) {
+        return SpinorField<2>{(__half2 *)p, (float *)((char *)p + 12 * g.V * sizeof(__half2))};
+    };
+    SapLat L{};
+    L.g = g;
+    L.b = sfh((void *)a.b);
+    L.s = sfh(a.s);
+    L.x = sfh(a.x);
+    L.u16 = (const __half2 *)a.links;
+    L.Ci = CloverField<2>{(const __half2 *)a.cinv};
+    L.ph = a.phase;
+    L.kappa = (float)a.kappa;
+    L.n_jac = a.n_jac;
+    L.ft = (h2 *)a.faces;
+    L.item0 = item0;
+    return L;
+}
+
+hipError_t launch_sap_half_pk_multi(hipStream_t st, const SapLat *lat, int nlat, int items, size_t lds, int colour,
+                                    int flags)
+{
+    if (nlat <= 0 || items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sap_half_pk_multi<4>, dim3(items), dim3(256), lds, st, lat, nlat, colour, flags);
     return hipGetLastError();
 }
 

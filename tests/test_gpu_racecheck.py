@@ -5,8 +5,8 @@ waits (W-1-w) sleep periods at entry and after every workgroup barrier, so the
 wavefronts of a workgroup run each phase in the reverse of their usual order.  A
 missing barrier would then change what some wavefront reads from LDS.  Every result
 must equal the product library's bit for bit: the operators, the SAP at every
-precision (single and batched), A M_SAP with the fused tail, norms, and whole solves
-(whose reductions are order-fixed).
+precision (single, batched and several lattices per launch), A M_SAP with the fused
+tail, norms, and whole solves (whose reductions are order-fixed).
 
 Lattices: 8^4 with 4^4 blocks (one block per workgroup everywhere) and 32^4 (4096
 blocks: the FP64 / FP32 / FP16-input applies walk four blocks per workgroup and hand
@@ -70,6 +70,10 @@ def outputs(dims, race):
                 xs.append(synth.gaussian_spinor(p.dims, 80 + k, device="cuda"))
             for k, y in enumerate(m.apply(xs)):
                 out[f"multi A {k}"] = y
+            sol, infos = m.solve(xs, tol=1e-10)
+            assert all(i["status"] == "DD_OK" for i in infos), infos
+            for k, y in enumerate(sol):
+                out[f"multi solve {k}"] = y
             m.close()
     torch.cuda.synchronize()
     return out, out_ms[0]
