@@ -513,6 +513,10 @@ DD_INL SpinorField<2> rhs_field(const SpinorField<2> &f, long long off)
 // fixes the block shape to B^4 at compile time: the block extents, in-block strides and the
 // block volume become constants, so every LDS offset of the sweeps is an immediate instead
 // of a register and the face index arithmetic folds; B = 0 takes the shape from the geometry.
+// blocks per workgroup of the packed-FP16 half-sweep: blocks of fewer than 64 sites share
+// one wavefront (a block volume is a power of two, at least 16)
+DD_HDI int sap_blocks_per_wg(int bvol) { return bvol < 64 ? 64 / bvol : 1; }
+
 // The body of the half-sweep for the w-th block of the swept colour; the kernels below
 // take w from their launch (one lattice) or from a table of lattices.
 template <int B>
@@ -523,15 +527,20 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
     extern __shared__ uint4 smem_pk[];
     const Geom g = fixed_shape<B>(gin);
     const int bvol = g.bvol;
-    uint4 *xs = smem_pk;                                    // 3 x bvol uint4
+    // blocks smaller than a wavefront are packed, several to a workgroup (one wavefront):
+    // block q of the workgroup is the work item's block bpw w + q, its sites lanes q bvol ..
+    const int bpw = sap_blocks_per_wg(bvol);
+    const int q = bpw > 1 ? (int)(threadIdx.x >> g.lbvol) : 0;
+    const int tid = bpw > 1 ? (int)(threadIdx.x & (bvol - 1)) : (int)threadIdx.x;  // site in the block
+    uint4 *xs = smem_pk + (size_t)q * 12 * bvol;            // 3 x bvol uint4
     h2 *ul = reinterpret_cast<h2 *>(xs + 3 * bvol);         // 36 x bvol half2
     __shared__ float wmax[4];
     const int P = face_offset(g, 3, 1) + (bvol >> log2b(g, 3));  // face sites of a block
     wg_skew();
 
     Site st;
-    st.l = colour_block(g, colour, w);
-    st.s = threadIdx.x;
+    st.l = colour_block(g, colour, w * bpw + q);
+    st.s = tid;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) st.c[mu] = (st.s >> g.sh[mu]) & (g.b[mu] - 1);
     block_coords(g, st.l, st.B);
@@ -608,12 +617,14 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(hc.v[a][c].re), fabsf(hc.v[a][c].im)));
-        const int wv = bvol < 64 ? bvol : 64;  // lanes of this workgroup in one wavefront
+        const int wv = bvol < 64 ? bvol : 64;  // lanes of one block in one wavefront
         for (int o2 = wv / 2; o2 >= 1; o2 >>= 1) m = fmaxf(m, __shfl_xor(m, o2, wv));
-        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+        if (bvol >= 64 && (threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
         wg_barrier();  // also: every link is staged
-        m = 0.f;
-        for (int q = 0; q < (bvol + 63) / 64; ++q) m = fmaxf(m, wmax[q]);
+        if (bvol >= 64) {  // smaller blocks have their maximum from the shuffles
+            m = 0.f;
+            for (int k = 0; k < bvol / 64; ++k) m = fmaxf(m, wmax[k]);
+        }
         const float sc = m > 0.f ? 1.f / m : 0.f;
 
         // x0 = s_c + kappa C_inv h (normalised): the first Jacobi step from x = 0; every later
@@ -672,7 +683,7 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
             wg_barrier();
             const bool equal_faces = g.b[0] == g.b[1] && g.b[1] == g.b[2] && g.b[2] == g.b[3];
             const int lnf = g.lbvol - log2b(g, 0);  // log2 of the sites per face
-            for (int p = threadIdx.x; p < P; p += bvol) {
+            for (int p = tid; p < P; p += bvol) {
                 int q = 0, base = 0;
                 if (equal_faces) {  // hypercubic block: face q holds sites q * nf ... q * nf + nf - 1
                     q = p >> lnf;
@@ -699,7 +710,7 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
                 default: face_out<3, 1>(g, st.l, kk, p, P, xs, ul, bvol, ft_r); break;
                 }
             }
-            if (threadIdx.x == 0) fs_r[st.l] = inv;
+            if (tid == 0) fs_r[st.l] = inv;
         }
     }
 }
@@ -764,7 +775,9 @@ hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, i
         rhs.n = 1;
     }
     if (rhs.n > SAP_RHS_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kern, dim3(g.nblk / 2), dim3(g.bvol), sap_pk_lds_bytes(g), st, g, colour, flags,
+    const int bpw = sap_blocks_per_wg(g.bvol);  // (g.nblk / 2 is a multiple of 8: every direction holds an even
+                                                 // number of blocks)
+    hipLaunchKernelGGL(kern, dim3(g.nblk / 2 / bpw), dim3(g.bvol * bpw), bpw * sap_pk_lds_bytes(g), st, g, colour, flags,
                        sfh((void *)a.b), sfh(a.s), sfh(a.x), (const __half2 *)a.links,
                        CloverField<2>{(const __half2 *)a.cinv}, a.phase, (float)a.kappa, a.n_jac, (h2 *)a.faces, rhs);
     return hipGetLastError();
