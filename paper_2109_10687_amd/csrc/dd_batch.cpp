@@ -3,6 +3,7 @@
 // work-queue launch: the internals and their C entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 
 #include "dd_host.h"
@@ -376,41 +377,56 @@ dd_status multi_launch(dd_multi *m, int t, int pin)
     return DD_OK;
 }
 
-// bring the first nv reduction results of every lattice's context to the host (one sync)
-dd_status multi_fetch(dd_multi *m, int nv, std::vector<std::array<double, 3>> &out)
+// a reducing vector kernel on lattice k whose nv sums go to that lattice's slots of the
+// multi-lattice result array
+static dd_status multi_reduce(dd_multi *m, int k, dd::BlasArgs a, int nv)
 {
-    for (dd_ctx *c : m->L)
-        MHIPCK(m, hipMemcpyAsync(c->red_host, c->red, nv * sizeof(double), hipMemcpyDeviceToHost, m->stream));
-    MHIPCK(m, hipStreamSynchronize(m->stream));
-    for (size_t k = 0; k < m->L.size(); ++k)
-        for (int v = 0; v < nv; ++v) out[k][v] = m->L[k]->red_host[v];
+    dd_ctx *c = m->L[k];
+    dd_status st = blas(c, a);
+    if (st != DD_OK) return lat_fail(m, k, st);
+    MHIPCK(m, dd::launch_finalize(m->stream, c->partials, dd::blas_grid(c->g), nv, m->red_all + 3 * k));
     return DD_OK;
 }
 
-// the packed-FP16 SAP of every lattice of the shared group, one launch per half-sweep
+// bring the first nv results of every lattice's last multi_reduce to the host (one copy,
+// one sync)
+dd_status multi_fetch(dd_multi *m, int nv, std::vector<std::array<double, 3>> &out)
+{
+    const size_t n = m->L.size();
+    MHIPCK(m, hipMemcpyAsync(m->red_all_host, m->red_all, 3 * n * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    MHIPCK(m, hipStreamSynchronize(m->stream));
+    for (size_t k = 0; k < n; ++k)
+        for (int v = 0; v < nv; ++v) out[k][v] = m->red_all_host[3 * k + v];
+    return DD_OK;
+}
+
+// the packed-FP16 SAP of the lattices of every group, one launch per half-sweep and group
 // (table v: 0 the SAP of p16 into M p, 1 of r16 into M r)
 static dd_status sap_multi(dd_multi *m, int v)
 {
-    if (m->sap_group.empty()) return DD_OK;
-    dd_ctx *c0 = m->L[m->sap_group[0]];  // its timers hold the shared launches
-    const int ng = (int)m->sap_group.size();
-    const dd::SapLat *tab = m->sap_dev + (size_t)v * m->L.size();
-    const size_t lds = dd::sap_pk_lds_bytes(c0->g);
     Range range("ddsolve: multi-lattice SAP preconditioner");
-    return sap_schedule(c0->prm.n_sap, true, false, [&](int colour, int flags) -> dd_status {
-        double bytes = 0, flops = 0;
-        for (int k : m->sap_group) {
-            double b, f;
-            sap_half_cost(m->L[k]->g, 2, true, flags, 1.0, m->L[k]->prm.n_jac, b, f);
-            bytes += b;
-            flops += f;
-        }
-        hipError_t e = timed(c0, DD_KT_SAP, bytes, flops, [&] {
-            return dd::launch_sap_half_pk_multi(m->stream, tab, ng, m->sap_items, lds, colour, flags);
+    dd_ctx *t0 = m->L[0];  // the first lattice's timers hold the multi-lattice launches
+    for (const auto &gr : m->sap_groups) {
+        dd_ctx *c0 = m->L[gr.lat[0]];
+        const dd::SapLat *tab = m->sap_dev + (size_t)v * m->L.size() + gr.off;
+        dd_status st = sap_schedule(c0->prm.n_sap, true, false, [&](int colour, int flags) -> dd_status {
+            double bytes = 0, flops = 0;
+            for (int k : gr.lat) {
+                double b, f;
+                sap_half_cost(m->L[k]->g, 2, true, flags, 1.0, m->L[k]->prm.n_jac, b, f);
+                bytes += b;
+                flops += f;
+            }
+            hipError_t e = timed(t0, DD_KT_SAP, bytes, flops, [&] {
+                return dd::launch_sap_half_pk_multi(c0->g, m->stream, tab, (int)gr.lat.size(), gr.items, colour, flags);
+            });
+            if (e != hipSuccess)
+                return mfail(m, DD_ERR_HIP, std::string("multi-lattice sap launch: ") + hipGetErrorString(e));
+            return DD_OK;
         });
-        if (e != hipSuccess) return mfail(m, DD_ERR_HIP, std::string("multi-lattice sap launch: ") + hipGetErrorString(e));
-        return DD_OK;
-    });
+        if (st != DD_OK) return st;
+    }
+    return DD_OK;
 }
 
 // the inner FP32 BiCGStab of every lattice in lockstep (Alg. 5 on A M_SAP with the FP16
@@ -444,7 +460,7 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
     for (int k = 0; k < n; ++k) {
         dd_ctx *c = m->L[k];
         MHIPCK(m, hipMemsetAsync(F(k, 1), 0, spinor_bytes(c->g, DD_F32), m->stream));
-        if ((st = reduce_to(c, mkb(dd::BLAS_NORM2, {F(k, 0)}, {1}), 1, 0)) != DD_OK) return lat_fail(m, k, st);
+        if ((st = multi_reduce(m, k, mkb(dd::BLAS_NORM2, {F(k, 0)}, {1}), 1)) != DD_OK) return st;
     }
     if ((st = multi_fetch(m, 1, red)) != DD_OK) return st;
     for (int k = 0; k < n; ++k) {
@@ -467,7 +483,8 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
     // write (as in solve_sap32); y takes alpha Mp + omega Mr in one pass
     // (one launch per half-sweep for the lattices of the shared SAP, converged ones included)
     std::vector<char> shared(n, 0);
-    for (int k : m->sap_group) shared[k] = 1;
+    for (const auto &gr : m->sap_groups)
+        for (int k : gr.lat) shared[k] = 1;
     auto precond = [&](int from16, int to) -> dd_status {
         dd_status s2;
         if ((s2 = sap_multi(m, from16 == 10 ? 0 : 1)) != DD_OK) return s2;
@@ -490,8 +507,8 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
         if ((st = precond(10, 7)) != DD_OK) return st;
         if ((st = multi_launch(m, 1, 2)) != DD_OK) return st;  // q = A M p, every lattice
         for (int k = 0; k < n; ++k)
-            if (R[k].active && (st = reduce_to(m->L[k], mkb(dd::BLAS_DOT, {F(k, 3), F(k, 5)}, {1, 1}), 2, 0)) != DD_OK)
-                return lat_fail(m, k, st);
+            if (R[k].active && (st = multi_reduce(m, k, mkb(dd::BLAS_DOT, {F(k, 3), F(k, 5)}, {1, 1}), 2)) != DD_OK)
+                return st;
         if ((st = multi_fetch(m, 2, red)) != DD_OK) return st;
         for (int k = 0; k < n; ++k) {
             BRhs &b = R[k];
@@ -503,10 +520,10 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
                 continue;
             }
             alpha[k] = b.rho0 / rq;
-            if ((st = reduce_to(m->L[k], mkb(dd::BLAS_UPDATE1_H, {F(k, 2), F(k, 5), F(k, 11)}, {1, 1, 2},
-                                             {alpha[k].real(), alpha[k].imag()}),
-                                1, 0)) != DD_OK)
-                return lat_fail(m, k, st);
+            if ((st = multi_reduce(m, k, mkb(dd::BLAS_UPDATE1_H, {F(k, 2), F(k, 5), F(k, 11)}, {1, 1, 2},
+                                            {alpha[k].real(), alpha[k].imag()}),
+                                    1)) != DD_OK)
+                return st;
         }
         if ((st = multi_fetch(m, 1, red)) != DD_OK) return st;
         for (int k = 0; k < n; ++k) {
@@ -524,8 +541,8 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
         if ((st = multi_launch(m, 2, 2)) != DD_OK) return st;  // t = A M r, every lattice
         for (int k = 0; k < n; ++k)
             if (R[k].active &&
-                (st = reduce_to(m->L[k], mkb(dd::BLAS_DOT_NORM, {F(k, 6), F(k, 2)}, {1, 1}), 3, 0)) != DD_OK)
-                return lat_fail(m, k, st);
+                (st = multi_reduce(m, k, mkb(dd::BLAS_DOT_NORM, {F(k, 6), F(k, 2)}, {1, 1}), 3)) != DD_OK)
+                return st;
         if ((st = multi_fetch(m, 3, red)) != DD_OK) return st;
         for (int k = 0; k < n; ++k) {
             BRhs &b = R[k];
@@ -537,12 +554,12 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
                 continue;
             }
             omega[k] = cplx(d[0], d[1]) / d[2];
-            if ((st = reduce_to(m->L[k],
-                                mkb(dd::BLAS_UPDATE2_MM, {F(k, 1), F(k, 7), F(k, 8), F(k, 2), F(k, 6), F(k, 3)},
-                                    {1, 2, 2, 1, 1, 1},
-                                    {alpha[k].real(), alpha[k].imag(), omega[k].real(), omega[k].imag()}),
-                                3, 0)) != DD_OK)
-                return lat_fail(m, k, st);
+            if ((st = multi_reduce(m, k,
+                                    mkb(dd::BLAS_UPDATE2_MM, {F(k, 1), F(k, 7), F(k, 8), F(k, 2), F(k, 6), F(k, 3)},
+                                        {1, 2, 2, 1, 1, 1},
+                                        {alpha[k].real(), alpha[k].imag(), omega[k].real(), omega[k].imag()}),
+                                    3)) != DD_OK)
+                return st;
         }
         if ((st = multi_fetch(m, 3, red)) != DD_OK) return st;
         for (int k = 0; k < n; ++k) {
@@ -803,15 +820,30 @@ dd_status dd_multi_create(const dd_params *params, int nlat, void *hip_stream, d
               hipMalloc((void **)&m->desc_dev, 3 * nlat * sizeof(dd::LatDesc)) == hipSuccess &&
               hipHostMalloc((void **)&m->desc_host, 3 * nlat * sizeof(dd::LatDesc), hipHostMallocDefault) == hipSuccess &&
               hipMalloc((void **)&m->sap_dev, 2 * nlat * sizeof(dd::SapLat)) == hipSuccess &&
-              hipHostMalloc((void **)&m->sap_host, 2 * nlat * sizeof(dd::SapLat), hipHostMallocDefault) == hipSuccess;
-    // the lattices whose SAP half-sweeps share one launch
+              hipHostMalloc((void **)&m->sap_host, 2 * nlat * sizeof(dd::SapLat), hipHostMallocDefault) == hipSuccess &&
+              hipMalloc((void **)&m->red_all, 3 * nlat * sizeof(double)) == hipSuccess &&
+              hipHostMalloc((void **)&m->red_all_host, 3 * nlat * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    // the groups of lattices whose SAP half-sweeps share one launch (same block shape and
+    // n_sap, packed-FP16 arithmetic)
+    int off = 0;
     for (int k = 0; k < nlat; ++k) {
         const dd_ctx *c = m->L[k];
-        const bool cube4 = c->g.b[0] == 4 && c->g.b[1] == 4 && c->g.b[2] == 4 && c->g.b[3] == 4;
-        if (!cube4 || !c->prm.sap_fp16_arith) continue;
-        if (!m->sap_group.empty() && c->prm.n_sap != m->L[m->sap_group[0]]->prm.n_sap) continue;
-        m->sap_group.push_back(k);
-        m->sap_items += c->g.nblk / 2;
+        if (!c->prm.sap_fp16_arith) continue;
+        dd_multi::SapGroup *grp = nullptr;
+        for (auto &gr : m->sap_groups) {
+            const dd_ctx *c0 = m->L[gr.lat[0]];
+            if (c0->prm.n_sap == c->prm.n_sap && std::equal(c0->g.b, c0->g.b + 4, c->g.b)) grp = &gr;
+        }
+        if (!grp) {
+            m->sap_groups.emplace_back();
+            grp = &m->sap_groups.back();
+        }
+        grp->lat.push_back(k);
+        grp->items += dd::sap_multi_items(c->g);
+    }
+    for (auto &gr : m->sap_groups) {
+        gr.off = off;
+        off += (int)gr.lat.size();
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -832,6 +864,8 @@ dd_status dd_multi_destroy(dd_multi *m)
     if (m->desc_host) (void)hipHostFree(m->desc_host);
     if (m->sap_dev) (void)hipFree(m->sap_dev);
     if (m->sap_host) (void)hipHostFree(m->sap_host);
+    if (m->red_all) (void)hipFree(m->red_all);
+    if (m->red_all_host) (void)hipHostFree(m->red_all_host);
     delete m;
     return DD_OK;
 }
@@ -909,26 +943,27 @@ dd_status bicgstab_solve_multi(dd_multi *m, void *const *x_dev, const void *cons
         MHIPCK(m, hipMemcpyAsync(m->desc_dev + n, m->desc_host + n, 2 * n * sizeof(dd::LatDesc), hipMemcpyHostToDevice,
                                  m->stream));
         // the shared SAP launches: p16 -> M p and r16 -> M r, the SAP work vector
-        for (int v = 0; v < 2; ++v) {
-            int item0 = 0;
-            for (size_t q = 0; q < m->sap_group.size(); ++q) {
-                dd_ctx *c = m->L[m->sap_group[q]];
-                dd::SapArgs a{};
-                a.b = c->f16[v];
-                a.x = c->f16[2 + v];
-                a.s = c->f16[4];
-                a.prec = 2;
-                a.links = c->U16;
-                a.cinv = c->cinv16;
-                a.n_jac = c->prm.n_jac;
-                a.kappa = c->prm.kappa;
-                a.phase = c->phase;
-                a.faces = c->faces;
-                m->sap_host[v * n + q] = dd::sap_lat(c->g, a, item0);
-                item0 += c->g.nblk / 2;
+        for (int v = 0; v < 2; ++v)
+            for (const auto &gr : m->sap_groups) {
+                int item0 = 0;
+                for (size_t q = 0; q < gr.lat.size(); ++q) {
+                    dd_ctx *c = m->L[gr.lat[q]];
+                    dd::SapArgs a{};
+                    a.b = c->f16[v];
+                    a.x = c->f16[2 + v];
+                    a.s = c->f16[4];
+                    a.prec = 2;
+                    a.links = c->U16;
+                    a.cinv = c->cinv16;
+                    a.n_jac = c->prm.n_jac;
+                    a.kappa = c->prm.kappa;
+                    a.phase = c->phase;
+                    a.faces = c->faces;
+                    m->sap_host[v * n + gr.off + q] = dd::sap_lat(c->g, a, item0);
+                    item0 += dd::sap_multi_items(c->g);
+                }
             }
-        }
-        if (!m->sap_group.empty())
+        if (!m->sap_groups.empty())
             MHIPCK(m, hipMemcpyAsync(m->sap_dev, m->sap_host, 2 * n * sizeof(dd::SapLat), hipMemcpyHostToDevice,
                                      m->stream));
         MHIPCK(m, hipStreamSynchronize(m->stream));

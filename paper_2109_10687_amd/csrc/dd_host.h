@@ -99,12 +99,17 @@ struct dd_multi {
     dd::LatDesc *desc_dev = nullptr;             // three descriptor tables: the caller's apply, A Mp, A Mr
     dd::LatDesc *desc_host = nullptr;            // pinned staging for the caller's apply
     int total = 0;                               // work items (256-site chunks) over all lattices
-    // the multi-lattice packed-FP16 SAP: the lattices with 4^4 blocks, packed-FP16 arithmetic and
-    // the first such lattice's n_sap share one launch per half-sweep; two tables (the SAP of p
-    // and of r in the inner solve), the others run their own SAP
+    // the multi-lattice packed-FP16 SAP: lattices with the same block shape and n_sap (and
+    // packed-FP16 arithmetic) share one launch per half-sweep; two tables of nlat entries (the
+    // SAP of p and of r in the inner solve), each group's lattices consecutive in them
+    struct SapGroup {
+        std::vector<int> lat;  // lattice indices
+        int items = 0;         // work items of a launch
+        int off = 0;           // first table entry
+    };
     dd::SapLat *sap_dev = nullptr, *sap_host = nullptr;
-    std::vector<int> sap_group;  // lattice indices in the shared launches
-    int sap_items = 0;           // blocks of one colour over the group
+    std::vector<SapGroup> sap_groups;
+    double *red_all = nullptr, *red_all_host = nullptr;  // three reduction results per lattice
 };
 
 namespace ddh {

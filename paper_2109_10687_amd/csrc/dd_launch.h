@@ -135,7 +135,7 @@ struct SapLat {
     float kappa;
     int n_jac;
     __half2 *ft;  // face hop terms (sap_face_bytes)
-    int item0;    // first work item (block of the swept colour) of this lattice
+    int item0;    // first work item of this lattice
 };
 
 struct ForceArgs {
@@ -190,11 +190,12 @@ hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int 
 size_t sap_pk_lds_bytes(const Geom &g);
 size_t sap_face_bytes(const Geom &g);
 hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
-// the table entry of one lattice for the multi-lattice half-sweep, and that launch: items =
-// the blocks of one colour summed over the nlat lattices of the table (device memory), all
-// with 4^4 blocks; lds = sap_pk_lds_bytes of such a block
+// the table entry of one lattice for the multi-lattice half-sweep, the work items of one
+// lattice in it, and that launch: the nlat lattices of the table (device memory) share the
+// block shape of g, items = sap_multi_items summed over them
 SapLat sap_lat(const Geom &g, const SapArgs &a, int item0);
-hipError_t launch_sap_half_pk_multi(hipStream_t st, const SapLat *lat, int nlat, int items, size_t lds, int colour,
+int sap_multi_items(const Geom &g);
+hipError_t launch_sap_half_pk_multi(const Geom &g, hipStream_t st, const SapLat *lat, int nlat, int items, int colour,
                                     int flags);
 int blas_grid(const Geom &g);
 // grid of a grid-stride loop over the sites (one thread per site, at most BLAS_MAX_WG workgroups)

@@ -725,9 +725,10 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
                         ft, rhs);
 }
 
-// The same half-sweep on several lattices in one launch: the work items are the blocks of
-// the swept colour, numbered lattice by lattice (item0 of each table entry); a workgroup
-// finds its lattice in the table and sweeps that block.  One right-hand side per lattice.
+// The same half-sweep on several lattices of one block shape in one launch: the work items
+// are the workgroups' shares of the blocks of the swept colour (sap_multi_items per lattice),
+// numbered lattice by lattice (item0 of each table entry); a workgroup finds its lattice in
+// the table and sweeps its blocks there.  One right-hand side per lattice.
 template <int B>
 __global__ void __launch_bounds__(256) k_sap_half_pk_multi(const SapLat *lat, int nlat, int colour, int flags)
 {
@@ -803,11 +804,16 @@ SapLat sap_lat(const Geom &g, const SapArgs &a, int item0)
     return L;
 }
 
-hipError_t launch_sap_half_pk_multi(hipStream_t st, const SapLat *lat, int nlat, int items, size_t lds, int colour,
+int sap_multi_items(const Geom &g) { return g.nblk / 2 / sap_blocks_per_wg(g.bvol); }
+
+hipError_t launch_sap_half_pk_multi(const Geom &g, hipStream_t st, const SapLat *lat, int nlat, int items, int colour,
                                     int flags)
 {
     if (nlat <= 0 || items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sap_half_pk_multi<4>, dim3(items), dim3(256), lds, st, lat, nlat, colour, flags);
+    const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
+    const int bpw = sap_blocks_per_wg(g.bvol);
+    hipLaunchKernelGGL(cube4 ? k_sap_half_pk_multi<4> : k_sap_half_pk_multi<0>, dim3(items), dim3(g.bvol * bpw),
+                       bpw * sap_pk_lds_bytes(g), st, lat, nlat, colour, flags);
     return hipGetLastError();
 }
 
