@@ -184,6 +184,38 @@ DD_INL void clov_pairs_ld(const CloverField<2> &Ci, const Geom &g, int l, int s,
     }
 }
 
+// The SAP-ready copy of C_inv holds these coefficients per site, 18 half2 per chiral
+// block: Ad[0..2], Au[0..2] (re, im), Bd[0..2], Bu[0..2] (re, im)
+DD_INL void clov_pairs_put(__half2 *p, const Geom &g, int l, int s, const ClovPair &P)
+{
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int o = blk * 18;
+            p[elem(g, l, s, 36, o + c)] = P.Ad[blk][c];
+            p[elem(g, l, s, 36, o + 3 + 2 * c)] = P.Au[blk][c].re;
+            p[elem(g, l, s, 36, o + 4 + 2 * c)] = P.Au[blk][c].im;
+            p[elem(g, l, s, 36, o + 9 + c)] = P.Bd[blk][c];
+            p[elem(g, l, s, 36, o + 12 + 2 * c)] = P.Bu[blk][c].re;
+            p[elem(g, l, s, 36, o + 13 + 2 * c)] = P.Bu[blk][c].im;
+        }
+}
+
+DD_INL void clov_pairs_get(const __half2 *p, const Geom &g, int l, int s, ClovPair &P)
+{
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int o = blk * 18;
+            P.Ad[blk][c] = ld_stream(&p[elem(g, l, s, 36, o + c)]);
+            P.Au[blk][c] = PC{ld_stream(&p[elem(g, l, s, 36, o + 3 + 2 * c)]), ld_stream(&p[elem(g, l, s, 36, o + 4 + 2 * c)])};
+            P.Bd[blk][c] = ld_stream(&p[elem(g, l, s, 36, o + 9 + c)]);
+            P.Bu[blk][c] = PC{ld_stream(&p[elem(g, l, s, 36, o + 12 + 2 * c)]), ld_stream(&p[elem(g, l, s, 36, o + 13 + 2 * c)])};
+        }
+}
+
 // (a (.) z): complex product lane by lane, accumulated into r
 DD_INL void cmac_pair(const PC &a, const PC &z, PC &r)
 {
@@ -315,6 +347,30 @@ DD_INL void load_link_pair(const __half2 *u16, const Geom &g, int l, int s, int 
         const float im = pr * qi + pi * qr - rr * ti - ri * tr;
         U[2][b] = __floats2half2_rn(re, -im);
     }
+}
+
+// The SAP-ready copies of the links and of C_inv, written once per gauge field: every
+// link as a full 3x3 FP16 matrix (row 2 rebuilt by load_link_pair), at
+// elem(l, s, 36, mu * 9 + a * 3 + b), and C_inv as its pair coefficients (clov_pairs_put).
+// A half-sweep then stages both with loads and stores alone.
+__global__ void __launch_bounds__(256) k_sap_prep(Geom g, const __half2 *u16, CloverField<2> Ci, __half2 *usap,
+                                                  __half2 *cpsap)
+{
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.V) return;
+    const int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        h2 U[3][3];
+        load_link_pair(u16, g, l, s, mu, U);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) usap[elem(g, l, s, 36, mu * 9 + a * 3 + b)] = U[a][b];
+    }
+    ClovPair P;
+    clov_pairs_ld(Ci, g, l, s, P);
+    clov_pairs_put(cpsap, g, l, s, P);
 }
 
 // o = fa a + fb b + fx x + ft t, component by component, accumulated in FP32 from the
@@ -519,9 +575,9 @@ DD_HDI int sap_blocks_per_wg(int bvol) { return bvol < 64 ? 64 / bvol : 1; }
 
 // The body of the half-sweep for the w-th block of the swept colour; the kernels below
 // take w from their launch (one lattice) or from a table of lattices.
-template <int B>
+template <int B, bool ONE>
 DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField<2> bsrc, SpinorField<2> sw,
-                             SpinorField<2> xw, const __half2 *u16, CloverField<2> Ci, Phase4 ph, float kappa,
+                             SpinorField<2> xw, const __half2 *usap, const __half2 *cpsap, Phase4 ph, float kappa,
                              int n_jac, h2 *ft, SapRhs rhs)
 {
     extern __shared__ uint4 smem_pk[];
@@ -545,26 +601,23 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
     for (int mu = 0; mu < 4; ++mu) st.c[mu] = (st.s >> g.sh[mu]) & (g.b[mu] - 1);
     block_coords(g, st.l, st.B);
 
-    // stage the block's links as full 3x3 FP16 matrices, and its C_inv as pair coefficients,
-    // once for all right-hand sides
+    // stage the block's links (full 3x3 FP16 matrices) and load its C_inv pair coefficients,
+    // both from the SAP-ready copies, once for all right-hand sides
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        h2 U[3][3];
-        load_link_pair(u16, g, st.l, st.s, mu, U);
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) ul[(mu * 9 + a * 3 + b) * bvol + st.s] = U[a][b];
-    }
+    for (int k = 0; k < 36; ++k) ul[k * bvol + st.s] = usap[elem(g, st.l, st.s, 36, k)];
     ClovPair CP;
-    clov_pairs_ld(Ci, g, st.l, st.s, CP);
+    clov_pairs_get(cpsap, g, st.l, st.s, CP);
     const bool pre = (flags & SAP_PRE) != 0;
 
-    for (int ri = 0; ri < rhs.n; ++ri) {
+    // ONE: the fields as given, a single right-hand side (no loop for the compiler to hoist
+    // the neighbour blocks' addresses out of, which would spill them)
+    const int nrhs = ONE ? 1 : rhs.n;
+    for (int ri = 0; ri < nrhs; ++ri) {
         if (ri > 0) wg_barrier();  // the previous right-hand side is done with LDS
-        const long long off = (long long)rhs.idx[ri] * rhs.sp_stride;
+        const long long ridx = ONE ? 0 : rhs.idx[ri];
+        const long long off = ONE ? 0 : ridx * rhs.sp_stride;
         const SpinorField<2> b_r = rhs_field(bsrc, off), s_r = rhs_field(sw, off), x_r = rhs_field(xw, off);
-        h2 *ft_r = (h2 *)((char *)ft + (long long)rhs.idx[ri] * rhs.face_stride);
+        h2 *ft_r = ONE ? ft : (h2 *)((char *)ft + ridx * rhs.face_stride);
         float *fs_r = reinterpret_cast<float *>(ft_r + (long long)g.nblk * 6 * P);  // one scale per block
 
         // s_c as stored: pair form relative to the site scale ssc
@@ -715,14 +768,14 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
     }
 }
 
-template <int B>
+template <int B, bool ONE>
 __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int flags, SpinorField<2> bsrc,
-                                                     SpinorField<2> sw, SpinorField<2> xw, const __half2 *u16,
-                                                     CloverField<2> Ci, Phase4 ph, float kappa, int n_jac, h2 *ft,
+                                                     SpinorField<2> sw, SpinorField<2> xw, const __half2 *usap,
+                                                     const __half2 *cpsap, Phase4 ph, float kappa, int n_jac, h2 *ft,
                                                      SapRhs rhs)
 {
-    sap_half_pk_body<B>(gin, xcd_remap(blockIdx.x, gridDim.x), colour, flags, bsrc, sw, xw, u16, Ci, ph, kappa, n_jac,
-                        ft, rhs);
+    sap_half_pk_body<B, ONE>(gin, xcd_remap(blockIdx.x, gridDim.x), colour, flags, bsrc, sw, xw, usap, cpsap, ph, kappa,
+                        n_jac, ft, rhs);
 }
 
 // The same half-sweep on several lattices of one block shape in one launch: the work items
@@ -738,7 +791,7 @@ __global__ void __launch_bounds__(256) k_sap_half_pk_multi(const SapLat *lat, in
     const SapLat &L = lat[k];
     SapRhs one{};
     one.n = 1;
-    sap_half_pk_body<B>(L.g, w - L.item0, colour, flags, L.b, L.s, L.x, L.u16, L.Ci, L.ph, L.kappa, L.n_jac, L.ft,
+    sap_half_pk_body<B, true>(L.g, w - L.item0, colour, flags, L.b, L.s, L.x, L.usap, L.cpsap, L.ph, L.kappa, L.n_jac, L.ft,
                         one);
 }
 
@@ -769,18 +822,27 @@ hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, i
         return SpinorField<2>{(__half2 *)p, (float *)((char *)p + 12 * g.V * sizeof(__half2))};
     };
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
-    auto kern = cube4 ? k_sap_half_pk<4> : k_sap_half_pk<0>;
     SapRhs rhs = a.rhs;
-    if (rhs.n <= 0) {  // one right-hand side (the fields as given)
+    const bool one = rhs.n <= 0;  // one right-hand side (the fields as given)
+    if (one) {
         rhs = SapRhs{};
         rhs.n = 1;
     }
     if (rhs.n > SAP_RHS_MAX) return hipErrorInvalidValue;
+    auto kern = cube4 ? (one ? k_sap_half_pk<4, true> : k_sap_half_pk<4, false>)
+                      : (one ? k_sap_half_pk<0, true> : k_sap_half_pk<0, false>);
     const int bpw = sap_blocks_per_wg(g.bvol);  // (g.nblk / 2 is a multiple of 8: every direction holds an even
                                                  // number of blocks)
     hipLaunchKernelGGL(kern, dim3(g.nblk / 2 / bpw), dim3(g.bvol * bpw), bpw * sap_pk_lds_bytes(g), st, g, colour, flags,
-                       sfh((void *)a.b), sfh(a.s), sfh(a.x), (const __half2 *)a.links,
-                       CloverField<2>{(const __half2 *)a.cinv}, a.phase, (float)a.kappa, a.n_jac, (h2 *)a.faces, rhs);
+                       sfh((void *)a.b), sfh(a.s), sfh(a.x), (const __half2 *)a.links, (const __half2 *)a.cinv, a.phase,
+                       (float)a.kappa, a.n_jac, (h2 *)a.faces, rhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_sap_prep(const Geom &g, hipStream_t st, const void *u16, const void *cinv16, void *usap, void *cpsap)
+{
+    hipLaunchKernelGGL(k_sap_prep, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, st, g, (const __half2 *)u16,
+                       CloverField<2>{(const __half2 *)cinv16}, (__half2 *)usap, (__half2 *)cpsap);
     return hipGetLastError();
 }
 
@@ -794,8 +856,8 @@ SapLat sap_lat(const Geom &g, const SapArgs &a, int item0)
     L.b = sfh((void *)a.b);
     L.s = sfh(a.s);
     L.x = sfh(a.x);
-    L.u16 = (const __half2 *)a.links;
-    L.Ci = CloverField<2>{(const __half2 *)a.cinv};
+    L.usap = (const __half2 *)a.links;
+    L.cpsap = (const __half2 *)a.cinv;
     L.ph = a.phase;
     L.kappa = (float)a.kappa;
     L.n_jac = a.n_jac;
