@@ -40,14 +40,15 @@ def class_kernels(block):
     """Kernel class of the library's timers -> the kernel instantiation rocprofv3 reports.
     With 4^4 blocks the FP64, FP32 and FP16-input Dirac applies run the t-streamed kernel
     (k_dirac_ts), the all-FP16 apply and the packed-FP16 SAP half-sweep their 4^4
-    specialisations (last template argument 4); other block shapes run the generic kernels (0)."""
+    specialisations (template argument 4; the half-sweep of one right-hand side is its <B, true>
+    form); other block shapes run the generic kernels (0)."""
     if tuple(block) == (4, 4, 4, 4):
         return {"dirac_f64": "k_dirac_ts<0, 0, 0, 0>", "dirac_f32": "k_dirac_ts<1, 1, 1, 1>",
                 "dirac_f16in": "k_dirac_ts<2, 1, 1, 1>", "dirac_f16": "k_dirac<2, 2, 2, 1, 4>",
-                "sap": "k_sap_half<2>", "sap_pk": "k_sap_half_pk<4>", "blas": "vector kernels"}
+                "sap": "k_sap_half<2>", "sap_pk": "k_sap_half_pk<4, true>", "blas": "vector kernels"}
     return {"dirac_f64": "k_dirac<0, 0, 0, 0, 0>", "dirac_f32": "k_dirac<1, 1, 1, 1, 0>",
             "dirac_f16in": "k_dirac<2, 1, 1, 1, 0>", "dirac_f16": "k_dirac<2, 2, 2, 1, 0>",
-            "sap": "k_sap_half<2>", "sap_pk": "k_sap_half_pk<0>", "blas": "vector kernels"}
+            "sap": "k_sap_half<2>", "sap_pk": "k_sap_half_pk<0, true>", "blas": "vector kernels"}
 
 
 def log(*a):

@@ -223,3 +223,23 @@ def test_solve_mixed(name, mode, fp16_arith):
     assert h["outer"][-1] == pytest.approx(info["relres_true"], rel=1e-6)
     ref = c.orc.solve(b.numpy(), op=O.OP_D, tol=1e-12, maxiter=20000)
     assert rel_l2(xn, ref.x) < 1e-7
+
+
+@pytest.mark.parametrize("name", ["4^4", "8^4"])
+def test_sap_fp16_after_gauge_reload(name):
+    """The packed-FP16 half-sweep reads per-gauge-field copies of the links and C_inv: after a
+    second gauge field is loaded into the same context its SAP must follow the new field."""
+    dims, block, kappa, csw, eps, phases = CASES[name]
+    op = O.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases, n_sap=2, n_jac=4)
+    gp = dd.Params(dims=dims, kappa=kappa, csw=csw, block=block, phases=phases, n_sap=2, n_jac=4, sap_fp16_arith=1)
+    U1 = synth.su3_links(dims, eps, 301)
+    U2 = synth.su3_links(dims, eps, 302)
+    s = dd.Solver(gp, U1.cuda())
+    b = synth.gaussian_spinor(dims, 7)
+    first = s.precondition(b.cuda(), prec=dd.DD_F16).cpu().numpy()
+    s.load_gauge(U2.cuda())
+    got = s.precondition(b.cuda(), prec=dd.DD_F16).cpu().numpy()
+    want = O.Oracle(op, U2.numpy()).sap(b.numpy())
+    assert rel_l2(got, want) < 3e-3
+    assert rel_l2(first, want) > 1e-1  # the two fields give different preconditioners
+    s.close()
