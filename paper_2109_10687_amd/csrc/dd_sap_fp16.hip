@@ -566,7 +566,7 @@ DD_INL SpinorField<2> rhs_field(const SpinorField<2> &f, long long off)
 // terms).  FACES_OUT leaves this half-sweep's terms for the next one.  The workgroup sweeps
 // its block for every right-hand side of `rhs` in turn (b, s, x and the face terms of each
 // at their own offsets) with the block's links staged and its C_inv loaded once.  B > 0
-// fixes the block shape to B^4 at compile time: the block extents, in-block strides and the
+// (4 or 2) fixes the block shape to B^4 at compile time: the block extents, in-block strides and the
 // block volume become constants, so every LDS offset of the sweeps is an immediate instead
 // of a register and the face index arithmetic folds; B = 0 takes the shape from the geometry.
 // blocks per workgroup of the packed-FP16 half-sweep: blocks of fewer than 64 sites share
@@ -603,10 +603,17 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
 
     // stage the block's links (full 3x3 FP16 matrices) and load its C_inv pair coefficients,
     // both from the SAP-ready copies, once for all right-hand sides
-#pragma unroll
-    for (int k = 0; k < 36; ++k) ul[k * bvol + st.s] = usap[elem(g, st.l, st.s, 36, k)];
+    // all loads first, then the LDS stores: where the pointers come from a table (the multi-lattice
+    // kernel) the loads are flat and an LDS store right after each would wait for it
     ClovPair CP;
-    clov_pairs_get(cpsap, g, st.l, st.s, CP);
+    {
+        h2 lk[36];
+#pragma unroll
+        for (int k = 0; k < 36; ++k) lk[k] = usap[elem(g, st.l, st.s, 36, k)];
+        clov_pairs_get(cpsap, g, st.l, st.s, CP);
+#pragma unroll
+        for (int k = 0; k < 36; ++k) ul[k * bvol + st.s] = lk[k];
+    }
     const bool pre = (flags & SAP_PRE) != 0;
 
     // ONE: the fields as given, a single right-hand side (no loop for the compiler to hoist
@@ -822,6 +829,7 @@ hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, i
         return SpinorField<2>{(__half2 *)p, (float *)((char *)p + 12 * g.V * sizeof(__half2))};
     };
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
+    const bool cube2 = g.b[0] == 2 && g.b[1] == 2 && g.b[2] == 2 && g.b[3] == 2;
     SapRhs rhs = a.rhs;
     const bool one = rhs.n <= 0;  // one right-hand side (the fields as given)
     if (one) {
@@ -829,8 +837,9 @@ hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, i
         rhs.n = 1;
     }
     if (rhs.n > SAP_RHS_MAX) return hipErrorInvalidValue;
-    auto kern = cube4 ? (one ? k_sap_half_pk<4, true> : k_sap_half_pk<4, false>)
-                      : (one ? k_sap_half_pk<0, true> : k_sap_half_pk<0, false>);
+    auto kern = cube4   ? (one ? k_sap_half_pk<4, true> : k_sap_half_pk<4, false>)
+                : cube2 ? (one ? k_sap_half_pk<2, true> : k_sap_half_pk<2, false>)
+                        : (one ? k_sap_half_pk<0, true> : k_sap_half_pk<0, false>);
     const int bpw = sap_blocks_per_wg(g.bvol);  // (g.nblk / 2 is a multiple of 8: every direction holds an even
                                                  // number of blocks)
     hipLaunchKernelGGL(kern, dim3(g.nblk / 2 / bpw), dim3(g.bvol * bpw), bpw * sap_pk_lds_bytes(g), st, g, colour, flags,
@@ -873,8 +882,9 @@ hipError_t launch_sap_half_pk_multi(const Geom &g, hipStream_t st, const SapLat 
 {
     if (nlat <= 0 || items <= 0) return hipSuccess;
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
+    const bool cube2 = g.b[0] == 2 && g.b[1] == 2 && g.b[2] == 2 && g.b[3] == 2;
     const int bpw = sap_blocks_per_wg(g.bvol);
-    hipLaunchKernelGGL(cube4 ? k_sap_half_pk_multi<4> : k_sap_half_pk_multi<0>, dim3(items), dim3(g.bvol * bpw),
+    hipLaunchKernelGGL(cube4 ? k_sap_half_pk_multi<4> : cube2 ? k_sap_half_pk_multi<2> : k_sap_half_pk_multi<0>, dim3(items), dim3(g.bvol * bpw),
                        bpw * sap_pk_lds_bytes(g), st, lat, nlat, colour, flags);
     return hipGetLastError();
 }
