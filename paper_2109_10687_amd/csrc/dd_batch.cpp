@@ -953,7 +953,7 @@ dd_status bicgstab_solve_multi(dd_multi *m, void *const *x_dev, const void *cons
                     a.x = c->f16[2 + v];
                     a.s = c->f16[4];
                     a.prec = 2;
-                    a.links = c->Usap;
+                    a.links = c->U16;
                     a.cinv = c->CPsap;
                     a.n_jac = c->prm.n_jac;
                     a.kappa = c->prm.kappa;

@@ -77,7 +77,7 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
     bool ok = alloc(&c->U64, (size_t)V * 36 * 16) && alloc(&c->U32, (size_t)V * 36 * 8) &&
               alloc(&c->U16, (size_t)V * 24 * 4) && alloc(&c->clov64, (size_t)V * 36 * 16) &&
               alloc(&c->cinv32, (size_t)V * 36 * 8) && alloc(&c->cinv16, (size_t)V * 36 * 4) &&
-              alloc(&c->Usap, (size_t)V * 36 * 4) && alloc(&c->CPsap, (size_t)V * 36 * 4) &&
+              alloc(&c->CPsap, (size_t)V * 36 * 4) &&
               alloc(&c->faces, dd::sap_face_bytes(g));
     for (int i = 0; ok && i < N64; ++i) ok = alloc(&c->f64[i], spinor_bytes(g, DD_F64));
     for (int i = 0; ok && i < N32; ++i) ok = alloc(&c->f32[i], spinor_bytes(g, DD_F32));
@@ -102,7 +102,7 @@ dd_status dd_destroy(dd_ctx *c)
 {
     if (!c) return DD_OK;
     (void)hipStreamSynchronize(c->stream);
-    void *bufs[] = {c->U64,   c->U32,     c->U16,     c->clov64,   c->cinv32, c->cinv16, c->Usap,
+    void *bufs[] = {c->U64,   c->U32,     c->U16,      c->clov64, c->cinv32, c->cinv16,
                     c->CPsap, c->faces, c->yforce, c->partials, c->red,    c->flag};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
@@ -150,7 +150,7 @@ dd_status dd_load_gauge(dd_ctx *c, const void *U)
     if (!sigma_blocks(sb)) return fail(c, DD_ERR_ARG, "sigma blocks not block diagonal");
     HIPCK(c, dd::launch_clover(c->g, c->stream, c->U64, sb, c->prm.kappa * c->prm.csw, c->clov64, c->cinv32,
                                c->cinv16, c->flag + 1));
-    HIPCK(c, dd::launch_sap_prep(c->g, c->stream, c->U16, c->cinv16, c->Usap, c->CPsap));
+    HIPCK(c, dd::launch_sap_prep(c->g, c->stream, c->cinv16, c->CPsap));
     int fl[2] = {0, 0};
     HIPCK(c, hipMemcpyAsync(fl, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));

@@ -54,7 +54,7 @@ struct dd_ctx {
     // packed gauge fields
     void *U64 = nullptr, *U32 = nullptr, *U16 = nullptr;
     void *clov64 = nullptr, *cinv32 = nullptr, *cinv16 = nullptr;
-    void *Usap = nullptr, *CPsap = nullptr;  // SAP-ready FP16 links and C_inv (launch_sap_prep)
+    void *CPsap = nullptr;  // SAP-ready FP16 C_inv (launch_sap_prep)
     void *faces = nullptr;  // face hop terms of the packed-FP16 SAP half-sweeps
     void *yforce = nullptr;  // force work field (54 complex per site), allocated by the first dd_force
     void *yscratch = nullptr;       // the fixed device array that dd_force_noalloc uses instead

@@ -60,7 +60,7 @@ struct SapArgs {
     const void *b;  // source (storage precision)
     void *s;        // work vector
     void *x;        // output M_SAP b
-    const void *links;  // FP32 or FP16 links; the packed-FP16 half-sweep: the SAP-ready links
+    const void *links;  // FP32 or FP16 links
     const void *cinv;   // FP32 or FP16 C_inv; the packed-FP16 half-sweep: the SAP-ready pair coefficients
     int prec;  // 1 FP32 storage, 2 FP16 storage
     int n_jac;
@@ -129,7 +129,7 @@ struct LatDesc {
 struct SapLat {
     Geom g;
     SpinorField<2> b, s, x;  // source, work vector, output (FP16 storage)
-    const __half2 *usap;     // SAP-ready FP16 links (launch_sap_prep)
+    const __half2 *u16;      // FP16 links (12 reals)
     const __half2 *cpsap;    // SAP-ready FP16 C_inv pair coefficients (launch_sap_prep)
     Phase4 ph;
     float kappa;
@@ -188,9 +188,9 @@ hipError_t launch_sap_half(const Geom &g, hipStream_t st, const SapArgs &a, int 
 // the same half-sweep with FP16 storage and packed FP16 block-local arithmetic; the cross-block
 // term travels between half-sweeps as face hop terms (sap_face_bytes per lattice)
 size_t sap_pk_lds_bytes(const Geom &g);
-// the SAP-ready copies the packed-FP16 half-sweep reads instead of the FP16 links and
-// C_inv: the links as full 3x3 matrices and C_inv as pair coefficients, 36 half2 per site each
-hipError_t launch_sap_prep(const Geom &g, hipStream_t st, const void *u16, const void *cinv16, void *usap, void *cpsap);
+// the SAP-ready copy of C_inv the packed-FP16 half-sweep reads instead of the FP16 C_inv:
+// its pair coefficients, 36 half2 per site
+hipError_t launch_sap_prep(const Geom &g, hipStream_t st, const void *cinv16, void *cpsap);
 size_t sap_face_bytes(const Geom &g);
 hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
 // the table entry of one lattice for the multi-lattice half-sweep, the work items of one

@@ -165,9 +165,7 @@ void sap_half_cost(const Geom &g, int prec, bool pk, int flags, double nr, int n
         face_sp += 2.0 / g.b[mu];
         face_lk += 1.0 / g.b[mu];
     }
-    // links and C_inv, once for all right-hand sides (packed FP16: the SAP-ready copies, the
-    // links as full 3x3 matrices)
-    const double stat = 4 * (pk ? 36.0 : lk_b(prec)) + cl_b(prec);
+    const double stat = 4 * lk_b(prec) + cl_b(prec);  // links and C_inv, once for all right-hand sides
     double per = sp_b(prec);
     if (!tail) per += (first ? 0.0 : sp_b(prec)) + sp_b(prec);
     if (!pk || tail) per += sp_b(prec);
@@ -233,7 +231,7 @@ static dd_status sap_sweeps(dd_ctx *c, int prec, const void *b, void *x, void *s
     a.x = x;
     a.prec = prec;
     const bool pk = prec == 2 && c->prm.sap_fp16_arith;
-    a.links = prec == 1 ? c->U32 : pk ? c->Usap : c->U16;
+    a.links = prec == 1 ? c->U32 : c->U16;
     a.cinv = prec == 1 ? c->cinv32 : pk ? c->CPsap : c->cinv16;
     a.n_jac = c->prm.n_jac;
     a.kappa = c->prm.kappa;

@@ -328,15 +328,19 @@ DD_INL void scale_pair(const SpH &a, float f, SpH &r)
     }
 }
 
-// an FP16 link as a 3x3 of (re, im) half2: rows 0 and 1 as stored, row 2 =
+// an FP16 link as a 3x3 of (re, im) half2: rows 0 and 1 as stored (link_rows), row 2 =
 // conj(row0 x row1) accumulated in FP32 from the FP16 entries (mixed-precision
-// FMAs) and rounded once
-DD_INL void load_link_pair(const __half2 *u16, const Geom &g, int l, int s, int mu, h2 (&U)[3][3])
+// FMAs) and rounded once (link_row2)
+DD_INL void link_rows(const __half2 *u16, const Geom &g, int l, int s, int mu, h2 (&U)[3][3])
 {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) U[a][b] = u16[elem(g, l, s, 24, mu * 6 + a * 3 + b)];
+}
+
+DD_INL void link_row2(h2 (&U)[3][3])
+{
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
@@ -349,25 +353,19 @@ DD_INL void load_link_pair(const __half2 *u16, const Geom &g, int l, int s, int 
     }
 }
 
-// The SAP-ready copies of the links and of C_inv, written once per gauge field: every
-// link as a full 3x3 FP16 matrix (row 2 rebuilt by load_link_pair), at
-// elem(l, s, 36, mu * 9 + a * 3 + b), and C_inv as its pair coefficients (clov_pairs_put).
-// A half-sweep then stages both with loads and stores alone.
-__global__ void __launch_bounds__(256) k_sap_prep(Geom g, const __half2 *u16, CloverField<2> Ci, __half2 *usap,
-                                                  __half2 *cpsap)
+DD_INL void load_link_pair(const __half2 *u16, const Geom &g, int l, int s, int mu, h2 (&U)[3][3])
+{
+    link_rows(u16, g, l, s, mu, U);
+    link_row2(U);
+}
+
+// The SAP-ready copy of C_inv, written once per gauge field: its pair coefficients
+// (clov_pairs_put), so a half-sweep loads them without regrouping.
+__global__ void __launch_bounds__(256) k_sap_prep(Geom g, CloverField<2> Ci, __half2 *cpsap)
 {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= g.V) return;
     const int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        h2 U[3][3];
-        load_link_pair(u16, g, l, s, mu, U);
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) usap[elem(g, l, s, 36, mu * 9 + a * 3 + b)] = U[a][b];
-    }
     ClovPair P;
     clov_pairs_ld(Ci, g, l, s, P);
     clov_pairs_put(cpsap, g, l, s, P);
@@ -577,7 +575,7 @@ DD_HDI int sap_blocks_per_wg(int bvol) { return bvol < 64 ? 64 / bvol : 1; }
 // take w from their launch (one lattice) or from a table of lattices.
 template <int B, bool ONE>
 DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField<2> bsrc, SpinorField<2> sw,
-                             SpinorField<2> xw, const __half2 *usap, const __half2 *cpsap, Phase4 ph, float kappa,
+                             SpinorField<2> xw, const __half2 *u16, const __half2 *cpsap, Phase4 ph, float kappa,
                              int n_jac, h2 *ft, SapRhs rhs)
 {
     extern __shared__ uint4 smem_pk[];
@@ -603,16 +601,23 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
 
     // stage the block's links (full 3x3 FP16 matrices) and load its C_inv pair coefficients,
     // both from the SAP-ready copies, once for all right-hand sides
-    // all loads first, then the LDS stores: where the pointers come from a table (the multi-lattice
-    // kernel) the loads are flat and an LDS store right after each would wait for it
+    // all loads first, then row 2 of each link and the LDS stores: where the pointers come from a
+    // table (the multi-lattice kernel) the loads are flat and an LDS store right after each would
+    // wait for it
     ClovPair CP;
     {
-        h2 lk[36];
+        h2 lk[4][3][3];
 #pragma unroll
-        for (int k = 0; k < 36; ++k) lk[k] = usap[elem(g, st.l, st.s, 36, k)];
+        for (int mu = 0; mu < 4; ++mu) link_rows(u16, g, st.l, st.s, mu, lk[mu]);
         clov_pairs_get(cpsap, g, st.l, st.s, CP);
 #pragma unroll
-        for (int k = 0; k < 36; ++k) ul[k * bvol + st.s] = lk[k];
+        for (int mu = 0; mu < 4; ++mu) {
+            link_row2(lk[mu]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) ul[(mu * 9 + a * 3 + b) * bvol + st.s] = lk[mu][a][b];
+        }
     }
     const bool pre = (flags & SAP_PRE) != 0;
 
@@ -777,11 +782,11 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
 
 template <int B, bool ONE>
 __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int flags, SpinorField<2> bsrc,
-                                                     SpinorField<2> sw, SpinorField<2> xw, const __half2 *usap,
+                                                     SpinorField<2> sw, SpinorField<2> xw, const __half2 *u16,
                                                      const __half2 *cpsap, Phase4 ph, float kappa, int n_jac, h2 *ft,
                                                      SapRhs rhs)
 {
-    sap_half_pk_body<B, ONE>(gin, xcd_remap(blockIdx.x, gridDim.x), colour, flags, bsrc, sw, xw, usap, cpsap, ph, kappa,
+    sap_half_pk_body<B, ONE>(gin, xcd_remap(blockIdx.x, gridDim.x), colour, flags, bsrc, sw, xw, u16, cpsap, ph, kappa,
                         n_jac, ft, rhs);
 }
 
@@ -798,7 +803,7 @@ __global__ void __launch_bounds__(256) k_sap_half_pk_multi(const SapLat *lat, in
     const SapLat &L = lat[k];
     SapRhs one{};
     one.n = 1;
-    sap_half_pk_body<B, true>(L.g, w - L.item0, colour, flags, L.b, L.s, L.x, L.usap, L.cpsap, L.ph, L.kappa, L.n_jac, L.ft,
+    sap_half_pk_body<B, true>(L.g, w - L.item0, colour, flags, L.b, L.s, L.x, L.u16, L.cpsap, L.ph, L.kappa, L.n_jac, L.ft,
                         one);
 }
 
@@ -848,10 +853,10 @@ hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, i
     return hipGetLastError();
 }
 
-hipError_t launch_sap_prep(const Geom &g, hipStream_t st, const void *u16, const void *cinv16, void *usap, void *cpsap)
+hipError_t launch_sap_prep(const Geom &g, hipStream_t st, const void *cinv16, void *cpsap)
 {
-    hipLaunchKernelGGL(k_sap_prep, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, st, g, (const __half2 *)u16,
-                       CloverField<2>{(const __half2 *)cinv16}, (__half2 *)usap, (__half2 *)cpsap);
+    hipLaunchKernelGGL(k_sap_prep, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, st, g,
+                       CloverField<2>{(const __half2 *)cinv16}, (__half2 *)cpsap);
     return hipGetLastError();
 }
 
@@ -865,7 +870,7 @@ SapLat sap_lat(const Geom &g, const SapArgs &a, int item0)
     L.b = sfh((void *)a.b);
     L.s = sfh(a.s);
     L.x = sfh(a.x);
-    L.usap = (const __half2 *)a.links;
+    L.u16 = (const __half2 *)a.links;
     L.cpsap = (const __half2 *)a.cinv;
     L.ph = a.phase;
     L.kappa = (float)a.kappa;
