@@ -9,8 +9,8 @@
 // a link entry, broadcast to both halves, multiplies both spins of the half
 // spinor in one packed FMA: a hop's two 3x3 complex products take 36 packed
 // FMAs.  The clover block (two 6x6 Hermitian blocks in the gamma_5-diagonal
-// basis) is rearranged once per launch, straight from its FP16 storage, into
-// pair coefficients,
+// basis) is rearranged once per gauge field, from its FP16 storage, into pair
+// coefficients (k_sap_prep),
 //   w_pair[c] = sum_c' A[c][c'] (.) z_pair[c'] + B[c][c'] (.) swap(z_pair[c']).
 // The cross-block term of Alg. 1 (the neighbouring blocks' x_{c'} hopping into
 // the block) travels between half-sweeps as face hop terms: each half-sweep leaves,
@@ -18,11 +18,10 @@
 // by its own link for the hops that run backwards into the neighbour), straight
 // from LDS in packed FP16, and the next half-sweep of the other colour reads them
 // instead of its neighbours' whole spinors and links.  x itself is written only by
-// the last two half-sweeps (the preconditioner's output).  The term is not
-// multiplied by C_inv on its own: with h = H_{c c'} x_{c'} the updated source is
-// s_c + kappa C_inv h, and every Jacobi step x <- s_c + kappa C_inv (H_in x + h)
-// carries h inside the clover product it already does; the first step, from
-// x = 0, yields the updated source itself.  The face terms are summed per site in
+// the last two half-sweeps (the preconditioner's output).  With h = H_{c c'} x_{c'}
+// the updated source x0 = s_c + kappa C_inv h takes one clover product (it is the
+// first Jacobi step, from x = 0), and every later step is x <- x0 + kappa C_inv H_in x,
+// which equals s_c + kappa C_inv (H_in x + h).  The face terms are summed per site in
 // FP32 (each neighbouring block has its own scale).  FP16 range: the block's
 // source and h are scaled by 1 / max|component| before the sweeps (the sweeps
 // are linear) and the result is scaled back in FP32; the final s update of
@@ -353,12 +352,6 @@ DD_INL void link_row2(h2 (&U)[3][3])
     }
 }
 
-DD_INL void load_link_pair(const __half2 *u16, const Geom &g, int l, int s, int mu, h2 (&U)[3][3])
-{
-    link_rows(u16, g, l, s, mu, U);
-    link_row2(U);
-}
-
 // The SAP-ready copy of C_inv, written once per gauge field: its pair coefficients
 // (clov_pairs_put), so a half-sweep loads them without regrouping.
 __global__ void __launch_bounds__(256) k_sap_prep(Geom g, CloverField<2> Ci, __half2 *cpsap)
@@ -599,11 +592,11 @@ DD_INL void sap_half_pk_body(Geom gin, int w, int colour, int flags, SpinorField
     for (int mu = 0; mu < 4; ++mu) st.c[mu] = (st.s >> g.sh[mu]) & (g.b[mu] - 1);
     block_coords(g, st.l, st.B);
 
-    // stage the block's links (full 3x3 FP16 matrices) and load its C_inv pair coefficients,
-    // both from the SAP-ready copies, once for all right-hand sides
-    // all loads first, then row 2 of each link and the LDS stores: where the pointers come from a
-    // table (the multi-lattice kernel) the loads are flat and an LDS store right after each would
-    // wait for it
+    // stage the block's links in LDS as full 3x3 FP16 matrices (row 2 rebuilt from the two stored
+    // rows) and load its C_inv pair coefficients from the SAP-ready copy, once for all right-hand
+    // sides; all loads first, then row 2 and the LDS stores: where the pointers come from a table
+    // (the multi-lattice kernel) the loads are flat, and an LDS store right after each would wait
+    // for it
     ClovPair CP;
     {
         h2 lk[4][3][3];
