@@ -388,7 +388,7 @@ static dd_status multi_reduce(dd_multi *m, int k, dd::BlasArgs a, int nv)
     return DD_OK;
 }
 
-// bring the first nv results of every lattice's last multi_reduce to the host (one copy,
+// bring the first nv results of every lattice's last multi_reduce or multi_blas to the host (one copy,
 // one sync)
 dd_status multi_fetch(dd_multi *m, int nv, std::vector<std::array<double, 3>> &out)
 {
@@ -397,6 +397,51 @@ dd_status multi_fetch(dd_multi *m, int nv, std::vector<std::array<double, 3>> &o
     MHIPCK(m, hipStreamSynchronize(m->stream));
     for (size_t k = 0; k < n; ++k)
         for (int v = 0; v < nv; ++v) out[k][v] = m->red_all_host[3 * k + v];
+    return DD_OK;
+}
+
+// one vector kernel of the lockstep solver on the lattices ks (fields and coefficients from
+// mk(k)), in table launches of up to MULTI_BLAS_MAX lattices whose partials fit the first
+// lattice's partials array; with nv > 0 each lattice's nv sums are finalised into its slots
+// of the result array (multi_fetch brings them over).  Timed on the first lattice's timers.
+static dd_status multi_blas(dd_multi *m, int kind, const std::vector<int> &ks,
+                            const std::function<dd::BlasArgs(int)> &mk, int nv)
+{
+    dd_ctx *c0 = m->L[0];
+    size_t i = 0;
+    while (i < ks.size()) {
+        dd::MultiBlasTab t{};
+        int slot[dd::MULTI_BLAS_MAX];
+        int total = 0;
+        long long poff = 0;
+        double bytes = 0, flops = 0;
+        for (; i < ks.size() && t.n < dd::MULTI_BLAS_MAX; ++i) {
+            dd_ctx *c = m->L[ks[i]];
+            const int nwg = dd::blas_grid(c->g);
+            const long long need = (long long)nwg * (nv > 0 ? nv : 1);
+            if (t.n > 0 && poff + need > dd::MAX_PARTIALS) break;
+            const dd::BlasArgs a = mk(ks[i]);
+            dd::MultiBlasLat &e = t.e[t.n];
+            e.g = c->g;
+            for (int j = 0; j < 6; ++j) e.v[j] = a.v[j];
+            for (int j = 0; j < 4; ++j) e.c[j] = a.c[j];
+            e.item0 = total;
+            e.nwg = nwg;
+            e.poff = poff;
+            slot[t.n] = ks[i];
+            total += nwg;
+            poff += need;
+            ++t.n;
+            double rw, fl;
+            blas_cost(a, rw, fl);
+            bytes += rw * (double)c->g.V;
+            flops += fl * (double)c->g.V;
+        }
+        hipError_t e = timed(c0, DD_KT_BLAS, bytes, flops,
+                             [&] { return dd::launch_blas_multi(m->stream, kind, t, total, c0->partials); });
+        if (e != hipSuccess) return mfail(m, DD_ERR_HIP, std::string("multi-lattice vector kernel: ") + hipGetErrorString(e));
+        if (nv > 0) MHIPCK(m, dd::launch_finalize_multi(m->stream, t, slot, c0->partials, nv, m->red_all));
+    }
     return DD_OK;
 }
 
@@ -456,7 +501,7 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
         }
     };
     int nact = 0;
-    std::vector<cplx> alpha(n), omega(n);
+    std::vector<cplx> alpha(n), omega(n), beta_k(n);
     for (int k = 0; k < n; ++k) {
         dd_ctx *c = m->L[k];
         MHIPCK(m, hipMemsetAsync(F(k, 1), 0, spinor_bytes(c->g, DD_F32), m->stream));
@@ -503,12 +548,19 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
         b.o.detail = detail;
         --nact;
     };
+    // the active lattices, for the table launches of the vector kernels
+    auto active = [&]() {
+        std::vector<int> ks;
+        for (int k = 0; k < n; ++k)
+            if (R[k].active) ks.push_back(k);
+        return ks;
+    };
     for (int it = 0; it < maxiter && nact > 0; ++it) {
         if ((st = precond(10, 7)) != DD_OK) return st;
         if ((st = multi_launch(m, 1, 2)) != DD_OK) return st;  // q = A M p, every lattice
-        for (int k = 0; k < n; ++k)
-            if (R[k].active && (st = multi_reduce(m, k, mkb(dd::BLAS_DOT, {F(k, 3), F(k, 5)}, {1, 1}), 2)) != DD_OK)
-                return st;
+        if ((st = multi_blas(m, dd::BLAS_DOT, active(), [&](int k) { return mkb(dd::BLAS_DOT, {F(k, 3), F(k, 5)}, {1, 1}); },
+                             2)) != DD_OK)
+            return st;
         if ((st = multi_fetch(m, 2, red)) != DD_OK) return st;
         for (int k = 0; k < n; ++k) {
             BRhs &b = R[k];
@@ -520,11 +572,11 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
                 continue;
             }
             alpha[k] = b.rho0 / rq;
-            if ((st = multi_reduce(m, k, mkb(dd::BLAS_UPDATE1_H, {F(k, 2), F(k, 5), F(k, 11)}, {1, 1, 2},
-                                            {alpha[k].real(), alpha[k].imag()}),
-                                    1)) != DD_OK)
-                return st;
         }
+        if ((st = multi_blas(m, dd::BLAS_UPDATE1_H, active(), [&](int k) {
+                 return mkb(dd::BLAS_UPDATE1_H, {F(k, 2), F(k, 5), F(k, 11)}, {1, 1, 2}, {alpha[k].real(), alpha[k].imag()});
+             }, 1)) != DD_OK)
+            return st;
         if ((st = multi_fetch(m, 1, red)) != DD_OK) return st;
         for (int k = 0; k < n; ++k) {
             BRhs &b = R[k];
@@ -539,10 +591,9 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
         if (nact == 0) break;
         if ((st = precond(11, 8)) != DD_OK) return st;
         if ((st = multi_launch(m, 2, 2)) != DD_OK) return st;  // t = A M r, every lattice
-        for (int k = 0; k < n; ++k)
-            if (R[k].active &&
-                (st = multi_reduce(m, k, mkb(dd::BLAS_DOT_NORM, {F(k, 6), F(k, 2)}, {1, 1}), 3)) != DD_OK)
-                return st;
+        if ((st = multi_blas(m, dd::BLAS_DOT_NORM, active(),
+                             [&](int k) { return mkb(dd::BLAS_DOT_NORM, {F(k, 6), F(k, 2)}, {1, 1}); }, 3)) != DD_OK)
+            return st;
         if ((st = multi_fetch(m, 3, red)) != DD_OK) return st;
         for (int k = 0; k < n; ++k) {
             BRhs &b = R[k];
@@ -554,13 +605,12 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
                 continue;
             }
             omega[k] = cplx(d[0], d[1]) / d[2];
-            if ((st = multi_reduce(m, k,
-                                    mkb(dd::BLAS_UPDATE2_MM, {F(k, 1), F(k, 7), F(k, 8), F(k, 2), F(k, 6), F(k, 3)},
-                                        {1, 2, 2, 1, 1, 1},
-                                        {alpha[k].real(), alpha[k].imag(), omega[k].real(), omega[k].imag()}),
-                                    3)) != DD_OK)
-                return st;
         }
+        if ((st = multi_blas(m, dd::BLAS_UPDATE2_MM, active(), [&](int k) {
+                 return mkb(dd::BLAS_UPDATE2_MM, {F(k, 1), F(k, 7), F(k, 8), F(k, 2), F(k, 6), F(k, 3)}, {1, 2, 2, 1, 1, 1},
+                            {alpha[k].real(), alpha[k].imag(), omega[k].real(), omega[k].imag()});
+             }, 3)) != DD_OK)
+            return st;
         if ((st = multi_fetch(m, 3, red)) != DD_OK) return st;
         for (int k = 0; k < n; ++k) {
             BRhs &b = R[k];
@@ -587,10 +637,13 @@ dd_status solve_multi32(dd_multi *m, std::vector<BRhs> &R, int maxiter)
                 continue;
             }
             b.rho0 = rho;
-            if ((st = blas(m->L[k], mkb(dd::BLAS_PUPDATE_H, {F(k, 4), F(k, 2), F(k, 5), F(k, 10)}, {1, 1, 1, 2},
-                                        {beta.real(), beta.imag(), omega[k].real(), omega[k].imag()}))) != DD_OK)
-                return lat_fail(m, k, st);
+            beta_k[k] = beta;
         }
+        if ((st = multi_blas(m, dd::BLAS_PUPDATE_H, active(), [&](int k) {
+                 return mkb(dd::BLAS_PUPDATE_H, {F(k, 4), F(k, 2), F(k, 5), F(k, 10)}, {1, 1, 1, 2},
+                            {beta_k[k].real(), beta_k[k].imag(), omega[k].real(), omega[k].imag()});
+             }, 0)) != DD_OK)
+            return st;
     }
     for (int k = 0; k < n; ++k)
         if (R[k].active) {

@@ -217,6 +217,7 @@ dd_status k_sap_batch(dd_ctx *c, const dd::SapRhs &rhs, const void *b, void *x, 
 dd_status blas(dd_ctx *c, dd::BlasArgs a);
 // run a reducing vector kernel and bring its nv sums to the host
 dd_status reduce(dd_ctx *c, dd::BlasArgs a, int nv, double *out);
+void blas_cost(const dd::BlasArgs &a, double &rw, double &fl);
 dd::BlasArgs mkb(int kind, std::initializer_list<void *> v, std::initializer_list<int> p,
                  std::initializer_list<double> cc = {});
 dd_status norm2(dd_ctx *c, void *v, int prec, double *out);

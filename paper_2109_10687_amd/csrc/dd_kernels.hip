@@ -734,13 +734,16 @@ __global__ void __launch_bounds__(256) k_finalize(const double *partials, int nw
 }
 
 #define GRID_STRIDE(o, N) for (long long o = (long long)blockIdx.x * BLAS_WG + threadIdx.x; o < (N); o += (long long)gridDim.x * BLAS_WG)
+// the same loop for workgroup wid of nwg (the bodies below, shared by the single-lattice
+// kernels and the multi-lattice launch)
+#define GRID_STRIDE_W(o, N) for (long long o = (long long)wid * BLAS_WG + threadIdx.x; o < (N); o += (long long)nwg * BLAS_WG)
 
 // <a|b> (2 values) and, with NV = 3, |a|^2 as the third
 template <int PA, int PB, int NV>
-__global__ void __launch_bounds__(BLAS_WG) k_dot(Geom g, SpinorField<PA> a, SpinorField<PB> b, double *partials)
+DD_INL void dot_body(const Geom &g, SpinorField<PA> a, SpinorField<PB> b, double *partials, int wid, int nwg)
 {
     double v[NV] = {};
-    GRID_STRIDE(o, 12 * g.V)
+    GRID_STRIDE_W(o, 12 * g.V)
     {
         cx<double> x = Elem<PA>::get(a, g, o), y = Elem<PB>::get(b, g, o);
         cx<double> d = cmulc(x, y);
@@ -748,7 +751,13 @@ __global__ void __launch_bounds__(BLAS_WG) k_dot(Geom g, SpinorField<PA> a, Spin
         v[1] += d.im;
         if (NV == 3) v[2] += norm2(x);
     }
-    wg_reduce_store<NV>(v, partials);
+    wg_reduce_store_at<NV>(v, partials, wid);
+}
+
+template <int PA, int PB, int NV>
+__global__ void __launch_bounds__(BLAS_WG) k_dot(Geom g, SpinorField<PA> a, SpinorField<PB> b, double *partials)
+{
+    dot_body<PA, PB, NV>(g, a, b, partials, blockIdx.x, gridDim.x);
 }
 
 template <int PA>
@@ -818,15 +827,15 @@ __global__ void __launch_bounds__(BLAS_WG) k_pupdate(Geom g, SpinorField<PR> p, 
 // storage scale belongs to the whole site), instead of by a separate conversion
 // pass that reads the vector again.  The grid is the vector kernels' grid, so the
 // partial sums line up with the finalising reduction.
-#define SITE_STRIDE(i) for (long long i = (long long)blockIdx.x * BLAS_WG + threadIdx.x; i < g.V; i += (long long)gridDim.x * BLAS_WG)
+#define SITE_STRIDE_W(i) for (long long i = (long long)wid * BLAS_WG + threadIdx.x; i < g.V; i += (long long)nwg * BLAS_WG)
 
 // r -= alpha q ; partial |r|^2 ; r16 = r
-__global__ void __launch_bounds__(BLAS_WG) k_update1_h(Geom g, SpinorField<1> r, SpinorField<1> q, SpinorField<2> r16,
-                                                       double are, double aim, double *partials)
+DD_INL void update1_h_body(const Geom &g, SpinorField<1> r, SpinorField<1> q, SpinorField<2> r16, double are, double aim,
+                           double *partials, int wid, int nwg)
 {
     double v[1] = {0};
     const cx<double> al = {are, aim};
-    SITE_STRIDE(i)
+    SITE_STRIDE_W(i)
     {
         const int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
         Spinor<float> rs;
@@ -842,18 +851,24 @@ __global__ void __launch_bounds__(BLAS_WG) k_update1_h(Geom g, SpinorField<1> r,
             }
         r16.store(g, l, s, rs);
     }
-    wg_reduce_store<1>(v, partials);
+    wg_reduce_store_at<1>(v, partials, wid);
+}
+
+__global__ void __launch_bounds__(BLAS_WG) k_update1_h(Geom g, SpinorField<1> r, SpinorField<1> q, SpinorField<2> r16,
+                                                       double are, double aim, double *partials)
+{
+    update1_h_body(g, r, q, r16, are, aim, partials, blockIdx.x, gridDim.x);
 }
 
 // x += alpha y1 + omega y2 ; r -= omega t ; partial |r|^2 and <rt|r>
 template <int PY>
-__global__ void __launch_bounds__(BLAS_WG) k_update2_mm(Geom g, SpinorField<1> x, SpinorField<PY> y1, SpinorField<PY> y2,
-                                                        SpinorField<1> r, SpinorField<1> t, SpinorField<1> rt,
-                                                        double are, double aim, double ore, double oim, double *partials)
+DD_INL void update2_mm_body(const Geom &g, SpinorField<1> x, SpinorField<PY> y1, SpinorField<PY> y2, SpinorField<1> r,
+                            SpinorField<1> t, SpinorField<1> rt, double are, double aim, double ore, double oim,
+                            double *partials, int wid, int nwg)
 {
     double v[3] = {0, 0, 0};
     const cx<double> al = {are, aim}, om = {ore, oim};
-    GRID_STRIDE(o, 12 * g.V)
+    GRID_STRIDE_W(o, 12 * g.V)
     {
         Elem<1>::put(x, g, o, Elem<1>::get(x, g, o) + al * Elem<PY>::get(y1, g, o) + om * Elem<PY>::get(y2, g, o));
         cx<double> rr = Elem<1>::get(r, g, o) - om * Elem<1>::get(t, g, o);
@@ -864,15 +879,23 @@ __global__ void __launch_bounds__(BLAS_WG) k_update2_mm(Geom g, SpinorField<1> x
         v[1] += d.re;
         v[2] += d.im;
     }
-    wg_reduce_store<3>(v, partials);
+    wg_reduce_store_at<3>(v, partials, wid);
+}
+
+template <int PY>
+__global__ void __launch_bounds__(BLAS_WG) k_update2_mm(Geom g, SpinorField<1> x, SpinorField<PY> y1, SpinorField<PY> y2,
+                                                        SpinorField<1> r, SpinorField<1> t, SpinorField<1> rt,
+                                                        double are, double aim, double ore, double oim, double *partials)
+{
+    update2_mm_body<PY>(g, x, y1, y2, r, t, rt, are, aim, ore, oim, partials, blockIdx.x, gridDim.x);
 }
 
 // p = r + beta (p - omega q) ; p16 = p
-__global__ void __launch_bounds__(BLAS_WG) k_pupdate_h(Geom g, SpinorField<1> p, SpinorField<1> r, SpinorField<1> q,
-                                                       SpinorField<2> p16, double bre, double bim, double ore, double oim)
+DD_INL void pupdate_h_body(const Geom &g, SpinorField<1> p, SpinorField<1> r, SpinorField<1> q, SpinorField<2> p16,
+                           double bre, double bim, double ore, double oim, int wid, int nwg)
 {
     const cx<double> be = {bre, bim}, om = {ore, oim};
-    SITE_STRIDE(i)
+    SITE_STRIDE_W(i)
     {
         const int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
         Spinor<float> ps;
@@ -886,6 +909,65 @@ __global__ void __launch_bounds__(BLAS_WG) k_pupdate_h(Geom g, SpinorField<1> p,
                 ps.v[a][c] = {(float)pv.re, (float)pv.im};
             }
         p16.store(g, l, s, ps);
+    }
+}
+
+__global__ void __launch_bounds__(BLAS_WG) k_pupdate_h(Geom g, SpinorField<1> p, SpinorField<1> r, SpinorField<1> q,
+                                                       SpinorField<2> p16, double bre, double bim, double ore, double oim)
+{
+    pupdate_h_body(g, p, r, q, p16, bre, bim, ore, oim, blockIdx.x, gridDim.x);
+}
+
+// The vector kernels of the lockstep multi-lattice solver, one launch for the lattices of a
+// table (each with its own fields, coefficients, workgroups and partials)
+template <int KIND>
+__global__ void __launch_bounds__(BLAS_WG) k_blas_multi(MultiBlasTab t, double *partials)
+{
+    int k = 0;
+    while (k + 1 < t.n && (int)blockIdx.x >= t.e[k + 1].item0) ++k;
+    const MultiBlasLat &L = t.e[k];
+    const Geom &g = L.g;
+    const int wid = (int)blockIdx.x - L.item0, nwg = L.nwg;
+    double *pp = partials + L.poff;
+    auto f1 = [&](int i) { return SpinorField<1>{(float2 *)L.v[i]}; };
+    auto f2 = [&](int i) {
+        return SpinorField<2>{(__half2 *)L.v[i], (float *)((char *)L.v[i] + 12 * g.V * sizeof(__half2))};
+    };
+    if constexpr (KIND == BLAS_DOT)
+        dot_body<1, 1, 2>(g, f1(0), f1(1), pp, wid, nwg);
+    else if constexpr (KIND == BLAS_DOT_NORM)
+        dot_body<1, 1, 3>(g, f1(0), f1(1), pp, wid, nwg);
+    else if constexpr (KIND == BLAS_UPDATE1_H)
+        update1_h_body(g, f1(0), f1(1), f2(2), L.c[0], L.c[1], pp, wid, nwg);
+    else if constexpr (KIND == BLAS_UPDATE2_MM)
+        update2_mm_body<2>(g, f1(0), f2(1), f2(2), f1(3), f1(4), f1(5), L.c[0], L.c[1], L.c[2], L.c[3], pp, wid, nwg);
+    else
+        pupdate_h_body(g, f1(0), f1(1), f1(2), f2(3), L.c[0], L.c[1], L.c[2], L.c[3], wid, nwg);
+}
+
+// per lattice of a table: out[3 slot + q] = sum_w partials[poff + w nv + q], one workgroup
+// per lattice, the fixed order of k_finalize
+struct MultiFin {
+    long long poff[MULTI_BLAS_MAX];
+    int nwg[MULTI_BLAS_MAX], slot[MULTI_BLAS_MAX];
+};
+
+__global__ void __launch_bounds__(256) k_finalize_multi(MultiFin f, const double *partials, int nv, double *out)
+{
+    __shared__ double sh[256];
+    const int k = blockIdx.x;
+    const double *pp = partials + f.poff[k];
+    for (int q = 0; q < nv; ++q) {
+        double t = 0;
+        for (int w = threadIdx.x; w < f.nwg[k]; w += 256) t += pp[(long long)w * nv + q];
+        sh[threadIdx.x] = t;
+        wg_barrier();
+        for (int h = 128; h >= 1; h >>= 1) {
+            if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+            wg_barrier();
+        }
+        if (threadIdx.x == 0) out[3 * f.slot[k] + q] = sh[0];
+        wg_barrier();
     }
 }
 
@@ -1288,6 +1370,35 @@ int blas_grid_sites(const Geom &g)
 hipError_t launch_finalize(hipStream_t st, const double *partials, int nwg, int nv, double *out)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, nwg, nv, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_blas_multi(hipStream_t st, int kind, const MultiBlasTab &t, int total, double *partials)
+{
+    if (t.n <= 0 || t.n > MULTI_BLAS_MAX || total <= 0) return hipErrorInvalidValue;
+    const dim3 G(total), B(BLAS_WG);
+    switch (kind) {
+    case BLAS_DOT: hipLaunchKernelGGL(k_blas_multi<BLAS_DOT>, G, B, 0, st, t, partials); break;
+    case BLAS_DOT_NORM: hipLaunchKernelGGL(k_blas_multi<BLAS_DOT_NORM>, G, B, 0, st, t, partials); break;
+    case BLAS_UPDATE1_H: hipLaunchKernelGGL(k_blas_multi<BLAS_UPDATE1_H>, G, B, 0, st, t, partials); break;
+    case BLAS_UPDATE2_MM: hipLaunchKernelGGL(k_blas_multi<BLAS_UPDATE2_MM>, G, B, 0, st, t, partials); break;
+    case BLAS_PUPDATE_H: hipLaunchKernelGGL(k_blas_multi<BLAS_PUPDATE_H>, G, B, 0, st, t, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_multi(hipStream_t st, const MultiBlasTab &t, const int *slot, const double *partials, int nv,
+                                 double *out)
+{
+    if (t.n <= 0 || t.n > MULTI_BLAS_MAX || nv < 1 || nv > 3) return hipErrorInvalidValue;
+    MultiFin f{};
+    for (int k = 0; k < t.n; ++k) {
+        f.poff[k] = t.e[k].poff;
+        f.nwg[k] = t.e[k].nwg;
+        f.slot[k] = slot[k];
+    }
+    hipLaunchKernelGGL(k_finalize_multi, dim3(t.n), dim3(256), 0, st, f, partials, nv, out);
     return hipGetLastError();
 }
 

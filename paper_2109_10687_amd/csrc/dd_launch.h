@@ -96,6 +96,24 @@ struct BlasArgs {
     double *partials;
 };
 
+// One launch of a vector kernel over several lattices (the lockstep multi-lattice
+// solver): lattice k of the table runs the kernel's grid-stride loop over its own sites
+// with nwg workgroups, launch workgroups item0 .. item0 + nwg - 1, its fields and
+// coefficients as in BlasArgs, and leaves its partial sums at partials[poff + w nv + q].
+// The table travels by value in the kernel arguments.
+constexpr int MULTI_BLAS_MAX = 16;
+struct MultiBlasLat {
+    Geom g;
+    void *v[6];
+    double c[4];
+    int item0, nwg;
+    long long poff;
+};
+struct MultiBlasTab {
+    MultiBlasLat e[MULTI_BLAS_MAX];
+    int n;
+};
+
 constexpr int MRHS_FIRST_VECTOR = 8;  // batched-A variants from here on are vector kernels (FP16 inputs too)
 
 // A = I - kappa C_inv H on a batch of FP32 internal-layout spinors (nrhs fields,
@@ -153,8 +171,8 @@ struct ForceArgs {
 };
 
 // sum of v over the workgroup (BLAS_WG threads): wavefront shuffles, then LDS;
-// thread 0 writes the workgroup's partials[blockIdx.x * NV + k]
-template <int NV> DD_INL void wg_reduce_store(double (&v)[NV], double *partials)
+// thread 0 writes the workgroup's partials[wid * NV + k]
+template <int NV> DD_INL void wg_reduce_store_at(double (&v)[NV], double *partials, long long wid)
 {
     __shared__ double red[NV][BLAS_WG / 64];
 #pragma unroll
@@ -171,8 +189,14 @@ template <int NV> DD_INL void wg_reduce_store(double (&v)[NV], double *partials)
         for (int k = 0; k < NV; ++k) {
             double t = 0;
             for (int q = 0; q < BLAS_WG / 64; ++q) t += red[k][q];
-            partials[(long long)blockIdx.x * NV + k] = t;
+            partials[wid * NV + k] = t;
         }
+}
+
+// ... at partials[blockIdx.x * NV + k]
+template <int NV> DD_INL void wg_reduce_store(double (&v)[NV], double *partials)
+{
+    wg_reduce_store_at<NV>(v, partials, blockIdx.x);
 }
 
 // canonical <-> internal spinor copies; g5 = true applies gamma_5 on the way
@@ -225,6 +249,12 @@ hipError_t launch_gcr_rupdate(const Geom &g, hipStream_t st, void *z, void *r, d
 // y (FP32) += sum_j coef_j p_j, p_j at precision pp (FP16 or FP32)
 hipError_t launch_multi_axpy(const Geom &g, hipStream_t st, const VecSet &ps, int k, int pp, void *y);
 hipError_t launch_finalize(hipStream_t st, const double *partials, int nwg, int nv, double *out);
+// kind in {BLAS_DOT, BLAS_DOT_NORM, BLAS_UPDATE1_H, BLAS_UPDATE2_MM (FP16 M p, M r), BLAS_PUPDATE_H}
+// on the lattices of t (total workgroups: the sum of their nwg)
+hipError_t launch_blas_multi(hipStream_t st, int kind, const MultiBlasTab &t, int total, double *partials);
+// out[3 slot[k] + q] = the fixed-order sum of lattice k's nv partials, for the lattices of t
+hipError_t launch_finalize_multi(hipStream_t st, const MultiBlasTab &t, const int *slot, const double *partials, int nv,
+                                 double *out);
 
 // A on several lattices in one persistent launch (work queue over (lattice, chunk)
 // items, desc_dev in device memory, counter: one device int, cleared here)

@@ -270,11 +270,11 @@ dd_status k_sap_batch(dd_ctx *c, const dd::SapRhs &rhs, const void *b, void *x, 
     return DD_OK;
 }
 
-dd_status blas(dd_ctx *c, dd::BlasArgs a)
+// bytes read + written per site, and flops per site, of a vector kernel
+void blas_cost(const dd::BlasArgs &a, double &rw, double &fl)
 {
-    a.partials = c->partials;
-    // vectors read + written per site, and flops per site
-    double rw = 0, fl = 0;
+    rw = 0;
+    fl = 0;
     const double P0 = sp_b(a.p[0]), P1 = sp_b(a.p[1]), P2 = sp_b(a.p[2]);
     switch (a.kind) {
     case dd::BLAS_DOT: rw = P0 + P1; fl = 96; break;
@@ -292,6 +292,13 @@ dd_status blas(dd_ctx *c, dd::BlasArgs a)
     case dd::BLAS_PUPDATE_H: rw = 4 * sp_b(1) + sp_b(2); fl = 192; break;                 // p r/w, r, q, p16 written
     case dd::BLAS_CAXPY: rw = 2 * sp_b(1) + P1; fl = 96; break;
     }
+}
+
+dd_status blas(dd_ctx *c, dd::BlasArgs a)
+{
+    a.partials = c->partials;
+    double rw, fl;
+    blas_cost(a, rw, fl);
     const double V = (double)c->g.V;
     hipError_t e = timed(c, DD_KT_BLAS, V * rw, V * fl, [&] { return dd::launch_blas(c->g, c->stream, a); });
     if (e != hipSuccess) return fail(c, DD_ERR_HIP, std::string("vector kernel: ") + hipGetErrorString(e));
