@@ -453,7 +453,7 @@ static dd_status sap_multi(dd_multi *m, int v)
     dd_ctx *t0 = m->L[0];  // the first lattice's timers hold the multi-lattice launches
     for (const auto &gr : m->sap_groups) {
         dd_ctx *c0 = m->L[gr.lat[0]];
-        const dd::SapLat *tab = m->sap_dev + (size_t)v * m->L.size() + gr.off;
+        const dd::SapLat *tab = m->sap_host + (size_t)v * m->L.size() + gr.off;
         dd_status st = sap_schedule(c0->prm.n_sap, true, false, [&](int colour, int flags) -> dd_status {
             double bytes = 0, flops = 0;
             for (int k : gr.lat) {
@@ -463,7 +463,7 @@ static dd_status sap_multi(dd_multi *m, int v)
                 flops += f;
             }
             hipError_t e = timed(t0, DD_KT_SAP, bytes, flops, [&] {
-                return dd::launch_sap_half_pk_multi(c0->g, m->stream, tab, (int)gr.lat.size(), gr.items, colour, flags);
+                return dd::launch_sap_half_pk_multi(c0->g, m->stream, tab, (int)gr.lat.size(), colour, flags);
             });
             if (e != hipSuccess)
                 return mfail(m, DD_ERR_HIP, std::string("multi-lattice sap launch: ") + hipGetErrorString(e));
@@ -872,7 +872,6 @@ dd_status dd_multi_create(const dd_params *params, int nlat, void *hip_stream, d
     bool ok = hipMalloc((void **)&m->counter, sizeof(int)) == hipSuccess &&
               hipMalloc((void **)&m->desc_dev, 3 * nlat * sizeof(dd::LatDesc)) == hipSuccess &&
               hipHostMalloc((void **)&m->desc_host, 3 * nlat * sizeof(dd::LatDesc), hipHostMallocDefault) == hipSuccess &&
-              hipMalloc((void **)&m->sap_dev, 2 * nlat * sizeof(dd::SapLat)) == hipSuccess &&
               hipHostMalloc((void **)&m->sap_host, 2 * nlat * sizeof(dd::SapLat), hipHostMallocDefault) == hipSuccess &&
               hipMalloc((void **)&m->red_all, 3 * nlat * sizeof(double)) == hipSuccess &&
               hipHostMalloc((void **)&m->red_all_host, 3 * nlat * sizeof(double), hipHostMallocDefault) == hipSuccess;
@@ -915,7 +914,6 @@ dd_status dd_multi_destroy(dd_multi *m)
     if (m->counter) (void)hipFree(m->counter);
     if (m->desc_dev) (void)hipFree(m->desc_dev);
     if (m->desc_host) (void)hipHostFree(m->desc_host);
-    if (m->sap_dev) (void)hipFree(m->sap_dev);
     if (m->sap_host) (void)hipHostFree(m->sap_host);
     if (m->red_all) (void)hipFree(m->red_all);
     if (m->red_all_host) (void)hipHostFree(m->red_all_host);
@@ -1016,9 +1014,6 @@ dd_status bicgstab_solve_multi(dd_multi *m, void *const *x_dev, const void *cons
                     item0 += dd::sap_multi_items(c->g);
                 }
             }
-        if (!m->sap_groups.empty())
-            MHIPCK(m, hipMemcpyAsync(m->sap_dev, m->sap_host, 2 * n * sizeof(dd::SapLat), hipMemcpyHostToDevice,
-                                     m->stream));
         MHIPCK(m, hipStreamSynchronize(m->stream));
     }
     std::vector<dd_solve_info> inf(n);

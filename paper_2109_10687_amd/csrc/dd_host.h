@@ -108,7 +108,7 @@ struct dd_multi {
         int items = 0;         // work items of a launch
         int off = 0;           // first table entry
     };
-    dd::SapLat *sap_dev = nullptr, *sap_host = nullptr;
+    dd::SapLat *sap_host = nullptr;  // the multi-lattice half-sweep tables (kernel arguments)
     std::vector<SapGroup> sap_groups;
     double *red_all = nullptr, *red_all_host = nullptr;  // three reduction results per lattice
 };

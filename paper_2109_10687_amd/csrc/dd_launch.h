@@ -156,6 +156,12 @@ struct SapLat {
     int item0;    // first work item of this lattice
 };
 
+constexpr int SAP_MULTI_MAX = 12;
+struct SapLatTab {
+    SapLat e[SAP_MULTI_MAX];
+    int n;
+};
+
 struct ForceArgs {
     const void *psi, *chi;  // FP64 internal-layout spinors
     const void *u64;        // FP64 links
@@ -218,11 +224,11 @@ hipError_t launch_sap_prep(const Geom &g, hipStream_t st, const void *cinv16, vo
 size_t sap_face_bytes(const Geom &g);
 hipError_t launch_sap_half_pk(const Geom &g, hipStream_t st, const SapArgs &a, int colour, int flags);
 // the table entry of one lattice for the multi-lattice half-sweep, the work items of one
-// lattice in it, and that launch: the nlat lattices of the table (device memory) share the
-// block shape of g, items = sap_multi_items summed over them
+// lattice in it, and that launch: the nlat lattices of the table (host memory; it travels in
+// the kernel arguments, SAP_MULTI_MAX lattices per launch) share the block shape of g
 SapLat sap_lat(const Geom &g, const SapArgs &a, int item0);
 int sap_multi_items(const Geom &g);
-hipError_t launch_sap_half_pk_multi(const Geom &g, hipStream_t st, const SapLat *lat, int nlat, int items, int colour,
+hipError_t launch_sap_half_pk_multi(const Geom &g, hipStream_t st, const SapLat *lat, int nlat, int colour,
                                     int flags);
 int blas_grid(const Geom &g);
 // grid of a grid-stride loop over the sites (one thread per site, at most BLAS_MAX_WG workgroups)

@@ -786,14 +786,16 @@ __global__ void __launch_bounds__(256) k_sap_half_pk(Geom gin, int colour, int f
 // The same half-sweep on several lattices of one block shape in one launch: the work items
 // are the workgroups' shares of the blocks of the swept colour (sap_multi_items per lattice),
 // numbered lattice by lattice (item0 of each table entry); a workgroup finds its lattice in
-// the table and sweeps its blocks there.  One right-hand side per lattice.
+// the table and sweeps its blocks there.  One right-hand side per lattice.  The table comes by
+// value in the kernel arguments, so the fields' pointers are known to be global ones (from a
+// table in device memory every access would be a flat one).
 template <int B>
-__global__ void __launch_bounds__(256) k_sap_half_pk_multi(const SapLat *lat, int nlat, int colour, int flags)
+__global__ void __launch_bounds__(256) k_sap_half_pk_multi(SapLatTab t, int colour, int flags)
 {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     int k = 0;
-    while (k + 1 < nlat && w >= lat[k + 1].item0) ++k;
-    const SapLat &L = lat[k];
+    while (k + 1 < t.n && w >= t.e[k + 1].item0) ++k;
+    const SapLat &L = t.e[k];
     SapRhs one{};
     one.n = 1;
     sap_half_pk_body<B, true>(L.g, w - L.item0, colour, flags, L.b, L.s, L.x, L.u16, L.cpsap, L.ph, L.kappa, L.n_jac, L.ft,
@@ -875,16 +877,26 @@ SapLat sap_lat(const Geom &g, const SapArgs &a, int item0)
 
 int sap_multi_items(const Geom &g) { return g.nblk / 2 / sap_blocks_per_wg(g.bvol); }
 
-hipError_t launch_sap_half_pk_multi(const Geom &g, hipStream_t st, const SapLat *lat, int nlat, int items, int colour,
-                                    int flags)
+hipError_t launch_sap_half_pk_multi(const Geom &g, hipStream_t st, const SapLat *lat, int nlat, int colour, int flags)
 {
-    if (nlat <= 0 || items <= 0) return hipSuccess;
+    if (nlat <= 0) return hipSuccess;
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
     const bool cube2 = g.b[0] == 2 && g.b[1] == 2 && g.b[2] == 2 && g.b[3] == 2;
     const int bpw = sap_blocks_per_wg(g.bvol);
-    hipLaunchKernelGGL(cube4 ? k_sap_half_pk_multi<4> : cube2 ? k_sap_half_pk_multi<2> : k_sap_half_pk_multi<0>, dim3(items), dim3(g.bvol * bpw),
-                       bpw * sap_pk_lds_bytes(g), st, lat, nlat, colour, flags);
-    return hipGetLastError();
+    auto kern = cube4 ? k_sap_half_pk_multi<4> : cube2 ? k_sap_half_pk_multi<2> : k_sap_half_pk_multi<0>;
+    for (int k0 = 0; k0 < nlat; k0 += SAP_MULTI_MAX) {  // up to SAP_MULTI_MAX lattices per launch
+        SapLatTab t{};
+        int items = 0;
+        for (; t.n < SAP_MULTI_MAX && k0 + t.n < nlat; ++t.n) {
+            t.e[t.n] = lat[k0 + t.n];
+            t.e[t.n].item0 = items;
+            items += sap_multi_items(t.e[t.n].g);
+        }
+        hipLaunchKernelGGL(kern, dim3(items), dim3(g.bvol * bpw), bpw * sap_pk_lds_bytes(g), st, t, colour, flags);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace dd
