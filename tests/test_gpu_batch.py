@@ -187,3 +187,27 @@ def test_sap_batch_matches_single_and_oracle(name, fp16_arith):
         err = rel_l2(xb[r], orc.sap(bs[r].cpu().numpy()))
         assert err < (3e-3 if fp16_arith else 1.2e-3), (r, err)
     s.close()
+
+
+def test_solve_multi_more_lattices_than_one_table_holds():
+    """Twenty lattices in one lockstep solve: more than one table launch of the vector kernels
+    (16 lattices each) and of the shared half-sweep (12 each).  Every lattice must reach the
+    requested true residual, recomputed by the oracle."""
+    specs = [((8, 8, 8, 8), (4, 4, 4, 4), 0.12 + 0.0005 * k, 1.0 + 0.05 * k) for k in range(18)]
+    specs += [((4, 4, 4, 4), (2, 2, 2, 2), 0.12, 1.0), ((4, 4, 4, 4), (2, 2, 2, 2), 0.118, 1.2)]
+    ops, gps, Us = [], [], []
+    for k, (dims, block, kappa, csw) in enumerate(specs):
+        ops.append(O.Params(dims=dims, kappa=kappa, csw=csw, block=block))
+        gps.append(dd.Params(dims=dims, kappa=kappa, csw=csw, block=block))
+        Us.append(synth.su3_links(dims, 0.3, 500 + k))
+    m = dd.Multi(gps)
+    for k, U in enumerate(Us):
+        m.load_gauge(k, U.cuda())
+    bs = [synth.gaussian_spinor(p.dims, 530 + k) for k, p in enumerate(ops)]
+    xs, infos = m.solve([b.cuda() for b in bs], tol=1e-10)
+    for k, (p, U, b, x, inf) in enumerate(zip(ops, Us, bs, xs, infos)):
+        assert inf["status"] == "DD_OK" and inf["relres_true"] < 1e-10, (k, inf)
+        orc = O.Oracle(p, U.numpy())
+        res = np.linalg.norm(orc.D(x.cpu().numpy()) - b.numpy()) / np.linalg.norm(b.numpy())
+        assert res < 1e-10, (k, res)
+    m.close()
