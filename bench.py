@@ -306,7 +306,7 @@ def single_prec_bench(dd, args, reps=3, apply_reps=20):
     (Alg. 5 on A M_SAP, FP32 SAP) to Alg. 5's single-precision tolerance 1e-6 on its recursive
     residual, against plain FP64 BiCGStab on D to a true residual of 1e-6 on the same GPU.  At this
     kappa plain BiCGStab breaks down before reaching 1e-6 on this ensemble: its time is then a lower
-    bound.  The FP32 apply of this lattice (0.8 GB per apply) partly stays in the 256 MB Infinity
+    bound.  The FP32 apply of this lattice (0.7 GB per apply) partly stays in the 256 MB Infinity
     Cache, so its GB/s are reported as such, not as HBM bandwidth."""
     import torch
     import synth
@@ -370,7 +370,7 @@ def single_prec_bench(dd, args, reps=3, apply_reps=20):
     r = s.timing_report()["dirac_f32"]
     s.timing(False)
     out["apply_f32_A"] = {"ms": round(r["ms"] / r["launches"], 4), "GBps": round(r["bytes"] / r["ms"] / 1e6, 1),
-                          "note": "partly Infinity-Cache resident (0.8 GB per apply against 256 MB): not an HBM figure"}
+                          "note": "partly Infinity-Cache resident (0.7 GB per apply against 256 MB): not an HBM figure"}
     s.close()
     del b, x, x64, fin, fout
     torch.cuda.synchronize()

@@ -74,7 +74,7 @@ dd_status dd_create(const dd_params *prm, void *hip_stream, dd_ctx **out)
     if (const char *v = std::getenv("DD_VERBOSE")) c->verbose = std::atoi(v);
 
     auto alloc = [&](void **p, size_t bytes) -> bool { return hipMalloc(p, bytes) == hipSuccess; };
-    bool ok = alloc(&c->U64, (size_t)V * 36 * 16) && alloc(&c->U32, (size_t)V * 36 * 8) &&
+    bool ok = alloc(&c->U64, (size_t)V * 36 * 16) && alloc(&c->U32, (size_t)V * 24 * 8) &&
               alloc(&c->U16, (size_t)V * 24 * 4) && alloc(&c->clov64, (size_t)V * 36 * 16) &&
               alloc(&c->cinv32, (size_t)V * 36 * 8) && alloc(&c->cinv16, (size_t)V * 36 * 4) &&
               alloc(&c->CPsap, (size_t)V * 36 * 4) &&

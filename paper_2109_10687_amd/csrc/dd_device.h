@@ -389,20 +389,6 @@ template <> struct LinkField<0> {
     }
 };
 
-template <> struct LinkField<1> {
-    const float2 *p;
-    template <typename R> DD_INL void load(const Geom &g, int l, int s, int mu, Mat3<R> &U) const
-    {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                float2 t = p[elem(g, l, s, 36, mu * 9 + a * 3 + b)];
-                U.m[a][b] = {R(t.x), R(t.y)};
-            }
-    }
-};
-
 // third row of an SU(3) matrix from its first two: conj(row0 x row1)
 template <typename R> DD_INL void su3_row3(Mat3<R> &U)
 {
@@ -410,6 +396,29 @@ template <typename R> DD_INL void su3_row3(Mat3<R> &U)
     U.m[2][1] = conj(U.m[0][2] * U.m[1][0] - U.m[0][0] * U.m[1][2]);
     U.m[2][2] = conj(U.m[0][0] * U.m[1][1] - U.m[0][1] * U.m[1][0]);
 }
+
+// FP32 links: rows 0 and 1 as stored (12 reals, elem(l, s, 24, mu * 6 + a * 3 + b)), row 2
+// rebuilt in FP32 (the traffic of the FP32 and FP16-input applies is HBM-bound; the
+// rebuild is ALU work they have to spare)
+template <> struct LinkField<1> {
+    const float2 *p;
+    template <typename R> DD_INL void load(const Geom &g, int l, int s, int mu, Mat3<R> &U) const
+    {
+        Mat3<float> W;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                float2 t = p[elem(g, l, s, 24, mu * 6 + a * 3 + b)];
+                W.m[a][b] = {t.x, t.y};
+            }
+        su3_row3(W);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) U.m[a][b] = {R(W.m[a][b].re), R(W.m[a][b].im)};
+    }
+};
 
 template <> struct LinkField<2> {
     const __half2 *p;

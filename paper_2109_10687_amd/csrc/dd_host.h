@@ -167,7 +167,7 @@ inline size_t spinor_bytes(const Geom &g, int prec)
 
 // ---- algorithmic bytes and flops per site (each field read or written once)
 inline double sp_b(int prec) { return prec == 0 ? 192.0 : prec == 1 ? 96.0 : 52.0; }   // spinor (+ FP16 scale)
-inline double lk_b(int prec) { return prec == 0 ? 144.0 : prec == 1 ? 72.0 : 24.0; }    // one link (FP16: 12 reals)
+inline double lk_b(int prec) { return prec == 0 ? 144.0 : prec == 1 ? 48.0 : 24.0; }    // one link (FP32, FP16: 12 reals)
 inline double cl_b(int prec) { return prec == 0 ? 576.0 : prec == 1 ? 288.0 : 144.0; }  // clover / C_inv block pair
 constexpr double HOPF[4] = {168, 168, 168, 156};                                            // flops of one hop per direction
 constexpr double CLOVF = 600;                                                      // clover multiply + combine

@@ -62,8 +62,8 @@ __global__ void __launch_bounds__(256) k_unpack_spinor(Geom g, double2 *dst, Spi
         for (int c = 0; c < 3; ++c) dst[n * 12 + c * 4 + a] = make_double2(x.v[a][c].re, x.v[a][c].im);
 }
 
-// canonical links [4][Lt][Lz][Ly][Lx][3][3] -> FP64, FP32 (18 reals) and FP16
-// (rows 0 and 1); flags non-finite entries
+// canonical links [4][Lt][Lz][Ly][Lx][3][3] -> FP64 (18 reals), FP32 and FP16 (rows 0 and
+// 1, 12 reals); flags non-finite entries
 __global__ void __launch_bounds__(256)
     k_pack_links(Geom g, const double2 *src, double2 *u64, float2 *u32, __half2 *u16, int *bad)
 {
@@ -80,8 +80,10 @@ __global__ void __launch_bounds__(256)
             double2 t = m[e];
             if (!isfinite(t.x) || !isfinite(t.y)) nonfinite = 1;
             u64[elem(g, st.l, st.s, 36, mu * 9 + e)] = t;
-            u32[elem(g, st.l, st.s, 36, mu * 9 + e)] = make_float2((float)t.x, (float)t.y);
-            if (e < 6) u16[elem(g, st.l, st.s, 24, mu * 6 + e)] = __floats2half2_rn((float)t.x, (float)t.y);
+            if (e < 6) {
+                u32[elem(g, st.l, st.s, 24, mu * 6 + e)] = make_float2((float)t.x, (float)t.y);
+                u16[elem(g, st.l, st.s, 24, mu * 6 + e)] = __floats2half2_rn((float)t.x, (float)t.y);
+            }
         }
     }
     if (nonfinite) atomicOr(bad, 1);

@@ -39,6 +39,18 @@ struct Cf {
 DD_INL Cf cadd(Cf a, Cf b) { return {a.re + b.re, a.im + b.im}; }
 DD_INL Cf cmul(Cf a, Cf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 DD_INL Cf cmulc_(Cf a, Cf b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }  // conj(a) b
+DD_INL Cf ld2(const float2 *p);
+
+// entry (a, b) of an FP32 link stored as rows 0 and 1; row 2 = conj(row0 x row1)
+DD_INL Cf link32(const float2 *u, const Geom &g, int l, int s, int mu, int a, int b)
+{
+    auto e = [&](int r, int c) { return ld2(&u[elem(g, l, s, 24, mu * 6 + r * 3 + c)]); };
+    if (a < 2) return e(a, b);
+    const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+    const Cf p = e(0, b1), q = e(1, b2), r = e(0, b2), t = e(1, b1);
+    return {p.re * q.re - p.im * q.im - r.re * t.re + r.im * t.im, -(p.re * q.im + p.im * q.re - r.re * t.im - r.im * t.re)};
+}
+
 DD_INL Cf ld2(const float2 *p)
 {
     float2 t = *p;
@@ -108,8 +120,7 @@ __global__ void __launch_bounds__(WGS) k_dirac_mrhs(Geom gin, MrhsArgs a)
 #pragma unroll
                         for (int kk = 0; kk < 3; ++kk) {
                             // W[rr][kk]: U[rr][kk] or conj(U[kk][rr])
-                            const int e = dir > 0 ? rr * 3 + kk : kk * 3 + rr;
-                            Cf u = ld2(&a.u[elem(g, ll, ss, 36, mu * 9 + e)]);
+                            Cf u = dir > 0 ? link32(a.u, g, ll, ss, mu, rr, kk) : link32(a.u, g, ll, ss, mu, kk, rr);
                             if (dir < 0) u.im = -u.im;
                             // real form [[Re, -Im], [Im, Re]]
                             A[mt][kk] = pad ? 0.f : (rim ? u.im : u.re);
