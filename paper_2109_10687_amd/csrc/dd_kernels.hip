@@ -287,6 +287,17 @@ __global__ void __launch_bounds__(256) k_dirac(Geom gin, SpinorField<POUT> out, 
 // by the next step rather than kept in LDS: the neighbouring columns read it at that time too
 // (their x, y and z faces), and those reads then share the L2 lines (measured: keeping it was
 // no faster).
+// Columns are taken x fastest, then the two columns of a z pair, then y, then the z pairs:
+// consecutive workgroups (which one XCD runs side by side) then hold a column's x neighbours,
+// its y neighbours 2 NB_x items away and, for one of its two z faces, its z neighbour NB_x
+// items away, so those faces come from the L2 while the neighbour's block is still there.  A
+// face's sites are short runs of a block's site-major storage (four sites for a y face,
+// sixteen for a z face), so a face read that misses the L2 fetches whole lines of which it
+// uses a quarter or a half.  Against the plain lexicographic order (whose z neighbours are
+// NB_x NB_y items away) with walks of 4, this order with walks of 2 takes 64^3x128 from 4.39
+// to 4.26-4.29 ms (FP16-input A), 5.20-5.22 to 5.12-5.14 ms (FP32 A) and 10.43-10.46 to
+// 10.33-10.39 ms (FP64 D); 2x2 or 4x4 tiles of (y, z) columns and longer z runs gain less or
+// lose.
 // The hop order and arithmetic are those of dirac_site; results agree to FP32 (FP64) rounding,
 // not bit for bit, since the compiler fuses multiply-adds differently in the two kernels.
 template <int P> struct StoreT;
@@ -336,7 +347,17 @@ __global__ void __launch_bounds__(256) k_dirac_ts(Geom gin, SpinorField<POUT> ou
     wg_skew();
     const int ncol = g.bstride[3];
     const int w = xcd_remap(blockIdx.x, gridDim.x);
-    const int seg = w / ncol, col = w - seg * ncol;  // consecutive items: neighbouring columns
+    const int seg = w / ncol, q = w - seg * ncol;
+    int col;  // item q -> column: x fastest, then z within a pair, then y, then the z pair
+    {
+        const int nx = g.NB[0], ny = g.NB[1];
+        int r = q / nx;
+        const int bx = q - r * nx;
+        const int zl = r & 1;
+        r >>= 1;
+        const int zp = r / ny, by = r - zp * ny;
+        col = bx + nx * (by + ny * (2 * zp + zl));
+    }
     const int s = threadIdx.x, tw = __builtin_amdgcn_readfirstlane(s >> 6);  // t' of the site: one per wavefront
     // the FP16 scale of internal site i (FP32 / FP64 inputs have none)
     auto scale_at = [&](long long i) -> const float * {
@@ -1255,15 +1276,14 @@ hipError_t launch_clover(const Geom &g, hipStream_t st, const void *u64, const S
     return hipGetLastError();
 }
 
-// blocks per workgroup of the t-streamed apply, 0 for a block per workgroup: 4, else 2 (the
-// blocks in t are even), as long as that leaves 1024 workgroups (four per CU) to fill the chip;
-// smaller lattices keep a block per workgroup.  Measured on 64^3x128: walks of 4 beat 2, 8 and 32
-// by 2-4 %; longer walks let the workgroups of neighbouring columns drift apart.
+// blocks per workgroup of the t-streamed apply, 0 for a block per workgroup: 2 (the blocks in t
+// are even) as long as that leaves 1024 workgroups (four per CU) to fill the chip; smaller
+// lattices keep a block per workgroup.  Measured on 64^3x128 with the z-pair column order: walks
+// of 2 beat 4 (FP64 D by 2 %, the others by up to 0.5 %) and 8; longer walks let the workgroups
+// of neighbouring columns drift apart.
 static int dirac_stream_len(const Geom &g)
 {
-    for (int ns = 4; ns > 1; ns >>= 1)
-        if (g.NB[3] % ns == 0 && g.nblk / ns >= 1024) return ns;
-    return 0;
+    return g.nblk / 2 >= 1024 ? 2 : 0;
 }
 
 // one operator / precision combination: the t-streamed kernel where dirac_stream_len allows it
