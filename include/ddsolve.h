@@ -148,8 +148,10 @@ typedef struct {
     int no_fallback;    /* DD_SOLVE_MIXED / DD_SOLVE_MIXED_GCR: 0 (default) falls back in
                            precision when a defect-correction pass stagnates or its inner
                            solve breaks down (the mode's FP16-SAP inner solve, then FP32
-                           SAP-BiCGStab, then plain FP64 BiCGStab from the current x);
-                           1 returns DD_BREAKDOWN there instead                       */
+                           SAP-BiCGStab, then plain FP64 BiCGStab from the current x),
+                           except that the first such pass of a level that still cut the
+                           true residual 10x is followed by a restarted pass of the same
+                           level; 1 returns DD_BREAKDOWN there instead                */
     int debug_flags;    /* forces failures from the host, for tests: DD_DEBUG_ZERO_OMEGA_F16
                            sets omega = 0 in every FP16-SAP BiCGStab iteration,
                            DD_DEBUG_ZERO_OMEGA_F32 in every FP32-SAP one (0 = none)   */
@@ -237,7 +239,9 @@ dd_status sap_precondition_amsap(dd_ctx *ctx, void *ax_dev, const void *b_dev, d
  * DD_SOLVE_FGMRES.  In the two defect-correction modes a pass that
  * stagnates or whose inner solve breaks down switches the remaining passes to
  * the FP32 SAP-BiCGStab, and a second such pass to plain FP64 BiCGStab from
- * the current x, capped at inner_maxiter iterations (unless
+ * the current x, capped at inner_maxiter iterations; the first such pass of a
+ * level that still cut the true residual 10x restarts that level once instead
+ * (unless
  * dd_params.no_fallback; info->precision_level tells which level ended the
  * solve).  Returns DD_OK, DD_NOT_CONVERGED or DD_BREAKDOWN
  * (x then holds the best iterate) and fills info (may be NULL).  A source

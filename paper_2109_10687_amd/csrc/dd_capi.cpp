@@ -305,6 +305,7 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
         int stall = 0, outer = 0;
         // 0: the mode's own inner solver (FP16 SAP), 1: FP32 SAP-BiCGStab, 2: plain FP64 BiCGStab
         int level = 0;
+        bool restarted = false;  // this level has had its one restart after a broken-down pass
         // a stagnating pass or a broken-down inner solve: fall back one level, or stop
         auto give_up = [&](int detail) -> bool {
             if (c->prm.no_fallback || level == 2) {
@@ -314,6 +315,7 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
             }
             ++level;
             stall = 0;
+            restarted = false;
             if (c->verbose) {
                 std::fprintf(stderr, "[ddsolve] falling back to %s after outer pass %d\n",
                              level == 1 ? "FP32 SAP-BiCGStab" : "plain FP64 BiCGStab", outer);
@@ -338,8 +340,13 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
                 ++outer;
                 inf.iters_inner_total += o.iters;
                 inf.relres_inner_last = o.relres;
+                const double before = rn2;
                 if ((st = residual64(c, r, b, x, tmp, &rn2)) != DD_OK) return st;
                 c->hist_outer.push_back(std::sqrt(rn2 / bn2));
+                if (sp == DD_BREAKDOWN && !restarted && rn2 <= 1e-2 * before) {
+                    restarted = true;  // broke down after a 10x gain: restart once from the new x
+                    continue;
+                }
                 if (sp != DD_OK || std::sqrt(rn2 / bn2) >= tol) {
                     res = sp == DD_OK ? DD_NOT_CONVERGED : sp;
                     inf.status_detail = o.detail;
@@ -379,15 +386,22 @@ static dd_status solve_entry(dd_ctx *c, void *x_dev, const void *b_dev, double t
                 std::fflush(stderr);
             }
             if (si == DD_BREAKDOWN && std::sqrt(rn2 / bn2) >= tol) {
-                // the inner solve broke down or stagnated (its stall window): the next passes
-                // run one level up; without the fallback, a stagnated pass that gained less
-                // than 10x ends the solve (further passes would crawl at that rate)
+                // the inner solve broke down or stagnated (its stall window).  The first time
+                // at a level, a pass that still gained 10x is followed by a pass of the same
+                // inner solver (restarted, with a fresh shadow residual, as after any pass);
+                // otherwise the next passes run one level up.  Without the fallback, a
+                // stagnated pass that gained less than 10x ends the solve (further passes
+                // would crawl at that rate)
+                const bool gained = rn2 <= 1e-2 * prev;
                 if (!c->prm.no_fallback && level < 2) {
-                    prev = rn2;
-                    give_up(o.detail);
-                    continue;
-                }
-                if (o.detail == DETAIL_INNER_STALL && rn2 > 1e-2 * prev) {
+                    if (gained && !restarted) {
+                        restarted = true;
+                    } else {
+                        prev = rn2;
+                        give_up(o.detail);
+                        continue;
+                    }
+                } else if (o.detail == DETAIL_INNER_STALL && !gained) {
                     inf.status_detail = DETAIL_INNER_STALL;
                     res = DD_BREAKDOWN;
                     break;

@@ -883,7 +883,8 @@ __global__ void __launch_bounds__(BLAS_WG) k_update1_h(Geom g, SpinorField<1> r,
     update1_h_body(g, r, q, r16, are, aim, partials, blockIdx.x, gridDim.x);
 }
 
-// x += alpha y1 + omega y2 ; r -= omega t ; partial |r|^2 and <rt|r>
+// x += alpha y1 + omega y2 ; r -= omega t ; partial |r|^2 and <rt|r>.  A thread takes whole sites (as the other
+// updates do): an FP16 operand's scale is read once per site, and no element index is divided back into its site.
 template <int PY>
 DD_INL void update2_mm_body(const Geom &g, SpinorField<1> x, SpinorField<PY> y1, SpinorField<PY> y2, SpinorField<1> r,
                             SpinorField<1> t, SpinorField<1> rt, double are, double aim, double ore, double oim,
@@ -891,16 +892,28 @@ DD_INL void update2_mm_body(const Geom &g, SpinorField<1> x, SpinorField<PY> y1,
 {
     double v[3] = {0, 0, 0};
     const cx<double> al = {are, aim}, om = {ore, oim};
-    GRID_STRIDE_W(o, 12 * g.V)
+    SITE_STRIDE_W(i)
     {
-        Elem<1>::put(x, g, o, Elem<1>::get(x, g, o) + al * Elem<PY>::get(y1, g, o) + om * Elem<PY>::get(y2, g, o));
-        cx<double> rr = Elem<1>::get(r, g, o) - om * Elem<1>::get(t, g, o);
-        Elem<1>::put(r, g, o, rr);
-        rr = Elem<1>::get(r, g, o);
-        v[0] += norm2(rr);
-        const cx<double> d = cmulc(Elem<1>::get(rt, g, o), rr);
-        v[1] += d.re;
-        v[2] += d.im;
+        const int l = (int)(i >> g.lbvol), s = (int)(i & (g.bvol - 1));
+        Spinor<float> u1, u2;  // as stored (FP16: times the site scale, in FP32)
+        y1.load(g, l, s, u1);
+        y2.load(g, l, s, u2);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long long o = elem(g, l, s, 12, a * 3 + c);
+                const cx<double> w1 = {(double)u1.v[a][c].re, (double)u1.v[a][c].im};
+                const cx<double> w2 = {(double)u2.v[a][c].re, (double)u2.v[a][c].im};
+                Elem<1>::put(x, g, o, Elem<1>::get(x, g, o) + al * w1 + om * w2);
+                const cx<double> rr = Elem<1>::get(r, g, o) - om * Elem<1>::get(t, g, o);
+                Elem<1>::put(r, g, o, rr);
+                const cx<double> rs = {(double)(float)rr.re, (double)(float)rr.im};  // the stored (rounded) value
+                v[0] += norm2(rs);
+                const cx<double> d = cmulc(Elem<1>::get(rt, g, o), rs);
+                v[1] += d.re;
+                v[2] += d.im;
+            }
     }
     wg_reduce_store_at<3>(v, partials, wid);
 }

@@ -201,8 +201,10 @@ def test_32x32x32x32_mixed_fp16_sap_stagnation(no_fallback):
     this ensemble): the inner stall window (200 iterations without a 10x drop of the recursive
     residual) ends the inner solve.  Without the precision fallback the defect correction goes on
     at the FP16 SAP while each pass gains at least 10x, and stops with a status otherwise, within
-    seconds, x the best iterate.  With it, the passes after the first stalled one run the FP32
-    SAP-BiCGStab and reach 1e-10, confirmed by the oracle's residual over the whole lattice.
+    seconds, x the best iterate.  With it, the FP16 level (after at most one restarted pass) hands
+    over to the FP32 SAP-BiCGStab, which reaches 1e-10 (a broken-down FP32 pass that still gained
+    10x is restarted once rather than handed to plain FP64, which fails at this kappa), confirmed by
+    the oracle's residual over the whole lattice.
     Either way the outer residual history is monotone."""
     import time
     dims = (32, 32, 32, 32)
