@@ -136,8 +136,9 @@ def test_fgmres_cycle_of_one_restarts_and_maxiter_caps():
                                          (dd.DD_DEBUG_ZERO_OMEGA_F16 | dd.DD_DEBUG_ZERO_OMEGA_F32, 2)])
 def test_precision_fallback_after_forced_breakdown(flags, level):
     """omega forced to zero from the host in every FP16-SAP inner iteration (and in every FP32-SAP
-    one): the first pass of each level breaks down, the solve falls back to FP32 SAP-BiCGStab (then
-    to plain FP64 BiCGStab) and still reaches 1e-10, checked by the oracle's residual."""
+    one): every pass of such a level breaks down after its first half step (a pass that still gained
+    10x is restarted once), the solve falls back to FP32 SAP-BiCGStab (then to plain FP64 BiCGStab)
+    and still reaches 1e-10, checked by the oracle's residual."""
     dims, kappa, csw = (8, 8, 8, 8), 0.13, 1.5
     U = synth.su3_links(dims, 0.3, 41)
     s = dd.Solver(dd.Params(dims=dims, kappa=kappa, csw=csw, debug_flags=flags), U.cuda())
