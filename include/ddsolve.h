@@ -331,9 +331,12 @@ typedef enum { DD_BATCH_INNER_SAP = 0, DD_BATCH_INNER_PLAIN = 1 } dd_batch_inner
  * 3x3 link times 3x(2 x 12) half-spinor product runs on the matrix cores
  * (sixteen sites per wavefront, one 4x4x1 block per site), or, in the
  * vector variants, each thread takes one site and 1-4 right-hand sides and
- * loads the links and C_inv once for them.  The kernel variant (matrix-core:
- * right-hand sides per pass and workgroup size; vector: right-hand sides per
- * thread) is picked by timing every variant on the first call for each tile
+ * loads the links and C_inv once for them, or, in the resident-field variant
+ * (4^4 blocks), a workgroup holds its block's links and C_inv for the whole
+ * tile and takes the right-hand sides in turn.  The kernel variant
+ * (matrix-core: right-hand sides per pass and workgroup size; vector:
+ * right-hand sides per thread; resident) is picked by timing every variant on
+ * the first call for each tile
  * size, unless dd_batch_set_variant forced one.  The SAP-preconditioned
  * batched solve reads FP16-storage fields and tunes the vector variants for
  * them separately (a forced matrix-core variant leaves that choice to its
@@ -355,9 +358,10 @@ dd_status dirac_apply_batch(dd_ctx *ctx, void *out_dev, const void *in_dev, int 
  * fails).  Asynchronous. */
 dd_status sap_precondition_batch(dd_ctx *ctx, void *x_dev, const void *b_dev, int nrhs);
 
-/* Force the batched kernel variant (0 .. 11: 0-7 matrix-core, 8-11 vector
- * with 1-4 right-hand sides per thread), or -1 to let the autotuner choose
- * (the default). */
+/* Force the batched kernel variant (0 .. 12: 0-7 matrix-core, 8-11 vector
+ * with 1-4 right-hand sides per thread, 12 resident links and C_inv with the
+ * right-hand sides in turn, for 4^4 blocks, else as 8), or -1 to let the
+ * autotuner choose (the default). */
 dd_status dd_batch_set_variant(dd_ctx *ctx, int variant);
 
 /* The variant in use for tiles of nrhs (1..12) right-hand sides of FP32

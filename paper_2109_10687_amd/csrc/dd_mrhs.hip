@@ -343,12 +343,134 @@ __global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom gin, MrhsArgs a)
     }
 }
 
+// The batched A with the block's links and C_inv resident for the whole tile (4^4 blocks): a
+// workgroup per block, a thread per site.  The block's forward links (their two stored rows)
+// are staged in LDS, where the in-block backward hops find them as well, and each thread keeps
+// its C_inv blocks in registers.  The right-hand sides then follow one another: each is staged
+// in LDS as stored (FP16 with its site scales, or FP32); in-block neighbours and backward links
+// are read from LDS and the others (sites on the block's faces) from global memory through the
+// same load, since both hold a site's elements 256 apart; row 2 of a link is rebuilt where it is
+// used.  The vector kernels read every link and C_inv block again, from L2, for each group of
+// right-hand sides; here the block's own fields are read once per tile, and a right-hand side
+// costs its own spinor, its cross-block neighbours (with their links) and the output.
+template <int PIN> struct ResT;
+template <> struct ResT<1> { using T = float2; };
+template <> struct ResT<2> { using T = __half2; };
+
+template <int PIN>
+__global__ void __launch_bounds__(256) k_dirac_rhs_res(Geom gin, MrhsArgs a)
+{
+    using T = typename ResT<PIN>::T;
+    const Geom g = fixed_shape<4>(gin);
+    __shared__ float2 lk[4][6][256];  // rows 0 and 1 of U_mu at each site of the block
+    __shared__ T tile[12][256];       // the right-hand side in turn, as stored
+    __shared__ float tsc[PIN == 2 ? 256 : 1];
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = threadIdx.x;
+    Site st;
+    decode(g, ((long long)w << 8) + s, st);
+    const long long RS = 12 * g.V;
+    auto elems = [&](int r) -> const T * {
+        if constexpr (PIN == 1)
+            return a.in + r * RS;
+        else
+            return (const T *)((const char *)a.in16 + r * g.V * (12 * sizeof(__half2) + sizeof(float)));
+    };
+    auto scales = [&](int r) -> const float * {
+        if constexpr (PIN == 1)
+            return nullptr;
+        else
+            return (const float *)(elems(r) + RS);
+    };
+    // the block's fields, once for the tile
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int e = 0; e < 6; ++e) lk[mu][e][s] = a.u[elem(g, st.l, s, 24, mu * 6 + e)];
+    Clov<float> cl;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            float2 t = a.cinv[elem(g, st.l, s, 36, b * 18 + jj)];
+            cl.d[b][2 * jj] = t.x;
+            cl.d[b][2 * jj + 1] = t.y;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 15; ++jj) {
+            float2 t = a.cinv[elem(g, st.l, s, 36, b * 18 + 3 + jj)];
+            cl.h[b][jj] = {t.x, t.y};
+        }
+    }
+    // one stored spinor from 12 elements 256 apart (LDS or global) and its scale
+    auto get = [&](const T *p, const float *sp, Spinor<float> &x) {
+        const float sc = PIN == 2 ? *sp : 1.f;
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+            float2 t;
+            if constexpr (PIN == 2)
+                t = __half22float2(p[e * 256]);
+            else
+                t = p[e * 256];
+            x.v[e / 3][e % 3] = {t.x * sc, t.y * sc};
+        }
+    };
+    for (int r = 0; r < a.nrhs; ++r) {
+        wg_barrier();  // the fields are staged; the previous right-hand side is done with the tile
+        // the site is decoded afresh for each right-hand side, from an index the compiler cannot
+        // follow across them: otherwise it keeps every hop's addresses in registers throughout
+        int sl = s;
+        asm volatile("" : "+v"(sl));
+        decode(g, ((long long)w << 8) + sl, st);
+        {
+            const T *p = elems(r) + elem(g, st.l, s, 12, 0);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) tile[e][s] = p[e * 256];
+            if constexpr (PIN == 2) tsc[s] = scales(r)[((long long)st.l << 8) + s];
+        }
+        wg_barrier();
+        Spinor<float> acc;
+        zero(acc);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+            for (int dir = 1; dir >= -1; dir -= 2) {
+                bool wrap, inblk;
+                const long long j = neighbour(g, st, mu, dir, wrap, inblk);
+                const int lj = (int)(j >> 8), sj = (int)(j & 255);
+                Spinor<float> psi;
+                get(inblk ? &tile[0][sj] : elems(r) + elem(g, lj, sj, 12, 0),
+                    PIN == 2 ? (inblk ? &tsc[sj] : scales(r) + j) : nullptr, psi);
+                Mat3<float> W;
+                const float2 *lp = dir > 0 ? &lk[mu][0][s] : inblk ? &lk[mu][0][sj] : a.u + elem(g, lj, sj, 24, mu * 6);
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    const float2 t = lp[e * 256];
+                    W.m[e / 3][e % 3] = {t.x, t.y};
+                }
+                su3_row3(W);
+                const cx<float> phase = {(float)a.phase.re[mu], (float)(dir > 0 ? a.phase.im[mu] : -a.phase.im[mu])};
+                hop(mu, dir, W, psi, wrap, phase, acc);
+            }
+        }
+        Spinor<float> x, t, o;
+        get(&tile[0][s], PIN == 2 ? &tsc[s] : nullptr, x);
+        clover_mul(cl, acc, t);
+#pragma unroll
+        for (int aa = 0; aa < 4; ++aa)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.v[aa][c] = x.v[aa][c] - (float)a.kappa * t.v[aa][c];
+        SpinorField<1>{a.out + r * RS}.store(g, st.l, s, o, true);
+    }
+}
+
 // variants 0-7: column tiles per pass (1, 2, 3 or 6: 2, 4, 6 or 12 right-hand sides per
 // pass) x workgroup size (64 or 256 threads); variants 8-11: the vector kernel above with
-// 1, 2, 3 or 4 right-hand sides per thread.  Fewer right-hand sides per pass or thread
+// 1, 2, 3 or 4 right-hand sides per thread; variant 12: the resident-field kernel (4^4 blocks;
+// other block shapes run variant 8 in its place).  Fewer right-hand sides per pass or thread
 // need fewer registers, so more wavefronts hide the load latency, at the price of
 // reading the links and C_inv more often.
-int mrhs_variant_count() { return 12; }
+int mrhs_variant_count() { return 13; }
 
 const char *mrhs_variant_name(int v)
 {
@@ -357,8 +479,9 @@ const char *mrhs_variant_name(int v)
                                   "mfma4x4x1 6 rhs/pass, 64-thread wg",  "mfma4x4x1 6 rhs/pass, 256-thread wg",
                                   "mfma4x4x1 12 rhs/pass, 64-thread wg", "mfma4x4x1 12 rhs/pass, 256-thread wg",
                                   "vector, 1 rhs per thread",            "vector, 2 rhs per thread",
-                                  "vector, 3 rhs per thread",            "vector, 4 rhs per thread"};
-    return (v >= 0 && v < 12) ? names[v] : "?";
+                                  "vector, 3 rhs per thread",            "vector, 4 rhs per thread",
+                                  "resident links and C_inv, rhs in turn"};
+    return (v >= 0 && v < 13) ? names[v] : "?";
 }
 
 // the vector kernel with NR right-hand sides per thread, FP32 or FP16 inputs
@@ -371,6 +494,16 @@ template <int PIN, int NR> static void launch_vec(const Geom &g, hipStream_t st,
         hipLaunchKernelGGL((k_dirac_rhs_vec<0, PIN, NR>), G, T, 0, st, g, a);
 }
 
+// the resident-field kernel: a workgroup per 4^4 block; other block shapes take the vector
+// kernel with one right-hand side per thread
+template <int PIN> static void launch_res(const Geom &g, hipStream_t st, const MrhsArgs &a, bool cube4)
+{
+    if (cube4)
+        hipLaunchKernelGGL((k_dirac_rhs_res<PIN>), dim3((unsigned)g.nblk), dim3(256), 0, st, g, a);
+    else
+        launch_vec<PIN, 1>(g, st, a, cube4);
+}
+
 hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, int variant)
 {
     auto grid = [&](int wgs) { return dim3((unsigned)((g.V * 4 + wgs - 1) / wgs)); };
@@ -379,6 +512,7 @@ hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, i
     const bool cube4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
     if (a.pin == 2) {  // FP16-storage inputs: the vector kernels only
         switch (variant) {
+        case 12: launch_res<2>(g, st, a, cube4); break;
         case 9: launch_vec<2, 2>(g, st, a, cube4); break;
         case 10: launch_vec<2, 3>(g, st, a, cube4); break;
         case 11: launch_vec<2, 4>(g, st, a, cube4); break;
@@ -396,6 +530,7 @@ hipError_t launch_dirac_mrhs(const Geom &g, hipStream_t st, const MrhsArgs &a, i
     case 5: hipLaunchKernelGGL((k_dirac_mrhs<3, 256, 0>), grid(256), dim3(256), 0, st, g, a); break;
     case 6: hipLaunchKernelGGL((k_dirac_mrhs<6, 64, 0>), grid(64), dim3(64), 0, st, g, a); break;
     case 7: hipLaunchKernelGGL((k_dirac_mrhs<6, 256, 0>), grid(256), dim3(256), 0, st, g, a); break;
+    case 12: launch_res<1>(g, st, a, cube4); break;
     case 9: launch_vec<1, 2>(g, st, a, cube4); break;
     case 10: launch_vec<1, 3>(g, st, a, cube4); break;
     case 11: launch_vec<1, 4>(g, st, a, cube4); break;

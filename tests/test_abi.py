@@ -118,10 +118,10 @@ def test_debug_flags_follow_the_header():
 
 
 def test_batch_variant_names():
-    names = [dd.dd_batch_variant_name(v) for v in range(12)]
-    assert all(n and n != "?" for n in names) and len(set(names)) == 12
-    assert any("mfma" in n for n in names) and any("vector" in n for n in names)
-    assert dd.dd_batch_variant_name(-1) == "?" and dd.dd_batch_variant_name(12) == "?"
+    names = [dd.dd_batch_variant_name(v) for v in range(13)]
+    assert all(n and n != "?" for n in names) and len(set(names)) == 13
+    assert any("mfma" in n for n in names) and any("vector" in n for n in names) and any("resident" in n for n in names)
+    assert dd.dd_batch_variant_name(-1) == "?" and dd.dd_batch_variant_name(13) == "?"
 
 
 def test_multi_create_checks_every_lattice_without_gpu():

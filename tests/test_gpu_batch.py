@@ -43,7 +43,7 @@ def rel_l2(a, b):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("variant", [-1] + list(range(12)))
+@pytest.mark.parametrize("variant", [-1] + list(range(13)))
 def test_apply_batch_fp32_matches_oracle(name, variant):
     op, gp, U, orc, s = setup(name)
     s.batch_variant(variant)
@@ -60,7 +60,7 @@ def test_apply_batch_fp32_matches_oracle(name, variant):
         s.batch_variant(-1)
     if variant == -1:
         t = s.batch_tuning(12)
-        assert t["variant"] >= 0 and t["timed"] == 12
+        assert t["variant"] >= 0 and t["timed"] == 13
         assert t["ms"][t["name"]] == min(t["ms"].values())
         print(f"{name}: autotuner picked '{t['name']}' from {t['ms']}")
 
