@@ -348,9 +348,8 @@ __global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom gin, MrhsArgs a)
 // are staged in LDS, where the in-block backward hops find them as well, and each thread keeps
 // its C_inv blocks in registers.  The right-hand sides then follow one another: each is staged
 // in LDS as stored (FP16 with its site scales, or FP32); in-block neighbours and backward links
-// are read from LDS and the others (sites on the block's faces) from global memory through the
-// same load, since both hold a site's elements 256 apart; row 2 of a link is rebuilt where it is
-// used.  The vector kernels read every link and C_inv block again, from L2, for each group of
+// are read from LDS and the others (sites on the block's faces) from global memory; row 2 of a
+// link is rebuilt where it is used.  The vector kernels read every link and C_inv block again, from L2, for each group of
 // right-hand sides; here the block's own fields are read once per tile, and a right-hand side
 // costs its own spinor, its cross-block neighbours (with their links) and the output.
 template <int PIN> struct ResT;
@@ -438,15 +437,24 @@ __global__ void __launch_bounds__(256) k_dirac_rhs_res(Geom gin, MrhsArgs a)
                 bool wrap, inblk;
                 const long long j = neighbour(g, st, mu, dir, wrap, inblk);
                 const int lj = (int)(j >> 8), sj = (int)(j & 255);
+                // in-block neighbours from LDS, the others from global memory (two paths: a
+                // pointer that may be either would make every read a flat load)
                 Spinor<float> psi;
-                get(inblk ? &tile[0][sj] : elems(r) + elem(g, lj, sj, 12, 0),
-                    PIN == 2 ? (inblk ? &tsc[sj] : scales(r) + j) : nullptr, psi);
                 Mat3<float> W;
-                const float2 *lp = dir > 0 ? &lk[mu][0][s] : inblk ? &lk[mu][0][sj] : a.u + elem(g, lj, sj, 24, mu * 6);
+                if (inblk) {
+                    get(&tile[0][sj], PIN == 2 ? &tsc[sj] : nullptr, psi);
 #pragma unroll
-                for (int e = 0; e < 6; ++e) {
-                    const float2 t = lp[e * 256];
-                    W.m[e / 3][e % 3] = {t.x, t.y};
+                    for (int e = 0; e < 6; ++e) {
+                        const float2 t = lk[mu][e][dir > 0 ? s : sj];
+                        W.m[e / 3][e % 3] = {t.x, t.y};
+                    }
+                } else {
+                    get(elems(r) + elem(g, lj, sj, 12, 0), PIN == 2 ? scales(r) + j : nullptr, psi);
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) {
+                        const float2 t = dir > 0 ? lk[mu][e][s] : a.u[elem(g, lj, sj, 24, mu * 6 + e)];
+                        W.m[e / 3][e % 3] = {t.x, t.y};
+                    }
                 }
                 su3_row3(W);
                 const cx<float> phase = {(float)a.phase.re[mu], (float)(dir > 0 ? a.phase.im[mu] : -a.phase.im[mu])};
