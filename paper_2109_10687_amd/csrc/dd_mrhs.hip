@@ -349,9 +349,10 @@ __global__ void __launch_bounds__(256) k_dirac_rhs_vec(Geom gin, MrhsArgs a)
 // its C_inv blocks in registers.  The right-hand sides then follow one another: each is staged
 // in LDS as stored (FP16 with its site scales, or FP32); in-block neighbours and backward links
 // are read from LDS and the others (sites on the block's faces) from global memory; row 2 of a
-// link is rebuilt where it is used.  The vector kernels read every link and C_inv block again, from L2, for each group of
-// right-hand sides; here the block's own fields are read once per tile, and a right-hand side
-// costs its own spinor, its cross-block neighbours (with their links) and the output.
+// link is rebuilt where it is used.  The vector kernels read every link and C_inv block again,
+// from L2, for each group of right-hand sides; here the block's own fields are read once per
+// tile, and a right-hand side costs its own spinor, its cross-block neighbours (with their
+// links) and the output.
 template <int PIN> struct ResT;
 template <> struct ResT<1> { using T = float2; };
 template <> struct ResT<2> { using T = __half2; };
